@@ -1,0 +1,192 @@
+/* qtx_rgf.h -- C ABI of the MI355X (gfx950) selected Green's-function solver.
+ *
+ * The library solves, independently for every energy E, the selected
+ * quadratic system of the paper (Section II-A, Eq. 2, G row of Table I):
+ *
+ *     M(E) = E*S - H - Sigma^R(E),   G^R = M^-1,
+ *     G^< = G^R Sigma^< G^R^H,       G^> = G^R Sigma^> G^R^H,
+ *
+ * returning only the blocks on the block-tridiagonal (BT) pattern: the
+ * diagonal and first off-diagonal blocks of G^R, and the diagonal and upper
+ * blocks of G^< / G^> (their lower blocks are -(upper)^H because lesser and
+ * greater functions are skew-Hermitian, Section II-A).  The method is block
+ * Gaussian elimination (Section IV-A) in its recursive Green's function
+ * form; each Schur complement is inverted by Gauss-Jordan elimination with
+ * partial pivoting in FP64.  The complex block products can run in FP64 or
+ * in lower precision on the matrix cores (Section IV, Section V-A); the
+ * inversions and the final accumulations of G^< / G^> stay FP64.
+ *
+ * Conventions shared by every entry point:
+ *  - Complex numbers are complex128: two doubles (re, im), interleaved.
+ *  - A b x b block is row-major and contiguous (b*b complex elements).
+ *  - Block arrays are contiguous: a per-device array [k][b][b]; a per-energy
+ *    array [n_e][k][b][b] (energy-major).
+ *  - Unless stated otherwise, array pointers are DEVICE pointers of the
+ *    context's device.  The caller allocates and owns every input and output
+ *    buffer; the library never keeps a caller pointer after the enqueued work
+ *    has completed.
+ *  - Calls validate their arguments synchronously, return a qtx_status, and
+ *    enqueue work on the given HIP stream (NULL = the default stream).  On an
+ *    argument error nothing is enqueued.  Inputs must not change and outputs
+ *    must not be read until the stream has passed the enqueued work.
+ *  - No exception crosses the ABI.  A context is not thread-safe: use one
+ *    host thread per context (several contexts may coexist).
+ *  - Outputs must not alias inputs.
+ */
+#ifndef QTX_RGF_H
+#define QTX_RGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qtx_rgf_ctx_s* qtx_rgf_ctx;
+
+typedef enum {
+  QTX_OK = 0,
+  QTX_ERR_ARG = 1,          /* invalid argument (nothing enqueued)                 */
+  QTX_ERR_NOMEM = 2,        /* workspace could not be allocated                    */
+  QTX_ERR_HIP = 3,          /* a HIP runtime call failed (sticky for the context)  */
+  QTX_ERR_UNSUPPORTED = 4,  /* valid request this build does not implement          */
+  QTX_ERR_SINGULAR = 5,     /* per energy: an exactly zero pivot in an inversion   */
+  QTX_ERR_NONFINITE = 6     /* per energy: NaN or Inf in the result                */
+} qtx_status;
+
+/* Arithmetic of the complex block products (Section IV: the ZGEMMs).
+ * QTX_FP64     : FP64 matrix cores (reference path).
+ * QTX_FP32     : operands rounded to FP32, FP32 matrix cores, FP32 accumulation.
+ * QTX_BF16_SPLIT / QTX_FP16_SPLIT : each operand split into n_slices terms of
+ *   the 16-bit format after power-of-two scaling per row (left operand) and per
+ *   column (right operand); slice products with i + j <= n_slices + 1 on the
+ *   matrix cores with FP32 accumulation, recombined in FP64 (Ozaki scheme I,
+ *   Section II-D).  n_slices = 2 is the "3-term" split (hi*hi + hi*lo + lo*hi).
+ * Inversions and the G^< / G^> epilogue sums are FP64 in every mode. */
+typedef enum {
+  QTX_FP64 = 0,
+  QTX_FP32 = 1,
+  QTX_BF16_SPLIT = 2,
+  QTX_FP16_SPLIT = 3
+} qtx_prec;
+
+enum {
+  QTX_S_IDENTITY = 1u,      /* S = I: S_d/S_u/S_l are ignored                        */
+  QTX_WANT_GREATER = 8u     /* also compute G^> from Sigma^> (SG_*)                   */
+};
+
+/* One BT problem: one device (H, S) and n_e energies.
+ * Inputs (device pointers unless noted):
+ *   energies  HOST pointer, [n_e] doubles (real energies).
+ *   H_d [n_b][b][b], H_u [n_b-1][b][b] = H_{i,i+1}, H_l [n_b-1][b][b] = H_{i+1,i}.
+ *   S_d/S_u/S_l  same layout as H (ignored with QTX_S_IDENTITY).
+ *   SR_d [n_e][n_b][b][b]   retarded self-energy, diagonal blocks (required).
+ *   SR_u/SR_l [n_e][n_b-1][b][b]  off-diagonal blocks of Sigma^R, or NULL (= 0).
+ *   SL_d [n_e][n_b][b][b]   lesser self-energy, diagonal blocks (required).
+ *   SL_u/SL_l  must be NULL in this build (block-diagonal Sigma^<), else
+ *              QTX_ERR_UNSUPPORTED.
+ *   SG_d  greater self-energy diagonal blocks (required with QTX_WANT_GREATER).
+ *   Sigma^< and Sigma^> must be skew-Hermitian (as lesser/greater functions
+ *   are): the backward pass uses that symmetry for one of its products.
+ * Outputs (device, caller-allocated, written entirely):
+ *   GR_d [n_e][n_b][b][b], GR_u [n_e][n_b-1][b][b] = G^R_{i,i+1},
+ *   GR_l [n_e][n_b-1][b][b] = G^R_{i+1,i},
+ *   GL_d [n_e][n_b][b][b], GL_u [n_e][n_b-1][b][b] = G^<_{i,i+1},
+ *   GG_d, GG_u  same as GL_* for G^> (with QTX_WANT_GREATER, else ignored).
+ *   status  [n_e] int32 per-energy qtx_status (QTX_OK, QTX_ERR_SINGULAR or
+ *           QTX_ERR_NONFINITE), or NULL.  An energy that fails has every
+ *           output block filled with NaN; other energies are unaffected.
+ * Limits: 1 <= b <= 1024, n_b >= 1, n_e >= 1. */
+typedef struct {
+  int32_t n_b, b, n_e;
+  int32_t prec;            /* qtx_prec                                          */
+  int32_t n_slices;        /* split modes: slices per operand, 0 = default (2)  */
+  uint32_t flags;          /* QTX_S_IDENTITY | QTX_WANT_GREATER                  */
+  const double* energies;  /* host                                              */
+  const void *H_d, *H_u, *H_l;
+  const void *S_d, *S_u, *S_l;
+  const void *SR_d, *SR_u, *SR_l;
+  const void *SL_d, *SL_u, *SL_l;
+  const void *SG_d, *SG_u, *SG_l;
+  void *GR_d, *GR_u, *GR_l;
+  void *GL_d, *GL_u;
+  void *GG_d, *GG_u;
+  int32_t* status;
+} qtx_rgf_problem;
+
+/* Create a context on HIP device `device`.  workspace_bytes caps the device
+ * workspace the context may hold (0 = automatic: up to 1/4 of the device's
+ * free memory at the first solve); energies are processed in chunks that fit.
+ * tune_cache_path: optional JSON file of tile choices (may be NULL).
+ * Returns QTX_ERR_ARG for a NULL `out` or an invalid device. */
+qtx_status qtx_rgf_create(qtx_rgf_ctx* out, int device, size_t workspace_bytes,
+                          const char* tune_cache_path);
+
+/* Solve n_probs problems (Section II-A, Eq. 2), enqueued on hip_stream
+ * (a hipStream_t, NULL = default stream).  Problems may differ in n_b, b,
+ * n_e and precision.  Validation is synchronous (QTX_ERR_ARG /
+ * QTX_ERR_UNSUPPORTED / QTX_ERR_NOMEM with nothing enqueued).  The per-energy
+ * numerical status lands in each problem's `status` array. */
+qtx_status qtx_rgf_solve(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int32_t n_probs,
+                         void* hip_stream);
+
+/* Free the context and its workspace (synchronizes the device first). */
+qtx_status qtx_rgf_destroy(qtx_rgf_ctx ctx);
+
+/* Device workspace bytes one energy of problem p needs; used for admission by
+ * HBM footprint.  Returns 0 for an invalid problem. */
+size_t qtx_rgf_footprint(const qtx_rgf_problem* p);
+
+/* Human-readable name of a status code (static string). */
+const char* qtx_status_str(qtx_status s);
+
+/* ---------------------------------------------------------------------------
+ * Kernel-level entry points (the building blocks of qtx_rgf_solve), exposed
+ * so each can be checked in isolation.
+ * ------------------------------------------------------------------------ */
+
+/* Batched complex GEMM  C_z = alpha * op(A_z) op(B_z) + beta * C_z,  z < batch,
+ * the complex block product of Section IV.  op: 'N' (as is) or 'C' (conjugate
+ * transpose).  op(A) is M x K, op(B) is K x N, C is M x N; all row-major with
+ * leading dimensions lda/ldb/ldc (in complex elements) and batch strides
+ * sA/sB/sC (in complex elements; 0 = the same matrix for every z).
+ * alpha, beta: complex (re, im) given as two doubles each.  prec: qtx_prec,
+ * n_slices as in qtx_rgf_problem.  beta = 0 never reads C.
+ * Limits: M, N, K >= 0, batch >= 1. */
+qtx_status qtx_zgemm(qtx_rgf_ctx ctx, char opA, char opB, int32_t M, int32_t N, int32_t K,
+                     double alpha_re, double alpha_im,
+                     const void* A, int64_t lda, int64_t sA,
+                     const void* B, int64_t ldb, int64_t sB,
+                     double beta_re, double beta_im,
+                     void* C, int64_t ldc, int64_t sC,
+                     int32_t batch, int32_t prec, int32_t n_slices, void* hip_stream);
+
+/* Batched inverse of n x n complex matrices by Gauss-Jordan elimination with
+ * partial pivoting (pivot = largest |re|+|im| among the rows not yet used,
+ * lowest row on ties), FP64 throughout.  A: [batch] matrices with stride sA
+ * (complex elements), row-major, leading dimension n; Ainv: output, same
+ * layout with stride sAinv.  A is not modified.  status: device [batch] int32
+ * (QTX_OK or QTX_ERR_SINGULAR; a singular matrix's inverse is NaN-filled), or
+ * NULL.  Limits: 1 <= n <= 1024. */
+qtx_status qtx_zinv(qtx_rgf_ctx ctx, int32_t n, const void* A, int64_t sA,
+                    void* Ainv, int64_t sAinv, int32_t batch, int32_t* status, void* hip_stream);
+
+/* Transport observables per energy from solver outputs (Section II-B uses the
+ * current as the accuracy criterion).  With A_11 = i(G^R_11 - G^R_11^H):
+ *   T_L[e] = Tr[Gamma_L A_11] - Tr[Gamma_L G^R_11 Gamma_L G^R_11^H]
+ *   j_L[e] = Re(i Tr[Gamma_L G^<_11]) + f_L[e] Tr[Gamma_L A_11]
+ * GR_11 / GL_11: [n_e] blocks with batch stride sG (complex elements), e.g.
+ * the solver's GR_d / GL_d with sG = n_b*b*b.  gamma_L: b x b device matrix
+ * (shared by all energies).  f_L: device [n_e] doubles.  T_L, j_L: device
+ * [n_e] double outputs.  Uses per-context scratch. */
+qtx_status qtx_rgf_observables(qtx_rgf_ctx ctx, int32_t b, int32_t n_e,
+                               const void* GR_11, const void* GL_11, int64_t sG,
+                               const void* gamma_L, const double* f_L,
+                               double* T_L, double* j_L, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QTX_RGF_H */

@@ -1,0 +1,111 @@
+// Small HBM-bound helper kernels: status handling, NaN fill of failed energies,
+// and the per-energy transport observables (traces of block products).
+#include "qtx_internal.h"
+
+namespace qtx {
+
+namespace {
+
+__global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Fill the per_batch elements of batch entry z with NaN when status[z] != 0.
+__global__ void nan_fill_kernel(double2* X, int64_t per_batch, int64_t stride, const int32_t* status) {
+  const int z = blockIdx.y;
+  if (status[z] == 0) return;
+  const double nan = __builtin_nan("");
+  double2* Xz = X + (int64_t)z * stride;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per_batch; i += (int64_t)gridDim.x * blockDim.x)
+    Xz[i] = cmk(nan, nan);
+}
+
+// status[z] = NONFINITE if any of the per_batch elements of entry z is NaN/Inf
+// (only a status that is still OK is changed).
+__global__ void check_finite_kernel(const double2* X, int64_t per_batch, int64_t stride, int32_t* status) {
+  const int z = blockIdx.y;
+  const double2* Xz = X + (int64_t)z * stride;
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per_batch; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = Xz[i];
+    bad |= !(isfinite(v.x) && isfinite(v.y));
+  }
+  bad = __syncthreads_or(bad);
+  if (bad && threadIdx.x == 0) atomicCAS(status + z, 0, 6);   // QTX_ERR_NONFINITE
+}
+
+// Per energy e (one workgroup): with M1 = Gamma G, M2 = Gamma G^H,
+//   Tr[Gamma A] = Re(i (Tr M1 - Tr M2)),   Tr[Gamma G Gamma G^H] = Tr[M1 M2],
+//   T = Tr[Gamma A] - Re Tr[M1 M2],  j = Re(i Tr[Gamma G^<]) + f Tr[Gamma A].
+// Fixed-order FP64 reduction (deterministic).
+__global__ __launch_bounds__(256) void observables_kernel(int b, const double2* GL, int64_t sG,
+                                                          const double2* M1, const double2* M2,
+                                                          const double2* gam, const double* fL,
+                                                          double* T, double* jout) {
+  const int e = blockIdx.x;
+  const double2* m1 = M1 + (int64_t)e * b * b;
+  const double2* m2 = M2 + (int64_t)e * b * b;
+  const double2* gl = GL + (int64_t)e * sG;
+  double acc[6] = {0, 0, 0, 0, 0, 0};   // Tr M1M2 (re), Im Tr M1, Im Tr M2, Tr Gamma G^< (re, im), unused
+  const int64_t bb = (int64_t)b * b;
+  for (int64_t idx = threadIdx.x; idx < bb; idx += blockDim.x) {
+    const int i = (int)(idx / b), j = (int)(idx - (int64_t)i * b);
+    const double2 p = cmul(m1[idx], m2[(int64_t)j * b + i]);
+    acc[0] += p.x;
+    const double2 q = cmul(gam[idx], gl[(int64_t)j * b + i]);
+    acc[3] += q.x;
+    acc[4] += q.y;
+    if (i == j) { acc[1] += m1[idx].y; acc[2] += m2[idx].y; }
+  }
+  __shared__ double sh[5][256];
+  for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double trGA = -(sh[1][0] - sh[2][0]);      // Re(i z) = -Im z
+    T[e] = trGA - sh[0][0];
+    jout[e] = -sh[4][0] + fL[e] * trGA;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_nan_fill_failed(double2* X, int64_t per_batch, int64_t stride, int batch,
+                                  const int32_t* status, hipStream_t s) {
+  if (per_batch <= 0 || batch <= 0) return hipSuccess;
+  int64_t g = (per_batch + 1023) / 1024;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(nan_fill_kernel, dim3((unsigned)g, batch), dim3(256), 0, s, X, per_batch, stride, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double2* X, int64_t per_batch, int64_t stride, int batch,
+                               int32_t* status, hipStream_t s) {
+  if (per_batch <= 0 || batch <= 0) return hipSuccess;
+  int64_t g = (per_batch + 1023) / 1024;
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)g, batch), dim3(256), 0, s, X, per_batch, stride, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_observables(int b, int n_e, const double2* G, const double2* GL, int64_t sG,
+                              const double2* M1, const double2* M2, const double2* gam,
+                              const double* fL, double* T, double* j, hipStream_t s) {
+  (void)G;
+  if (n_e <= 0) return hipSuccess;
+  hipLaunchKernelGGL(observables_kernel, dim3(n_e), dim3(256), 0, s, b, GL, sG, M1, M2, gam, fL, T, j);
+  return hipGetLastError();
+}
+
+}  // namespace qtx

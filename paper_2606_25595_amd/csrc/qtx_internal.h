@@ -1,0 +1,88 @@
+// Internal declarations shared by the gfx950 kernels and the host engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace qtx {
+
+// ---------------------------------------------------------------- complex helpers
+__host__ __device__ inline double2 cmk(double re, double im) { double2 r; r.x = re; r.y = im; return r; }
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return cmk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return cmk(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+  return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cconj(double2 a) { return cmk(a.x, -a.y); }
+__host__ __device__ inline double2 cinv(double2 a) {
+  // 1/a with Smith's scaling to avoid overflow of |a|^2
+  if (fabs(a.x) >= fabs(a.y)) {
+    double r = a.y / a.x, den = a.x + a.y * r;
+    return cmk(1.0 / den, -r / den);
+  } else {
+    double r = a.x / a.y, den = a.x * r + a.y;
+    return cmk(r / den, -1.0 / den);
+  }
+}
+
+enum Op { OP_N = 0, OP_C = 1 };
+
+// An epilogue addend: out += coef * (scale_by_batch ? bscal[z] : 1) * op(X_z)
+struct Addend {
+  const double2* X = nullptr;
+  int64_t ld = 0, stride = 0;
+  double2 coef = {0.0, 0.0};
+  int op = OP_N;
+  int scale_by_batch = 0;
+};
+
+constexpr int kMaxAddends = 3;
+
+// Batched complex GEMM with a fused epilogue:
+//   C_z = alpha * op(A_z) op(B_z) + sum_t addend_t + diag * (diag_by_batch ? bscal[z] : 1) * I
+// op(A) is M x K, op(B) is K x N, C is M x N, row-major; batch strides in elements.
+struct GemmDesc {
+  int M = 0, N = 0, K = 0;
+  int opA = OP_N, opB = OP_N;
+  const double2* A = nullptr; int64_t lda = 0, sA = 0;
+  const double2* B = nullptr; int64_t ldb = 0, sB = 0;
+  double2* C = nullptr; int64_t ldc = 0, sC = 0;
+  double2 alpha = {1.0, 0.0};
+  Addend add[kMaxAddends];
+  double2 diag = {0.0, 0.0};
+  int diag_by_batch = 0;
+  const double* bscal = nullptr;   // per-batch real scalars (the energies), device
+  int batch = 1;
+};
+
+// Precision schemes of the complex block products.
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16_SPLIT = 2, PREC_FP16_SPLIT = 3 };
+
+hipError_t launch_zgemm_f64(const GemmDesc& d, hipStream_t s);
+
+// Gauss-Jordan inversion with implicit partial pivoting, batched.
+// X_z (n x n, ld n, stride sX) is overwritten; the inverse is written to Out_z.
+struct GjeWork {
+  double2* Wp = nullptr;      // [batch][n][nb]   panel transform minus pivot unit columns
+  double2* Tp = nullptr;      // [batch][nb][n]   pivot rows (panel columns zeroed)
+  int32_t* prow = nullptr;    // [batch][n]       physical pivot row of each step
+  int32_t* used = nullptr;    // [batch][n]       row already used as pivot
+};
+int gje_panel_width(int n);
+size_t gje_work_bytes(int n, int batch);
+GjeWork gje_carve(void* base, int n, int batch);
+hipError_t launch_gje_invert(int n, double2* X, int64_t sX, double2* Out, int64_t sOut, int batch,
+                             const GjeWork& w, int32_t* status, hipStream_t s);
+
+// Status / NaN fill / observables helpers.
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_nan_fill_failed(double2* X, int64_t per_batch, int64_t stride, int batch,
+                                  const int32_t* status, hipStream_t s);
+hipError_t launch_check_finite(const double2* X, int64_t per_batch, int64_t stride, int batch,
+                               int32_t* status, hipStream_t s);
+hipError_t launch_observables(int b, int n_e, const double2* G, const double2* GL, int64_t sG,
+                              const double2* M1, const double2* M2, const double2* gam,
+                              const double* fL, double* T, double* j, hipStream_t s);
+
+}  // namespace qtx

@@ -271,3 +271,51 @@ def bt_from_dense(M: np.ndarray, n_b: int):
     lo = np.stack([M[(i + 1) * b:(i + 2) * b, i * b:(i + 1) * b] for i in range(n_b - 1)]) if n_b > 1 \
         else np.zeros((0, b, b), M.dtype)
     return np.ascontiguousarray(d), np.ascontiguousarray(u), np.ascontiguousarray(lo)
+
+
+# --------------------------------------------------------------------------
+# Device-side construction of large synthetic workloads
+# --------------------------------------------------------------------------
+
+def random_bt_scalars(n_b: int, energies, eta: float = 1e-3, gamma: float = 0.5, mu_L: float = 0.1,
+                      mu_R: float = -0.1, kT: float = 0.025):
+    """Per-(energy, block) scalars of the synthetic device's self-energies:
+    Sigma^R_ii = sr[e, i] * I and Sigma^<_ii = sl[e, i] * I (same recipe as
+    random_bt_problem, so host and device inputs are bitwise identical)."""
+    energies = np.atleast_1d(np.asarray(energies, dtype=np.float64))
+    gam = np.zeros(n_b)
+    gam[0] += gamma
+    gam[-1] += gamma
+    broad = eta + gam
+    mu = np.linspace(mu_L, mu_R, n_b)
+    f = fermi(energies[:, None], mu[None, :], kT)
+    sr = np.broadcast_to(-1j * broad[None, :], (energies.size, n_b)).astype(np.complex128)
+    sl = (2j * f * broad[None, :]).astype(np.complex128)
+    return sr, sl
+
+
+def diag_blocks_device(scal: np.ndarray, b: int, device="cuda"):
+    """[n_e][n_b] complex scalars -> device tensor [n_e][n_b][b][b] of scal*I."""
+    import torch
+    n_e, n_b = scal.shape
+    out = torch.zeros((n_e, n_b, b, b), dtype=torch.complex128, device=device)
+    s = torch.from_numpy(np.ascontiguousarray(scal)).to(device)
+    idx = torch.arange(b, device=device)
+    out[:, :, idx, idx] = s[:, :, None].expand(n_e, n_b, b)
+    return out
+
+
+def device_random_problem(n_b: int, b: int, energies, seed: int = 0, device="cuda", **kw):
+    """The synthetic device of random_bt_problem with its per-energy
+    self-energies built directly in device memory (no host copy of the
+    [n_e][n_b][b][b] arrays).  Returns a dict of device tensors plus the host
+    energies; values are bitwise equal to random_bt_problem's."""
+    import torch
+    energies = np.atleast_1d(np.asarray(energies, dtype=np.float64))
+    H_d, H_u, H_l = random_hamiltonian(n_b, b, seed)
+    sr, sl = random_bt_scalars(n_b, energies, **kw)
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    return dict(energies=energies, H_d=dev(H_d), H_u=dev(H_u), H_l=dev(H_l),
+                SR_d=diag_blocks_device(sr, b, device), SL_d=diag_blocks_device(sl, b, device))

@@ -1,0 +1,305 @@
+"""Python binding of libqtx_rgf.so (ctypes; argument marshalling only).
+
+Every step of the solve runs in the library's HIP kernels; torch provides the
+device memory (complex128 tensors) and the current HIP stream.  The names
+mirror the C ABI in include/qtx_rgf.h:
+
+  Context                  qtx_rgf_create / qtx_rgf_destroy
+  Context.solve            qtx_rgf_solve
+  Context.footprint        qtx_rgf_footprint
+  Context.zgemm            qtx_zgemm
+  Context.zinv             qtx_zinv
+  Context.observables      qtx_rgf_observables
+
+There is no fallback: if the shared library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqtx_rgf.so")
+
+QTX_OK, QTX_ERR_ARG, QTX_ERR_NOMEM, QTX_ERR_HIP, QTX_ERR_UNSUPPORTED, QTX_ERR_SINGULAR, QTX_ERR_NONFINITE = range(7)
+QTX_FP64, QTX_FP32, QTX_BF16_SPLIT, QTX_FP16_SPLIT = range(4)
+QTX_S_IDENTITY = 1
+QTX_WANT_GREATER = 8
+PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16": QTX_FP16_SPLIT}
+
+EXPORTED = ("qtx_rgf_create", "qtx_rgf_solve", "qtx_rgf_destroy", "qtx_rgf_footprint", "qtx_status_str",
+            "qtx_zgemm", "qtx_zinv", "qtx_rgf_observables")
+
+
+class QtxError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__("%s failed: %s" % (what, status_str(code)))
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("n_b", ctypes.c_int32), ("b", ctypes.c_int32), ("n_e", ctypes.c_int32),
+        ("prec", ctypes.c_int32), ("n_slices", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("energies", ctypes.POINTER(ctypes.c_double)),
+        ("H_d", ctypes.c_void_p), ("H_u", ctypes.c_void_p), ("H_l", ctypes.c_void_p),
+        ("S_d", ctypes.c_void_p), ("S_u", ctypes.c_void_p), ("S_l", ctypes.c_void_p),
+        ("SR_d", ctypes.c_void_p), ("SR_u", ctypes.c_void_p), ("SR_l", ctypes.c_void_p),
+        ("SL_d", ctypes.c_void_p), ("SL_u", ctypes.c_void_p), ("SL_l", ctypes.c_void_p),
+        ("SG_d", ctypes.c_void_p), ("SG_u", ctypes.c_void_p), ("SG_l", ctypes.c_void_p),
+        ("GR_d", ctypes.c_void_p), ("GR_u", ctypes.c_void_p), ("GR_l", ctypes.c_void_p),
+        ("GL_d", ctypes.c_void_p), ("GL_u", ctypes.c_void_p),
+        ("GG_d", ctypes.c_void_p), ("GG_u", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libqtx_rgf.so not found at %s: run __graft_entry__.build() "
+                          "(or python -m paper_2606_25595_amd.build_lib) first" % path)
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    lib.qtx_rgf_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, sz, ctypes.c_char_p]
+    lib.qtx_rgf_create.restype = ctypes.c_int
+    lib.qtx_rgf_solve.argtypes = [vp, ctypes.POINTER(_Problem), i32, vp]
+    lib.qtx_rgf_solve.restype = ctypes.c_int
+    lib.qtx_rgf_destroy.argtypes = [vp]
+    lib.qtx_rgf_destroy.restype = ctypes.c_int
+    lib.qtx_rgf_footprint.argtypes = [ctypes.POINTER(_Problem)]
+    lib.qtx_rgf_footprint.restype = sz
+    lib.qtx_status_str.argtypes = [ctypes.c_int]
+    lib.qtx_status_str.restype = ctypes.c_char_p
+    lib.qtx_zgemm.argtypes = [vp, ctypes.c_char, ctypes.c_char, i32, i32, i32, dbl, dbl, vp, i64, i64, vp, i64, i64,
+                              dbl, dbl, vp, i64, i64, i32, i32, i32, vp]
+    lib.qtx_zgemm.restype = ctypes.c_int
+    lib.qtx_zinv.argtypes = [vp, i32, vp, i64, vp, i64, i32, vp, vp]
+    lib.qtx_zinv.restype = ctypes.c_int
+    lib.qtx_rgf_observables.argtypes = [vp, i32, i32, vp, vp, i64, vp, vp, vp, vp, vp]
+    lib.qtx_rgf_observables.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def status_str(code: int) -> str:
+    return load_library().qtx_status_str(int(code)).decode()
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+@dataclasses.dataclass
+class DeviceProblem:
+    """Device tensors of one problem (inputs and caller-allocated outputs)."""
+    energies: np.ndarray
+    H_d: object
+    H_u: object
+    H_l: object
+    SR_d: object
+    SL_d: object
+    GR_d: object
+    GR_u: object
+    GR_l: object
+    GL_d: object
+    GL_u: object
+    status: object
+    S_d: object = None
+    S_u: object = None
+    S_l: object = None
+    SR_u: object = None
+    SR_l: object = None
+    SG_d: object = None
+    GG_d: object = None
+    GG_u: object = None
+
+    @property
+    def n_b(self):
+        return int(self.H_d.shape[0])
+
+    @property
+    def b(self):
+        return int(self.H_d.shape[1])
+
+    @property
+    def n_e(self):
+        return int(self.energies.shape[0])
+
+    def outputs(self):
+        """Host copies of the outputs, keyed like the oracle's results."""
+        out = {k: getattr(self, k).cpu().numpy() for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")}
+        if self.GG_d is not None:
+            out["GG_d"] = self.GG_d.cpu().numpy()
+            out["GG_u"] = self.GG_u.cpu().numpy()
+        out["status"] = self.status.cpu().numpy()
+        return out
+
+
+def to_device(p, device="cuda", greater: Optional[bool] = None) -> DeviceProblem:
+    """Copy a host problem (paper_2606_25595_amd.inputs.BTProblem) to the device
+    and allocate its outputs (uninitialised)."""
+    import torch
+
+    def dev(a):
+        if a is None:
+            return None
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to(device)
+
+    n_e, n_b, b = p.n_e, p.n_b, p.b
+    if greater is None:
+        greater = p.SG_d is not None
+    kw = dict(dtype=torch.complex128, device=device)
+    dp = DeviceProblem(
+        energies=np.ascontiguousarray(p.energies, dtype=np.float64),
+        H_d=dev(p.H_d), H_u=dev(p.H_u), H_l=dev(p.H_l), SR_d=dev(p.SR_d), SL_d=dev(p.SL_d),
+        GR_d=torch.empty((n_e, n_b, b, b), **kw), GR_u=torch.empty((n_e, max(n_b - 1, 0), b, b), **kw),
+        GR_l=torch.empty((n_e, max(n_b - 1, 0), b, b), **kw), GL_d=torch.empty((n_e, n_b, b, b), **kw),
+        GL_u=torch.empty((n_e, max(n_b - 1, 0), b, b), **kw),
+        status=torch.full((n_e,), -1, dtype=torch.int32, device=device),
+        S_d=dev(p.S_d), S_u=dev(p.S_u), S_l=dev(p.S_l), SR_u=dev(p.SR_u), SR_l=dev(p.SR_l))
+    if greater:
+        dp.SG_d = dev(p.SG_d)
+        dp.GG_d = torch.empty((n_e, n_b, b, b), **kw)
+        dp.GG_u = torch.empty((n_e, max(n_b - 1, 0), b, b), **kw)
+    return dp
+
+
+def _problem_struct(dp: DeviceProblem, prec: int, n_slices: int):
+    st = _Problem()
+    st.n_b, st.b, st.n_e = dp.n_b, dp.b, dp.n_e
+    st.prec, st.n_slices = int(prec), int(n_slices)
+    flags = 0
+    if dp.S_d is None:
+        flags |= QTX_S_IDENTITY
+    if dp.GG_d is not None:
+        flags |= QTX_WANT_GREATER
+    st.flags = flags
+    en = np.ascontiguousarray(dp.energies, dtype=np.float64)
+    st.energies = en.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for name in ("H_d", "H_u", "H_l", "S_d", "S_u", "S_l", "SR_d", "SR_u", "SR_l", "SL_d", "SG_d",
+                 "GR_d", "GR_u", "GR_l", "GL_d", "GL_u", "GG_d", "GG_u", "status"):
+        t = getattr(dp, name)
+        if t is not None and t.numel() == 0:
+            t = None
+        setattr(st, name, _ptr(t))
+    return st, en
+
+
+class Context:
+    """One library context on one device (qtx_rgf_create)."""
+
+    def __init__(self, device: int = 0, workspace_bytes: int = 0, tune_cache: Optional[str] = None):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        rc = self.lib.qtx_rgf_create(ctypes.byref(h), int(device), int(workspace_bytes),
+                                     tune_cache.encode() if tune_cache else None)
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_rgf_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.qtx_rgf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- qtx_rgf_solve
+    def solve(self, problems, prec="fp64", n_slices: int = 0, stream=None, check: bool = True) -> int:
+        if isinstance(problems, DeviceProblem):
+            problems = [problems]
+        precs = prec if isinstance(prec, (list, tuple)) else [prec] * len(problems)
+        arr = (_Problem * len(problems))()
+        keep = []
+        for k, (dp, pr) in enumerate(zip(problems, precs)):
+            st, en = _problem_struct(dp, PREC_NAMES.get(pr, pr), n_slices)
+            arr[k] = st
+            keep.append(en)
+        rc = self.lib.qtx_rgf_solve(self.handle, arr, len(problems), _stream_ptr(stream))
+        if check and rc != QTX_OK:
+            raise QtxError(rc, "qtx_rgf_solve")
+        return rc
+
+    def footprint(self, dp: DeviceProblem, prec="fp64") -> int:
+        st, _ = _problem_struct(dp, PREC_NAMES.get(prec, prec), 0)
+        return int(self.lib.qtx_rgf_footprint(ctypes.byref(st)))
+
+    # -- qtx_zgemm:  C = alpha op(A) op(B) + beta C  over a batch
+    def zgemm(self, A, B, C, opA="N", opB="N", alpha=1.0, beta=0.0, prec="fp64", n_slices=0, stream=None,
+              check=True):
+        """A, B, C: complex128 tensors [batch][rows][cols] (or 2-D, batch 1)."""
+        def as3(t):
+            return t if t.dim() == 3 else t.unsqueeze(0)
+        A3, B3, C3 = as3(A), as3(B), as3(C)
+        batch = C3.shape[0]
+        M, N = C3.shape[1], C3.shape[2]
+        K = A3.shape[2] if opA == "N" else A3.shape[1]
+        sA = A3.shape[1] * A3.shape[2] if A3.shape[0] > 1 else 0
+        sB = B3.shape[1] * B3.shape[2] if B3.shape[0] > 1 else 0
+        alpha, beta = complex(alpha), complex(beta)
+        rc = self.lib.qtx_zgemm(self.handle, opA.encode(), opB.encode(), M, N, K, alpha.real, alpha.imag,
+                                _ptr(A3), A3.shape[2], sA, _ptr(B3), B3.shape[2], sB, beta.real, beta.imag,
+                                _ptr(C3), C3.shape[2], M * N, batch, PREC_NAMES.get(prec, prec), n_slices,
+                                _stream_ptr(stream))
+        if check and rc != QTX_OK:
+            raise QtxError(rc, "qtx_zgemm")
+        return rc
+
+    # -- qtx_zinv
+    def zinv(self, A, Ainv, status=None, stream=None, check=True):
+        A3 = A if A.dim() == 3 else A.unsqueeze(0)
+        O3 = Ainv if Ainv.dim() == 3 else Ainv.unsqueeze(0)
+        n = A3.shape[1]
+        rc = self.lib.qtx_zinv(self.handle, n, _ptr(A3), n * n, _ptr(O3), n * n, A3.shape[0], _ptr(status),
+                               _stream_ptr(stream))
+        if check and rc != QTX_OK:
+            raise QtxError(rc, "qtx_zinv")
+        return rc
+
+    # -- qtx_rgf_observables
+    def observables(self, dp: DeviceProblem, gamma_L, f_L, stream=None):
+        """(T_L, j_L) per energy as device float64 tensors."""
+        import torch
+        T = torch.empty(dp.n_e, dtype=torch.float64, device=dp.GR_d.device)
+        j = torch.empty_like(T)
+        fL = torch.as_tensor(np.ascontiguousarray(f_L, dtype=np.float64)).to(dp.GR_d.device)
+        g = torch.as_tensor(np.ascontiguousarray(gamma_L, dtype=np.complex128)).to(dp.GR_d.device)
+        rc = self.lib.qtx_rgf_observables(self.handle, dp.b, dp.n_e, _ptr(dp.GR_d), _ptr(dp.GL_d),
+                                          dp.n_b * dp.b * dp.b, _ptr(g), _ptr(fL), _ptr(T), _ptr(j),
+                                          _stream_ptr(stream))
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_rgf_observables")
+        return T, j

@@ -1,0 +1,280 @@
+"""GPU parity of the HIP library against the FP64 oracle (through the C ABI).
+
+Floating-point bar for the FP64 path: relative Frobenius error per output
+block <= 1e-10 against the oracle.  Eq. 6 predicts an error of about
+kappa * eps_64; kappa(M) <= ||M|| / eta is at most ~5e3 for these inputs
+(eta = 1e-3, |E| <= 2, ||H|| ~ 2.8), i.e. ~1e-12, and 1e-10 leaves margin for
+the accumulation order of the matrix-core products.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_25595_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_25595_amd import qtx
+    c = qtx.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def crand(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def check_blocks(out, ref, tol=TOL, keys=("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")):
+    worst = {}
+    for k in keys:
+        if ref[k].size == 0:
+            continue
+        err = oracle.rel_fro_err(out[k], ref[k])
+        worst[k] = float(err.max())
+        assert err.max() <= tol, "%s: max rel err %.3e (energy %s, block %s)" % (
+            k, err.max(), *np.unravel_index(np.argmax(err), err.shape))
+    return worst
+
+
+# ----------------------------------------------------------------- GEMM kernel
+
+@pytest.mark.parametrize("opA", ["N", "C"])
+@pytest.mark.parametrize("opB", ["N", "C"])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 33, 5), (64, 64, 64), (70, 45, 129), (416, 416, 416)])
+def test_zgemm_fp64(ctx, opA, opB, M, N, K):
+    import torch
+    rng = np.random.default_rng(M * 7 + N * 3 + K)
+    batch = 3
+    A = crand(rng, batch, *((M, K) if opA == "N" else (K, M)))
+    B = crand(rng, batch, *((K, N) if opB == "N" else (N, K)))
+    C0 = crand(rng, batch, M, N)
+    alpha, beta = 0.5 - 1.25j, -1.0 + 0.0j
+    dA, dB, dC = (torch.from_numpy(x).cuda() for x in (A, B, C0))
+    ctx.zgemm(dA, dB, dC, opA=opA, opB=opB, alpha=alpha, beta=beta)
+    got = dC.cpu().numpy()
+    opa = A if opA == "N" else np.conj(np.transpose(A, (0, 2, 1)))
+    opb = B if opB == "N" else np.conj(np.transpose(B, (0, 2, 1)))
+    ref = alpha * (opa @ opb) + beta * C0
+    scale = np.abs(alpha) * np.abs(opa) @ np.abs(opb) + np.abs(beta) * np.abs(C0)
+    assert np.all(np.abs(got - ref) <= 64 * max(K, 1) * 2.2e-16 * scale + 1e-300)
+
+
+def test_zgemm_shared_operand_and_k0(ctx):
+    import torch
+    rng = np.random.default_rng(5)
+    A = crand(rng, 1, 40, 40)            # shared across the batch (stride 0)
+    B = crand(rng, 4, 40, 40)
+    C = torch.zeros(4, 40, 40, dtype=torch.complex128, device="cuda")
+    ctx.zgemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), C)
+    assert rel(C.cpu().numpy(), A @ B) < 1e-14
+
+
+# ----------------------------------------------------------------- inversion kernel
+
+@pytest.mark.parametrize("n", [1, 2, 7, 31, 32, 33, 64, 100, 416, 512, 513, 1000])
+def test_zinv_random(ctx, n):
+    import torch
+    rng = np.random.default_rng(n)
+    batch = 3 if n <= 512 else 2
+    A = crand(rng, batch, n, n)
+    dA = torch.from_numpy(A).cuda()
+    out = torch.empty_like(dA)
+    st = torch.full((batch,), -1, dtype=torch.int32, device="cuda")
+    ctx.zinv(dA, out, st)
+    X = out.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    assert np.array_equal(dA.cpu().numpy(), A)          # input untouched
+    for z in range(batch):
+        ref = np.linalg.inv(A[z])
+        kappa = np.linalg.cond(A[z])
+        assert rel(X[z], ref) <= 200 * kappa * 2.2e-16, (z, rel(X[z], ref), kappa)
+
+
+def test_zinv_forced_pivoting(ctx):
+    """Zero leading entries force row exchanges in every panel."""
+    import torch
+    rng = np.random.default_rng(1)
+    n = 96
+    P = np.eye(n)[rng.permutation(n)]
+    A = (P @ np.diag(rng.uniform(1, 2, n) * np.exp(1j * rng.uniform(0, 6, n))) + 1e-3 * crand(rng, n, n))
+    A[np.abs(A) < 1e-2] = 0.0                           # exact zeros on most of the matrix
+    dA = torch.from_numpy(A[None]).cuda()
+    out = torch.empty_like(dA)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.zinv(dA, out, st)
+    assert st.item() == 0
+    assert rel(out.cpu().numpy()[0], np.linalg.inv(A)) < 1e-12
+
+
+def test_zinv_singular_is_flagged(ctx):
+    import torch
+    rng = np.random.default_rng(2)
+    A = crand(rng, 3, 20, 20)
+    A[1, :, 5] = 0.0                                    # a zero column: exactly singular
+    dA = torch.from_numpy(A).cuda()
+    out = torch.empty_like(dA)
+    st = torch.zeros(3, dtype=torch.int32, device="cuda")
+    ctx.zinv(dA, out, st)
+    s = st.cpu().numpy()
+    X = out.cpu().numpy()
+    assert s[0] == 0 and s[1] == 5 and s[2] == 0
+    assert np.all(np.isnan(X[1]))
+    assert rel(X[0], np.linalg.inv(A[0])) < 1e-12 and rel(X[2], np.linalg.inv(A[2])) < 1e-12
+
+
+# ----------------------------------------------------------------- full solve
+
+def solve_gpu(ctx, p, **kw):
+    from paper_2606_25595_amd import qtx
+    dp = qtx.to_device(p)
+    ctx.solve(dp, **kw)
+    return dp, dp.outputs()
+
+
+def test_rgf_tiny_workload_all_energies(ctx):
+    p = inputs.config_problem("tiny")
+    _, out = solve_gpu(ctx, p)
+    assert np.all(out["status"] == 0)
+    ref = oracle.dense_selected(p)
+    check_blocks(out, ref)
+
+
+@pytest.mark.parametrize("n_b,b,n_e", [(1, 5, 3), (2, 3, 2), (3, 65, 3), (5, 33, 4), (4, 100, 2), (2, 130, 2)])
+def test_rgf_ragged_shapes(ctx, n_b, b, n_e):
+    p = inputs.random_bt_problem(n_b, b, np.linspace(-1.9, 1.7, n_e), seed=n_b * 100 + b)
+    _, out = solve_gpu(ctx, p)
+    assert np.all(out["status"] == 0)
+    check_blocks(out, oracle.rgf_selected(p))
+
+
+def test_rgf_general_overlap_and_bt_sigma_r(ctx):
+    rng = np.random.default_rng(9)
+    n_b, b = 4, 24
+    p = inputs.random_bt_problem(n_b, b, np.array([-0.7, 0.2, 1.1]), seed=4)
+    p.S_d = np.stack([np.eye(b) + 0.05 * (lambda X: X + X.conj().T)(crand(rng, b, b)) for _ in range(n_b)])
+    p.S_u = 0.05 * crand(rng, n_b - 1, b, b)
+    p.S_l = np.ascontiguousarray(np.conj(np.transpose(p.S_u, (0, 2, 1))))
+    p.SR_u = -0.02j * crand(rng, p.n_e, n_b - 1, b, b)
+    p.SR_l = -0.02j * crand(rng, p.n_e, n_b - 1, b, b)
+    _, out = solve_gpu(ctx, p)
+    assert np.all(out["status"] == 0)
+    check_blocks(out, oracle.rgf_selected(p))
+
+
+def test_rgf_greater_and_identity(ctx):
+    p = inputs.random_bt_problem(5, 40, np.linspace(-1.5, 1.5, 5), seed=12, with_greater=True)
+    _, out = solve_gpu(ctx, p)
+    ref = oracle.rgf_selected(p)
+    check_blocks(out, ref, keys=("GR_d", "GR_u", "GR_l", "GL_d", "GL_u", "GG_d", "GG_u"))
+    # G^R - G^A = G^> - G^< on the GPU outputs
+    for k in range(p.n_e):
+        for i in range(p.n_b):
+            lhs = out["GR_d"][k, i] - out["GR_d"][k, i].conj().T
+            assert rel(out["GG_d"][k, i] - out["GL_d"][k, i], lhs) < 1e-10
+
+
+def test_rgf_chain_transmission_is_one(ctx):
+    E = np.array([-1.7, -0.25, 0.4, 1.85, 2.6])
+    p = inputs.uniform_chain(6, 8, E, t=-1.0)
+    dp, out = solve_gpu(ctx, p)
+    gam = np.array([inputs.chain_gamma(x, 0.0, -1.0) for x in E])
+    gL = np.zeros((E.size, 8, 8), complex)
+    gL[:, 0, 0] = gam
+    T = oracle.transmission_left(out["GR_d"][:, 0], gL)
+    np.testing.assert_allclose(T, (np.abs(E) < 2).astype(float), atol=1e-10)
+
+
+def test_rgf_power_of_two_scaling_bitwise(ctx):
+    p = inputs.random_bt_problem(4, 48, np.array([-0.3, 0.9]), seed=21)
+    _, o1 = solve_gpu(ctx, p)
+    q = inputs.BTProblem(**{**p.__dict__})
+    q.SL_d = p.SL_d * 8.0
+    _, o2 = solve_gpu(ctx, q)
+    for k in ("GL_d", "GL_u"):
+        assert np.array_equal(o2[k], o1[k] * 8.0)
+    for k in ("GR_d", "GR_u", "GR_l"):
+        assert np.array_equal(o2[k], o1[k])
+
+
+def test_rgf_energy_alone_equals_in_batch(ctx):
+    p = inputs.random_bt_problem(4, 70, np.linspace(-2, 2, 6), seed=33)
+    _, full = solve_gpu(ctx, p)
+    _, one = solve_gpu(ctx, p.subset([4]))
+    for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u"):
+        assert np.array_equal(one[k][0], full[k][4])
+
+
+def test_rgf_status_singular_and_nonfinite(ctx):
+    p = inputs.random_bt_problem(3, 16, np.array([0.5, 0.25, -0.5]), seed=2)
+    # energy 1: A_0 = E I - H_00 - Sigma^R_00 = 0 exactly (singular first block)
+    p.H_d[0] = 0.25 * np.eye(16)
+    p.SR_d[1, 0] = 0.0
+    # energy 2: NaN in Sigma^<
+    p.SL_d[2, 1, 3, 3] = np.nan
+    _, out = solve_gpu(ctx, p)
+    assert list(out["status"]) == [0, 5, 6]
+    for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u"):
+        assert np.all(np.isnan(out[k][1])) and np.all(np.isnan(out[k][2]))
+        assert np.all(np.isfinite(out[k][0]))
+    ref = oracle.rgf_selected(p.subset([0]))
+    check_blocks({k: v[:1] for k, v in out.items() if k != "status"}, ref)
+
+
+def test_rgf_observables_kernel(ctx):
+    p = inputs.random_bt_problem(4, 32, np.linspace(-1.8, 1.8, 7), seed=5)
+    dp, out = solve_gpu(ctx, p)
+    T, j = ctx.observables(dp, p.gamma_L, p.f_L)
+    ref = oracle.rgf_selected(p)
+    Tref = oracle.transmission_left(ref["GR_d"][:, 0], p.gamma_L)
+    jref = oracle.contact_current_left(ref["GR_d"][:, 0], ref["GL_d"][:, 0], p.gamma_L, p.f_L)
+    np.testing.assert_allclose(T.cpu().numpy(), Tref, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(j.cpu().numpy(), jref, rtol=1e-10, atol=1e-12)
+
+
+def test_abi_argument_errors(ctx):
+    from paper_2606_25595_amd import qtx
+    p = inputs.random_bt_problem(2, 8, np.array([0.1]), seed=1)
+    dp = qtx.to_device(p)
+    dp.H_u = None
+    assert ctx.solve(dp, check=False) == qtx.QTX_ERR_ARG
+    dp = qtx.to_device(p)
+    assert ctx.solve(dp, prec=7, check=False) == qtx.QTX_ERR_UNSUPPORTED
+
+
+# ----------------------------------------------------------------- realistic size, sampled
+
+def test_rgf_realistic_workload_sampled(ctx):
+    """n_b = 32, b = 416, all 256 energies solved in one call (the benchmark's
+    launch configuration); 3 sampled energies checked against the oracle."""
+    import torch
+    from paper_2606_25595_amd import qtx
+    c = inputs.CONFIGS["realistic"]
+    grid = np.linspace(-2.0, 2.0, c["n_e"])
+    d = inputs.device_random_problem(c["n_b"], c["b"], grid, seed=0)
+    kw = dict(dtype=torch.complex128, device="cuda")
+    n_e, n_b, b = c["n_e"], c["n_b"], c["b"]
+    dp = qtx.DeviceProblem(energies=d["energies"], H_d=d["H_d"], H_u=d["H_u"], H_l=d["H_l"], SR_d=d["SR_d"],
+                           SL_d=d["SL_d"], GR_d=torch.empty((n_e, n_b, b, b), **kw),
+                           GR_u=torch.empty((n_e, n_b - 1, b, b), **kw), GR_l=torch.empty((n_e, n_b - 1, b, b), **kw),
+                           GL_d=torch.empty((n_e, n_b, b, b), **kw), GL_u=torch.empty((n_e, n_b - 1, b, b), **kw),
+                           status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"))
+    ctx.solve(dp)
+    torch.cuda.synchronize()
+    assert np.all(dp.status.cpu().numpy() == 0)
+    sample = [0, 133, 255]
+    ref = oracle.rgf_selected(inputs.config_problem("realistic", energy_index=sample))
+    out = {k: getattr(dp, k)[sample].cpu().numpy() for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")}
+    worst = check_blocks(out, ref)
+    print("realistic sampled worst rel err:", worst)
