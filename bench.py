@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Throughput of the selected Green's-function solve on one MI355X.
+
+One step = one qtx_rgf_solve call over the realistic workload: a synthetic
+device with n_b = 32 diagonal blocks of size b = 416 (complex128, S = I,
+random Hermitian H, eta = 1e-3, contact broadening gamma = 0.5) at all 256
+energies of linspace(-2, 2, 256) -- forward and backward passes for G^R and
+G^< with every block inversion, inputs resident in HBM.  The metric is energy
+points per second.  Precision schemes: fp64 (reference) and the mixed schemes
+of the complex block products; `value` is the fastest scheme whose sampled
+per-block error against the FP64 oracle is <= 1e-6 (the FP64 path always
+qualifies), and every scheme's rate and error is reported beside it.
+
+Also reported:
+  roofline     the dominant kernel (the b x b x b complex block products),
+               algorithmic flops per launch / average launch duration, both from
+               HIP events recorded by the library on the launch stream
+  cpu_baseline the FP64 oracle (numpy/LAPACK) on the host cores, on a bounded
+               sample of the same workload's energies, in energy points per second
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precs fp64,...]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "RGF energy points/sec: mixed-prec vs FP64 at rel err ≤1e-6; p50/p99 latency"
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}   # dense TFLOP/s, MI355X
+TOL_MIXED = 1e-6
+PMC_FILE = os.path.join(ROOT, "profiles", "zgemm_f64_product_realistic_pmc.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2606_25595_amd", "csrc", "zgemm_f64.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was
+    taken on the current kernel source (else None)."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    kv = {}
+    for line in open(PMC_FILE):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precs", default="fp64")
+    ap.add_argument("--cpu-energies", type=int, default=8, help="energies in the oracle's timed sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build's hot path runs on a single MI355X; "
+              "energies shard across GPUs with no exchange (see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2606_25595_amd import inputs, qtx
+
+    cfg = inputs.CONFIGS["realistic"]
+    n_b, b, n_e = cfg["n_b"], cfg["b"], cfg["n_e"]
+    grid = np.linspace(-2.0, 2.0, n_e)
+    log("bench: building realistic workload n_b=%d b=%d n_e=%d on the device" % (n_b, b, n_e))
+    d = inputs.device_random_problem(n_b, b, grid, seed=0)
+    kw = dict(dtype=torch.complex128, device="cuda")
+    dp = qtx.DeviceProblem(energies=d["energies"], H_d=d["H_d"], H_u=d["H_u"], H_l=d["H_l"], SR_d=d["SR_d"],
+                           SL_d=d["SL_d"], GR_d=torch.empty((n_e, n_b, b, b), **kw),
+                           GR_u=torch.empty((n_e, n_b - 1, b, b), **kw), GR_l=torch.empty((n_e, n_b - 1, b, b), **kw),
+                           GL_d=torch.empty((n_e, n_b, b, b), **kw), GL_u=torch.empty((n_e, n_b - 1, b, b), **kw),
+                           status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"))
+    ctx = qtx.Context(0)
+    sample = list(range(0, n_e, max(1, n_e // args.cpu_energies)))[: args.cpu_energies]
+
+    # ---- CPU oracle on the sample (also the parity reference for the sampled outputs)
+    ref = None
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([t.get("num_threads", 1) for t in threadpool_info() if t.get("user_api") == "blas"] or [1])
+        except Exception:
+            threads = os.cpu_count() or 1
+        p_s = inputs.config_problem("realistic", energy_index=sample)
+        log("bench: oracle on %d sampled energies (%d BLAS threads)" % (len(sample), threads))
+        t0 = time.perf_counter()
+        ref = oracle.rgf_selected(p_s)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": len(sample) / t_cpu, "unit": "energy points/s", "cores": int(threads), "kind": "oracle",
+               "sample": "%d of the 256 energies (every %dth) of the realistic workload, block recurrences in "
+                         "numpy/LAPACK FP64, %.1f s" % (len(sample), n_e // len(sample), t_cpu)}
+
+    results = {}
+    for prec in args.precs.split(","):
+        log("bench: %s warmup x%d" % (prec, args.warmup))
+        for _ in range(args.warmup):
+            ctx.solve(dp, prec=prec)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read(qtx.QTX_KERNEL_GEMM)
+        ctx.profile_read(qtx.QTX_KERNEL_INV)
+        log("bench: %s timed x%d" % (prec, args.steps))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            ctx.solve(dp, prec=prec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.profile(False)
+        g_ms, g_n, g_fl = ctx.profile_read(qtx.QTX_KERNEL_GEMM)
+        i_ms, i_n, i_fl = ctx.profile_read(qtx.QTX_KERNEL_INV)
+        ms_step = (t1 - t0) * 1e3 / args.steps
+        st = dp.status.cpu().numpy()
+        errs = None
+        if ref is not None:
+            import oracle
+            errs = {}
+            for key in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u"):
+                got = getattr(dp, key)[sample].cpu().numpy()
+                errs[key] = float(oracle.rel_fro_err(got, ref[key]).max())
+        results[prec] = dict(ms_per_step=ms_step, value=n_e / (ms_step / 1e3), status_ok=bool(np.all(st == 0)),
+                             gemm=(g_ms, g_n, g_fl), inv=(i_ms, i_n, i_fl), errs=errs)
+        log("bench: %s %.1f ms/step, %.1f energies/s, gemm avg %.3f ms x%d, inv avg %.3f ms x%d, err %s" % (
+            prec, ms_step, n_e / (ms_step / 1e3), g_ms / max(g_n, 1), g_n, i_ms / max(i_n, 1), i_n, errs))
+
+    # headline: fastest scheme meeting the error bar (FP64 always qualifies)
+    def qualifies(p):
+        r = results[p]
+        if not r["status_ok"]:
+            return False
+        if p == "fp64":
+            return True
+        return r["errs"] is not None and max(r["errs"].values()) <= TOL_MIXED
+    best = max([p for p in results if qualifies(p)] or ["fp64"], key=lambda p: results[p]["value"])
+    r = results[best]
+    g_ms, g_n, g_fl = r["gemm"]
+    achieved = (g_fl / max(g_n, 1)) / (g_ms / max(g_n, 1) / 1e3) / 1e12 if g_n else None
+    peak = PEAK["fp64" if best == "fp64" else best]
+    traffic = traffic_from_profile() if best == "fp64" else None
+    line = {
+        "metric": METRIC,
+        "value": r["value"],
+        "unit": "energy points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if best == "fp64" else "f64+" + best,
+        "data": "synthetic",
+        "config": {"workload": "realistic selected RGF solve: n_b=32 blocks, b=416, N_E=256 energies in [-2,2], "
+                               "complex128, S=I, random Hermitian H (seed 0), eta=1e-3, gamma=0.5",
+                   "precision": best, "energies_per_step": n_e},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": (achieved / peak) if achieved else None, "traffic": traffic,
+                     "kernel": "zgemm_f64_kernel<N|C,N|C,product> (b x b x b complex block products)",
+                     "flops_per_launch": g_fl / max(g_n, 1), "avg_launch_ms": g_ms / max(g_n, 1),
+                     "launches": g_n},
+        "cpu_baseline": cpu,
+        "schemes": {p: {"energies_per_s": v["value"], "ms_per_step": v["ms_per_step"], "max_rel_err": v["errs"],
+                        "status_ok": v["status_ok"],
+                        "gemm_tflops_fp64eq": (v["gemm"][2] / (v["gemm"][0] / 1e3) / 1e12) if v["gemm"][1] else None,
+                        "inversion_ms_per_step": v["inv"][0] / args.steps,
+                        "gemm_ms_per_step": v["gemm"][0] / args.steps}
+                    for p, v in results.items()},
+        "fp64_energies_per_s": results["fp64"]["value"] if "fp64" in results else None,
+        "algorithmic_tflops_fp64eq": (144 * (n_b - 1) + 24) * b ** 3 * n_e / (r["ms_per_step"] / 1e3) / 1e12,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -185,6 +185,23 @@ qtx_status qtx_rgf_observables(qtx_rgf_ctx ctx, int32_t b, int32_t n_e,
                                const void* gamma_L, const double* f_L,
                                double* T_L, double* j_L, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Per-launch timing of the library's own kernels (roofline measurement).
+ * While enabled, every launch of the families below is bracketed by HIP events
+ * recorded on the stream it runs on.  qtx_rgf_profile_read waits for those
+ * events, returns the summed duration (ms), the launch count and the
+ * algorithmic flop count of the launches since the previous read of that
+ * family, and resets them.  Families:
+ *   QTX_KERNEL_GEMM : the b x b x b complex block products of qtx_rgf_solve,
+ *                     8 b^3 real flop per energy (FP64-equivalent);
+ *   QTX_KERNEL_INV  : one batched inversion of a Schur complement (all panels,
+ *                     trailing updates and the final gather), 8 b^3 per energy.
+ * Any NULL output pointer is skipped. */
+enum { QTX_KERNEL_GEMM = 0, QTX_KERNEL_INV = 1 };
+qtx_status qtx_rgf_profile(qtx_rgf_ctx ctx, int enable);
+qtx_status qtx_rgf_profile_read(qtx_rgf_ctx ctx, int family, double* total_ms, int64_t* launches,
+                                double* flops);
+
 #ifdef __cplusplus
 }
 #endif

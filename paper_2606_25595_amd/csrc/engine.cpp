@@ -33,6 +33,13 @@
 
 using namespace qtx;
 
+struct ProfFamily {
+  struct Rec { hipEvent_t a, b; double flops; };
+  std::vector<Rec> pending;
+  double ms = 0.0, flops = 0.0;
+  int64_t launches = 0;
+};
+
 struct qtx_rgf_ctx_s {
   int device = 0;
   size_t ws_cap = 0;       // 0 = automatic
@@ -40,7 +47,45 @@ struct qtx_rgf_ctx_s {
   size_t ws_size = 0;
   qtx_status sticky = QTX_OK;
   std::string tune_path;
+  bool profiling = false;
+  ProfFamily prof[2];
+  std::vector<hipEvent_t> event_pool;
 };
+
+namespace {
+
+hipEvent_t pool_event(qtx_rgf_ctx ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Bracket a launch with events when profiling is on.
+struct ProfScope {
+  qtx_rgf_ctx ctx;
+  int fam;
+  hipStream_t s;
+  double flops;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(qtx_rgf_ctx c, int f, hipStream_t st, double fl) : ctx(c), fam(f), s(st), flops(fl) {
+    if (!ctx || !ctx->profiling) return;
+    a = pool_event(ctx);
+    b = pool_event(ctx);
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, s);
+    ctx->prof[fam].pending.push_back({a, b, flops});
+  }
+};
+
+}  // namespace
 
 namespace {
 
@@ -137,6 +182,10 @@ struct Gemm {
     d.diag_by_batch = 1;
     d.bscal = energies;
     d.batch = batch;
+    if (d.K == b) {
+      ProfScope ps(ctx, QTX_KERNEL_GEMM, s, 8.0 * (double)b * b * b * batch);
+      return launch_zgemm_f64(d, s);
+    }
     return launch_zgemm_f64(d, s);
   }
 };
@@ -284,7 +333,10 @@ qtx_status solve_chunk(qtx_rgf_ctx ctx, const qtx_rgf_problem& p, int e0, int ne
       QTX_TRY(g.run(OP_N, L, OP_N, Mat{GR_d + (int64_t)(i - 1) * bb, sE, b}, Tm[0], bb, one, {}));
       QTX_TRY(g.run(OP_N, Mat{Tm[0], bb, b}, OP_N, U, X, bb, cmk(-sL * sU, 0), {aa[0], aa[1], aa[2]}, dg));
     }
-    QTX_TRY(launch_gje_invert(b, X, bb, GR_d + (int64_t)i * bb, sE, ne, gw, st, s));
+    {
+      ProfScope ps(ctx, QTX_KERNEL_INV, s, 8.0 * (double)b * b * b * ne);
+      QTX_TRY(launch_gje_invert(b, X, bb, GR_d + (int64_t)i * bb, sE, ne, gw, st, s));
+    }
     const Mat xi{GR_d + (int64_t)i * bb, sE, b};
     for (const Rhs& r : rhs) {
       const double2* Bi = r.B + (int64_t)i * bb;
@@ -383,12 +435,44 @@ qtx_status qtx_rgf_create(qtx_rgf_ctx* out, int device, size_t workspace_bytes, 
   return QTX_OK;
 }
 
+qtx_status qtx_rgf_profile(qtx_rgf_ctx ctx, int enable) {
+  if (!ctx) return QTX_ERR_ARG;
+  ctx->profiling = enable != 0;
+  return QTX_OK;
+}
+
+qtx_status qtx_rgf_profile_read(qtx_rgf_ctx ctx, int family, double* total_ms, int64_t* launches,
+                                double* flops) {
+  if (!ctx || family < 0 || family > 1) return QTX_ERR_ARG;
+  DeviceGuard guard(ctx->device);
+  ProfFamily& f = ctx->prof[family];
+  for (auto& r : f.pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+      return hip_fail(ctx, hipErrorUnknown);
+    f.ms += ms;
+    f.flops += r.flops;
+    f.launches += 1;
+    ctx->event_pool.push_back(r.a);
+    ctx->event_pool.push_back(r.b);
+  }
+  f.pending.clear();
+  if (total_ms) *total_ms = f.ms;
+  if (launches) *launches = f.launches;
+  if (flops) *flops = f.flops;
+  f.ms = 0.0; f.flops = 0.0; f.launches = 0;
+  return QTX_OK;
+}
+
 qtx_status qtx_rgf_destroy(qtx_rgf_ctx ctx) {
   if (!ctx) return QTX_ERR_ARG;
   {
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->ws) (void)hipFree(ctx->ws);
+    for (auto& f : ctx->prof)
+      for (auto& r : f.pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   }
   delete ctx;
   return QTX_OK;

@@ -59,7 +59,9 @@ struct GemmDesc {
 // Precision schemes of the complex block products.
 enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16_SPLIT = 2, PREC_FP16_SPLIT = 3 };
 
-hipError_t launch_zgemm_f64(const GemmDesc& d, hipStream_t s);
+// Kernel symbol families of the complex GEMM (same code, separate names).
+enum GemmKind { GEMM_PRODUCT = 0, GEMM_INV_UPDATE = 1, GEMM_ELEMENTWISE = 2 };
+hipError_t launch_zgemm_f64(const GemmDesc& d, hipStream_t s, int kind = GEMM_PRODUCT);
 
 // Gauss-Jordan inversion with implicit partial pivoting, batched.
 // X_z (n x n, ld n, stride sX) is overwritten; the inverse is written to Out_z.

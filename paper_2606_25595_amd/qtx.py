@@ -32,7 +32,8 @@ QTX_WANT_GREATER = 8
 PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16": QTX_FP16_SPLIT}
 
 EXPORTED = ("qtx_rgf_create", "qtx_rgf_solve", "qtx_rgf_destroy", "qtx_rgf_footprint", "qtx_status_str",
-            "qtx_zgemm", "qtx_zinv", "qtx_rgf_observables")
+            "qtx_zgemm", "qtx_zinv", "qtx_rgf_observables", "qtx_rgf_profile", "qtx_rgf_profile_read")
+QTX_KERNEL_GEMM, QTX_KERNEL_INV = 0, 1
 
 
 class QtxError(RuntimeError):
@@ -88,6 +89,11 @@ def load_library(path: str = LIB_PATH):
     lib.qtx_zinv.restype = ctypes.c_int
     lib.qtx_rgf_observables.argtypes = [vp, i32, i32, vp, vp, i64, vp, vp, vp, vp, vp]
     lib.qtx_rgf_observables.restype = ctypes.c_int
+    lib.qtx_rgf_profile.argtypes = [vp, ctypes.c_int]
+    lib.qtx_rgf_profile.restype = ctypes.c_int
+    lib.qtx_rgf_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(i64),
+                                         ctypes.POINTER(dbl)]
+    lib.qtx_rgf_profile_read.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -288,6 +294,21 @@ class Context:
         if check and rc != QTX_OK:
             raise QtxError(rc, "qtx_zinv")
         return rc
+
+    # -- qtx_rgf_profile / qtx_rgf_profile_read
+    def profile(self, enable: bool = True):
+        rc = self.lib.qtx_rgf_profile(self.handle, 1 if enable else 0)
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_rgf_profile")
+
+    def profile_read(self, family: int = QTX_KERNEL_GEMM):
+        """(total_ms, launches, flops) of the family's launches since the last read."""
+        ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        rc = self.lib.qtx_rgf_profile_read(self.handle, int(family), ctypes.byref(ms), ctypes.byref(n),
+                                           ctypes.byref(fl))
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_rgf_profile_read")
+        return ms.value, n.value, fl.value
 
     # -- qtx_rgf_observables
     def observables(self, dp: DeviceProblem, gamma_L, f_L, stream=None):
