@@ -4,18 +4,20 @@
 // paper); this is the FP64 reference scheme.  A complex product is four real
 // MFMA chains: C_re += A_re B_re - A_im B_im, C_im += A_re B_im + A_im B_re.
 //
-// Tiling: a 256-thread workgroup computes a 64 x 64 complex tile of C; its four
-// waves each own a 32 x 32 sub-tile (2 x 2 MFMA blocks of 16 x 16, with separate
-// real and imaginary accumulators: 8 independent MFMA chains per wave, so
-// consecutive MFMAs never wait on each other).  K advances in steps of 16
-// complex elements staged through LDS as interleaved (re, im) pairs laid out
-// k-major, so that the MFMA operand of lane l (row l%16, k l/16) is one 16-byte
-// LDS read.  Global loads are coalesced along the contiguous dimension of each
-// operand and transposed into LDS when needed (op = N for A, op = C for B); the
-// next K tile is prefetched into registers while the current one is consumed.
-// Tiles are assigned XCD-aware: consecutive workgroup ids land on different
-// XCDs, so tile ids are remapped so that all tiles of one batch entry execute on
-// one XCD and share its L2.
+// Tiling: a 256-thread workgroup computes a 64 x 64 complex tile of C.  Each of
+// its four waves owns four 16 x 16 MFMA blocks, interleaved (wave (wm, wn) takes
+// row blocks wm, wm+2 and column blocks wn, wn+2), with separate real and
+// imaginary accumulators: 8 independent MFMA chains per wave.  Blocks that lie
+// entirely outside C are skipped (wave-uniform), and the interleaving spreads
+// such blocks of an edge tile evenly over the waves (b = 416 is 6.5 tiles).
+// K advances 32 complex elements per step.  Operand tiles are copied to LDS in
+// their natural global layout (row-major, coalesced loads, padded rows, the
+// conjugate applied on the way in); the MFMA fragment reads do any transpose
+// through the padded stride, so no LDS write is transposed.  The next K tile is
+// prefetched into registers while the current one is consumed.  Tiles are
+// assigned XCD-aware: consecutive workgroup ids land on different XCDs, so tile
+// ids are remapped so that all tiles of one batch entry run on one XCD and
+// share its L2.
 #include "qtx_internal.h"
 
 namespace qtx {
@@ -24,7 +26,12 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 1, NT = 256;
+constexpr int BM = 64, BN = 64, BK = 32, NT = 256;
+// LDS row strides (complex elements) of the two natural layouts of a tile:
+// 64 rows x 32 (+1 pad) or 32 rows x 64 (+1 pad).
+constexpr int RS_WIDE = BK + 1;    // rows are M (or N), columns K
+constexpr int RS_LONG = BM + 1;    // rows are K, columns M (or N)
+constexpr int TILE_ELEMS = (BM * RS_WIDE > BK * RS_LONG) ? BM * RS_WIDE : BK * RS_LONG;
 
 __device__ inline int xcd_remap(int pid, int total) {
   // Workgroup `pid` is dispatched to XCD pid % 8.  Give XCD x a contiguous
@@ -35,17 +42,40 @@ __device__ inline int xcd_remap(int pid, int total) {
   return (x < rem) ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
 }
 
-__device__ inline double2 ldg_or_zero(const double2* p, bool ok) {
-  return ok ? *p : cmk(0.0, 0.0);
-}
+// One operand tile in its natural layout: ROWS x COLS elements of a row-major
+// source (leading dimension ld), rows [r0, r0+ROWS) bounded by nrows, columns
+// [c0, c0+COLS) bounded by ncols; zero outside.  2048 elements, 8 per thread:
+// element e = tid + 256 j, so each wave loads and stores contiguous 1 KB runs
+// (coalesced global reads, conflict-free LDS writes).
+template <int ROWS, int COLS>
+struct TileLoader {
+  double2 v[8];
+  __device__ inline void load(const double2* __restrict__ src, int64_t ld, int r0, int c0, int nrows, int ncols,
+                              int tid) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + NT * j;
+      const int r = r0 + e / COLS, c = c0 + e % COLS;
+      v[j] = (r < nrows && c < ncols) ? src[(int64_t)r * ld + c] : cmk(0.0, 0.0);
+    }
+  }
+  template <bool CONJ>
+  __device__ inline void store(double2* lds, int rs, int tid) const {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = tid + NT * j;
+      lds[(e / COLS) * rs + e % COLS] = CONJ ? cconj(v[j]) : v[j];
+    }
+  }
+};
 
 // KIND only separates kernel symbols by use (block products of the solve, the
 // inversion's trailing update, elementwise assembly with K = 0) so profilers
 // report them apart; the code is the same.
 template <int OPA, int OPB, int KIND>
 __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmDesc d) {
-  __shared__ double2 As[BK][BM + PAD];
-  __shared__ double2 Bs[BK][BN + PAD];
+  __shared__ double2 As[TILE_ELEMS];
+  __shared__ double2 Bs[TILE_ELEMS];
 
   const int tiles_m = (d.M + BM - 1) / BM;
   const int tiles_n = (d.N + BN - 1) / BN;
@@ -63,6 +93,15 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmDesc d) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
+  const int M = d.M, N = d.N, K = d.K;
+
+  // this wave's blocks: rows m0 + 16*(wm + 2i), columns n0 + 16*(wn + 2j)
+  bool rv[2], cv[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    rv[i] = m0 + 16 * (wm + 2 * i) < M;
+    cv[i] = n0 + 16 * (wn + 2 * i) < N;
+  }
 
   d4 acc_re[2][2], acc_im[2][2];
 #pragma unroll
@@ -73,91 +112,60 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmDesc d) {
       acc_im[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
-  double2 ra[4], rb[4];
-  const int M = d.M, N = d.N, K = d.K;
-
-  // Global -> registers for the K tile starting at k0.
+  // natural tiles: op(A) = N -> A rows are M (64 x 32); op(A) = C -> source rows are K (32 x 64)
+  TileLoader<OPA == OP_N ? BM : BK, OPA == OP_N ? BK : BM> la;
+  TileLoader<OPB == OP_N ? BK : BN, OPB == OP_N ? BN : BK> lb;
   auto gload = [&](int k0) {
-    if (OPA == OP_N) {          // A is M x K: thread -> row tid/4, 4 consecutive k
-      int m = m0 + (tid >> 2), kb = k0 + (tid & 3) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) ra[j] = ldg_or_zero(A + (int64_t)m * d.lda + kb + j, m < M && kb + j < K);
-    } else {                    // source is K x M: thread -> k tid/16, 4 consecutive m
-      int k = k0 + (tid >> 4), mb = m0 + (tid & 15) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) ra[j] = ldg_or_zero(A + (int64_t)k * d.lda + mb + j, k < K && mb + j < M);
-    }
-    if (OPB == OP_N) {          // B is K x N: thread -> k tid/16, 4 consecutive n
-      int k = k0 + (tid >> 4), nb = n0 + (tid & 15) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) rb[j] = ldg_or_zero(B + (int64_t)k * d.ldb + nb + j, k < K && nb + j < N);
-    } else {                    // source is N x K: thread -> n tid/4, 4 consecutive k
-      int n = n0 + (tid >> 2), kb = k0 + (tid & 3) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) rb[j] = ldg_or_zero(B + (int64_t)n * d.ldb + kb + j, n < N && kb + j < K);
-    }
-  };
-  // Registers -> LDS (k-major, conjugated for op = C).
-  auto lstore = [&]() {
-    if (OPA == OP_N) {
-      int m = tid >> 2, kb = (tid & 3) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) As[kb + j][m] = ra[j];
-    } else {
-      int k = tid >> 4, mb = (tid & 15) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) As[k][mb + j] = cconj(ra[j]);
-    }
-    if (OPB == OP_N) {
-      int k = tid >> 4, nb = (tid & 15) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) Bs[k][nb + j] = rb[j];
-    } else {
-      int n = tid >> 2, kb = (tid & 3) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) Bs[kb + j][n] = cconj(rb[j]);
-    }
+    if (OPA == OP_N) la.load(A, d.lda, m0, k0, M, K, tid);
+    else la.load(A, d.lda, k0, m0, K, M, tid);
+    if (OPB == OP_N) lb.load(B, d.ldb, k0, n0, K, N, tid);
+    else lb.load(B, d.ldb, n0, k0, N, K, tid);
   };
 
   const int nk = (K + BK - 1) / BK;
   if (nk > 0) gload(0);
+  const int li = lane & 15;
+  const int lk = lane >> 4;
   for (int kt = 0; kt < nk; ++kt) {
     __syncthreads();
-    lstore();
+    la.template store<OPA == OP_C>(As, OPA == OP_N ? RS_WIDE : RS_LONG, tid);
+    lb.template store<OPB == OP_C>(Bs, OPB == OP_N ? RS_LONG : RS_WIDE, tid);
     __syncthreads();
     if (kt + 1 < nk) gload((kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      const int li = lane & 15;
+      const int kr = kk + lk;
       double2 a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[kr][wm * 32 + i * 16 + li];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wn * 32 + j * 16 + li];
-      double na[2] = {-a[0].y, -a[1].y};
-      // Four product kinds, each over the 4 blocks: a chain is revisited only
-      // after 8 MFMAs.
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc_re[i][j], 0, 0, 0);
+      for (int i = 0; i < 2; ++i) {
+        const int m = 16 * (wm + 2 * i) + li;
+        a[i] = (OPA == OP_N) ? As[m * RS_WIDE + kr] : As[kr * RS_LONG + m];
+        const int n = 16 * (wn + 2 * i) + li;
+        b[i] = (OPB == OP_N) ? Bs[kr * RS_LONG + n] : Bs[n * RS_WIDE + kr];
+      }
+      const double na[2] = {-a[0].y, -a[1].y};
+      // Four product kinds over the (up to) 4 blocks: a chain is revisited only
+      // after 8 MFMAs.  Skipped blocks are wave-uniform.
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, acc_im[i][j], 0, 0, 0);
+          if (rv[i] && cv[j]) acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc_re[i][j], 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(na[i], b[j].y, acc_re[i][j], 0, 0, 0);
+          if (rv[i] && cv[j]) acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, acc_im[i][j], 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].x, acc_im[i][j], 0, 0, 0);
+          if (rv[i] && cv[j]) acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(na[i], b[j].y, acc_re[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          if (rv[i] && cv[j]) acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].x, acc_im[i][j], 0, 0, 0);
     }
   }
 
@@ -176,11 +184,12 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmDesc d) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j) {
+      if (!(rv[i] && cv[j])) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * v;
-        const int c = n0 + wn * 32 + j * 16 + (lane & 15);
+        const int r = m0 + 16 * (wm + 2 * i) + lk + 4 * v;
+        const int c = n0 + 16 * (wn + 2 * j) + li;
         if (r < M && c < N) {
           double2 out = cmul(d.alpha, cmk(acc_re[i][j][v], acc_im[i][j][v]));
 #pragma unroll
@@ -195,6 +204,7 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmDesc d) {
           C[(int64_t)r * d.ldc + c] = out;
         }
       }
+    }
 }
 
 }  // namespace

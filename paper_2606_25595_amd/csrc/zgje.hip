@@ -139,9 +139,16 @@ __global__ __launch_bounds__(PT) void gje_panel_kernel(int n, int k0, double2* X
         for (int q = 0; q < 8; ++q) pr[q] = piv_row[buf][k8 + q];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          const double2 elim = csub(v[j][k8 + q], cmul(fd, pr[q]));
-          const double2 scal = cmul(v[j][k8 + q], dinv);
-          v[j][k8 + q] = (k8 + q == k) ? newk : (isp ? scal : elim);
+          // the pivot row becomes pr*dinv, every other row v - fd*pr; the column
+          // being eliminated is replaced by the transform entry newk
+          const double2 m = isp ? dinv : fd;
+          const double2 t = cmul(m, isp ? v[j][k8 + q] : pr[q]);
+          double2 nv;
+          nv.x = isp ? t.x : v[j][k8 + q].x - t.x;
+          nv.y = isp ? t.y : v[j][k8 + q].y - t.y;
+          const bool col = (k8 + q == k);
+          v[j][k8 + q].x = col ? newk.x : nv.x;
+          v[j][k8 + q].y = col ? newk.y : nv.y;
         }
         asm volatile("" ::: "memory");
       }
