@@ -35,7 +35,7 @@ METRIC = "RGF energy points/sec: mixed-prec vs FP64 at rel err ≤1e-6; p50/p99 
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}   # dense TFLOP/s, MI355X
 TOL_MIXED = 1e-6
 PMC_FILE = os.path.join(ROOT, "profiles", "zgemm_f64_product_realistic_pmc.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2606_25595_amd", "csrc", "zgemm_f64.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2606_25595_amd", "csrc", "zgemm_mfma.hip")
 
 
 def log(*a):
@@ -70,7 +70,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precs", default="fp64")
+    ap.add_argument("--precs", default="fp64,fp32,bf16:5,bf16:4/bf16:5",
+                    help="comma list of schemes: fp64 | fp32 | bf16:NS | fp16:NS | <retarded>/<lesser>")
     ap.add_argument("--cpu-energies", type=int, default=8, help="energies in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -116,11 +117,25 @@ def main():
                "sample": "%d of the 256 energies (every %dth) of the realistic workload, block recurrences in "
                          "numpy/LAPACK FP64, %.1f s" % (len(sample), n_e // len(sample), t_cpu)}
 
+    def parse(spec):
+        # "fp64", "bf16:5", or "<retarded>/<lesser>", e.g. "bf16:4/bf16:5"
+        parts = spec.split("/")
+        def one(p):
+            name, _, ns = p.partition(":")
+            return name, int(ns or 0)
+        r = one(parts[0])
+        lsr = one(parts[1]) if len(parts) > 1 else None
+        kw = dict(prec=r[0], n_slices=r[1])
+        if lsr:
+            kw.update(prec_lesser=lsr[0], n_slices_lesser=lsr[1])
+        return kw
+
     results = {}
     for prec in args.precs.split(","):
+        skw = parse(prec)
         log("bench: %s warmup x%d" % (prec, args.warmup))
         for _ in range(args.warmup):
-            ctx.solve(dp, prec=prec)
+            ctx.solve(dp, **skw)
         torch.cuda.synchronize()
         ctx.profile(True)
         ctx.profile_read(qtx.QTX_KERNEL_GEMM)
@@ -129,7 +144,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
-            ctx.solve(dp, prec=prec)
+            ctx.solve(dp, **skw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         ctx.profile(False)
@@ -161,7 +176,7 @@ def main():
     r = results[best]
     g_ms, g_n, g_fl = r["gemm"]
     achieved = (g_fl / max(g_n, 1)) / (g_ms / max(g_n, 1) / 1e3) / 1e12 if g_n else None
-    peak = PEAK["fp64" if best == "fp64" else best]
+    peak = PEAK[parse(best)["prec"]]
     traffic = traffic_from_profile() if best == "fp64" else None
     line = {
         "metric": METRIC,
@@ -174,14 +189,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if best == "fp64" else "f64+" + best,
+        "dtype": "f64" if best == "fp64" else "f64+" + best.replace(":", "x"),
         "data": "synthetic",
         "config": {"workload": "realistic selected RGF solve: n_b=32 blocks, b=416, N_E=256 energies in [-2,2], "
                                "complex128, S=I, random Hermitian H (seed 0), eta=1e-3, gamma=0.5",
                    "precision": best, "energies_per_step": n_e},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": (achieved / peak) if achieved else None, "traffic": traffic,
-                     "kernel": "zgemm_f64_kernel<N|C,N|C,product> (b x b x b complex block products)",
+                     "kernel": "complex b x b x b block products of the solve (%s scheme)" % best,
                      "flops_per_launch": g_fl / max(g_n, 1), "avg_launch_ms": g_ms / max(g_n, 1),
                      "launches": g_n},
         "cpu_baseline": cpu,

@@ -97,11 +97,18 @@ enum {
  *   status  [n_e] int32 per-energy qtx_status (QTX_OK, QTX_ERR_SINGULAR or
  *           QTX_ERR_NONFINITE), or NULL.  An energy that fails has every
  *           output block filled with NaN; other energies are unaffected.
+ * Precision per chain: the products that build x_i and G^R (forward Schur
+ * complements, backward G^R blocks) use (prec, n_slices); the products of the
+ * lesser/greater recurrences use (prec_lesser, n_slices_lesser).  The lesser
+ * chain is the more sensitive one, as the paper chooses slice counts per
+ * motif (Section V-B, Table IV).
  * Limits: 1 <= b <= 1024, n_b >= 1, n_e >= 1. */
 typedef struct {
   int32_t n_b, b, n_e;
-  int32_t prec;            /* qtx_prec                                          */
+  int32_t prec;            /* qtx_prec of the retarded-chain products           */
   int32_t n_slices;        /* split modes: slices per operand, 0 = default (2)  */
+  int32_t prec_lesser;     /* qtx_prec of the lesser/greater-chain products,    */
+  int32_t n_slices_lesser; /*   -1 = same as prec / n_slices                    */
   uint32_t flags;          /* QTX_S_IDENTITY | QTX_WANT_GREATER                  */
   const double* energies;  /* host                                              */
   const void *H_d, *H_u, *H_l;

@@ -151,14 +151,92 @@ struct Mat {
   int64_t ld = 0;
 };
 
+// Precision scheme of the block products: qtx_prec -> (kind, 16-bit format, slices).
+struct Scheme {
+  int prec = QTX_FP64;
+  int fmt = 0;      // split: 0 = FP16 digits, 1 = BF16 digits
+  int ns = 0;       // split: slices per operand
+  bool split() const { return prec == QTX_BF16_SPLIT || prec == QTX_FP16_SPLIT; }
+};
+
+bool make_scheme(int prec, int n_slices, Scheme* out) {
+  Scheme sc;
+  sc.prec = prec;
+  if (prec == QTX_FP64 || prec == QTX_FP32) { *out = sc; return true; }
+  if (prec != QTX_BF16_SPLIT && prec != QTX_FP16_SPLIT) return false;
+  sc.fmt = (prec == QTX_BF16_SPLIT) ? 1 : 0;
+  sc.ns = n_slices > 0 ? n_slices : 2;
+  if (!split_supported(sc.fmt, sc.ns)) return false;
+  *out = sc;
+  return true;
+}
+
+// Workspace of one split operand (rows = cols = b), per batch entry.
+size_t split_operand_bytes(int b, const Scheme& sc) {
+  return sc.split() ? split_bytes(b, b, sc.ns, 1) + 512 : 0;
+}
+
+struct SplitBufs {
+  uint16_t* S[2] = {nullptr, nullptr};
+  int32_t* E[2] = {nullptr, nullptr};
+};
+
+// Carve two split operands for `batch` entries from w (advances w).
+SplitBufs carve_split(char*& w, int b, const Scheme& sc, int batch) {
+  SplitBufs sb;
+  if (!sc.split()) return sb;
+  for (int q = 0; q < 2; ++q) {
+    const size_t dig = (size_t)split_digit_stride(b, b, sc.ns) * sizeof(uint16_t) * batch;
+    const size_t ex = (size_t)split_exp_stride(b, b) * sizeof(int32_t) * batch;
+    sb.S[q] = (uint16_t*)w; w += align_up(dig);
+    sb.E[q] = (int32_t*)w; w += align_up(ex);
+  }
+  return sb;
+}
+
+// One batched complex block product with the context's precision scheme.
+// Elementwise (K = 0) launches and anything but b x b x b products stay FP64.
+hipError_t run_product(const GemmDesc& d, const Scheme& sc, const SplitBufs& sb, hipStream_t s) {
+  if (d.K == 0 || sc.prec == QTX_FP64) return launch_zgemm_f64(d, s);
+  if (sc.prec == QTX_FP32) return launch_zgemm_f32(d, s);
+  // split: operand A as rows of op(A) (M x K), operand B as columns of op(B) (N x K)
+  SplitDesc sa;
+  sa.X = d.A; sa.ld = d.lda; sa.stride = d.sA;
+  sa.rows = d.M; sa.cols = d.K;
+  sa.trans = (d.opA == OP_C); sa.conj = (d.opA == OP_C);
+  sa.S = sb.S[0]; sa.E = sb.E[0];
+  sa.s_stride = split_digit_stride(d.M, d.K, sc.ns);
+  sa.e_stride = split_exp_stride(d.M, d.K);
+  sa.batch = d.sA == 0 ? 1 : d.batch;
+  SplitDesc sbd;
+  sbd.X = d.B; sbd.ld = d.ldb; sbd.stride = d.sB;
+  sbd.rows = d.N; sbd.cols = d.K;
+  sbd.trans = (d.opB == OP_N); sbd.conj = (d.opB == OP_C);
+  sbd.S = sb.S[1]; sbd.E = sb.E[1];
+  sbd.s_stride = split_digit_stride(d.N, d.K, sc.ns);
+  sbd.e_stride = split_exp_stride(d.N, d.K);
+  sbd.batch = d.sB == 0 ? 1 : d.batch;
+  hipError_t e = launch_split(sa, sc.fmt, sc.ns, s);
+  if (e != hipSuccess) return e;
+  e = launch_split(sbd, sc.fmt, sc.ns, s);
+  if (e != hipSuccess) return e;
+  SplitGemmDesc g;
+  g.d = d;
+  g.SA = sa.S; g.sa_stride = (d.sA == 0) ? 0 : sa.s_stride;
+  g.SB = sbd.S; g.sb_stride = (d.sB == 0) ? 0 : sbd.s_stride;
+  g.EA = sa.E; g.ea_stride = (d.sA == 0) ? 0 : sa.e_stride;
+  g.EB = sbd.E; g.eb_stride = (d.sB == 0) ? 0 : sbd.e_stride;
+  return launch_zgemm_split(g, sc.fmt, sc.ns, s);
+}
+
 struct Gemm {
   qtx_rgf_ctx ctx;
   hipStream_t s;
   int b;
   int batch;
   const double* energies;   // device, per batch entry
-  int prec;
-  int n_slices;
+  Scheme sc;
+  SplitBufs sb;
 
   // C = alpha * op(A) op(B) + addends (+ diag * E_z I)
   hipError_t run(int opA, Mat A, int opB, Mat B, double2* C, int64_t sC, double2 alpha,
@@ -184,9 +262,9 @@ struct Gemm {
     d.batch = batch;
     if (d.K == b) {
       ProfScope ps(ctx, QTX_KERNEL_GEMM, s, 8.0 * (double)b * b * b * batch);
-      return launch_zgemm_f64(d, s);
+      return run_product(d, sc, sb, s);
     }
-    return launch_zgemm_f64(d, s);
+    return run_product(d, sc, sb, s);
   }
 };
 
@@ -200,9 +278,9 @@ inline Addend addend(const double2* X, int64_t stride, double2 coef, int op = OP
 // Per-energy workspace of the RGF path, in b*b blocks.
 constexpr int kTemps = 6;
 
-size_t per_energy_bytes(int b) {
+size_t per_energy_bytes(int b, const Scheme& sc) {
   const size_t bb = (size_t)b * b * sizeof(double2);
-  return align_up(bb) * (1 + kTemps + 2) + align_up(gje_work_bytes(b, 1)) + 64;
+  return align_up(bb) * (1 + kTemps + 2) + align_up(gje_work_bytes(b, 1)) + 2 * split_operand_bytes(b, sc) + 64;
 }
 
 bool valid_problem(const qtx_rgf_problem* p) {
@@ -227,7 +305,9 @@ bool valid_problem(const qtx_rgf_problem* p) {
 
 qtx_status check_supported(const qtx_rgf_problem* p) {
   if (p->SL_u || p->SL_l || p->SG_u || p->SG_l) return QTX_ERR_UNSUPPORTED;   // BT Sigma^<, Sigma^>
-  if (p->prec != QTX_FP64) return QTX_ERR_UNSUPPORTED;
+  Scheme sc;
+  if (!make_scheme(p->prec, p->n_slices, &sc)) return QTX_ERR_UNSUPPORTED;
+  if (p->prec_lesser >= 0 && !make_scheme(p->prec_lesser, p->n_slices_lesser, &sc)) return QTX_ERR_UNSUPPORTED;
   if (p->flags & ~(uint32_t)(QTX_S_IDENTITY | QTX_WANT_GREATER)) return QTX_ERR_ARG;
   return QTX_OK;
 }
@@ -253,6 +333,13 @@ qtx_status solve_chunk(qtx_rgf_ctx ctx, const qtx_rgf_problem& p, int e0, int ne
   GjeWork gw = gje_carve(w, b, ne); w += align_up(gje_work_bytes(b, ne));
   int32_t* st = (int32_t*)w; w += align_up((size_t)ne * sizeof(int32_t));
   const double* en = d_en + e0;
+  Scheme scheme, scheme_l;
+  make_scheme(p.prec, p.n_slices, &scheme);
+  if (p.prec_lesser >= 0) make_scheme(p.prec_lesser, p.n_slices_lesser, &scheme_l);
+  else scheme_l = scheme;
+  // split buffers sized for the larger of the two schemes
+  Scheme big = (scheme_l.split() && (!scheme.split() || scheme_l.ns > scheme.ns)) ? scheme_l : scheme;
+  SplitBufs sbufs = carve_split(w, b, big, ne);
 
   const double2* H_d = (const double2*)p.H_d;
   const double2* H_u = (const double2*)p.H_u;
@@ -281,7 +368,8 @@ qtx_status solve_chunk(qtx_rgf_ctx ctx, const qtx_rgf_problem& p, int e0, int ne
 
   QTX_TRY(launch_fill_i32(st, 0, ne, s));
 
-  Gemm g{ctx, s, b, ne, en, p.prec, p.n_slices};
+  Gemm g{ctx, s, b, ne, en, scheme, sbufs};     // retarded chain
+  Gemm gl{ctx, s, b, ne, en, scheme_l, sbufs};  // lesser / greater chain
   const double2 one = cmk(1, 0), mone = cmk(-1, 0), zero = cmk(0, 0);
 
   // The coupling operands: U_i = E S_{i,i+1} - H_{i,i+1} - Sigma^R_{i,i+1}(E) and the
@@ -341,15 +429,15 @@ qtx_status solve_chunk(qtx_rgf_ctx ctx, const qtx_rgf_problem& p, int e0, int ne
     for (const Rhs& r : rhs) {
       const double2* Bi = r.B + (int64_t)i * bb;
       if (i == 0) {
-        QTX_TRY(g.run(OP_N, xi, OP_N, Mat{Bi, sE, b}, Tm[2], bb, one, {}));
+        QTX_TRY(gl.run(OP_N, xi, OP_N, Mat{Bi, sE, b}, Tm[2], bb, one, {}));
       } else {
         // Y' = L' xl_{i-1};  Q = B_i + Y' L'^H;  Z = x_i Q
-        QTX_TRY(g.run(OP_N, L, OP_N, Mat{r.Gd + (int64_t)(i - 1) * bb, sE, b}, Tm[1], bb, one, {}));
-        QTX_TRY(g.run(OP_N, Mat{Tm[1], bb, b}, OP_C, L, Tm[3], bb, one, {addend(Bi, sE, one)}));
-        QTX_TRY(g.run(OP_N, xi, OP_N, Mat{Tm[3], bb, b}, Tm[2], bb, one, {}));
+        QTX_TRY(gl.run(OP_N, L, OP_N, Mat{r.Gd + (int64_t)(i - 1) * bb, sE, b}, Tm[1], bb, one, {}));
+        QTX_TRY(gl.run(OP_N, Mat{Tm[1], bb, b}, OP_C, L, Tm[3], bb, one, {addend(Bi, sE, one)}));
+        QTX_TRY(gl.run(OP_N, xi, OP_N, Mat{Tm[3], bb, b}, Tm[2], bb, one, {}));
       }
       // xl_i = Z x_i^H
-      QTX_TRY(g.run(OP_N, Mat{Tm[2], bb, b}, OP_C, xi, r.Gd + (int64_t)i * bb, sE, one, {}));
+      QTX_TRY(gl.run(OP_N, Mat{Tm[2], bb, b}, OP_C, xi, r.Gd + (int64_t)i * bb, sE, one, {}));
     }
   }
   // ------------------------------------------------------------ backward
@@ -371,18 +459,18 @@ qtx_status solve_chunk(qtx_rgf_ctx ctx, const qtx_rgf_problem& p, int e0, int ne
     QTX_TRY(g.run(OP_N, Gn, OP_N, Mat{Rp, bb, b}, GRl, sEu, cmk(-sL, 0), {}));   // G_{i+1,i}
     QTX_TRY(g.run(OP_N, Mat{GRu, sEu, b}, OP_N, Mat{Rp, bb, b}, GR_d + (int64_t)i * bb, sE, cmk(-sL, 0),
                   {addend(GR_d + (int64_t)i * bb, sE, one)}));                 // G_ii (in place)
-    QTX_TRY(g.run(OP_N, Mat{GRu, sEu, b}, OP_N, L, Wp, bb, one, {}));         // W' = G_{i,i+1} L'
+    QTX_TRY(gl.run(OP_N, Mat{GRu, sEu, b}, OP_N, L, Wp, bb, one, {}));        // W' = G_{i,i+1} L' (lesser chain)
     for (const Rhs& r : rhs) {
       const Mat xl{r.Gd + (int64_t)i * bb, sE, b};
       const Mat Gln{r.Gd + (int64_t)(i + 1) * bb, sE, b};
-      QTX_TRY(g.run(OP_N, Mat{Pp, bb, b}, OP_N, Gln, Vp, bb, one, {}));       // V' = P' G<_{i+1}
-      QTX_TRY(g.run(OP_N, Mat{Wp, bb, b}, OP_N, xl, Yp, bb, one, {}));        // Y' = W' xl_i
-      QTX_TRY(g.run(OP_N, xl, OP_C, L, Zp, bb, one, {}));                     // Z' = xl_i L'^H
+      QTX_TRY(gl.run(OP_N, Mat{Pp, bb, b}, OP_N, Gln, Vp, bb, one, {}));       // V' = P' G<_{i+1}
+      QTX_TRY(gl.run(OP_N, Mat{Wp, bb, b}, OP_N, xl, Yp, bb, one, {}));        // Y' = W' xl_i
+      QTX_TRY(gl.run(OP_N, xl, OP_C, L, Zp, bb, one, {}));                     // Z' = xl_i L'^H
       // G<_{i,i+1} = -sU V' - sL Z' G_{i+1}^H
-      QTX_TRY(g.run(OP_N, Mat{Zp, bb, b}, OP_C, Gn, r.Gu + (int64_t)i * bb, sEu, cmk(-sL, 0),
+      QTX_TRY(gl.run(OP_N, Mat{Zp, bb, b}, OP_C, Gn, r.Gu + (int64_t)i * bb, sEu, cmk(-sL, 0),
                     {addend(Vp, bb, cmk(-sU, 0))}));
       // G<_ii = xl_i + V' P'^H - sL Y' + sL Y'^H   (in place)
-      QTX_TRY(g.run(OP_N, Mat{Vp, bb, b}, OP_C, Mat{Pp, bb, b}, r.Gd + (int64_t)i * bb, sE, one,
+      QTX_TRY(gl.run(OP_N, Mat{Vp, bb, b}, OP_C, Mat{Pp, bb, b}, r.Gd + (int64_t)i * bb, sE, one,
                     {addend(r.Gd + (int64_t)i * bb, sE, one), addend(Yp, bb, cmk(-sL, 0)),
                      addend(Yp, bb, cmk(sL, 0), OP_C)}));
     }
@@ -480,7 +568,12 @@ qtx_status qtx_rgf_destroy(qtx_rgf_ctx ctx) {
 
 size_t qtx_rgf_footprint(const qtx_rgf_problem* p) {
   if (!valid_problem(p)) return 0;
-  return per_energy_bytes(p->b);
+  Scheme sc, scl;
+  if (!make_scheme(p->prec, p->n_slices, &sc)) return 0;
+  if (p->prec_lesser >= 0 && make_scheme(p->prec_lesser, p->n_slices_lesser, &scl) &&
+      scl.split() && (!sc.split() || scl.ns > sc.ns))
+    sc = scl;
+  return per_energy_bytes(p->b, sc);
 }
 
 qtx_status qtx_rgf_solve(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int32_t n_probs, void* hip_stream) {
@@ -500,7 +593,11 @@ qtx_status qtx_rgf_solve(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int32_t 
   int max_ne = 0;
   for (int k = 0; k < n_probs; ++k) {
     const qtx_rgf_problem& p = probs[k];
-    const size_t per = per_energy_bytes(p.b);
+    Scheme sc, scl;
+    make_scheme(p.prec, p.n_slices, &sc);
+    if (p.prec_lesser >= 0) make_scheme(p.prec_lesser, p.n_slices_lesser, &scl);
+    if (scl.split() && (!sc.split() || scl.ns > sc.ns)) sc = scl;
+    const size_t per = per_energy_bytes(p.b, sc);
     size_t c = budget > per ? budget / per : 1;
     if (c > (size_t)p.n_e) c = p.n_e;
     if (c < 1) c = 1;
@@ -534,8 +631,8 @@ qtx_status qtx_zgemm(qtx_rgf_ctx ctx, char opA, char opB, int32_t M, int32_t N, 
   if (M < 0 || N < 0 || K < 0 || batch < 1 || !C || ldc < N) return QTX_ERR_ARG;
   if (K > 0 && (!A || !B)) return QTX_ERR_ARG;
   if (K > 0 && (lda < (opA == 'N' ? K : M) || ldb < (opB == 'N' ? N : K))) return QTX_ERR_ARG;
-  if (prec != QTX_FP64) return QTX_ERR_UNSUPPORTED;
-  (void)n_slices;
+  Scheme sc;
+  if (!make_scheme(prec, n_slices, &sc)) return QTX_ERR_UNSUPPORTED;
   DeviceGuard guard(ctx->device);
   GemmDesc d;
   d.M = M; d.N = N; d.K = K;
@@ -549,7 +646,18 @@ qtx_status qtx_zgemm(qtx_rgf_ctx ctx, char opA, char opB, int32_t M, int32_t N, 
     d.add[0].X = (const double2*)C; d.add[0].ld = ldc; d.add[0].stride = sC; d.add[0].coef = cmk(beta_re, beta_im);
   }
   d.batch = batch;
-  QTX_TRY(launch_zgemm_f64(d, (hipStream_t)hip_stream));
+  SplitBufs sb;
+  if (sc.split() && K > 0) {
+    const size_t need = split_bytes(M, K, sc.ns, batch) + split_bytes(N, K, sc.ns, batch) + 4096;
+    qtx_status st = ensure_ws(ctx, need);
+    if (st != QTX_OK) return st;
+    char* w = (char*)ctx->ws;
+    sb.S[0] = (uint16_t*)w; w += align_up((size_t)split_digit_stride(M, K, sc.ns) * 2 * batch);
+    sb.E[0] = (int32_t*)w; w += align_up((size_t)split_exp_stride(M, K) * 4 * batch);
+    sb.S[1] = (uint16_t*)w; w += align_up((size_t)split_digit_stride(N, K, sc.ns) * 2 * batch);
+    sb.E[1] = (int32_t*)w;
+  }
+  QTX_TRY(run_product(d, sc, sb, (hipStream_t)hip_stream));
   return QTX_OK;
 }
 

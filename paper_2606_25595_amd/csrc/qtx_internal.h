@@ -62,6 +62,33 @@ enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16_SPLIT = 2, PREC_FP16_SPLIT =
 // Kernel symbol families of the complex GEMM (same code, separate names).
 enum GemmKind { GEMM_PRODUCT = 0, GEMM_INV_UPDATE = 1, GEMM_ELEMENTWISE = 2 };
 hipError_t launch_zgemm_f64(const GemmDesc& d, hipStream_t s, int kind = GEMM_PRODUCT);
+// Same product with operands rounded to FP32 and FP32 accumulation (epilogue in FP64).
+hipError_t launch_zgemm_f32(const GemmDesc& d, hipStream_t s);
+
+// Split operands for the slice-product GEMM (FP16 / BF16 digits, FP64 recombination).
+// S = op(X) viewed as rows x cols (cols = the contraction dimension K):
+// S[r][k] = X[r][k] (trans = 0) or X[k][r] (trans = 1), conjugated if conj = 1.
+struct SplitDesc {
+  const double2* X = nullptr; int64_t ld = 0, stride = 0;
+  int rows = 0, cols = 0;
+  int trans = 0, conj = 0;
+  uint16_t* S = nullptr; int64_t s_stride = 0;   // digits per batch entry (16-bit words)
+  int32_t* E = nullptr; int64_t e_stride = 0;    // strip exponents per batch entry
+  int batch = 1;
+};
+struct SplitGemmDesc {
+  GemmDesc d;                                     // M, N, K, C, alpha, epilogue (A/B unused)
+  const uint16_t* SA = nullptr; int64_t sa_stride = 0;   // rows = M
+  const uint16_t* SB = nullptr; int64_t sb_stride = 0;   // rows = N
+  const int32_t* EA = nullptr; int64_t ea_stride = 0;
+  const int32_t* EB = nullptr; int64_t eb_stride = 0;
+};
+bool split_supported(int fmt, int ns);                    // fmt 0 = FP16, 1 = BF16
+size_t split_bytes(int rows, int cols, int ns, int batch);
+int64_t split_digit_stride(int rows, int cols, int ns);
+int64_t split_exp_stride(int rows, int cols);
+hipError_t launch_split(const SplitDesc& sd, int fmt, int ns, hipStream_t s);
+hipError_t launch_zgemm_split(const SplitGemmDesc& g, int fmt, int ns, hipStream_t s);
 
 // Gauss-Jordan inversion with implicit partial pivoting, batched.
 // X_z (n x n, ld n, stride sX) is overwritten; the inverse is written to Out_z.

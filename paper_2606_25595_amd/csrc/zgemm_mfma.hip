@@ -1,4 +1,5 @@
-// Batched complex GEMM on the gfx950 FP64 matrix cores (v_mfma_f64_16x16x4_f64).
+// Batched complex GEMM on the gfx950 matrix cores: FP64 (v_mfma_f64_16x16x4_f64)
+// and FP32 (v_mfma_f32_16x16x4_f32) schemes.
 //
 // The complex block products dominate the selected solve (Section IV of the
 // paper); this is the FP64 reference scheme.  A complex product is four real
@@ -23,6 +24,32 @@
 namespace qtx {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Arithmetic of the block products: FP64 MFMA (reference) or FP32 MFMA with the
+// operands rounded to FP32 (round to nearest even) on their way into LDS.
+// Accumulator layouts of the 16x16x4 instructions on gfx950 (lane l, element v):
+//   f64: row l/16 + 4v, column l%16;   f32: row 4(l/16) + v, column l%16.
+struct MathF64 {
+  typedef double2 lds_t;
+  typedef d4 acc_t;
+  static __device__ inline lds_t cvt(double2 x) { return x; }
+  static __device__ inline acc_t zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ inline acc_t mfma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int v) { return lk + 4 * v; }
+};
+struct MathF32 {
+  typedef float2 lds_t;
+  typedef f4 acc_t;
+  static __device__ inline lds_t cvt(double2 x) { float2 r; r.x = (float)x.x; r.y = (float)x.y; return r; }
+  static __device__ inline acc_t zero() { return f4{0.0f, 0.0f, 0.0f, 0.0f}; }
+  static __device__ inline acc_t mfma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int v) { return 4 * lk + v; }
+};
 
 namespace {
 
@@ -59,12 +86,12 @@ struct TileLoader {
       v[j] = (r < nrows && c < ncols) ? src[(int64_t)r * ld + c] : cmk(0.0, 0.0);
     }
   }
-  template <bool CONJ>
-  __device__ inline void store(double2* lds, int rs, int tid) const {
+  template <bool CONJ, class MATH, class L>
+  __device__ inline void store(L* lds, int rs, int tid) const {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int e = tid + NT * j;
-      lds[(e / COLS) * rs + e % COLS] = CONJ ? cconj(v[j]) : v[j];
+      lds[(e / COLS) * rs + e % COLS] = MATH::cvt(CONJ ? cconj(v[j]) : v[j]);
     }
   }
 };
@@ -72,10 +99,12 @@ struct TileLoader {
 // KIND only separates kernel symbols by use (block products of the solve, the
 // inversion's trailing update, elementwise assembly with K = 0) so profilers
 // report them apart; the code is the same.
-template <int OPA, int OPB, int KIND>
-__global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmDesc d) {
-  __shared__ double2 As[TILE_ELEMS];
-  __shared__ double2 Bs[TILE_ELEMS];
+template <int OPA, int OPB, int KIND, class MATH>
+__global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
+  typedef typename MATH::lds_t lds_t;
+  typedef typename MATH::acc_t acc_t;
+  __shared__ lds_t As[TILE_ELEMS];
+  __shared__ lds_t Bs[TILE_ELEMS];
 
   const int tiles_m = (d.M + BM - 1) / BM;
   const int tiles_n = (d.N + BN - 1) / BN;
@@ -103,13 +132,13 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmDesc d) {
     cv[i] = n0 + 16 * (wn + 2 * i) < N;
   }
 
-  d4 acc_re[2][2], acc_im[2][2];
+  acc_t acc_re[2][2], acc_im[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      acc_re[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      acc_im[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      acc_re[i][j] = MATH::zero();
+      acc_im[i][j] = MATH::zero();
     }
 
   // natural tiles: op(A) = N -> A rows are M (64 x 32); op(A) = C -> source rows are K (32 x 64)
@@ -128,14 +157,14 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmDesc d) {
   const int lk = lane >> 4;
   for (int kt = 0; kt < nk; ++kt) {
     __syncthreads();
-    la.template store<OPA == OP_C>(As, OPA == OP_N ? RS_WIDE : RS_LONG, tid);
-    lb.template store<OPB == OP_C>(Bs, OPB == OP_N ? RS_LONG : RS_WIDE, tid);
+    la.template store<OPA == OP_C, MATH>(As, OPA == OP_N ? RS_WIDE : RS_LONG, tid);
+    lb.template store<OPB == OP_C, MATH>(Bs, OPB == OP_N ? RS_LONG : RS_WIDE, tid);
     __syncthreads();
     if (kt + 1 < nk) gload((kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + lk;
-      double2 a[2], b[2];
+      lds_t a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int m = 16 * (wm + 2 * i) + li;
@@ -143,33 +172,33 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmDesc d) {
         const int n = 16 * (wn + 2 * i) + li;
         b[i] = (OPB == OP_N) ? Bs[kr * RS_LONG + n] : Bs[n * RS_WIDE + kr];
       }
-      const double na[2] = {-a[0].y, -a[1].y};
+      const decltype(a[0].y) na[2] = {-a[0].y, -a[1].y};
       // Four product kinds over the (up to) 4 blocks: a chain is revisited only
       // after 8 MFMAs.  Skipped blocks are wave-uniform.
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          if (rv[i] && cv[j]) acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc_re[i][j], 0, 0, 0);
+          if (rv[i] && cv[j]) acc_re[i][j] = MATH::mfma(a[i].x, b[j].x, acc_re[i][j]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          if (rv[i] && cv[j]) acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, acc_im[i][j], 0, 0, 0);
+          if (rv[i] && cv[j]) acc_im[i][j] = MATH::mfma(a[i].x, b[j].y, acc_im[i][j]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          if (rv[i] && cv[j]) acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(na[i], b[j].y, acc_re[i][j], 0, 0, 0);
+          if (rv[i] && cv[j]) acc_re[i][j] = MATH::mfma(na[i], b[j].y, acc_re[i][j]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          if (rv[i] && cv[j]) acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].x, acc_im[i][j], 0, 0, 0);
+          if (rv[i] && cv[j]) acc_im[i][j] = MATH::mfma(a[i].y, b[j].x, acc_im[i][j]);
     }
   }
 
-  // Epilogue.  f64 16x16x4 result layout: lane l, element v -> row l/16 + 4v, col l%16.
+  // Epilogue (FP64): accumulator element v of lane l sits at MATH::row(l/16, v), column l%16.
   double2* __restrict__ C = d.C + (int64_t)z * d.sC;
   const double bs = d.bscal ? d.bscal[z] : 1.0;
   double2 coef[kMaxAddends];
@@ -188,10 +217,10 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmDesc d) {
       if (!(rv[i] && cv[j])) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = m0 + 16 * (wm + 2 * i) + lk + 4 * v;
+        const int r = m0 + 16 * (wm + 2 * i) + MATH::row(lk, v);
         const int c = n0 + 16 * (wn + 2 * j) + li;
         if (r < M && c < N) {
-          double2 out = cmul(d.alpha, cmk(acc_re[i][j][v], acc_im[i][j][v]));
+          double2 out = cmul(d.alpha, cmk((double)acc_re[i][j][v], (double)acc_im[i][j][v]));
 #pragma unroll
           for (int q = 0; q < kMaxAddends; ++q) {
             if (X[q]) {
@@ -209,15 +238,15 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmDesc d) {
 
 }  // namespace
 
-template <int KIND>
+template <int KIND, class MATH>
 static void launch_kind(const GemmDesc& d, dim3 grid, dim3 block, hipStream_t s) {
-  if (d.opA == OP_N && d.opB == OP_N) hipLaunchKernelGGL((zgemm_f64_kernel<OP_N, OP_N, KIND>), grid, block, 0, s, d);
-  else if (d.opA == OP_N) hipLaunchKernelGGL((zgemm_f64_kernel<OP_N, OP_C, KIND>), grid, block, 0, s, d);
-  else if (d.opB == OP_N) hipLaunchKernelGGL((zgemm_f64_kernel<OP_C, OP_N, KIND>), grid, block, 0, s, d);
-  else hipLaunchKernelGGL((zgemm_f64_kernel<OP_C, OP_C, KIND>), grid, block, 0, s, d);
+  if (d.opA == OP_N && d.opB == OP_N) hipLaunchKernelGGL((zgemm_mfma_kernel<OP_N, OP_N, KIND, MATH>), grid, block, 0, s, d);
+  else if (d.opA == OP_N) hipLaunchKernelGGL((zgemm_mfma_kernel<OP_N, OP_C, KIND, MATH>), grid, block, 0, s, d);
+  else if (d.opB == OP_N) hipLaunchKernelGGL((zgemm_mfma_kernel<OP_C, OP_N, KIND, MATH>), grid, block, 0, s, d);
+  else hipLaunchKernelGGL((zgemm_mfma_kernel<OP_C, OP_C, KIND, MATH>), grid, block, 0, s, d);
 }
 
-hipError_t launch_zgemm_f64(const GemmDesc& d, hipStream_t s, int kind) {
+static hipError_t launch_zgemm_mfma(const GemmDesc& d, hipStream_t s, int kind, bool fp32) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
   const int tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
   const int64_t total = (int64_t)tiles * d.batch;
@@ -226,13 +255,23 @@ hipError_t launch_zgemm_f64(const GemmDesc& d, hipStream_t s, int kind) {
   if (d.K == 0) {
     GemmDesc e = d;
     e.opA = OP_N; e.opB = OP_N;
-    launch_kind<GEMM_ELEMENTWISE>(e, grid, block, s);
+    launch_kind<GEMM_ELEMENTWISE, MathF64>(e, grid, block, s);
   } else if (kind == GEMM_INV_UPDATE) {
-    launch_kind<GEMM_INV_UPDATE>(d, grid, block, s);
+    launch_kind<GEMM_INV_UPDATE, MathF64>(d, grid, block, s);
+  } else if (fp32) {
+    launch_kind<GEMM_PRODUCT, MathF32>(d, grid, block, s);
   } else {
-    launch_kind<GEMM_PRODUCT>(d, grid, block, s);
+    launch_kind<GEMM_PRODUCT, MathF64>(d, grid, block, s);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_zgemm_f64(const GemmDesc& d, hipStream_t s, int kind) {
+  return launch_zgemm_mfma(d, s, kind, false);
+}
+
+hipError_t launch_zgemm_f32(const GemmDesc& d, hipStream_t s) {
+  return launch_zgemm_mfma(d, s, GEMM_PRODUCT, true);
 }
 
 }  // namespace qtx

@@ -45,7 +45,8 @@ class QtxError(RuntimeError):
 class _Problem(ctypes.Structure):
     _fields_ = [
         ("n_b", ctypes.c_int32), ("b", ctypes.c_int32), ("n_e", ctypes.c_int32),
-        ("prec", ctypes.c_int32), ("n_slices", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("prec", ctypes.c_int32), ("n_slices", ctypes.c_int32),
+        ("prec_lesser", ctypes.c_int32), ("n_slices_lesser", ctypes.c_int32), ("flags", ctypes.c_uint32),
         ("energies", ctypes.POINTER(ctypes.c_double)),
         ("H_d", ctypes.c_void_p), ("H_u", ctypes.c_void_p), ("H_l", ctypes.c_void_p),
         ("S_d", ctypes.c_void_p), ("S_u", ctypes.c_void_p), ("S_l", ctypes.c_void_p),
@@ -193,10 +194,11 @@ def to_device(p, device="cuda", greater: Optional[bool] = None) -> DeviceProblem
     return dp
 
 
-def _problem_struct(dp: DeviceProblem, prec: int, n_slices: int):
+def _problem_struct(dp: DeviceProblem, prec: int, n_slices: int, prec_lesser: int = -1, n_slices_lesser: int = -1):
     st = _Problem()
     st.n_b, st.b, st.n_e = dp.n_b, dp.b, dp.n_e
     st.prec, st.n_slices = int(prec), int(n_slices)
+    st.prec_lesser, st.n_slices_lesser = int(prec_lesser), int(n_slices_lesser)
     flags = 0
     if dp.S_d is None:
         flags |= QTX_S_IDENTITY
@@ -244,14 +246,18 @@ class Context:
         self.close()
 
     # -- qtx_rgf_solve
-    def solve(self, problems, prec="fp64", n_slices: int = 0, stream=None, check: bool = True) -> int:
+    def solve(self, problems, prec="fp64", n_slices: int = 0, stream=None, check: bool = True,
+              prec_lesser=None, n_slices_lesser: int = -1) -> int:
+        """prec / n_slices: scheme of the retarded-chain products; prec_lesser /
+        n_slices_lesser: scheme of the lesser-chain products (None = same)."""
         if isinstance(problems, DeviceProblem):
             problems = [problems]
         precs = prec if isinstance(prec, (list, tuple)) else [prec] * len(problems)
+        pl = -1 if prec_lesser is None else PREC_NAMES.get(prec_lesser, prec_lesser)
         arr = (_Problem * len(problems))()
         keep = []
         for k, (dp, pr) in enumerate(zip(problems, precs)):
-            st, en = _problem_struct(dp, PREC_NAMES.get(pr, pr), n_slices)
+            st, en = _problem_struct(dp, PREC_NAMES.get(pr, pr), n_slices, pl, n_slices_lesser)
             arr[k] = st
             keep.append(en)
         rc = self.lib.qtx_rgf_solve(self.handle, arr, len(problems), _stream_ptr(stream))
