@@ -134,9 +134,28 @@ qtx_status qtx_rgf_create(qtx_rgf_ctx* out, int device, size_t workspace_bytes,
  * (a hipStream_t, NULL = default stream).  Problems may differ in n_b, b,
  * n_e and precision.  Validation is synchronous (QTX_ERR_ARG /
  * QTX_ERR_UNSUPPORTED / QTX_ERR_NOMEM with nothing enqueued).  The per-energy
- * numerical status lands in each problem's `status` array. */
+ * numerical status lands in each problem's `status` array.
+ * All energies of all problems that share b and the precision schemes are
+ * solved together: one launch per recurrence step covers every such energy
+ * (energies are independent, Section II-A); problems of other block sizes run
+ * concurrently on internal streams that join back into hip_stream.  The call
+ * may wait for its own previous table upload (host pointers in the problem
+ * structs are read during the call only). */
 qtx_status qtx_rgf_solve(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int32_t n_probs,
                          void* hip_stream);
+
+/* Context options (qtx_rgf_set_option):
+ *   QTX_OPT_GRAPH  value != 0: qtx_rgf_solve captures its whole launch sequence
+ *                  (all batches, on parallel streams for different block sizes)
+ *                  into a hipGraph on the first call with a given set of problems
+ *                  and replays it with one graph launch on later identical calls
+ *                  (same problem structs, energies and workspace).  Needs a
+ *                  non-NULL stream; with the NULL stream the solve runs eagerly.
+ * Counters (qtx_rgf_get_stat): graph launches, graph captures, workspace bytes. */
+enum { QTX_OPT_GRAPH = 1 };
+enum { QTX_STAT_GRAPH_LAUNCHES = 1, QTX_STAT_GRAPH_CAPTURES = 2, QTX_STAT_WORKSPACE_BYTES = 3 };
+qtx_status qtx_rgf_set_option(qtx_rgf_ctx ctx, int option, int64_t value);
+qtx_status qtx_rgf_get_stat(qtx_rgf_ctx ctx, int stat, int64_t* value);
 
 /* Free the context and its workspace (synchronizes the device first). */
 qtx_status qtx_rgf_destroy(qtx_rgf_ctx ctx);

@@ -35,6 +35,33 @@ __global__ void check_finite_kernel(const double2* X, int64_t per_batch, int64_t
   if (bad && threadIdx.x == 0) atomicCAS(status + z, 0, 6);   // QTX_ERR_NONFINITE
 }
 
+__global__ void check_finite_entries_kernel(const double2* const* t, int64_t count, int32_t* status) {
+  const int z = blockIdx.y;
+  const double2* Xz = t[z];
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = Xz[i];
+    bad |= !(isfinite(v.x) && isfinite(v.y));
+  }
+  bad = __syncthreads_or(bad);
+  if (bad && threadIdx.x == 0) atomicCAS(status + z, 0, 6);   // QTX_ERR_NONFINITE
+}
+
+__global__ void nan_fill_entries_kernel(double2* const* t, const int64_t* counts, const int32_t* status) {
+  const int z = blockIdx.y;
+  if (status[z] == 0) return;
+  const double nan = __builtin_nan("");
+  double2* Xz = t[z];
+  const int64_t n = counts[z];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    Xz[i] = cmk(nan, nan);
+}
+
+__global__ void scatter_status_kernel(const int32_t* st, int32_t* const* dst, int n) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z < n && dst[z]) *dst[z] = st[z];
+}
+
 // Per energy e (one workgroup): with M1 = Gamma G, M2 = Gamma G^H,
 //   Tr[Gamma A] = Re(i (Tr M1 - Tr M2)),   Tr[Gamma G Gamma G^H] = Tr[M1 M2],
 //   T = Tr[Gamma A] - Re Tr[M1 M2],  j = Re(i Tr[Gamma G^<]) + f Tr[Gamma A].
@@ -96,6 +123,28 @@ hipError_t launch_check_finite(const double2* X, int64_t per_batch, int64_t stri
   int64_t g = (per_batch + 1023) / 1024;
   if (g > 1024) g = 1024;
   hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)g, batch), dim3(256), 0, s, X, per_batch, stride, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite_entries(const double2* const* t, int64_t count, int batch, int32_t* status,
+                                       hipStream_t s) {
+  if (count <= 0 || batch <= 0) return hipSuccess;
+  int64_t g = (count + 1023) / 1024;
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(check_finite_entries_kernel, dim3((unsigned)g, batch), dim3(256), 0, s, t, count, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_nan_fill_entries(double2* const* t, const int64_t* counts, int batch, const int32_t* status,
+                                   hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(nan_fill_entries_kernel, dim3(256, batch), dim3(256), 0, s, t, counts, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_status(const int32_t* st, int32_t* const* dst, int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_status_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, st, dst, batch);
   return hipGetLastError();
 }
 

@@ -3,9 +3,7 @@
 // Per energy the solve is block Gaussian elimination of the BT system
 // M(E) = E S - H - Sigma^R(E) (Section IV-A) in recursive Green's function form,
 // applied to the quadratic system M G^< M^H = Sigma^< of Eq. 2 (G row of
-// Table I, Section II-A).  All energies of a chunk advance together: every
-// step below is one batched launch over the chunk (energies are independent,
-// Section II-A), so each launch carries chunk x (tiles per block) workgroups.
+// Table I, Section II-A).
 //
 // Forward (i = 0 .. n_b-1), x_i = left-connected G^R, xl_i = left-connected G^<:
 //   x_0 = A_0^-1,  x_i = (A_i - L_{i-1} x_{i-1} U_{i-1})^-1
@@ -19,13 +17,26 @@
 //                                           xl_i is skew-Hermitian, Section II-A)
 // x_i is stored in the G^R_ii output slot and xl_i in the G^<_ii slot, and both
 // are overwritten in place by the backward pass.
+//
+// Batching.  Energies are independent (Section II-A).  A batch is a set of
+// entries -- one entry per (problem, energy) -- that share the block size b and
+// the precision schemes; its entries are sorted by n_b (descending) so that the
+// entries still active at a step form a prefix, and every step of the
+// recurrences is one launch over that prefix.  Operands are addressed per entry
+// through pointer tables built on the host: a dry pass over the step sequence
+// collects every table, one copy uploads them, and the second pass launches.
+// Tables that are affine in the entry index (all energies of one problem)
+// collapse to base + z * stride.  Batches of different block size run on
+// parallel streams; with the graph option the solve is captured once into a
+// hipGraph (cached by its signature) and replayed with a single launch.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <mutex>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "qtx_internal.h"
@@ -40,6 +51,11 @@ struct ProfFamily {
   int64_t launches = 0;
 };
 
+struct GraphCacheEntry {
+  uint64_t sig = 0;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct qtx_rgf_ctx_s {
   int device = 0;
   size_t ws_cap = 0;       // 0 = automatic
@@ -48,44 +64,20 @@ struct qtx_rgf_ctx_s {
   qtx_status sticky = QTX_OK;
   std::string tune_path;
   bool profiling = false;
+  bool use_graph = false;
+  bool capturing = false;
   ProfFamily prof[2];
   std::vector<hipEvent_t> event_pool;
+  // pinned staging of the pointer tables, and the event of its last upload
+  void* pinned = nullptr;
+  size_t pinned_size = 0;
+  hipEvent_t upload_done = nullptr;
+  // auxiliary streams (default priority) and fork/join events for parallel batches
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> fork_ev, join_ev;
+  std::vector<GraphCacheEntry> graphs;
+  int64_t graph_launches = 0, graph_captures = 0;
 };
-
-namespace {
-
-hipEvent_t pool_event(qtx_rgf_ctx ctx) {
-  if (!ctx->event_pool.empty()) {
-    hipEvent_t e = ctx->event_pool.back();
-    ctx->event_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-// Bracket a launch with events when profiling is on.
-struct ProfScope {
-  qtx_rgf_ctx ctx;
-  int fam;
-  hipStream_t s;
-  double flops;
-  hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(qtx_rgf_ctx c, int f, hipStream_t st, double fl) : ctx(c), fam(f), s(st), flops(fl) {
-    if (!ctx || !ctx->profiling) return;
-    a = pool_event(ctx);
-    b = pool_event(ctx);
-    if (a) (void)hipEventRecord(a, s);
-  }
-  ~ProfScope() {
-    if (!a || !b) return;
-    (void)hipEventRecord(b, s);
-    ctx->prof[fam].pending.push_back({a, b, flops});
-  }
-};
-
-}  // namespace
 
 namespace {
 
@@ -104,6 +96,12 @@ qtx_status hip_fail(qtx_rgf_ctx ctx, hipError_t e) {
     if (_e != hipSuccess) return hip_fail(ctx, _e);    \
   } while (0)
 
+#define QTX_TRYS(expr)                                 \
+  do {                                                 \
+    qtx_status _s = (expr);                            \
+    if (_s != QTX_OK) return _s;                       \
+  } while (0)
+
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
@@ -115,11 +113,19 @@ struct DeviceGuard {
   }
 };
 
+void drop_graphs(qtx_rgf_ctx ctx) {
+  for (auto& g : ctx->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  ctx->graphs.clear();
+}
+
 // Make sure the context holds at least `bytes` of workspace.  Growing waits for
-// all work on the device first (the old buffer may still be in use).
+// all work on the device first (the old buffer may still be in use) and drops
+// cached graphs (they hold addresses inside the old buffer).
 qtx_status ensure_ws(qtx_rgf_ctx ctx, size_t bytes) {
   if (bytes <= ctx->ws_size) return QTX_OK;
   QTX_TRY(hipDeviceSynchronize());
+  drop_graphs(ctx);
   if (ctx->ws) {
     QTX_TRY(hipFree(ctx->ws));
     ctx->ws = nullptr;
@@ -135,6 +141,36 @@ qtx_status ensure_ws(qtx_rgf_ctx ctx, size_t bytes) {
   return QTX_OK;
 }
 
+qtx_status ensure_pinned(qtx_rgf_ctx ctx, size_t bytes) {
+  if (ctx->upload_done) QTX_TRY(hipEventSynchronize(ctx->upload_done));   // the last upload has read it
+  if (bytes <= ctx->pinned_size) return QTX_OK;
+  if (ctx->pinned) QTX_TRY(hipHostFree(ctx->pinned));
+  ctx->pinned = nullptr;
+  ctx->pinned_size = 0;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return QTX_ERR_NOMEM;
+  }
+  ctx->pinned = p;
+  ctx->pinned_size = bytes;
+  return QTX_OK;
+}
+
+qtx_status ensure_aux(qtx_rgf_ctx ctx, size_t n) {
+  while (ctx->aux.size() < n) {
+    hipStream_t st;
+    hipEvent_t a, b;
+    QTX_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    QTX_TRY(hipEventCreateWithFlags(&a, hipEventDisableTiming));
+    QTX_TRY(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+    ctx->aux.push_back(st);
+    ctx->fork_ev.push_back(a);
+    ctx->join_ev.push_back(b);
+  }
+  return QTX_OK;
+}
+
 size_t ws_budget(qtx_rgf_ctx ctx) {
   if (ctx->ws_cap) return ctx->ws_cap;
   size_t fr = 0, tot = 0;
@@ -142,21 +178,45 @@ size_t ws_budget(qtx_rgf_ctx ctx) {
   return (fr + ctx->ws_size) / 4;
 }
 
-// ---------------------------------------------------------------- operands
+hipEvent_t pool_event(qtx_rgf_ctx ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
 
-// A per-batch matrix operand: element (z, r, c) at p + z*stride + r*ld + c.
-struct Mat {
-  const double2* p = nullptr;
-  int64_t stride = 0;
-  int64_t ld = 0;
+// Bracket a launch with events when profiling is on (never inside a capture).
+struct ProfScope {
+  qtx_rgf_ctx ctx;
+  int fam;
+  hipStream_t s;
+  double flops;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(qtx_rgf_ctx c, int f, hipStream_t st, double fl, bool active) : ctx(c), fam(f), s(st), flops(fl) {
+    if (!active || !ctx || !ctx->profiling || ctx->capturing) return;
+    a = pool_event(ctx);
+    b = pool_event(ctx);
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, s);
+    ctx->prof[fam].pending.push_back({a, b, flops});
+  }
 };
 
-// Precision scheme of the block products: qtx_prec -> (kind, 16-bit format, slices).
+// ---------------------------------------------------------------- precision schemes
+
 struct Scheme {
   int prec = QTX_FP64;
   int fmt = 0;      // split: 0 = FP16 digits, 1 = BF16 digits
   int ns = 0;       // split: slices per operand
   bool split() const { return prec == QTX_BF16_SPLIT || prec == QTX_FP16_SPLIT; }
+  bool operator==(const Scheme& o) const { return prec == o.prec && fmt == o.fmt && ns == o.ns; }
 };
 
 bool make_scheme(int prec, int n_slices, Scheme* out) {
@@ -171,9 +231,15 @@ bool make_scheme(int prec, int n_slices, Scheme* out) {
   return true;
 }
 
-// Workspace of one split operand (rows = cols = b), per batch entry.
-size_t split_operand_bytes(int b, const Scheme& sc) {
-  return sc.split() ? split_bytes(b, b, sc.ns, 1) + 512 : 0;
+void problem_schemes(const qtx_rgf_problem& p, Scheme* r, Scheme* l) {
+  make_scheme(p.prec, p.n_slices, r);
+  if (p.prec_lesser >= 0) make_scheme(p.prec_lesser, p.n_slices_lesser, l);
+  else *l = *r;
+}
+
+Scheme larger_split(const Scheme& a, const Scheme& b) {
+  if (b.split() && (!a.split() || b.ns > a.ns)) return b;
+  return a;
 }
 
 struct SplitBufs {
@@ -181,7 +247,13 @@ struct SplitBufs {
   int32_t* E[2] = {nullptr, nullptr};
 };
 
-// Carve two split operands for `batch` entries from w (advances w).
+size_t split_pair_bytes(int b, const Scheme& sc, int batch) {
+  if (!sc.split()) return 0;
+  const size_t dig = (size_t)split_digit_stride(b, b, sc.ns) * sizeof(uint16_t) * batch;
+  const size_t ex = (size_t)split_exp_stride(b, b) * sizeof(int32_t) * batch;
+  return 2 * (align_up(dig) + align_up(ex));
+}
+
 SplitBufs carve_split(char*& w, int b, const Scheme& sc, int batch) {
   SplitBufs sb;
   if (!sc.split()) return sb;
@@ -194,94 +266,43 @@ SplitBufs carve_split(char*& w, int b, const Scheme& sc, int batch) {
   return sb;
 }
 
-// One batched complex block product with the context's precision scheme.
-// Elementwise (K = 0) launches and anything but b x b x b products stay FP64.
+// One batched complex block product with a precision scheme.  Elementwise (K = 0)
+// launches stay FP64.
 hipError_t run_product(const GemmDesc& d, const Scheme& sc, const SplitBufs& sb, hipStream_t s) {
   if (d.K == 0 || sc.prec == QTX_FP64) return launch_zgemm_f64(d, s);
   if (sc.prec == QTX_FP32) return launch_zgemm_f32(d, s);
   // split: operand A as rows of op(A) (M x K), operand B as columns of op(B) (N x K)
+  const bool shA = (d.sA == 0 && !d.tA), shB = (d.sB == 0 && !d.tB);
   SplitDesc sa;
-  sa.X = d.A; sa.ld = d.lda; sa.stride = d.sA;
+  sa.tX = d.tA; sa.X = d.A; sa.ld = d.lda; sa.stride = d.sA;
   sa.rows = d.M; sa.cols = d.K;
   sa.trans = (d.opA == OP_C); sa.conj = (d.opA == OP_C);
   sa.S = sb.S[0]; sa.E = sb.E[0];
   sa.s_stride = split_digit_stride(d.M, d.K, sc.ns);
   sa.e_stride = split_exp_stride(d.M, d.K);
-  sa.batch = d.sA == 0 ? 1 : d.batch;
+  sa.batch = shA ? 1 : d.batch;
   SplitDesc sbd;
-  sbd.X = d.B; sbd.ld = d.ldb; sbd.stride = d.sB;
+  sbd.tX = d.tB; sbd.X = d.B; sbd.ld = d.ldb; sbd.stride = d.sB;
   sbd.rows = d.N; sbd.cols = d.K;
   sbd.trans = (d.opB == OP_N); sbd.conj = (d.opB == OP_C);
   sbd.S = sb.S[1]; sbd.E = sb.E[1];
   sbd.s_stride = split_digit_stride(d.N, d.K, sc.ns);
   sbd.e_stride = split_exp_stride(d.N, d.K);
-  sbd.batch = d.sB == 0 ? 1 : d.batch;
+  sbd.batch = shB ? 1 : d.batch;
   hipError_t e = launch_split(sa, sc.fmt, sc.ns, s);
   if (e != hipSuccess) return e;
   e = launch_split(sbd, sc.fmt, sc.ns, s);
   if (e != hipSuccess) return e;
   SplitGemmDesc g;
   g.d = d;
-  g.SA = sa.S; g.sa_stride = (d.sA == 0) ? 0 : sa.s_stride;
-  g.SB = sbd.S; g.sb_stride = (d.sB == 0) ? 0 : sbd.s_stride;
-  g.EA = sa.E; g.ea_stride = (d.sA == 0) ? 0 : sa.e_stride;
-  g.EB = sbd.E; g.eb_stride = (d.sB == 0) ? 0 : sbd.e_stride;
+  g.SA = sa.S; g.sa_stride = shA ? 0 : sa.s_stride;
+  g.SB = sbd.S; g.sb_stride = shB ? 0 : sbd.s_stride;
+  g.EA = sa.E; g.ea_stride = shA ? 0 : sa.e_stride;
+  g.EB = sbd.E; g.eb_stride = shB ? 0 : sbd.e_stride;
   return launch_zgemm_split(g, sc.fmt, sc.ns, s);
 }
 
-struct Gemm {
-  qtx_rgf_ctx ctx;
-  hipStream_t s;
-  int b;
-  int batch;
-  const double* energies;   // device, per batch entry
-  Scheme sc;
-  SplitBufs sb;
-
-  // C = alpha * op(A) op(B) + addends (+ diag * E_z I)
-  hipError_t run(int opA, Mat A, int opB, Mat B, double2* C, int64_t sC, double2 alpha,
-                 std::initializer_list<Addend> adds, double2 diag = cmk(0, 0), int K = -1) const {
-    GemmDesc d;
-    d.M = b; d.N = b; d.K = (K < 0) ? b : K;
-    d.opA = opA; d.opB = opB;
-    d.A = A.p; d.lda = A.ld ? A.ld : b; d.sA = A.stride;
-    d.B = B.p; d.ldb = B.ld ? B.ld : b; d.sB = B.stride;
-    d.C = C; d.ldc = b; d.sC = sC;
-    d.alpha = alpha;
-    int q = 0;
-    for (const Addend& a : adds) {
-      if (q < kMaxAddends) {
-        d.add[q] = a;
-        if (d.add[q].ld == 0) d.add[q].ld = b;   // blocks are b x b unless stated
-        ++q;
-      }
-    }
-    d.diag = diag;
-    d.diag_by_batch = 1;
-    d.bscal = energies;
-    d.batch = batch;
-    if (d.K == b) {
-      ProfScope ps(ctx, QTX_KERNEL_GEMM, s, 8.0 * (double)b * b * b * batch);
-      return run_product(d, sc, sb, s);
-    }
-    return run_product(d, sc, sb, s);
-  }
-};
-
-inline Addend addend(const double2* X, int64_t stride, double2 coef, int op = OP_N, int64_t ld = 0,
-                     int by_batch = 0) {
-  Addend a;
-  a.X = X; a.stride = stride; a.coef = coef; a.op = op; a.ld = ld; a.scale_by_batch = by_batch;
-  return a;
-}
-
-// Per-energy workspace of the RGF path, in b*b blocks.
-constexpr int kTemps = 6;
-
-size_t per_energy_bytes(int b, const Scheme& sc) {
-  const size_t bb = (size_t)b * b * sizeof(double2);
-  return align_up(bb) * (1 + kTemps + 2) + align_up(gje_work_bytes(b, 1)) + 2 * split_operand_bytes(b, sc) + 64;
-}
+// ---------------------------------------------------------------- problem validation
 
 bool valid_problem(const qtx_rgf_problem* p) {
   if (!p) return false;
@@ -312,184 +333,569 @@ qtx_status check_supported(const qtx_rgf_problem* p) {
   return QTX_OK;
 }
 
-// One energy chunk [e0, e0+ne) of problem p.
-qtx_status solve_chunk(qtx_rgf_ctx ctx, const qtx_rgf_problem& p, int e0, int ne, hipStream_t s,
-                       const double* d_en) {
-  const int b = p.b, nb = p.n_b;
+// ---------------------------------------------------------------- batches
+
+constexpr int kTemps = 6;
+
+// Arrays an operand can come from.
+enum Arr {
+  A_HD, A_HU, A_HL, A_SD, A_SU, A_SL,               // per problem, [n_b] / [n_b-1] blocks
+  A_SRD, A_SLD, A_SGD, A_GRD, A_GLD, A_GGD,         // per energy, [n_b] blocks
+  A_SRU, A_SRL, A_GRU, A_GRL, A_GLU, A_GGU          // per energy, [n_b-1] blocks
+};
+
+struct Entry {
+  const qtx_rgf_problem* p;
+  int e;
+};
+
+// The common properties of a batch's entries.
+struct BatchKey {
+  int b = 0;
+  Scheme r, l;
+  bool s_id = true, greater = false, coupled = false;
+  bool operator==(const BatchKey& o) const {
+    return b == o.b && r == o.r && l == o.l && s_id == o.s_id && greater == o.greater && coupled == o.coupled;
+  }
+};
+
+BatchKey key_of(const qtx_rgf_problem& p) {
+  BatchKey k;
+  k.b = p.b;
+  problem_schemes(p, &k.r, &k.l);
+  k.s_id = (p.flags & QTX_S_IDENTITY) != 0;
+  k.greater = (p.flags & QTX_WANT_GREATER) != 0;
+  k.coupled = !k.s_id || p.SR_u || p.SR_l;
+  return k;
+}
+
+// Workspace of a batch of Z entries (excluding its pointer tables).
+size_t batch_ws_bytes(const BatchKey& k, int Z) {
+  const size_t blk = align_up((size_t)Z * k.b * k.b * sizeof(double2));
+  return blk * (1 + kTemps + 2) + align_up(gje_work_bytes(k.b, Z)) + align_up((size_t)Z * sizeof(int32_t)) +
+         split_pair_bytes(k.b, larger_split(k.r, k.l), Z) + 1024;
+}
+
+size_t per_entry_bytes(const BatchKey& k) { return batch_ws_bytes(k, 1); }
+
+struct Batch {
+  BatchKey key;
+  std::vector<Entry> ent;     // sorted by n_b, descending
+  int max_nb = 0;
+  int lane = 0;               // stream lane (batches of one lane run in order)
+  size_t ws_off = 0;          // workspace region (bytes from the workspace start)
+  size_t tab_off = 0;         // table area (bytes from the table block start)
+};
+
+// A pointer table request: array, indexing mode, step, block offset.
+// mode 0: forward step i -> block i + delta (active prefix of step i)
+// mode 1: backward step k -> block n_b - 2 - k + delta (active prefix of step k)
+// mode 2: block delta of every entry, always a table (status handling)
+struct TabKey {
+  int arr, mode, step, delta;
+  bool operator<(const TabKey& o) const {
+    return std::tie(arr, mode, step, delta) < std::tie(o.arr, o.mode, o.step, o.delta);
+  }
+};
+
+struct TabVal {
+  const double2* base = nullptr;   // affine: base + z * stride
+  int64_t stride = 0;
+  int64_t off = -1;                // table: byte offset in the batch's table area
+};
+
+// Operand handle: affine (p, stride) or a device table.
+struct Mat {
+  const double2* p = nullptr;
+  int64_t stride = 0;
+  const double2* const* tab = nullptr;
+};
+
+// Per-entry data at the head of a batch's table area.
+struct EntryData {
+  size_t en, ust, cnt_d, cnt_u, end;
+};
+EntryData entry_data_layout(int Z) {
+  EntryData d;
+  d.en = 0;
+  d.ust = align_up(d.en + (size_t)Z * sizeof(double));
+  d.cnt_d = align_up(d.ust + (size_t)Z * sizeof(void*));
+  d.cnt_u = align_up(d.cnt_d + (size_t)Z * sizeof(int64_t));
+  d.end = align_up(d.cnt_u + (size_t)Z * sizeof(int64_t));
+  return d;
+}
+
+// State of one batch run: the dry pass plans tables, the launch pass uses them.
+struct Run {
+  qtx_rgf_ctx ctx;
+  hipStream_t s = nullptr;
+  Batch* B = nullptr;
+  bool dry = true;
+  std::map<TabKey, TabVal> tabs;
+  std::vector<char> host;          // this batch's table area (per-entry data + tables)
+  char* dev = nullptr;             // its device copy (launch pass)
+  int64_t bb = 0;
+
+  int nb_of(int z) const { return B->ent[z].p->n_b; }
+  int active_fwd(int i) const {
+    int n = 0;
+    while (n < (int)B->ent.size() && nb_of(n) > i) ++n;
+    return n;
+  }
+  int active_bwd(int k) const {
+    int n = 0;
+    while (n < (int)B->ent.size() && nb_of(n) - 2 >= k) ++n;
+    return n;
+  }
+
+  // Base pointer of array a for entry z at block j (nullptr for an absent array).
+  const double2* ptr(int a, int z, int j) const {
+    const qtx_rgf_problem& p = *B->ent[z].p;
+    const int64_t e = B->ent[z].e;
+    const int64_t nd = p.n_b, nu = (int64_t)p.n_b - 1;
+    const void* base = nullptr;
+    int64_t idx = 0;
+    switch (a) {
+      case A_HD: base = p.H_d; idx = j; break;
+      case A_HU: base = p.H_u; idx = j; break;
+      case A_HL: base = p.H_l; idx = j; break;
+      case A_SD: base = p.S_d; idx = j; break;
+      case A_SU: base = p.S_u; idx = j; break;
+      case A_SL: base = p.S_l; idx = j; break;
+      case A_SRD: base = p.SR_d; idx = e * nd + j; break;
+      case A_SLD: base = p.SL_d; idx = e * nd + j; break;
+      case A_SGD: base = p.SG_d; idx = e * nd + j; break;
+      case A_GRD: base = p.GR_d; idx = e * nd + j; break;
+      case A_GLD: base = p.GL_d; idx = e * nd + j; break;
+      case A_GGD: base = p.GG_d; idx = e * nd + j; break;
+      case A_SRU: base = p.SR_u; idx = e * nu + j; break;
+      case A_SRL: base = p.SR_l; idx = e * nu + j; break;
+      case A_GRU: base = p.GR_u; idx = e * nu + j; break;
+      case A_GRL: base = p.GR_l; idx = e * nu + j; break;
+      case A_GLU: base = p.GL_u; idx = e * nu + j; break;
+      case A_GGU: base = p.GG_u; idx = e * nu + j; break;
+    }
+    if (!base) return nullptr;
+    return (const double2*)base + idx * bb;
+  }
+
+  Mat get(int a, int mode, int step, int delta) {
+    const TabKey key{a, mode, step, delta};
+    auto it = tabs.find(key);
+    if (it == tabs.end()) {
+      const int Z = mode == 0 ? active_fwd(step) : (mode == 1 ? active_bwd(step) : (int)B->ent.size());
+      std::vector<const double2*> v(Z);
+      bool any_null = false;
+      for (int z = 0; z < Z; ++z) {
+        const int j = mode == 0 ? step + delta : (mode == 1 ? nb_of(z) - 2 - step + delta : delta);
+        v[z] = ptr(a, z, j);
+        any_null |= (v[z] == nullptr);
+      }
+      TabVal tv;
+      bool affine = mode != 2 && Z > 0 && !any_null;
+      int64_t stride = 0;
+      if (affine && Z > 1) {
+        stride = v[1] - v[0];
+        for (int z = 2; z < Z && affine; ++z) affine = (v[z] - v[z - 1] == stride);
+      }
+      if (Z == 0 || (mode != 2 && v[0] == nullptr)) {
+        tv.base = nullptr;
+      } else if (affine) {
+        tv.base = v[0];
+        tv.stride = stride;
+      } else {
+        const size_t off = align_up(host.size());
+        host.resize(off + (size_t)Z * sizeof(void*));
+        std::memcpy(host.data() + off, v.data(), (size_t)Z * sizeof(void*));
+        tv.off = (int64_t)off;
+      }
+      it = tabs.emplace(key, tv).first;
+    }
+    const TabVal& tv = it->second;
+    Mat m;
+    if (tv.off >= 0) {
+      // a placeholder in the dry pass (non-null so operand presence is preserved)
+      m.tab = dry ? (const double2* const*)(uintptr_t)1 : (const double2* const*)(dev + tv.off);
+    } else {
+      m.p = tv.base;
+      m.stride = tv.stride;
+    }
+    return m;
+  }
+};
+
+inline Addend addend_of(const Mat& m, double2 coef, int op = OP_N, int by_batch = 0) {
+  Addend a;
+  a.X = m.p; a.stride = m.stride; a.tX = m.tab; a.coef = coef; a.op = op; a.scale_by_batch = by_batch;
+  return a;
+}
+
+struct Gemm {
+  Run* run;
+  int b;
+  const double* energies;   // device, per entry
+  Scheme sc;
+  SplitBufs sb;
+
+  // C = alpha * op(A) op(B) + addends (+ diag * E_z I), over the first Z entries
+  hipError_t go(int Z, int opA, Mat A, int opB, Mat B, Mat C, double2 alpha, std::initializer_list<Addend> adds,
+                double2 diag = cmk(0, 0), int K = -1) const {
+    if (run->dry || Z <= 0) return hipSuccess;
+    GemmDesc d;
+    d.M = b; d.N = b; d.K = (K < 0) ? b : K;
+    d.opA = opA; d.opB = opB;
+    d.A = A.p; d.sA = A.stride; d.tA = A.tab; d.lda = b;
+    d.B = B.p; d.sB = B.stride; d.tB = B.tab; d.ldb = b;
+    d.C = (double2*)C.p; d.sC = C.stride; d.tC = (double2* const*)C.tab; d.ldc = b;
+    d.alpha = alpha;
+    int q = 0;
+    for (const Addend& a : adds) {
+      if (q < kMaxAddends && (a.X || a.tX)) {
+        d.add[q] = a;
+        if (d.add[q].ld == 0) d.add[q].ld = b;   // blocks are b x b
+        ++q;
+      }
+    }
+    d.diag = diag;
+    d.diag_by_batch = 1;
+    d.bscal = energies;
+    d.batch = Z;
+    ProfScope ps(run->ctx, QTX_KERNEL_GEMM, run->s, 8.0 * (double)b * b * b * Z, d.K == b);
+    return run_product(d, sc, sb, run->s);
+  }
+};
+
+// Device layout of a batch's workspace.
+struct BatchWs {
+  double2* X = nullptr;
+  double2* Tm[kTemps] = {};
+  double2* Uw = nullptr;
+  double2* Lw = nullptr;
+  GjeWork gw;
+  int32_t* st = nullptr;
+  SplitBufs sb;
+  // per-entry data (inside the table area)
+  const double* en = nullptr;
+  int32_t* const* ust = nullptr;
+  const int64_t* cnt_d = nullptr;
+  const int64_t* cnt_u = nullptr;
+};
+
+BatchWs carve_batch(char* w, const BatchKey& k, int Z) {
+  BatchWs L;
+  const size_t blk = align_up((size_t)Z * k.b * k.b * sizeof(double2));
+  L.X = (double2*)w; w += blk;
+  for (int t = 0; t < kTemps; ++t) { L.Tm[t] = (double2*)w; w += blk; }
+  L.Uw = (double2*)w; w += blk;
+  L.Lw = (double2*)w; w += blk;
+  L.gw = gje_carve(w, k.b, Z); w += align_up(gje_work_bytes(k.b, Z));
+  L.st = (int32_t*)w; w += align_up((size_t)Z * sizeof(int32_t));
+  L.sb = carve_split(w, k.b, larger_split(k.r, k.l), Z);
+  return L;
+}
+
+// The step sequence of one batch (the dry pass and the launch pass both run it).
+qtx_status run_batch(Run& R, const BatchWs& W) {
+  qtx_rgf_ctx ctx = R.ctx;
+  Batch& B = *R.B;
+  const BatchKey& k = B.key;
+  const int b = k.b;
   const int64_t bb = (int64_t)b * b;
-  const int64_t sE = (int64_t)nb * bb;           // per-energy stride of [n_e][n_b] arrays
-  const int64_t sEu = (int64_t)(nb - 1) * bb;    // per-energy stride of [n_e][n_b-1] arrays
-  const bool S_id = (p.flags & QTX_S_IDENTITY) != 0;
-  const bool greater = (p.flags & QTX_WANT_GREATER) != 0;
-
-  // carve the workspace
-  char* w = (char*)ctx->ws;
-  const size_t blk = align_up((size_t)ne * bb * sizeof(double2));
-  double2* X = (double2*)w; w += blk;
-  double2* Tm[kTemps];
-  for (int t = 0; t < kTemps; ++t) { Tm[t] = (double2*)w; w += blk; }
-  double2* Uw = (double2*)w; w += blk;           // per-energy U_i when it depends on E
-  double2* Lw = (double2*)w; w += blk;           // per-energy L_i when it depends on E
-  GjeWork gw = gje_carve(w, b, ne); w += align_up(gje_work_bytes(b, ne));
-  int32_t* st = (int32_t*)w; w += align_up((size_t)ne * sizeof(int32_t));
-  const double* en = d_en + e0;
-  Scheme scheme, scheme_l;
-  make_scheme(p.prec, p.n_slices, &scheme);
-  if (p.prec_lesser >= 0) make_scheme(p.prec_lesser, p.n_slices_lesser, &scheme_l);
-  else scheme_l = scheme;
-  // split buffers sized for the larger of the two schemes
-  Scheme big = (scheme_l.split() && (!scheme.split() || scheme_l.ns > scheme.ns)) ? scheme_l : scheme;
-  SplitBufs sbufs = carve_split(w, b, big, ne);
-
-  const double2* H_d = (const double2*)p.H_d;
-  const double2* H_u = (const double2*)p.H_u;
-  const double2* H_l = (const double2*)p.H_l;
-  const double2* S_d = (const double2*)p.S_d;
-  const double2* S_u = (const double2*)p.S_u;
-  const double2* S_l = (const double2*)p.S_l;
-  const double2* SR_d = (const double2*)p.SR_d + (int64_t)e0 * sE;
-  const double2* SR_u = p.SR_u ? (const double2*)p.SR_u + (int64_t)e0 * sEu : nullptr;
-  const double2* SR_l = p.SR_l ? (const double2*)p.SR_l + (int64_t)e0 * sEu : nullptr;
-  double2* GR_d = (double2*)p.GR_d + (int64_t)e0 * sE;
-  double2* GR_u = nb > 1 ? (double2*)p.GR_u + (int64_t)e0 * sEu : nullptr;
-  double2* GR_l = nb > 1 ? (double2*)p.GR_l + (int64_t)e0 * sEu : nullptr;
-
-  struct Rhs {
-    const double2* B;   // diagonal blocks of Sigma^< or Sigma^>
-    double2* Gd;
-    double2* Gu;
-  };
-  std::vector<Rhs> rhs;
-  rhs.push_back({(const double2*)p.SL_d + (int64_t)e0 * sE, (double2*)p.GL_d + (int64_t)e0 * sE,
-                 nb > 1 ? (double2*)p.GL_u + (int64_t)e0 * sEu : nullptr});
-  if (greater)
-    rhs.push_back({(const double2*)p.SG_d + (int64_t)e0 * sE, (double2*)p.GG_d + (int64_t)e0 * sE,
-                   nb > 1 ? (double2*)p.GG_u + (int64_t)e0 * sEu : nullptr});
-
-  QTX_TRY(launch_fill_i32(st, 0, ne, s));
-
-  Gemm g{ctx, s, b, ne, en, scheme, sbufs};     // retarded chain
-  Gemm gl{ctx, s, b, ne, en, scheme_l, sbufs};  // lesser / greater chain
+  const int Zall = (int)B.ent.size();
+  hipStream_t s = R.s;
+  const bool dry = R.dry;
+  Gemm g{&R, b, W.en, k.r, W.sb};     // retarded chain
+  Gemm gl{&R, b, W.en, k.l, W.sb};    // lesser / greater chain
   const double2 one = cmk(1, 0), mone = cmk(-1, 0), zero = cmk(0, 0);
+  auto ws = [&](double2* p) { Mat m; m.p = p; m.stride = bb; return m; };
+
+  if (!dry) QTX_TRY(launch_fill_i32(W.st, 0, Zall, s));
+
+  struct Rhs { int S, Gd, Gu; };
+  std::vector<Rhs> rhs{{A_SLD, A_GLD, A_GLU}};
+  if (k.greater) rhs.push_back({A_SGD, A_GGD, A_GGU});
 
   // The coupling operands: U_i = E S_{i,i+1} - H_{i,i+1} - Sigma^R_{i,i+1}(E) and the
-  // same for L_i.  With S = I and no Sigma^R coupling they are -H_u, -H_l, shared
-  // by all energies: the operand is H with sign -1.  Otherwise they are assembled
-  // per energy into the workspace (sign +1).
-  const bool shared_UL = S_id && !SR_u && !SR_l;
-  auto coupling = [&](int i, Mat& U, double& sU, Mat& L, double& sL) -> hipError_t {
-    if (shared_UL) {
-      U = Mat{H_u + (int64_t)i * bb, 0, b}; sU = -1.0;
-      L = Mat{H_l + (int64_t)i * bb, 0, b}; sL = -1.0;
+  // same for L_i.  With S = I and no Sigma^R coupling they are -H_u, -H_l: the
+  // operand is H with sign -1.  Otherwise they are assembled per entry (sign +1).
+  Mat U, L;
+  double sU = -1.0, sL = -1.0;
+  auto coupling = [&](int Z, int mode, int step, int delta) -> hipError_t {
+    if (!k.coupled) {
+      U = R.get(A_HU, mode, step, delta); sU = -1.0;
+      L = R.get(A_HL, mode, step, delta); sL = -1.0;
       return hipSuccess;
     }
-    hipError_t e;
-    // U_i
-    e = g.run(OP_N, Mat{}, OP_N, Mat{}, Uw, bb, zero,
-              {addend(S_id ? nullptr : S_u + (int64_t)i * bb, 0, one, OP_N, 0, 1),
-               addend(H_u + (int64_t)i * bb, 0, mone),
-               addend(SR_u ? SR_u + (int64_t)i * bb : nullptr, sEu, mone)}, zero, 0);
+    const Mat SU = k.s_id ? Mat{} : R.get(A_SU, mode, step, delta);
+    const Mat SL = k.s_id ? Mat{} : R.get(A_SL, mode, step, delta);
+    hipError_t e = g.go(Z, OP_N, Mat{}, OP_N, Mat{}, ws(W.Uw), zero,
+                        {addend_of(SU, one, OP_N, 1), addend_of(R.get(A_HU, mode, step, delta), mone),
+                         addend_of(R.get(A_SRU, mode, step, delta), mone)}, zero, 0);
     if (e != hipSuccess) return e;
-    e = g.run(OP_N, Mat{}, OP_N, Mat{}, Lw, bb, zero,
-              {addend(S_id ? nullptr : S_l + (int64_t)i * bb, 0, one, OP_N, 0, 1),
-               addend(H_l + (int64_t)i * bb, 0, mone),
-               addend(SR_l ? SR_l + (int64_t)i * bb : nullptr, sEu, mone)}, zero, 0);
-    U = Mat{Uw, bb, b}; sU = 1.0;
-    L = Mat{Lw, bb, b}; sL = 1.0;
+    e = g.go(Z, OP_N, Mat{}, OP_N, Mat{}, ws(W.Lw), zero,
+             {addend_of(SL, one, OP_N, 1), addend_of(R.get(A_HL, mode, step, delta), mone),
+              addend_of(R.get(A_SRL, mode, step, delta), mone)}, zero, 0);
+    U = ws(W.Uw); sU = 1.0;
+    L = ws(W.Lw); sL = 1.0;
     return e;
   };
-  // The diagonal block A_i = E S_ii - H_ii - Sigma^R_ii(E) as epilogue addends.
-  auto A_addends = [&](int i, Addend out[3], double2& dg) {
-    out[0] = addend(H_d + (int64_t)i * bb, 0, mone);
-    out[1] = addend(SR_d + (int64_t)i * bb, sE, mone);
-    if (S_id) { out[2] = Addend{}; dg = one; }
-    else { out[2] = addend(S_d + (int64_t)i * bb, 0, one, OP_N, 0, 1); dg = zero; }
-  };
 
-  Mat U, L;
-  double sU = 0, sL = 0;
   // ------------------------------------------------------------ forward
-  for (int i = 0; i < nb; ++i) {
-    Addend aa[3];
-    double2 dg;
-    A_addends(i, aa, dg);
+  for (int i = 0; i < B.max_nb; ++i) {
+    const int Z = R.active_fwd(i);
+    // A_i = E S_ii - H_ii - Sigma^R_ii(E) as epilogue addends
+    const Addend aH = addend_of(R.get(A_HD, 0, i, 0), mone);
+    const Addend aS = addend_of(R.get(A_SRD, 0, i, 0), mone);
+    const Addend aO = k.s_id ? Addend{} : addend_of(R.get(A_SD, 0, i, 0), one, OP_N, 1);
+    const double2 dg = k.s_id ? one : zero;
     if (i == 0) {
-      QTX_TRY(g.run(OP_N, Mat{}, OP_N, Mat{}, X, bb, zero, {aa[0], aa[1], aa[2]}, dg, 0));
+      QTX_TRY(g.go(Z, OP_N, Mat{}, OP_N, Mat{}, ws(W.X), zero, {aH, aS, aO}, dg, 0));
     } else {
-      QTX_TRY(coupling(i - 1, U, sU, L, sL));
+      QTX_TRY(coupling(Z, 0, i, -1));
       // T' = L' x_{i-1};   X = A_i - sL sU T' U'
-      QTX_TRY(g.run(OP_N, L, OP_N, Mat{GR_d + (int64_t)(i - 1) * bb, sE, b}, Tm[0], bb, one, {}));
-      QTX_TRY(g.run(OP_N, Mat{Tm[0], bb, b}, OP_N, U, X, bb, cmk(-sL * sU, 0), {aa[0], aa[1], aa[2]}, dg));
+      QTX_TRY(g.go(Z, OP_N, L, OP_N, R.get(A_GRD, 0, i, -1), ws(W.Tm[0]), one, {}));
+      QTX_TRY(g.go(Z, OP_N, ws(W.Tm[0]), OP_N, U, ws(W.X), cmk(-sL * sU, 0), {aH, aS, aO}, dg));
     }
-    {
-      ProfScope ps(ctx, QTX_KERNEL_INV, s, 8.0 * (double)b * b * b * ne);
-      QTX_TRY(launch_gje_invert(b, X, bb, GR_d + (int64_t)i * bb, sE, ne, gw, st, s));
+    const Mat xi = R.get(A_GRD, 0, i, 0);
+    if (!dry && Z > 0) {
+      ProfScope ps(ctx, QTX_KERNEL_INV, s, 8.0 * (double)b * b * b * Z, true);
+      QTX_TRY(launch_gje_invert(b, W.X, bb, (double2*)xi.p, xi.stride, Z, W.gw, W.st, s, (double2* const*)xi.tab));
     }
-    const Mat xi{GR_d + (int64_t)i * bb, sE, b};
     for (const Rhs& r : rhs) {
-      const double2* Bi = r.B + (int64_t)i * bb;
+      const Mat Bi = R.get(r.S, 0, i, 0);
       if (i == 0) {
-        QTX_TRY(gl.run(OP_N, xi, OP_N, Mat{Bi, sE, b}, Tm[2], bb, one, {}));
+        QTX_TRY(gl.go(Z, OP_N, xi, OP_N, Bi, ws(W.Tm[2]), one, {}));
       } else {
         // Y' = L' xl_{i-1};  Q = B_i + Y' L'^H;  Z = x_i Q
-        QTX_TRY(gl.run(OP_N, L, OP_N, Mat{r.Gd + (int64_t)(i - 1) * bb, sE, b}, Tm[1], bb, one, {}));
-        QTX_TRY(gl.run(OP_N, Mat{Tm[1], bb, b}, OP_C, L, Tm[3], bb, one, {addend(Bi, sE, one)}));
-        QTX_TRY(gl.run(OP_N, xi, OP_N, Mat{Tm[3], bb, b}, Tm[2], bb, one, {}));
+        QTX_TRY(gl.go(Z, OP_N, L, OP_N, R.get(r.Gd, 0, i, -1), ws(W.Tm[1]), one, {}));
+        QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one, {addend_of(Bi, one)}));
+        QTX_TRY(gl.go(Z, OP_N, xi, OP_N, ws(W.Tm[3]), ws(W.Tm[2]), one, {}));
       }
       // xl_i = Z x_i^H
-      QTX_TRY(gl.run(OP_N, Mat{Tm[2], bb, b}, OP_C, xi, r.Gd + (int64_t)i * bb, sE, one, {}));
+      QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[2]), OP_C, xi, R.get(r.Gd, 0, i, 0), one, {}));
     }
   }
-  // ------------------------------------------------------------ backward
-  double2* Pp = Tm[0];
-  double2* Rp = Tm[1];
-  double2* Vp = Tm[2];
-  double2* Wp = Tm[3];
-  double2* Yp = Tm[4];
-  double2* Zp = Tm[5];
-  for (int i = nb - 2; i >= 0; --i) {
-    QTX_TRY(coupling(i, U, sU, L, sL));
-    const Mat xi{GR_d + (int64_t)i * bb, sE, b};
-    const Mat Gn{GR_d + (int64_t)(i + 1) * bb, sE, b};
-    double2* GRu = GR_u + (int64_t)i * bb;
-    double2* GRl = GR_l + (int64_t)i * bb;
-    QTX_TRY(g.run(OP_N, xi, OP_N, U, Pp, bb, one, {}));                       // P' = x_i U'
-    QTX_TRY(g.run(OP_N, L, OP_N, xi, Rp, bb, one, {}));                       // R' = L' x_i
-    QTX_TRY(g.run(OP_N, Mat{Pp, bb, b}, OP_N, Gn, GRu, sEu, cmk(-sU, 0), {}));   // G_{i,i+1}
-    QTX_TRY(g.run(OP_N, Gn, OP_N, Mat{Rp, bb, b}, GRl, sEu, cmk(-sL, 0), {}));   // G_{i+1,i}
-    QTX_TRY(g.run(OP_N, Mat{GRu, sEu, b}, OP_N, Mat{Rp, bb, b}, GR_d + (int64_t)i * bb, sE, cmk(-sL, 0),
-                  {addend(GR_d + (int64_t)i * bb, sE, one)}));                 // G_ii (in place)
-    QTX_TRY(gl.run(OP_N, Mat{GRu, sEu, b}, OP_N, L, Wp, bb, one, {}));        // W' = G_{i,i+1} L' (lesser chain)
+  // ------------------------------------------------------------ backward (i = n_b - 2 - kk per entry)
+  const Mat Pp = ws(W.Tm[0]), Rp = ws(W.Tm[1]), Vp = ws(W.Tm[2]), Wp = ws(W.Tm[3]), Yp = ws(W.Tm[4]),
+            Zp = ws(W.Tm[5]);
+  for (int kk = 0; kk + 2 <= B.max_nb; ++kk) {
+    const int Z = R.active_bwd(kk);
+    if (Z == 0) break;
+    QTX_TRY(coupling(Z, 1, kk, 0));
+    const Mat xi = R.get(A_GRD, 1, kk, 0);
+    const Mat Gn = R.get(A_GRD, 1, kk, 1);
+    const Mat GRu = R.get(A_GRU, 1, kk, 0);
+    const Mat GRl = R.get(A_GRL, 1, kk, 0);
+    QTX_TRY(g.go(Z, OP_N, xi, OP_N, U, Pp, one, {}));                           // P' = x_i U'
+    QTX_TRY(g.go(Z, OP_N, L, OP_N, xi, Rp, one, {}));                           // R' = L' x_i
+    QTX_TRY(g.go(Z, OP_N, Pp, OP_N, Gn, GRu, cmk(-sU, 0), {}));                 // G_{i,i+1}
+    QTX_TRY(g.go(Z, OP_N, Gn, OP_N, Rp, GRl, cmk(-sL, 0), {}));                 // G_{i+1,i}
+    QTX_TRY(g.go(Z, OP_N, GRu, OP_N, Rp, xi, cmk(-sL, 0), {addend_of(xi, one)}));   // G_ii (in place)
+    QTX_TRY(gl.go(Z, OP_N, GRu, OP_N, L, Wp, one, {}));                         // W' = G_{i,i+1} L'
     for (const Rhs& r : rhs) {
-      const Mat xl{r.Gd + (int64_t)i * bb, sE, b};
-      const Mat Gln{r.Gd + (int64_t)(i + 1) * bb, sE, b};
-      QTX_TRY(gl.run(OP_N, Mat{Pp, bb, b}, OP_N, Gln, Vp, bb, one, {}));       // V' = P' G<_{i+1}
-      QTX_TRY(gl.run(OP_N, Mat{Wp, bb, b}, OP_N, xl, Yp, bb, one, {}));        // Y' = W' xl_i
-      QTX_TRY(gl.run(OP_N, xl, OP_C, L, Zp, bb, one, {}));                     // Z' = xl_i L'^H
+      const Mat xl = R.get(r.Gd, 1, kk, 0);
+      const Mat Gln = R.get(r.Gd, 1, kk, 1);
+      QTX_TRY(gl.go(Z, OP_N, Pp, OP_N, Gln, Vp, one, {}));                      // V' = P' G<_{i+1}
+      QTX_TRY(gl.go(Z, OP_N, Wp, OP_N, xl, Yp, one, {}));                       // Y' = W' xl_i
+      QTX_TRY(gl.go(Z, OP_N, xl, OP_C, L, Zp, one, {}));                        // Z' = xl_i L'^H
       // G<_{i,i+1} = -sU V' - sL Z' G_{i+1}^H
-      QTX_TRY(gl.run(OP_N, Mat{Zp, bb, b}, OP_C, Gn, r.Gu + (int64_t)i * bb, sEu, cmk(-sL, 0),
-                    {addend(Vp, bb, cmk(-sU, 0))}));
+      QTX_TRY(gl.go(Z, OP_N, Zp, OP_C, Gn, R.get(r.Gu, 1, kk, 0), cmk(-sL, 0), {addend_of(Vp, cmk(-sU, 0))}));
       // G<_ii = xl_i + V' P'^H - sL Y' + sL Y'^H   (in place)
-      QTX_TRY(gl.run(OP_N, Mat{Vp, bb, b}, OP_C, Mat{Pp, bb, b}, r.Gd + (int64_t)i * bb, sE, one,
-                    {addend(r.Gd + (int64_t)i * bb, sE, one), addend(Yp, bb, cmk(-sL, 0)),
-                     addend(Yp, bb, cmk(sL, 0), OP_C)}));
+      QTX_TRY(gl.go(Z, OP_N, Vp, OP_C, Pp, xl, one,
+                    {addend_of(xl, one), addend_of(Yp, cmk(-sL, 0)), addend_of(Yp, cmk(sL, 0), OP_C)}));
     }
   }
   // ------------------------------------------------------------ status
-  // Non-finite values propagate into the first blocks; check them.
-  QTX_TRY(launch_check_finite(GR_d, bb, sE, ne, st, s));
-  for (const Rhs& r : rhs) QTX_TRY(launch_check_finite(r.Gd, bb, sE, ne, st, s));
-  QTX_TRY(launch_nan_fill_failed(GR_d, sE, sE, ne, st, s));
-  if (nb > 1) {
-    QTX_TRY(launch_nan_fill_failed(GR_u, sEu, sEu, ne, st, s));
-    QTX_TRY(launch_nan_fill_failed(GR_l, sEu, sEu, ne, st, s));
+  // Non-finite values propagate into the first blocks: check those; then every
+  // output of a failed entry is NaN-filled and the status is scattered out.
+  std::vector<int> first{A_GRD};
+  for (const Rhs& r : rhs) first.push_back(r.Gd);
+  for (int a : first) {
+    const Mat m = R.get(a, 2, 0, 0);
+    if (!dry) QTX_TRY(launch_check_finite_entries(m.tab, bb, Zall, W.st, s));
   }
-  for (const Rhs& r : rhs) {
-    QTX_TRY(launch_nan_fill_failed(r.Gd, sE, sE, ne, st, s));
-    if (nb > 1) QTX_TRY(launch_nan_fill_failed(r.Gu, sEu, sEu, ne, st, s));
+  std::vector<std::pair<int, bool>> outs{{A_GRD, true}, {A_GRU, false}, {A_GRL, false}};
+  for (const Rhs& r : rhs) { outs.push_back({r.Gd, true}); outs.push_back({r.Gu, false}); }
+  for (auto& o : outs) {
+    const Mat m = R.get(o.first, 2, 0, 0);
+    if (!dry) QTX_TRY(launch_nan_fill_entries((double2* const*)m.tab, o.second ? W.cnt_d : W.cnt_u, Zall, W.st, s));
   }
-  if (p.status) QTX_TRY(hipMemcpyAsync(p.status + e0, st, ne * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  if (!dry) QTX_TRY(launch_scatter_status(W.st, W.ust, Zall, s));
   return QTX_OK;
+}
+
+// FNV-1a over bytes.
+struct Hasher {
+  uint64_t h = 1469598103934665603ull;
+  void add(const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  }
+  template <class T> void val(const T& v) { add(&v, sizeof(v)); }
+};
+
+// Plan, upload and run (or capture / replay) a full solve.
+qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs, hipStream_t s) {
+  // 1. group entries by batch key; each group becomes one or more batches (chunks)
+  std::vector<BatchKey> keys;
+  std::vector<std::vector<Entry>> groups;
+  for (int q = 0; q < n_probs; ++q) {
+    const BatchKey k = key_of(probs[q]);
+    size_t g = 0;
+    while (g < keys.size() && !(keys[g] == k)) ++g;
+    if (g == keys.size()) { keys.push_back(k); groups.emplace_back(); }
+    for (int e = 0; e < probs[q].n_e; ++e) groups[g].push_back({&probs[q], e});
+  }
+  size_t total_need = 0;
+  for (size_t g = 0; g < keys.size(); ++g) total_need += per_entry_bytes(keys[g]) * groups[g].size();
+  const size_t budget = ws_budget(ctx);
+  std::vector<Batch> batches;
+  std::vector<size_t> lane_bytes;
+  for (size_t g = 0; g < keys.size(); ++g) {
+    auto& ent = groups[g];
+    std::stable_sort(ent.begin(), ent.end(), [](const Entry& a, const Entry& b) { return a.p->n_b > b.p->n_b; });
+    const size_t per = per_entry_bytes(keys[g]);
+    const double share = total_need > budget ? (double)(per * ent.size()) / (double)total_need : 1.0;
+    size_t chunk = ent.size();
+    if (total_need > budget) chunk = std::max<size_t>(1, (size_t)(share * (double)budget) / per);
+    chunk = std::min(chunk, ent.size());
+    size_t lane_need = 0;
+    for (size_t c0 = 0; c0 < ent.size(); c0 += chunk) {
+      Batch B;
+      B.key = keys[g];
+      B.ent.assign(ent.begin() + c0, ent.begin() + std::min(ent.size(), c0 + chunk));
+      B.max_nb = B.ent.front().p->n_b;
+      B.lane = (int)g;
+      lane_need = std::max(lane_need, batch_ws_bytes(B.key, (int)B.ent.size()));
+      batches.push_back(std::move(B));
+    }
+    lane_bytes.push_back(align_up(lane_need));
+  }
+  const int n_lanes = (int)keys.size();
+  // 2. dry pass: tables and per-entry data of every batch
+  std::vector<Run> runs(batches.size());
+  size_t tab_total = 0;
+  for (size_t bi = 0; bi < batches.size(); ++bi) {
+    Run& R = runs[bi];
+    R.ctx = ctx;
+    R.B = &batches[bi];
+    R.dry = true;
+    R.bb = (int64_t)R.B->key.b * R.B->key.b;
+    const int Z = (int)R.B->ent.size();
+    const EntryData ed = entry_data_layout(Z);
+    R.host.assign(ed.end, 0);
+    for (int z = 0; z < Z; ++z) {
+      const Entry& en = R.B->ent[z];
+      const double E = en.p->energies[en.e];
+      int32_t* us = en.p->status ? en.p->status + en.e : nullptr;
+      const int64_t cd = (int64_t)en.p->n_b * R.bb, cu = (int64_t)(en.p->n_b - 1) * R.bb;
+      std::memcpy(R.host.data() + ed.en + z * sizeof(double), &E, sizeof(double));
+      std::memcpy(R.host.data() + ed.ust + z * sizeof(void*), &us, sizeof(void*));
+      std::memcpy(R.host.data() + ed.cnt_d + z * sizeof(int64_t), &cd, sizeof(int64_t));
+      std::memcpy(R.host.data() + ed.cnt_u + z * sizeof(int64_t), &cu, sizeof(int64_t));
+    }
+    BatchWs W;
+    qtx_status st = run_batch(R, W);
+    if (st != QTX_OK) return st;
+    batches[bi].tab_off = tab_total;
+    tab_total += align_up(R.host.size());
+  }
+  // 3. workspace: lane regions, then the table block
+  size_t ws_total = 0;
+  std::vector<size_t> lane_off(n_lanes);
+  for (int l = 0; l < n_lanes; ++l) { lane_off[l] = ws_total; ws_total += lane_bytes[l]; }
+  const size_t tab_start = ws_total;
+  ws_total += tab_total + 4096;
+  QTX_TRYS(ensure_ws(ctx, ws_total));
+  QTX_TRYS(ensure_pinned(ctx, tab_total + 256));
+  char* pin = (char*)ctx->pinned;
+  for (size_t bi = 0; bi < batches.size(); ++bi)
+    std::memcpy(pin + batches[bi].tab_off, runs[bi].host.data(), runs[bi].host.size());
+  char* dev_tab = (char*)ctx->ws + tab_start;
+  QTX_TRY(hipMemcpyAsync(dev_tab, pin, tab_total, hipMemcpyHostToDevice, s));
+  if (!ctx->upload_done) QTX_TRY(hipEventCreateWithFlags(&ctx->upload_done, hipEventDisableTiming));
+  QTX_TRY(hipEventRecord(ctx->upload_done, s));
+
+  // 4. launch (optionally captured into a cached graph)
+  uint64_t sig = 0;
+  bool replay = false;
+  bool capture = ctx->use_graph && s != nullptr;
+  if (capture) {
+    Hasher h;
+    h.val(n_probs);
+    for (int q = 0; q < n_probs; ++q) {
+      h.val(probs[q]);
+      h.add(probs[q].energies, sizeof(double) * probs[q].n_e);
+    }
+    h.val(ctx->ws);
+    h.val(ctx->ws_size);
+    sig = h.h;
+    for (auto& gce : ctx->graphs)
+      if (gce.sig == sig) {
+        QTX_TRY(hipGraphLaunch(gce.exec, s));
+        ++ctx->graph_launches;
+        replay = true;
+      }
+  }
+  if (replay) return QTX_OK;
+  if (n_lanes > 1) QTX_TRYS(ensure_aux(ctx, n_lanes));
+  if (capture) {
+    QTX_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    ctx->capturing = true;
+  }
+  qtx_status result = QTX_OK;
+  for (int l = 0; l < n_lanes && result == QTX_OK; ++l) {
+    hipStream_t ls = s;
+    if (n_lanes > 1) {
+      ls = ctx->aux[l];
+      if (hipEventRecord(ctx->fork_ev[l], s) != hipSuccess || hipStreamWaitEvent(ls, ctx->fork_ev[l], 0) != hipSuccess) {
+        result = hip_fail(ctx, hipErrorUnknown);
+        break;
+      }
+    }
+    for (size_t bi = 0; bi < batches.size() && result == QTX_OK; ++bi) {
+      if (batches[bi].lane != l) continue;
+      Run& R = runs[bi];
+      R.dry = false;
+      R.s = ls;
+      R.dev = dev_tab + batches[bi].tab_off;
+      const int Z = (int)R.B->ent.size();
+      BatchWs W = carve_batch((char*)ctx->ws + lane_off[l], R.B->key, Z);
+      const EntryData ed = entry_data_layout(Z);
+      W.en = (const double*)(R.dev + ed.en);
+      W.ust = (int32_t* const*)(R.dev + ed.ust);
+      W.cnt_d = (const int64_t*)(R.dev + ed.cnt_d);
+      W.cnt_u = (const int64_t*)(R.dev + ed.cnt_u);
+      result = run_batch(R, W);
+    }
+    if (n_lanes > 1 && result == QTX_OK) {
+      if (hipEventRecord(ctx->join_ev[l], ls) != hipSuccess || hipStreamWaitEvent(s, ctx->join_ev[l], 0) != hipSuccess)
+        result = hip_fail(ctx, hipErrorUnknown);
+    }
+  }
+  if (capture) {
+    ctx->capturing = false;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (result != QTX_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return result;
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(ctx, e);
+    if (ctx->graphs.size() >= 8) {
+      (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+      ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back({sig, exec});
+    ++ctx->graph_captures;
+    QTX_TRY(hipGraphLaunch(exec, s));
+    ++ctx->graph_launches;
+  }
+  return result;
 }
 
 }  // namespace
@@ -521,6 +927,27 @@ qtx_status qtx_rgf_create(qtx_rgf_ctx* out, int device, size_t workspace_bytes, 
   if (tune_cache_path) ctx->tune_path = tune_cache_path;
   *out = ctx;
   return QTX_OK;
+}
+
+qtx_status qtx_rgf_set_option(qtx_rgf_ctx ctx, int option, int64_t value) {
+  if (!ctx) return QTX_ERR_ARG;
+  switch (option) {
+    case QTX_OPT_GRAPH:
+      ctx->use_graph = value != 0;
+      return QTX_OK;
+    default:
+      return QTX_ERR_ARG;
+  }
+}
+
+qtx_status qtx_rgf_get_stat(qtx_rgf_ctx ctx, int stat, int64_t* value) {
+  if (!ctx || !value) return QTX_ERR_ARG;
+  switch (stat) {
+    case QTX_STAT_GRAPH_LAUNCHES: *value = ctx->graph_launches; return QTX_OK;
+    case QTX_STAT_GRAPH_CAPTURES: *value = ctx->graph_captures; return QTX_OK;
+    case QTX_STAT_WORKSPACE_BYTES: *value = (int64_t)ctx->ws_size; return QTX_OK;
+    default: return QTX_ERR_ARG;
+  }
 }
 
 qtx_status qtx_rgf_profile(qtx_rgf_ctx ctx, int enable) {
@@ -557,23 +984,26 @@ qtx_status qtx_rgf_destroy(qtx_rgf_ctx ctx) {
   {
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
+    drop_graphs(ctx);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->upload_done) (void)hipEventDestroy(ctx->upload_done);
     for (auto& f : ctx->prof)
       for (auto& r : f.pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+    for (size_t i = 0; i < ctx->aux.size(); ++i) {
+      (void)hipStreamDestroy(ctx->aux[i]);
+      (void)hipEventDestroy(ctx->fork_ev[i]);
+      (void)hipEventDestroy(ctx->join_ev[i]);
+    }
   }
   delete ctx;
   return QTX_OK;
 }
 
 size_t qtx_rgf_footprint(const qtx_rgf_problem* p) {
-  if (!valid_problem(p)) return 0;
-  Scheme sc, scl;
-  if (!make_scheme(p->prec, p->n_slices, &sc)) return 0;
-  if (p->prec_lesser >= 0 && make_scheme(p->prec_lesser, p->n_slices_lesser, &scl) &&
-      scl.split() && (!sc.split() || scl.ns > sc.ns))
-    sc = scl;
-  return per_energy_bytes(p->b, sc);
+  if (!valid_problem(p) || check_supported(p) != QTX_OK) return 0;
+  return per_entry_bytes(key_of(*p));
 }
 
 qtx_status qtx_rgf_solve(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int32_t n_probs, void* hip_stream) {
@@ -585,40 +1015,7 @@ qtx_status qtx_rgf_solve(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int32_t 
     if (st != QTX_OK) return st;
   }
   DeviceGuard guard(ctx->device);
-  hipStream_t s = (hipStream_t)hip_stream;
-  // plan: energies per chunk from the workspace budget
-  const size_t budget = ws_budget(ctx);
-  size_t need = 0;
-  std::vector<int> chunk(n_probs);
-  int max_ne = 0;
-  for (int k = 0; k < n_probs; ++k) {
-    const qtx_rgf_problem& p = probs[k];
-    Scheme sc, scl;
-    make_scheme(p.prec, p.n_slices, &sc);
-    if (p.prec_lesser >= 0) make_scheme(p.prec_lesser, p.n_slices_lesser, &scl);
-    if (scl.split() && (!sc.split() || scl.ns > sc.ns)) sc = scl;
-    const size_t per = per_energy_bytes(p.b, sc);
-    size_t c = budget > per ? budget / per : 1;
-    if (c > (size_t)p.n_e) c = p.n_e;
-    if (c < 1) c = 1;
-    chunk[k] = (int)c;
-    need = std::max(need, per * c + 4096);
-    max_ne = std::max(max_ne, p.n_e);
-  }
-  const size_t en_bytes = align_up((size_t)max_ne * sizeof(double));
-  qtx_status st = ensure_ws(ctx, need + en_bytes);
-  if (st != QTX_OK) return st;
-  double* d_en = (double*)((char*)ctx->ws + ctx->ws_size - en_bytes);
-  for (int k = 0; k < n_probs; ++k) {
-    const qtx_rgf_problem& p = probs[k];
-    QTX_TRY(hipMemcpyAsync(d_en, p.energies, p.n_e * sizeof(double), hipMemcpyHostToDevice, s));
-    for (int e0 = 0; e0 < p.n_e; e0 += chunk[k]) {
-      const int ne = std::min(chunk[k], p.n_e - e0);
-      st = solve_chunk(ctx, p, e0, ne, s, d_en);
-      if (st != QTX_OK) return st;
-    }
-  }
-  return QTX_OK;
+  return solve_all(ctx, probs, n_probs, (hipStream_t)hip_stream);
 }
 
 qtx_status qtx_zgemm(qtx_rgf_ctx ctx, char opA, char opB, int32_t M, int32_t N, int32_t K, double alpha_re,

@@ -30,6 +30,7 @@ enum Op { OP_N = 0, OP_C = 1 };
 
 // An epilogue addend: out += coef * (scale_by_batch ? bscal[z] : 1) * op(X_z)
 struct Addend {
+  const double2* const* tX = nullptr;   // per-batch-entry pointers (overrides X + z*stride)
   const double2* X = nullptr;
   int64_t ld = 0, stride = 0;
   double2 coef = {0.0, 0.0};
@@ -43,6 +44,11 @@ constexpr int kMaxAddends = 3;
 //   C_z = alpha * op(A_z) op(B_z) + sum_t addend_t + diag * (diag_by_batch ? bscal[z] : 1) * I
 // op(A) is M x K, op(B) is K x N, C is M x N, row-major; batch strides in elements.
 struct GemmDesc {
+  // Optional per-batch-entry operand pointers (device arrays indexed by z); when
+  // set they replace base + z * stride.
+  const double2* const* tA = nullptr;
+  const double2* const* tB = nullptr;
+  double2* const* tC = nullptr;
   int M = 0, N = 0, K = 0;
   int opA = OP_N, opB = OP_N;
   const double2* A = nullptr; int64_t lda = 0, sA = 0;
@@ -69,6 +75,7 @@ hipError_t launch_zgemm_f32(const GemmDesc& d, hipStream_t s);
 // S = op(X) viewed as rows x cols (cols = the contraction dimension K):
 // S[r][k] = X[r][k] (trans = 0) or X[k][r] (trans = 1), conjugated if conj = 1.
 struct SplitDesc {
+  const double2* const* tX = nullptr;   // per-batch-entry source pointers (optional)
   const double2* X = nullptr; int64_t ld = 0, stride = 0;
   int rows = 0, cols = 0;
   int trans = 0, conj = 0;
@@ -102,7 +109,8 @@ int gje_panel_width(int n);
 size_t gje_work_bytes(int n, int batch);
 GjeWork gje_carve(void* base, int n, int batch);
 hipError_t launch_gje_invert(int n, double2* X, int64_t sX, double2* Out, int64_t sOut, int batch,
-                             const GjeWork& w, int32_t* status, hipStream_t s);
+                             const GjeWork& w, int32_t* status, hipStream_t s,
+                             double2* const* tOut = nullptr);
 
 // Status / NaN fill / observables helpers.
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
@@ -110,6 +118,12 @@ hipError_t launch_nan_fill_failed(double2* X, int64_t per_batch, int64_t stride,
                                   const int32_t* status, hipStream_t s);
 hipError_t launch_check_finite(const double2* X, int64_t per_batch, int64_t stride, int batch,
                                int32_t* status, hipStream_t s);
+// Per-entry variants (pointer tables): entry z covers counts[z] elements at t[z].
+hipError_t launch_check_finite_entries(const double2* const* t, int64_t count, int batch, int32_t* status,
+                                       hipStream_t s);
+hipError_t launch_nan_fill_entries(double2* const* t, const int64_t* counts, int batch, const int32_t* status,
+                                   hipStream_t s);
+hipError_t launch_scatter_status(const int32_t* st, int32_t* const* dst, int batch, hipStream_t s);
 hipError_t launch_observables(int b, int n_e, const double2* G, const double2* GL, int64_t sG,
                               const double2* M1, const double2* M2, const double2* gam,
                               const double* fL, double* T, double* j, hipStream_t s);

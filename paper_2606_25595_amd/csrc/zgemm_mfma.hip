@@ -115,8 +115,8 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
   const int m0 = (t % tiles_m) * BM;
   const int n0 = (t / tiles_m) * BN;
 
-  const double2* __restrict__ A = d.A + (int64_t)z * d.sA;
-  const double2* __restrict__ B = d.B + (int64_t)z * d.sB;
+  const double2* __restrict__ A = d.tA ? d.tA[z] : d.A + (int64_t)z * d.sA;
+  const double2* __restrict__ B = d.tB ? d.tB[z] : d.B + (int64_t)z * d.sB;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
   }
 
   // Epilogue (FP64): accumulator element v of lane l sits at MATH::row(l/16, v), column l%16.
-  double2* __restrict__ C = d.C + (int64_t)z * d.sC;
+  double2* __restrict__ C = d.tC ? d.tC[z] : d.C + (int64_t)z * d.sC;
   const double bs = d.bscal ? d.bscal[z] : 1.0;
   double2 coef[kMaxAddends];
   const double2* X[kMaxAddends];
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
   for (int q = 0; q < kMaxAddends; ++q) {
     coef[q] = d.add[q].coef;
     if (d.add[q].scale_by_batch) coef[q] = cmk(coef[q].x * bs, coef[q].y * bs);
-    X[q] = d.add[q].X ? d.add[q].X + (int64_t)z * d.add[q].stride : nullptr;
+    X[q] = d.add[q].tX ? d.add[q].tX[z] : (d.add[q].X ? d.add[q].X + (int64_t)z * d.add[q].stride : nullptr);
   }
   const double2 dg = d.diag_by_batch ? cmk(d.diag.x * bs, d.diag.y * bs) : d.diag;
 #pragma unroll

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(NT) void split_kernel(SplitDesc sd) {
   const int r0 = blockIdx.x * 64;
   const int k0 = kt * KS;
   const int tid = threadIdx.x;
-  const double2* X = sd.X + (int64_t)z * sd.stride;
+  const double2* X = sd.tX ? sd.tX[z] : sd.X + (int64_t)z * sd.stride;
   // coalesced load of the 64 x 32 strip of S
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(SplitGemmDesc g) {
   }
 
   // epilogue in FP64 (same addend semantics as the FP64 kernels)
-  double2* __restrict__ C = d.C + (int64_t)z * d.sC;
+  double2* __restrict__ C = d.tC ? d.tC[z] : d.C + (int64_t)z * d.sC;
   const double bs = d.bscal ? d.bscal[z] : 1.0;
   double2 coef[kMaxAddends];
   const double2* X[kMaxAddends];
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(SplitGemmDesc g) {
   for (int q = 0; q < kMaxAddends; ++q) {
     coef[q] = d.add[q].coef;
     if (d.add[q].scale_by_batch) coef[q] = cmk(coef[q].x * bs, coef[q].y * bs);
-    X[q] = d.add[q].X ? d.add[q].X + (int64_t)z * d.add[q].stride : nullptr;
+    X[q] = d.add[q].tX ? d.add[q].tX[z] : (d.add[q].X ? d.add[q].X + (int64_t)z * d.add[q].stride : nullptr);
   }
   const double2 dg = d.diag_by_batch ? cmk(d.diag.x * bs, d.diag.y * bs) : d.diag;
 #pragma unroll

@@ -191,6 +191,7 @@ __global__ void gje_reset_kernel(int n, int batch, int32_t* used) {
 // Out[r][c] = X[pivot(r)][pivot^-1(c)]; NaN for singular matrices.
 __global__ __launch_bounds__(256) void gje_unscramble_kernel(int n, const double2* X, int64_t sX,
                                                              double2* Out, int64_t sOut,
+                                                             double2* const* tOut,
                                                              const int32_t* prow_all,
                                                              const int32_t* status) {
   extern __shared__ int perm[];   // [2n]: pivot, inverse pivot
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(256) void gje_unscramble_kernel(int n, const double
   const bool bad = status && status[z] == 5;
   const double nan = __builtin_nan("");
   const double2* Xz = X + (int64_t)z * sX;
-  double2* Oz = Out + (int64_t)z * sOut;
+  double2* Oz = tOut ? tOut[z] : Out + (int64_t)z * sOut;
   const int64_t nn = (int64_t)n * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x) {
     const int r = (int)(e / n), c = (int)(e - (int64_t)r * n);
@@ -245,7 +246,7 @@ GjeWork gje_carve(void* base, int n, int batch) {
 }
 
 hipError_t launch_gje_invert(int n, double2* X, int64_t sX, double2* Out, int64_t sOut, int batch,
-                             const GjeWork& w, int32_t* status, hipStream_t s) {
+                             const GjeWork& w, int32_t* status, hipStream_t s, double2* const* tOut) {
   if (n <= 0 || batch <= 0) return hipSuccess;
   if (n > 1024) return hipErrorInvalidValue;
   const int nb = gje_panel_width(n);
@@ -277,7 +278,7 @@ hipError_t launch_gje_invert(int n, double2* X, int64_t sX, double2* Out, int64_
   unsigned gx = (unsigned)((nn + 256 * 4 - 1) / (256 * 4));
   if (gx < 1) gx = 1;
   hipLaunchKernelGGL(gje_unscramble_kernel, dim3(gx, batch), dim3(256), 2 * n * sizeof(int), s, n, X, sX, Out, sOut,
-                     w.prow, status);
+                     tOut, w.prow, status);
   return hipGetLastError();
 }
 

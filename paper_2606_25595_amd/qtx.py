@@ -32,7 +32,10 @@ QTX_WANT_GREATER = 8
 PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16": QTX_FP16_SPLIT}
 
 EXPORTED = ("qtx_rgf_create", "qtx_rgf_solve", "qtx_rgf_destroy", "qtx_rgf_footprint", "qtx_status_str",
-            "qtx_zgemm", "qtx_zinv", "qtx_rgf_observables", "qtx_rgf_profile", "qtx_rgf_profile_read")
+            "qtx_zgemm", "qtx_zinv", "qtx_rgf_observables", "qtx_rgf_profile", "qtx_rgf_profile_read",
+            "qtx_rgf_set_option", "qtx_rgf_get_stat")
+QTX_OPT_GRAPH = 1
+QTX_STAT_GRAPH_LAUNCHES, QTX_STAT_GRAPH_CAPTURES, QTX_STAT_WORKSPACE_BYTES = 1, 2, 3
 QTX_KERNEL_GEMM, QTX_KERNEL_INV = 0, 1
 
 
@@ -95,6 +98,10 @@ def load_library(path: str = LIB_PATH):
     lib.qtx_rgf_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(i64),
                                          ctypes.POINTER(dbl)]
     lib.qtx_rgf_profile_read.restype = ctypes.c_int
+    lib.qtx_rgf_set_option.argtypes = [vp, ctypes.c_int, i64]
+    lib.qtx_rgf_set_option.restype = ctypes.c_int
+    lib.qtx_rgf_get_stat.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64)]
+    lib.qtx_rgf_get_stat.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -315,6 +322,19 @@ class Context:
         if rc != QTX_OK:
             raise QtxError(rc, "qtx_rgf_profile_read")
         return ms.value, n.value, fl.value
+
+    # -- qtx_rgf_set_option / qtx_rgf_get_stat
+    def set_graph(self, enable: bool = True):
+        rc = self.lib.qtx_rgf_set_option(self.handle, QTX_OPT_GRAPH, 1 if enable else 0)
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_rgf_set_option")
+
+    def stat(self, which: int) -> int:
+        v = ctypes.c_int64()
+        rc = self.lib.qtx_rgf_get_stat(self.handle, int(which), ctypes.byref(v))
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_rgf_get_stat")
+        return v.value
 
     # -- qtx_rgf_observables
     def observables(self, dp: DeviceProblem, gamma_L, f_L, stream=None):

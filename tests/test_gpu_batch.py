@@ -1,0 +1,102 @@
+"""Batched solves of many problems with uneven block size and block count
+(one qtx_rgf_solve call, optionally captured into a hipGraph)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_25595_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_25595_amd import qtx
+    c = qtx.Context(0)
+    yield c
+    c.close()
+
+
+KEYS = ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")
+
+
+def mixed_problems(seed=0, count=9):
+    """Problems with b in {24, 40, 64}, n_b in {2, 3, 5}, one or two energies each."""
+    rng = np.random.default_rng(seed)
+    probs = []
+    for q in range(count):
+        b = int(rng.choice([24, 40, 64]))
+        n_b = int(rng.choice([2, 3, 5]))
+        n_e = int(rng.integers(1, 3))
+        E = rng.uniform(-2.0, 2.0, n_e)
+        probs.append(inputs.random_bt_problem(n_b, b, E, seed=1000 + q))
+    return probs
+
+
+def test_batch_matches_oracle_and_alone(ctx):
+    import torch
+    from paper_2606_25595_amd import qtx
+    probs = mixed_problems()
+    dps = [qtx.to_device(p) for p in probs]
+    ctx.solve(dps)
+    torch.cuda.synchronize()
+    for p, dp in zip(probs, dps):
+        out = dp.outputs()
+        assert np.all(out["status"] == 0)
+        ref = oracle.rgf_selected(p)
+        for k in KEYS:
+            assert oracle.rel_fro_err(out[k], ref[k]).max() <= 1e-10, k
+        # the same problem alone gives bit-identical blocks
+        alone = qtx.to_device(p)
+        ctx.solve(alone)
+        a = alone.outputs()
+        for k in KEYS:
+            assert np.array_equal(a[k], out[k]), k
+
+
+def test_batch_graph_replay_equals_eager(ctx):
+    import torch
+    from paper_2606_25595_amd import qtx
+    probs = mixed_problems(seed=3, count=7)
+    dps = [qtx.to_device(p) for p in probs]
+    ctx.solve(dps)
+    torch.cuda.synchronize()
+    eager = [dp.outputs() for dp in dps]
+    stream = torch.cuda.Stream()
+    ctx.set_graph(True)
+    try:
+        cap0 = ctx.stat(qtx.QTX_STAT_GRAPH_CAPTURES)
+        for rep in range(3):
+            for dp in dps:
+                for k in KEYS:
+                    getattr(dp, k).fill_(float("nan"))
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                ctx.solve(dps, stream=stream)
+            stream.synchronize()
+            for dp, ref in zip(dps, eager):
+                out = dp.outputs()
+                for k in KEYS:
+                    assert np.array_equal(out[k], ref[k]), (rep, k)
+        assert ctx.stat(qtx.QTX_STAT_GRAPH_CAPTURES) == cap0 + 1      # captured once, replayed after
+    finally:
+        ctx.set_graph(False)
+
+
+def test_batch_mixed_precision_per_problem(ctx):
+    """Problems with different schemes in one call form separate batches."""
+    import torch
+    from paper_2606_25595_amd import qtx
+    probs = mixed_problems(seed=5, count=4)
+    dps = [qtx.to_device(p) for p in probs]
+    ctx.solve(dps, prec=["fp64", "bf16", "fp64", "bf16"], n_slices=5)
+    torch.cuda.synchronize()
+    for q, (p, dp) in enumerate(zip(probs, dps)):
+        out = dp.outputs()
+        ref = oracle.rgf_selected(p)
+        tol = 1e-10 if q % 2 == 0 else 1e-7
+        for k in KEYS:
+            assert oracle.rel_fro_err(out[k], ref[k]).max() <= tol, (q, k)
