@@ -74,15 +74,28 @@ def main():
                     help="comma list of schemes: fp64 | fp32 | bf16:NS | fp16:NS | <retarded>/<lesser>")
     ap.add_argument("--cpu-energies", type=int, default=8, help="energies in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="realistic", choices=["realistic", "batch", "serve"],
+                    help="realistic (default, the headline line) | batch (512 uneven problems, one graph "
+                         "launch) | serve (Poisson arrivals, continuous batching, p50/p99)")
+    ap.add_argument("--problems", type=int, default=512, help="batch workload: number of problems")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve workload: arrivals per second")
+    ap.add_argument("--duration", type=float, default=10.0, help="serve workload: arrival window (s)")
+    ap.add_argument("--time-limit", type=float, default=60.0, help="serve workload: wall-clock cap (s)")
+    ap.add_argument("--prec", default="fp64", help="batch workload scheme (fp64 | bf16:5 | ...)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build's hot path runs on a single MI355X; "
-              "energies shard across GPUs with no exchange (see the design notes).", file=sys.stderr)
+        print("bench.py runs on one GPU only: energies shard across GPUs with no exchange inside a solve, "
+              "so the per-GPU rate is the single-GPU figure; multi-GPU runs are not supported.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
     from paper_2606_25595_amd import inputs, qtx
+
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     cfg = inputs.CONFIGS["realistic"]
     n_b, b, n_e = cfg["n_b"], cfg["b"], cfg["n_e"]
@@ -211,6 +224,107 @@ def main():
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def bench_batch(args):
+    """Batching workload: independent problems with b in {128, 256, 384, 512} and
+    n_b in {16, 24, 32}, one energy each (E uniform in [-2, 2]), random devices
+    generated on the GPU from per-problem seeds, all solved by one qtx_rgf_solve
+    captured into a hipGraph and replayed."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2606_25595_amd import inputs, qtx
+    from paper_2606_25595_amd.serve import GpuExecutor, Request
+    rng = np.random.default_rng(0)
+    n = args.problems
+    spec = [(int(rng.choice([128, 256, 384, 512])), int(rng.choice([16, 24, 32])), float(rng.uniform(-2, 2)))
+            for _ in range(n)]
+    need = sum((8 * nb - 5) * b * b * 16 for b, nb, _ in spec)
+    log("bench batch: %d problems, %.1f GB of inputs and outputs" % (n, need / 1e9))
+    ex = GpuExecutor(n_slots=1)              # only its device generator is used here
+    kw = dict(dtype=torch.complex128, device="cuda")
+    dps, reqs = [], []
+    for q, (b, nb, E) in enumerate(spec):
+        r = Request(rid=q, b=b, n_b=nb, n_e=1, seed=5000 + q)
+        ex.start_request(r)
+        H_d, H_u, H_l = ex.H.pop(q)
+        sr, sl = inputs.random_bt_scalars(nb, [E])
+        dps.append(qtx.DeviceProblem(
+            energies=np.array([E]), H_d=H_d, H_u=H_u, H_l=H_l, SR_d=inputs.diag_blocks_device(sr, b),
+            SL_d=inputs.diag_blocks_device(sl, b), GR_d=torch.empty((1, nb, b, b), **kw),
+            GR_u=torch.empty((1, nb - 1, b, b), **kw), GR_l=torch.empty((1, nb - 1, b, b), **kw),
+            GL_d=torch.empty((1, nb, b, b), **kw), GL_u=torch.empty((1, nb - 1, b, b), **kw),
+            status=torch.full((1,), -1, dtype=torch.int32, device="cuda")))
+    ex.close()
+    torch.cuda.synchronize()
+    name, _, ns = args.prec.partition(":")
+    ctx = qtx.Context(0)
+    ctx.set_graph(True)
+    stream = torch.cuda.Stream()
+    flops = sum((144 * (nb - 1) + 24) * b ** 3 for b, nb, _ in spec)
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        ctx.solve(dps, prec=name, n_slices=int(ns or 0), stream=stream)     # capture + first run
+        stream.synchronize()
+        t_first = time.perf_counter() - t0
+        for _ in range(args.warmup):
+            ctx.solve(dps, prec=name, n_slices=int(ns or 0), stream=stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.solve(dps, prec=name, n_slices=int(ns or 0), stream=stream)
+        stream.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+    ok = all(int(dp.status.item()) == 0 for dp in dps)
+    sample = list(range(0, n, max(1, n // 8)))[:8]
+    errs = {k: 0.0 for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")}
+    for q in sample:
+        dp = dps[q]
+        b, nb, E = spec[q]
+        sr, sl = inputs.random_bt_scalars(nb, [E])
+        p = inputs.BTProblem(energies=np.array([E]), H_d=dp.H_d.cpu().numpy(), H_u=dp.H_u.cpu().numpy(),
+                             H_l=dp.H_l.cpu().numpy(), SR_d=inputs._diag_blocks(sr, b), SL_d=inputs._diag_blocks(sl, b))
+        ref = oracle.rgf_selected(p)
+        out = dp.outputs()
+        for k in errs:
+            errs[k] = max(errs[k], float(oracle.rel_fro_err(out[k], ref[k]).max()))
+    line = {"metric": "batched RGF energy points/sec (uneven problems, one hipGraph launch)",
+            "value": n / t, "unit": "energy points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": t * 1e3, "higher_is_better": True, "dtype": "f64" if name == "fp64" else "f64+" + args.prec,
+            "data": "synthetic",
+            "config": {"workload": "batch: %d problems, b in {128,256,384,512}, n_b in {16,24,32}, 1 energy each" % n,
+                       "precision": args.prec},
+            "fp64eq_tflops": flops / t / 1e12, "first_call_ms": t_first * 1e3, "status_ok": ok,
+            "graph_captures": ctx.stat(qtx.QTX_STAT_GRAPH_CAPTURES),
+            "graph_launches": ctx.stat(qtx.QTX_STAT_GRAPH_LAUNCHES),
+            "sampled_max_rel_err": errs, "sampled_problems": len(sample)}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def bench_serve(args):
+    """Serving workload: Poisson arrivals (b in 128..512 step 32, n_b in 8..48,
+    N_E in 16..128, FP64 or mixed with probability 1/2, seed 1000 + id), continuous
+    batching by HBM footprint, p50/p99 latency of completed requests."""
+    import torch
+    from paper_2606_25595_amd.serve import GpuExecutor, Server, request_stream
+    free, total = torch.cuda.mem_get_info()
+    budget = int(free * 0.55)
+    reqs = request_stream(rate=args.rate, duration=args.duration, seed=0)
+    log("bench serve: %d requests over %.1f s at %.1f/s, budget %.1f GB" % (len(reqs), args.duration, args.rate,
+                                                                           budget / 1e9))
+    ex = GpuExecutor(n_slots=3, workspace_per_slot=int(free * 0.08))
+    srv = Server(ex, hbm_budget=budget, chunk_energies=16, max_pending=512)
+    rep = srv.run(reqs, time_limit=args.time_limit)
+    ex.close()
+    line = {"metric": "served RGF energy points/sec with p50/p99 request latency",
+            "value": rep["energy_points_per_s"], "unit": "energy points/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f64 / f64+bf16:5", "data": "synthetic",
+            "config": {"workload": "serve: Poisson %.1f/s for %.1f s, b 128..512, n_b 8..48, N_E 16..128"
+                                   % (args.rate, args.duration)},
+            "p50_latency_s": rep["p50_latency_s"], "p99_latency_s": rep["p99_latency_s"], "report": rep}
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -151,8 +151,11 @@ qtx_status qtx_rgf_solve(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int32_t 
  *                  and replays it with one graph launch on later identical calls
  *                  (same problem structs, energies and workspace).  Needs a
  *                  non-NULL stream; with the NULL stream the solve runs eagerly.
- * Counters (qtx_rgf_get_stat): graph launches, graph captures, workspace bytes. */
-enum { QTX_OPT_GRAPH = 1 };
+ * Counters (qtx_rgf_get_stat): graph launches, graph captures, workspace bytes.
+ *   QTX_OPT_RESERVE_WORKSPACE  value = bytes: allocate the device workspace now
+ *                  (grows only; for callers that must claim memory before other
+ *                  allocators do).  Returns QTX_ERR_NOMEM if it cannot. */
+enum { QTX_OPT_GRAPH = 1, QTX_OPT_RESERVE_WORKSPACE = 2 };
 enum { QTX_STAT_GRAPH_LAUNCHES = 1, QTX_STAT_GRAPH_CAPTURES = 2, QTX_STAT_WORKSPACE_BYTES = 3 };
 qtx_status qtx_rgf_set_option(qtx_rgf_ctx ctx, int option, int64_t value);
 qtx_status qtx_rgf_get_stat(qtx_rgf_ctx ctx, int stat, int64_t* value);

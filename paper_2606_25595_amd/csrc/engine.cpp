@@ -935,6 +935,11 @@ qtx_status qtx_rgf_set_option(qtx_rgf_ctx ctx, int option, int64_t value) {
     case QTX_OPT_GRAPH:
       ctx->use_graph = value != 0;
       return QTX_OK;
+    case QTX_OPT_RESERVE_WORKSPACE: {
+      if (value < 0) return QTX_ERR_ARG;
+      DeviceGuard guard(ctx->device);
+      return ensure_ws(ctx, (size_t)value);
+    }
     default:
       return QTX_ERR_ARG;
   }

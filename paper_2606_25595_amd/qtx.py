@@ -34,7 +34,7 @@ PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16"
 EXPORTED = ("qtx_rgf_create", "qtx_rgf_solve", "qtx_rgf_destroy", "qtx_rgf_footprint", "qtx_status_str",
             "qtx_zgemm", "qtx_zinv", "qtx_rgf_observables", "qtx_rgf_profile", "qtx_rgf_profile_read",
             "qtx_rgf_set_option", "qtx_rgf_get_stat")
-QTX_OPT_GRAPH = 1
+QTX_OPT_GRAPH, QTX_OPT_RESERVE_WORKSPACE = 1, 2
 QTX_STAT_GRAPH_LAUNCHES, QTX_STAT_GRAPH_CAPTURES, QTX_STAT_WORKSPACE_BYTES = 1, 2, 3
 QTX_KERNEL_GEMM, QTX_KERNEL_INV = 0, 1
 
@@ -328,6 +328,11 @@ class Context:
         rc = self.lib.qtx_rgf_set_option(self.handle, QTX_OPT_GRAPH, 1 if enable else 0)
         if rc != QTX_OK:
             raise QtxError(rc, "qtx_rgf_set_option")
+
+    def reserve_workspace(self, nbytes: int):
+        rc = self.lib.qtx_rgf_set_option(self.handle, QTX_OPT_RESERVE_WORKSPACE, int(nbytes))
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_rgf_set_option(reserve)")
 
     def stat(self, which: int) -> int:
         v = ctypes.c_int64()
