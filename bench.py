@@ -32,7 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "RGF energy points/sec: mixed-prec vs FP64 at rel err ≤1e-6; p50/p99 latency"
-PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}   # dense TFLOP/s, MI355X
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "int8": 5000.0}   # dense TFLOP/s (TOP/s), MI355X
 TOL_MIXED = 1e-6
 PMC_FILE = os.path.join(ROOT, "profiles", "zgemm_f64_product_realistic_pmc.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2606_25595_amd", "csrc", "zgemm_mfma.hip")
@@ -70,8 +70,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precs", default="fp64,fp32,bf16:5,bf16:4/bf16:5",
-                    help="comma list of schemes: fp64 | fp32 | bf16:NS | fp16:NS | <retarded>/<lesser>")
+    ap.add_argument("--precs", default="fp64,fp32,bf16:5,int8:11,int8:10/int8:11",
+                    help="comma list of schemes: fp64 | fp32 | bf16:NS | fp16:NS | int8:P (P moduli) | "
+                         "<retarded>/<lesser>")
     ap.add_argument("--cpu-energies", type=int, default=8, help="energies in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="realistic", choices=["realistic", "batch", "serve"],
@@ -151,8 +152,8 @@ def main():
             ctx.solve(dp, **skw)
         torch.cuda.synchronize()
         ctx.profile(True)
-        ctx.profile_read(qtx.QTX_KERNEL_GEMM)
-        ctx.profile_read(qtx.QTX_KERNEL_INV)
+        for fam in (qtx.QTX_KERNEL_GEMM, qtx.QTX_KERNEL_INV, qtx.QTX_KERNEL_CONVERT):
+            ctx.profile_read(fam)
         log("bench: %s timed x%d" % (prec, args.steps))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -163,6 +164,7 @@ def main():
         ctx.profile(False)
         g_ms, g_n, g_fl = ctx.profile_read(qtx.QTX_KERNEL_GEMM)
         i_ms, i_n, i_fl = ctx.profile_read(qtx.QTX_KERNEL_INV)
+        c_ms, c_n, c_by = ctx.profile_read(qtx.QTX_KERNEL_CONVERT)
         ms_step = (t1 - t0) * 1e3 / args.steps
         st = dp.status.cpu().numpy()
         errs = None
@@ -173,9 +175,10 @@ def main():
                 got = getattr(dp, key)[sample].cpu().numpy()
                 errs[key] = float(oracle.rel_fro_err(got, ref[key]).max())
         results[prec] = dict(ms_per_step=ms_step, value=n_e / (ms_step / 1e3), status_ok=bool(np.all(st == 0)),
-                             gemm=(g_ms, g_n, g_fl), inv=(i_ms, i_n, i_fl), errs=errs)
-        log("bench: %s %.1f ms/step, %.1f energies/s, gemm avg %.3f ms x%d, inv avg %.3f ms x%d, err %s" % (
-            prec, ms_step, n_e / (ms_step / 1e3), g_ms / max(g_n, 1), g_n, i_ms / max(i_n, 1), i_n, errs))
+                             gemm=(g_ms, g_n, g_fl), inv=(i_ms, i_n, i_fl), conv=(c_ms, c_n, c_by), errs=errs)
+        log("bench: %s %.1f ms/step, %.1f energies/s, product kernel avg %.3f ms x%d, conversion %.1f ms/step, "
+            "inv avg %.3f ms x%d, err %s" % (prec, ms_step, n_e / (ms_step / 1e3), g_ms / max(g_n, 1), g_n,
+                                             c_ms / args.steps, i_ms / max(i_n, 1), i_n, errs))
 
     # headline: fastest scheme meeting the error bar (FP64 always qualifies)
     def qualifies(p):
@@ -191,6 +194,11 @@ def main():
     achieved = (g_fl / max(g_n, 1)) / (g_ms / max(g_n, 1) / 1e3) / 1e12 if g_n else None
     peak = PEAK[parse(best)["prec"]]
     traffic = traffic_from_profile() if best == "fp64" else None
+    kernel_name = {"fp64": "zgemm_mfma_kernel (v_mfma_f64_16x16x4)", "fp32": "zgemm_mfma_kernel (v_mfma_f32)",
+                   "bf16": "zgemm_split_kernel (v_mfma_f32_16x16x32_bf16)",
+                   "fp16": "zgemm_split_kernel (v_mfma_f32_16x16x32_f16)",
+                   "int8": "zgemm_o2_kernel (v_mfma_i32_32x32x32_i8)"}[parse(best)["prec"]]
+    gemm_fp64eq = (136 * (n_b - 1) + 16) * b ** 3 * n_e   # FP64-equivalent product flops per step
     line = {
         "metric": METRIC,
         "value": r["value"],
@@ -209,15 +217,21 @@ def main():
                    "precision": best, "energies_per_step": n_e},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": (achieved / peak) if achieved else None, "traffic": traffic,
-                     "kernel": "complex b x b x b block products of the solve (%s scheme)" % best,
+                     "kernel": "%s: matrix-core kernel of the complex b x b x b block products (%s scheme); "
+                               "operations counted in its own arithmetic" % (kernel_name, best),
                      "flops_per_launch": g_fl / max(g_n, 1), "avg_launch_ms": g_ms / max(g_n, 1),
                      "launches": g_n},
         "cpu_baseline": cpu,
         "schemes": {p: {"energies_per_s": v["value"], "ms_per_step": v["ms_per_step"], "max_rel_err": v["errs"],
                         "status_ok": v["status_ok"],
-                        "gemm_tflops_fp64eq": (v["gemm"][2] / (v["gemm"][0] / 1e3) / 1e12) if v["gemm"][1] else None,
-                        "inversion_ms_per_step": v["inv"][0] / args.steps,
-                        "gemm_ms_per_step": v["gemm"][0] / args.steps}
+                        "products_tflops_fp64eq": gemm_fp64eq * args.steps / ((v["gemm"][0] + v["conv"][0]) / 1e3)
+                        / 1e12 if v["gemm"][1] else None,
+                        "product_kernel_ms_per_step": v["gemm"][0] / args.steps,
+                        "product_kernel_rate_own_arith": (v["gemm"][2] / (v["gemm"][0] / 1e3) / 1e12)
+                        if v["gemm"][1] else None,
+                        "conversion_ms_per_step": v["conv"][0] / args.steps,
+                        "conversion_GBps": (v["conv"][2] / (v["conv"][0] / 1e3) / 1e9) if v["conv"][1] else None,
+                        "inversion_ms_per_step": v["inv"][0] / args.steps}
                     for p, v in results.items()},
         "fp64_energies_per_s": results["fp64"]["value"] if "fp64" in results else None,
         "algorithmic_tflops_fp64eq": (144 * (n_b - 1) + 24) * b ** 3 * n_e / (r["ms_per_step"] / 1e3) / 1e12,

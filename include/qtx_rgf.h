@@ -63,12 +63,26 @@ typedef enum {
  *   column (right operand); slice products with i + j <= n_slices + 1 on the
  *   matrix cores with FP32 accumulation, recombined in FP64 (Ozaki scheme I,
  *   Section II-D).  n_slices = 2 is the "3-term" split (hi*hi + hi*lo + lo*hi).
+ *   Supported: BF16 n_slices 2..5, FP16 n_slices 2..3.
+ * QTX_INT8_OZAKI2 : modular emulation on the INT8 matrix cores (Ozaki scheme II,
+ *   the paper's emulation in Section V-A), with n_slices = p moduli (2..16,
+ *   default 11).  Each row of the left operand and column of the right operand
+ *   is scaled by a power of two and rounded to integers of at most kbits bits
+ *   (the only rounding of the scheme); the integer products are computed exactly
+ *   modulo each of the p odd, pairwise coprime moduli 255, 253, 251, 247, 241,
+ *   239, 233, 229, 227, 223, 217, 211, 199, 197, 193, 191 (first p), with INT32
+ *   accumulation over all of K, and recombined by the Chinese remainder theorem
+ *   in FP64.  kbits is the largest value with 8 K 4^kbits < prod(moduli), and p
+ *   is clipped so that kbits <= 47 (qtx_ozaki2_bits); the error of a product is about
+ *   K 2^-kbits max|row of A| max|column of B|.  Complex products use four real
+ *   products (4M).  K <= 65536.
  * Inversions and the G^< / G^> epilogue sums are FP64 in every mode. */
 typedef enum {
   QTX_FP64 = 0,
   QTX_FP32 = 1,
   QTX_BF16_SPLIT = 2,
-  QTX_FP16_SPLIT = 3
+  QTX_FP16_SPLIT = 3,
+  QTX_INT8_OZAKI2 = 4
 } qtx_prec;
 
 enum {
@@ -170,6 +184,16 @@ size_t qtx_rgf_footprint(const qtx_rgf_problem* p);
 /* Human-readable name of a status code (static string). */
 const char* qtx_status_str(qtx_status s);
 
+/* Parameters of QTX_INT8_OZAKI2 asked for p moduli at contraction length K
+ * (host only, no device work).  The scheme uses the first p_used <= p moduli
+ * (p is clipped where more moduli would need operands wider than 47 bits) and
+ * operand integers of kbits bits, the largest width with 8 K 4^kbits < M, M the
+ * product of the moduli used.  Writes the moduli to moduli[0..p_used-1] (host
+ * array of at least p entries), p_used and kbits; each pointer may be NULL.
+ * Returns QTX_ERR_UNSUPPORTED if (p, K) is outside the scheme's range
+ * (p in 2..16, K in 1..65536, kbits >= 1). */
+qtx_status qtx_ozaki2_bits(int32_t p, int32_t K, int32_t* moduli, int32_t* p_used, int32_t* kbits);
+
 /* ---------------------------------------------------------------------------
  * Kernel-level entry points (the building blocks of qtx_rgf_solve), exposed
  * so each can be checked in isolation.
@@ -219,14 +243,21 @@ qtx_status qtx_rgf_observables(qtx_rgf_ctx ctx, int32_t b, int32_t n_e,
  * While enabled, every launch of the families below is bracketed by HIP events
  * recorded on the stream it runs on.  qtx_rgf_profile_read waits for those
  * events, returns the summed duration (ms), the launch count and the
- * algorithmic flop count of the launches since the previous read of that
- * family, and resets them.  Families:
- *   QTX_KERNEL_GEMM : the b x b x b complex block products of qtx_rgf_solve,
- *                     8 b^3 real flop per energy (FP64-equivalent);
- *   QTX_KERNEL_INV  : one batched inversion of a Schur complement (all panels,
- *                     trailing updates and the final gather), 8 b^3 per energy.
+ * algorithmic work of the launches since the previous read of that family, and
+ * resets them.  Families (qtx_rgf_solve and qtx_zgemm launches):
+ *   QTX_KERNEL_GEMM    : the matrix-core kernel of one complex block product
+ *                        (M x N x K, batched); work = the real multiply-adds x 2
+ *                        its scheme issues on the matrix cores, in that scheme's
+ *                        own arithmetic: 4 real products (FP64, FP32), 4 per
+ *                        kept slice pair (BF16/FP16 split), 4 per modulus (INT8);
+ *   QTX_KERNEL_INV     : one batched inversion of a Schur complement (all panels,
+ *                        trailing updates and the final gather), 8 b^3 flop per
+ *                        energy;
+ *   QTX_KERNEL_CONVERT : the operand conversion passes of a split / INT8 product
+ *                        (both operands); work = bytes read (16 per complex
+ *                        element) plus digit / residue bytes written.
  * Any NULL output pointer is skipped. */
-enum { QTX_KERNEL_GEMM = 0, QTX_KERNEL_INV = 1 };
+enum { QTX_KERNEL_GEMM = 0, QTX_KERNEL_INV = 1, QTX_KERNEL_CONVERT = 2 };
 qtx_status qtx_rgf_profile(qtx_rgf_ctx ctx, int enable);
 qtx_status qtx_rgf_profile_read(qtx_rgf_ctx ctx, int family, double* total_ms, int64_t* launches,
                                 double* flops);

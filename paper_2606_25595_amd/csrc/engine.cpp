@@ -66,7 +66,7 @@ struct qtx_rgf_ctx_s {
   bool profiling = false;
   bool use_graph = false;
   bool capturing = false;
-  ProfFamily prof[2];
+  ProfFamily prof[3];
   std::vector<hipEvent_t> event_pool;
   // pinned staging of the pointer tables, and the event of its last upload
   void* pinned = nullptr;
@@ -214,15 +214,26 @@ struct ProfScope {
 struct Scheme {
   int prec = QTX_FP64;
   int fmt = 0;      // split: 0 = FP16 digits, 1 = BF16 digits
-  int ns = 0;       // split: slices per operand
+  int ns = 0;       // split: slices per operand; Ozaki II: moduli
   bool split() const { return prec == QTX_BF16_SPLIT || prec == QTX_FP16_SPLIT; }
+  bool o2() const { return prec == QTX_INT8_OZAKI2; }
+  bool sliced() const { return split() || o2(); }   // operands converted into a workspace first
   bool operator==(const Scheme& o) const { return prec == o.prec && fmt == o.fmt && ns == o.ns; }
 };
+
+constexpr int kO2DefaultModuli = 11;
 
 bool make_scheme(int prec, int n_slices, Scheme* out) {
   Scheme sc;
   sc.prec = prec;
   if (prec == QTX_FP64 || prec == QTX_FP32) { *out = sc; return true; }
+  if (prec == QTX_INT8_OZAKI2) {
+    sc.ns = n_slices > 0 ? n_slices : kO2DefaultModuli;
+    O2Params P;
+    if (!o2_params(sc.ns, 1024, &P)) return false;   // every block size up to 1024
+    *out = sc;
+    return true;
+  }
   if (prec != QTX_BF16_SPLIT && prec != QTX_FP16_SPLIT) return false;
   sc.fmt = (prec == QTX_BF16_SPLIT) ? 1 : 0;
   sc.ns = n_slices > 0 ? n_slices : 2;
@@ -237,48 +248,72 @@ void problem_schemes(const qtx_rgf_problem& p, Scheme* r, Scheme* l) {
   else *l = *r;
 }
 
+// Converted-operand bytes (digits or residues, then row exponents) of a rows x cols
+// operand, per batch entry.
+size_t operand_digit_bytes(int rows, int cols, const Scheme& sc) {
+  if (sc.split()) return (size_t)split_digit_stride(rows, cols, sc.ns) * sizeof(uint16_t);
+  if (sc.o2()) return (size_t)o2_res_stride(rows, cols, sc.ns);
+  return 0;
+}
+size_t operand_bytes(int rows, int cols, const Scheme& sc, int batch) {
+  if (!sc.sliced()) return 0;
+  return align_up(operand_digit_bytes(rows, cols, sc) * batch) +
+         align_up((size_t)split_exp_stride(rows, cols) * sizeof(int32_t) * batch);
+}
+
+// The scheme of the two whose converted operands need more room.
 Scheme larger_split(const Scheme& a, const Scheme& b) {
-  if (b.split() && (!a.split() || b.ns > a.ns)) return b;
-  return a;
+  return operand_bytes(64, 64, b, 1) > operand_bytes(64, 64, a, 1) ? b : a;
 }
 
 struct SplitBufs {
-  uint16_t* S[2] = {nullptr, nullptr};
+  void* S[2] = {nullptr, nullptr};
   int32_t* E[2] = {nullptr, nullptr};
 };
 
-size_t split_pair_bytes(int b, const Scheme& sc, int batch) {
-  if (!sc.split()) return 0;
-  const size_t dig = (size_t)split_digit_stride(b, b, sc.ns) * sizeof(uint16_t) * batch;
-  const size_t ex = (size_t)split_exp_stride(b, b) * sizeof(int32_t) * batch;
-  return 2 * (align_up(dig) + align_up(ex));
-}
+size_t split_pair_bytes(int b, const Scheme& sc, int batch) { return 2 * operand_bytes(b, b, sc, batch); }
 
 SplitBufs carve_split(char*& w, int b, const Scheme& sc, int batch) {
   SplitBufs sb;
-  if (!sc.split()) return sb;
+  if (!sc.sliced()) return sb;
   for (int q = 0; q < 2; ++q) {
-    const size_t dig = (size_t)split_digit_stride(b, b, sc.ns) * sizeof(uint16_t) * batch;
-    const size_t ex = (size_t)split_exp_stride(b, b) * sizeof(int32_t) * batch;
-    sb.S[q] = (uint16_t*)w; w += align_up(dig);
-    sb.E[q] = (int32_t*)w; w += align_up(ex);
+    sb.S[q] = w; w += align_up(operand_digit_bytes(b, b, sc) * batch);
+    sb.E[q] = (int32_t*)w; w += align_up((size_t)split_exp_stride(b, b) * sizeof(int32_t) * batch);
   }
   return sb;
 }
 
 // One batched complex block product with a precision scheme.  Elementwise (K = 0)
 // launches stay FP64.
-hipError_t run_product(const GemmDesc& d, const Scheme& sc, const SplitBufs& sb, hipStream_t s) {
-  if (d.K == 0 || sc.prec == QTX_FP64) return launch_zgemm_f64(d, s);
-  if (sc.prec == QTX_FP32) return launch_zgemm_f32(d, s);
-  // split: operand A as rows of op(A) (M x K), operand B as columns of op(B) (N x K)
+hipError_t run_product(qtx_rgf_ctx ctx, const GemmDesc& d, const Scheme& sc, const SplitBufs& sb, hipStream_t s) {
+  // per-launch timers: the matrix-core kernel (its own operations) and the operand
+  // conversion passes (their algorithmic bytes) separately
+  const double mnk = 2.0 * d.M * d.N * d.K * d.batch;
+  double core_ops = 4.0 * mnk;   // FP64 / FP32: four real products
+  if (sc.split()) core_ops = 4.0 * (sc.ns * (sc.ns + 1) / 2) * mnk;
+  const bool prof = d.K > 0;
+  if (d.K == 0 || sc.prec == QTX_FP64) {
+    ProfScope ps(ctx, QTX_KERNEL_GEMM, s, core_ops, prof);
+    return launch_zgemm_f64(d, s);
+  }
+  if (sc.prec == QTX_FP32) {
+    ProfScope ps(ctx, QTX_KERNEL_GEMM, s, core_ops, prof);
+    return launch_zgemm_f32(d, s);
+  }
+  O2Params P;
+  if (sc.o2() && !o2_params(sc.ns, d.K, &P)) return hipErrorInvalidValue;
+  if (sc.o2()) core_ops = 4.0 * P.p * mnk;
+  // operand A as rows of op(A) (M x K), operand B as columns of op(B) (N x K)
   const bool shA = (d.sA == 0 && !d.tA), shB = (d.sB == 0 && !d.tB);
+  auto stride = [&](int rows) {
+    return sc.o2() ? o2_res_stride(rows, d.K, sc.ns) : split_digit_stride(rows, d.K, sc.ns);
+  };
   SplitDesc sa;
   sa.tX = d.tA; sa.X = d.A; sa.ld = d.lda; sa.stride = d.sA;
   sa.rows = d.M; sa.cols = d.K;
   sa.trans = (d.opA == OP_C); sa.conj = (d.opA == OP_C);
   sa.S = sb.S[0]; sa.E = sb.E[0];
-  sa.s_stride = split_digit_stride(d.M, d.K, sc.ns);
+  sa.s_stride = stride(d.M);
   sa.e_stride = split_exp_stride(d.M, d.K);
   sa.batch = shA ? 1 : d.batch;
   SplitDesc sbd;
@@ -286,19 +321,32 @@ hipError_t run_product(const GemmDesc& d, const Scheme& sc, const SplitBufs& sb,
   sbd.rows = d.N; sbd.cols = d.K;
   sbd.trans = (d.opB == OP_N); sbd.conj = (d.opB == OP_C);
   sbd.S = sb.S[1]; sbd.E = sb.E[1];
-  sbd.s_stride = split_digit_stride(d.N, d.K, sc.ns);
+  sbd.s_stride = stride(d.N);
   sbd.e_stride = split_exp_stride(d.N, d.K);
   sbd.batch = shB ? 1 : d.batch;
-  hipError_t e = launch_split(sa, sc.fmt, sc.ns, s);
-  if (e != hipSuccess) return e;
-  e = launch_split(sbd, sc.fmt, sc.ns, s);
-  if (e != hipSuccess) return e;
   SplitGemmDesc g;
   g.d = d;
   g.SA = sa.S; g.sa_stride = shA ? 0 : sa.s_stride;
   g.SB = sbd.S; g.sb_stride = shB ? 0 : sbd.s_stride;
   g.EA = sa.E; g.ea_stride = shA ? 0 : sa.e_stride;
   g.EB = sbd.E; g.eb_stride = shB ? 0 : sbd.e_stride;
+  // conversion bytes: read the operand, write digits / residues and exponents
+  const double conv_bytes =
+      (double)sa.batch * ((double)d.M * d.K * 16.0 + (double)operand_digit_bytes(d.M, d.K, sc)) +
+      (double)sbd.batch * ((double)d.N * d.K * 16.0 + (double)operand_digit_bytes(d.N, d.K, sc));
+  hipError_t e;
+  {
+    ProfScope ps(ctx, QTX_KERNEL_CONVERT, s, conv_bytes, prof);
+    if (sc.o2()) {
+      if ((e = launch_o2_convert(sa, P, s)) != hipSuccess) return e;
+      if ((e = launch_o2_convert(sbd, P, s)) != hipSuccess) return e;
+    } else {
+      if ((e = launch_split(sa, sc.fmt, sc.ns, s)) != hipSuccess) return e;
+      if ((e = launch_split(sbd, sc.fmt, sc.ns, s)) != hipSuccess) return e;
+    }
+  }
+  ProfScope ps(ctx, QTX_KERNEL_GEMM, s, core_ops, prof);
+  if (sc.o2()) return launch_zgemm_o2(g, P, s);
   return launch_zgemm_split(g, sc.fmt, sc.ns, s);
 }
 
@@ -560,8 +608,7 @@ struct Gemm {
     d.diag_by_batch = 1;
     d.bscal = energies;
     d.batch = Z;
-    ProfScope ps(run->ctx, QTX_KERNEL_GEMM, run->s, 8.0 * (double)b * b * b * Z, d.K == b);
-    return run_product(d, sc, sb, run->s);
+    return run_product(run->ctx, d, sc, sb, run->s);
   }
 };
 
@@ -902,6 +949,16 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
 
 extern "C" {
 
+qtx_status qtx_ozaki2_bits(int32_t p, int32_t K, int32_t* moduli, int32_t* p_used, int32_t* kbits) {
+  O2Params P;
+  if (!o2_params(p, K, &P)) return QTX_ERR_UNSUPPORTED;
+  if (moduli)
+    for (int i = 0; i < P.p; ++i) moduli[i] = o2_modulus(i);
+  if (p_used) *p_used = P.p;
+  if (kbits) *kbits = P.kbits;
+  return QTX_OK;
+}
+
 const char* qtx_status_str(qtx_status s) {
   switch (s) {
     case QTX_OK: return "QTX_OK";
@@ -963,7 +1020,7 @@ qtx_status qtx_rgf_profile(qtx_rgf_ctx ctx, int enable) {
 
 qtx_status qtx_rgf_profile_read(qtx_rgf_ctx ctx, int family, double* total_ms, int64_t* launches,
                                 double* flops) {
-  if (!ctx || family < 0 || family > 1) return QTX_ERR_ARG;
+  if (!ctx || family < 0 || family > 2) return QTX_ERR_ARG;
   DeviceGuard guard(ctx->device);
   ProfFamily& f = ctx->prof[family];
   for (auto& r : f.pending) {
@@ -1049,17 +1106,21 @@ qtx_status qtx_zgemm(qtx_rgf_ctx ctx, char opA, char opB, int32_t M, int32_t N, 
   }
   d.batch = batch;
   SplitBufs sb;
-  if (sc.split() && K > 0) {
-    const size_t need = split_bytes(M, K, sc.ns, batch) + split_bytes(N, K, sc.ns, batch) + 4096;
+  if (sc.o2() && K > 0) {
+    O2Params P;
+    if (!o2_params(sc.ns, K, &P)) return QTX_ERR_UNSUPPORTED;
+  }
+  if (sc.sliced() && K > 0) {
+    const size_t need = operand_bytes(M, K, sc, batch) + operand_bytes(N, K, sc, batch) + 4096;
     qtx_status st = ensure_ws(ctx, need);
     if (st != QTX_OK) return st;
     char* w = (char*)ctx->ws;
-    sb.S[0] = (uint16_t*)w; w += align_up((size_t)split_digit_stride(M, K, sc.ns) * 2 * batch);
+    sb.S[0] = w; w += align_up(operand_digit_bytes(M, K, sc) * batch);
     sb.E[0] = (int32_t*)w; w += align_up((size_t)split_exp_stride(M, K) * 4 * batch);
-    sb.S[1] = (uint16_t*)w; w += align_up((size_t)split_digit_stride(N, K, sc.ns) * 2 * batch);
+    sb.S[1] = w; w += align_up(operand_digit_bytes(N, K, sc) * batch);
     sb.E[1] = (int32_t*)w;
   }
-  QTX_TRY(run_product(d, sc, sb, (hipStream_t)hip_stream));
+  QTX_TRY(run_product(ctx, d, sc, sb, (hipStream_t)hip_stream));
   return QTX_OK;
 }
 

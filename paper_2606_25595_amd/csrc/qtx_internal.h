@@ -63,7 +63,7 @@ struct GemmDesc {
 };
 
 // Precision schemes of the complex block products.
-enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16_SPLIT = 2, PREC_FP16_SPLIT = 3 };
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16_SPLIT = 2, PREC_FP16_SPLIT = 3, PREC_INT8_OZAKI2 = 4 };
 
 // Kernel symbol families of the complex GEMM (same code, separate names).
 enum GemmKind { GEMM_PRODUCT = 0, GEMM_INV_UPDATE = 1, GEMM_ELEMENTWISE = 2 };
@@ -79,14 +79,14 @@ struct SplitDesc {
   const double2* X = nullptr; int64_t ld = 0, stride = 0;
   int rows = 0, cols = 0;
   int trans = 0, conj = 0;
-  uint16_t* S = nullptr; int64_t s_stride = 0;   // digits per batch entry (16-bit words)
-  int32_t* E = nullptr; int64_t e_stride = 0;    // strip exponents per batch entry
+  void* S = nullptr; int64_t s_stride = 0;       // digits / residues per batch entry (elements)
+  int32_t* E = nullptr; int64_t e_stride = 0;    // row exponents per batch entry
   int batch = 1;
 };
 struct SplitGemmDesc {
   GemmDesc d;                                     // M, N, K, C, alpha, epilogue (A/B unused)
-  const uint16_t* SA = nullptr; int64_t sa_stride = 0;   // rows = M
-  const uint16_t* SB = nullptr; int64_t sb_stride = 0;   // rows = N
+  const void* SA = nullptr; int64_t sa_stride = 0;   // rows = M
+  const void* SB = nullptr; int64_t sb_stride = 0;   // rows = N
   const int32_t* EA = nullptr; int64_t ea_stride = 0;
   const int32_t* EB = nullptr; int64_t eb_stride = 0;
 };
@@ -96,6 +96,30 @@ int64_t split_digit_stride(int rows, int cols, int ns);
 int64_t split_exp_stride(int rows, int cols);
 hipError_t launch_split(const SplitDesc& sd, int fmt, int ns, hipStream_t s);
 hipError_t launch_zgemm_split(const SplitGemmDesc& g, int fmt, int ns, hipStream_t s);
+// Row exponents only: E[r] with max_k |S[r][k]| 2^-E[r] in [1/4, 1/2) (0 for a zero row).
+hipError_t launch_split_exp(const SplitDesc& sd, hipStream_t s);
+
+// Modular (Ozaki II) INT8 products.  Moduli m_0 > m_1 > ... are odd and pairwise
+// coprime (kO2Moduli); an operand row r becomes the integer vector
+// X'[r][k] = rint(S[r][k] 2^{k_bits + 1 - E[r]}), |X'| <= 2^k_bits, stored as its
+// symmetric residues mod every m_i (int8).  The product of the residues is exact
+// in INT32 and the CRT gives sum_k A' B' exactly modulo M = prod m_i, which holds
+// the true value because 2 K 4^k_bits < M / 2.
+constexpr int kO2MaxModuli = 16;
+struct O2Params {
+  int p = 0;                     // number of moduli
+  int kbits = 0;                 // operand integer bits
+  double m[kO2MaxModuli];        // moduli
+  double inv_m[kO2MaxModuli];    // 1 / m_i (rounded)
+  double u[kO2MaxModuli];        // (M / m_i)^-1 mod m_i
+  double M = 0.0;                // prod m_i (rounded)
+};
+bool o2_params(int p, int K, O2Params* out);               // false if p or K is out of range
+int o2_modulus(int i);                                      // i-th modulus (0 outside 0..15)
+int64_t o2_res_stride(int rows, int cols, int p);           // bytes of residues per batch entry
+// Row exponents (as launch_split_exp) and residues of one operand.
+hipError_t launch_o2_convert(const SplitDesc& sd, const O2Params& P, hipStream_t s);
+hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_t s);
 
 // Gauss-Jordan inversion with implicit partial pivoting, batched.
 // X_z (n x n, ld n, stride sX) is overwritten; the inverse is written to Out_z.

@@ -1,0 +1,487 @@
+// Complex GEMM emulated with INT8 modular products (Ozaki scheme II, the
+// emulation of Section V-A), on the gfx950 v_mfma_i32_32x32x32_i8 matrix cores.
+//
+// Scaling.  Every row r of op(A) (every column of op(B)) gets the power-of-two
+// exponent E[r] of the split pass (max |x| 2^-E in [1/4, 1/2), real and imaginary
+// parts together) and becomes the integer vector X' = rint(x 2^{kbits + 1 - E}),
+// |X'| <= 2^kbits.  The only approximation of the scheme is this rounding.
+//
+// Residues.  For odd, pairwise coprime moduli m_0..m_{p-1} <= 255 each integer is
+// stored as its symmetric residue in [-(m-1)/2, (m-1)/2] (fits int8).  Layout per
+// batch entry: [p][KT][R][2][64] bytes (KT = ceil(K / 64) strips of 64 k, plane 0
+// = real, 1 = imaginary; k beyond K is zero), so the 64-row tile of one modulus
+// and one strip is one contiguous 8 KB block.
+//
+// Product (4M).  For each modulus the INT32 matrix cores accumulate, exactly,
+//   rr = sum Ar' Br',  ii = sum Ai' Bi',  ri = sum Ar' Bi' + Ai' Br'
+// over all of K (|sum| <= 2 K 127^2 < 2^31).  Then Cr = rr - ii and Ci = ri are
+// folded into a CRT sum per output, in FP64:
+//   S += ((c u_i) mod m_i) / m_i,   u_i = (M / m_i)^-1 mod m_i,  M = prod m_i,
+// which is C' / M modulo 1.  Since |C'| <= 2 K 4^kbits < M / 4, C' = M (S - rint(S))
+// up to the FP64 rounding of S (p terms below 2^-50, against C' / M >= 1/16 of
+// the largest possible |C'| / M), and C = C' 2^{E_A + E_B - 2 kbits - 2}.
+#include "qtx_internal.h"
+
+namespace qtx {
+
+typedef int i4 __attribute__((ext_vector_type(4)));
+typedef int i16v __attribute__((ext_vector_type(16)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int KS = 64;                 // k per strip (two MFMA k-steps of 32)
+constexpr int BM = 64, BN = 64, NT = 256;
+
+// Odd, pairwise coprime moduli (largest first).
+constexpr int kModuli[kO2MaxModuli] = {255, 253, 251, 247, 241, 239, 233, 229,
+                                       227, 223, 217, 211, 199, 197, 193, 191};
+
+__device__ inline int xcd_remap(int pid, int total) {
+  const int nx = 8;
+  int per = total / nx, rem = total % nx;
+  int x = pid % nx, local = pid / nx;
+  return (x < rem) ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
+__device__ inline double pow2(int e) {
+  e = e < -1020 ? -1020 : (e > 1020 ? 1020 : e);
+  return __builtin_bit_cast(double, (uint64_t)(e + 1023) << 52);
+}
+
+// 64 rows x 32 k of S = op(X) into LDS (coalesced along the contiguous index),
+// zero outside rows x cols.
+__device__ inline void load_half_strip(const SplitDesc& sd, const double2* X, int r0, int k0, int tid,
+                                       double2 (*tile)[33]) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int e = tid + NT * j;
+    int r, k;
+    if (!sd.trans) { r = e / 32; k = e % 32; }
+    else { k = e / 64; r = e % 64; }
+    double2 v = cmk(0.0, 0.0);
+    if (r0 + r < sd.rows && k0 + k < sd.cols)
+      v = sd.trans ? X[(int64_t)(k0 + k) * sd.ld + r0 + r] : X[(int64_t)(r0 + r) * sd.ld + k0 + k];
+    tile[r][k] = sd.conj ? cconj(v) : v;
+  }
+}
+
+// One workgroup per (64 rows, one 64-k strip, batch entry).  Thread t handles row
+// t/4 and k = 8 (t%4) .. +7 of each 32-k half.
+__global__ __launch_bounds__(NT) void o2_residue_kernel(SplitDesc sd, O2Params P) {
+  __shared__ double2 tile[64][33];
+  const int z = blockIdx.z, kt = blockIdx.y, r0 = blockIdx.x * 64, tid = threadIdx.x;
+  const double2* X = sd.tX ? sd.tX[z] : sd.X + (int64_t)z * sd.stride;
+  const int r = tid >> 2, kq = (tid & 3) * 8;
+  const bool live = r0 + r < sd.rows;
+  const int KT = (sd.cols + KS - 1) / KS;
+  const double sc = live ? pow2(P.kbits + 1 - sd.E[(int64_t)z * sd.e_stride + r0 + r]) : 0.0;
+  int8_t* out = (int8_t*)sd.S + (int64_t)z * sd.s_stride;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+    load_half_strip(sd, X, r0, kt * KS + 32 * h, tid, tile);
+    __syncthreads();
+    if (!live) continue;
+    double a[2][8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double2 v = tile[r][kq + j];
+      a[0][j] = rint(v.x * sc);   // exact scaling, then the one rounding of the scheme
+      a[1][j] = rint(v.y * sc);
+    }
+    for (int i = 0; i < P.p; ++i) {
+      const double m = P.m[i], im = P.inv_m[i];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        uint32_t w[2] = {0u, 0u};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          // |a| <= 2^47: a/m is off an integer + 1/2 by >= 1/(2m), far above the
+          // rounding of a * (1/m), so q = rint(a / m) exactly and r is exact.
+          const double q = rint(a[c][j] * im);
+          const int rr = (int)fma(-q, m, a[c][j]);
+          w[j >> 2] |= ((uint32_t)rr & 0xffu) << (8 * (j & 3));
+        }
+        uint2 pk;
+        pk.x = w[0];
+        pk.y = w[1];
+        *(uint2*)(out + ((((int64_t)i * KT + kt) * sd.rows + r0 + r) * 2 + c) * KS + 32 * h + kq) = pk;
+      }
+    }
+  }
+}
+
+// Single-pass conversion for K <= kO2FusedMaxK: one workgroup holds RB = 8 rows of
+// S = op(X) over all of K in LDS (coalesced loads; element (r, k) at r KP + (k ^ r),
+// so the 8 rows of one k fall in distinct banks), finds the row exponents, and
+// writes every (modulus, strip) block of those rows: 8 rows x 2 planes x 64 bytes
+// = 1 KB contiguous, one 16-byte store per lane of a wave (lane -> row l / 8,
+// plane (l / 4) % 2, k = 16 (l % 4) .. +15 of the strip).
+constexpr int kO2FusedRows = 8;
+constexpr int kO2FusedMaxK = 512;   // 8 rows x 512 x 16 B = 64 KB of LDS
+
+__global__ __launch_bounds__(NT) void o2_convert_kernel(SplitDesc sd, O2Params P) {
+  extern __shared__ double2 rows_lds[];   // [RB][KP], KP = KT * 64 (zero-padded), swizzled
+  constexpr int RB = kO2FusedRows;
+  const int z = blockIdx.y, r0 = blockIdx.x * RB, tid = threadIdx.x;
+  const int K = sd.cols, KT = (K + KS - 1) / KS, KP = KT * KS, pitch = KP;
+  const double2* X = sd.tX ? sd.tX[z] : sd.X + (int64_t)z * sd.stride;
+  // load (zero outside rows x K, conjugate on the way in): thread t takes row t / 32
+  // (trans 0: rows contiguous) or t % 8 (trans 1: 8 adjacent columns of X = 128
+  // bytes), and k = its base + 32 j; all loads are issued before the LDS stores.
+  {
+    const int r = sd.trans ? (tid & 7) : (tid >> 5);
+    const int kb = sd.trans ? (tid >> 3) : (tid & 31);
+    const bool rok = r0 + r < sd.rows;
+    const int nj = KP / 32;   // <= 16
+    double2 v[kO2FusedMaxK / 32];
+#pragma unroll
+    for (int j = 0; j < kO2FusedMaxK / 32; ++j) {
+      const int k = kb + 32 * j;
+      v[j] = cmk(0.0, 0.0);
+      if (j < nj && rok && k < K)
+        v[j] = sd.trans ? X[(int64_t)k * sd.ld + r0 + r] : X[(int64_t)(r0 + r) * sd.ld + k];
+    }
+#pragma unroll
+    for (int j = 0; j < kO2FusedMaxK / 32; ++j) {
+      const int k = kb + 32 * j;
+      if (j < nj) rows_lds[r * pitch + (k ^ r)] = sd.conj ? cconj(v[j]) : v[j];
+    }
+  }
+  __syncthreads();
+  // row exponents: 32 threads per row
+  {
+    const int r = tid >> 5, q = tid & 31;
+    double mx = 0.0;
+    for (int k = q; k < KP; k += 32) {
+      const double2 v = rows_lds[r * pitch + k];   // any order: all k of the row
+      mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+    }
+#pragma unroll
+    for (int o = 16; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    int e = 0;
+    if (mx > 0.0 && mx <= 1.7e308) e = ilogb(mx) + 2;   // max * 2^-e in [1/4, 1/2)
+    if (q == 0 && r0 + r < sd.rows) sd.E[(int64_t)z * sd.e_stride + r0 + r] = e;
+  }
+  __syncthreads();   // the exponents are read back below (same workgroup)
+  const int lane = tid & 63, wave = tid >> 6;
+  const int r = lane >> 3, c = (lane >> 2) & 1, ks = lane & 3;
+  const bool live = r0 + r < sd.rows;
+  const double sc = live ? pow2(P.kbits + 1 - sd.E[(int64_t)z * sd.e_stride + r0 + r]) : 0.0;
+  int8_t* out = (int8_t*)sd.S + (int64_t)z * sd.s_stride;
+  for (int kt = wave; kt < KT; kt += NT / 64) {
+    double a[16];
+    const double2* src = rows_lds + r * pitch;
+    const int k0 = kt * KS + 16 * ks;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double2 v = src[(k0 + j) ^ r];
+      a[j] = rint((c ? v.y : v.x) * sc);
+    }
+    for (int i = 0; i < P.p; ++i) {
+      const double m = P.m[i], im = P.inv_m[i];
+      uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double q = rint(a[j] * im);
+        const int rr = (int)fma(-q, m, a[j]);
+        w[j >> 2] |= ((uint32_t)rr & 0xffu) << (8 * (j & 3));
+      }
+      if (live) {
+        u4 pk = {w[0], w[1], w[2], w[3]};
+        *(u4*)(out + ((((int64_t)i * KT + kt) * sd.rows + r0 + r) * 2 + c) * KS + 16 * ks) = pk;
+      }
+    }
+  }
+}
+
+__device__ inline i16v mfma_i8(i4 a, i4 b, i16v c) {
+  return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+}
+
+// S += ((c u) mod m) / m.  |c| < 2^31 and u < 2^8, so c u is exact in FP64; its
+// quotient by m is never within 1/(2m) of a half-integer (m odd), so q is exact and
+// so is the remainder.
+__device__ inline void crt_fold(int c, double m, double im, double u, double& S) {
+  const double cu = (double)c * u;
+  const double q = rint(cu * im);
+  const double r = fma(-q, m, cu);
+  S = fma(r, im, S);
+}
+
+// 128 x 64 complex output tile per 512-thread workgroup (one per CU); wave w owns
+// the 32 x 32 block (w % 4, w / 4).  MFMA 32x32x32 i8 layouts: operand lane l
+// holds row (column) l % 32 and k = 16 (l / 32) .. +15 of a 32-k step; result
+// lane l, element v -> row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
+//
+// The (modulus, strip) tiles, modulus-major, stream through an NSTAGE-deep LDS
+// ring filled by direct global->LDS loads (no registers held for them), so
+// NSTAGE - 1 strips (~120 KB per CU) are in flight while one feeds the matrix
+// cores.  A stage holds the 128 A rows then the 64 B rows, 128 bytes each (two
+// planes x 64 k); the 16-byte slot s of row r sits at slot s ^ (r % 8), which keeps
+// the fragment reads (32 rows, one slot) free of bank conflicts.  Each thread
+// issues exactly LPT loads per strip, so "strip j has landed" is a fixed count
+// of outstanding vector-memory operations.  Rows beyond M (N) load row M - 1
+// (N - 1): they only feed outputs that are never stored.
+constexpr int O2_BM = 128, O2_BN = 64, O2_NT = 512;
+constexpr int NSTAGE = 6;
+constexpr int STAGE_U4 = (O2_BM + O2_BN) * 8;   // 16-byte slots per stage (24 KB)
+constexpr int LPT = STAGE_U4 / O2_NT;           // loads per thread per strip (3)
+
+// Four 16-byte LDS reads (byte addresses) that complete inside the block: the
+// compiler does not see them as LDS accesses, so it does not drain the pending
+// global->LDS loads of the other ring stages before them.
+__device__ inline void lds_read4(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, i4& r0, i4& r1, i4& r2,
+                                 i4& r3) {
+  asm volatile(
+      "ds_read_b128 %0, %4\n\t"
+      "ds_read_b128 %1, %5\n\t"
+      "ds_read_b128 %2, %6\n\t"
+      "ds_read_b128 %3, %7\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
+      : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
+      : "memory");
+}
+
+__device__ inline void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// s_waitcnt vmcnt(N) (expcnt and lgkmcnt left unconstrained)
+template <int N>
+__device__ inline void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+__global__ __launch_bounds__(O2_NT) void zgemm_o2_kernel(SplitGemmDesc g, O2Params P) {
+  __shared__ u4 ring[NSTAGE][STAGE_U4];
+  __shared__ int Ea[O2_BM], Eb[O2_BN];
+
+  const GemmDesc& d = g.d;
+  const int tiles_m = (d.M + O2_BM - 1) / O2_BM;
+  const int tiles_n = (d.N + O2_BN - 1) / O2_BN;
+  const int per = tiles_m * tiles_n;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int z = tile / per;
+  const int t = tile - z * per;
+  const int m0 = (t % tiles_m) * O2_BM;
+  const int n0 = (t / tiles_m) * O2_BN;
+  const int M = d.M, N = d.N, K = d.K;
+  const int KT = (K + KS - 1) / KS;
+  const int NSTRIP = P.p * KT;                  // (modulus, strip) pairs, modulus-major
+
+  const int8_t* SA = (const int8_t*)g.SA + (int64_t)z * g.sa_stride;
+  const int8_t* SB = (const int8_t*)g.SB + (int64_t)z * g.sb_stride;
+  const int32_t* EA = g.EA + (int64_t)z * g.ea_stride;
+  const int32_t* EB = g.EB + (int64_t)z * g.eb_stride;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 3, wn = wave >> 2;
+  const bool wlive = (m0 + 32 * wm < M) && (n0 + 32 * wn < N);   // wave-uniform
+
+  if (tid < O2_BM) Ea[tid] = (m0 + tid < M) ? EA[m0 + tid] : 0;
+  else if (tid < O2_BM + O2_BN) Eb[tid - O2_BM] = (n0 + tid - O2_BM < N) ? EB[n0 + tid - O2_BM] : 0;
+  __syncthreads();   // also drains these loads before the counted ring loads start
+
+  // Per-thread source of each of its LPT slots of a stage (the strip offset added
+  // per strip): slot c = q * 512 + tid; A rows first, then B rows.
+  const int8_t* src[LPT];
+  int64_t sstride[LPT];                     // bytes between consecutive strips
+#pragma unroll
+  for (int q = 0; q < LPT; ++q) {
+    const int c = q * O2_NT + tid;
+    const int row = c >> 3, slot = c & 7;
+    const int word = slot ^ (row & 7);
+    if (row < O2_BM) {
+      const int rg = min(m0 + row, M - 1);
+      src[q] = SA + (int64_t)rg * 128 + 16 * word;
+      sstride[q] = (int64_t)M * 128;
+    } else {
+      const int rg = min(n0 + row - O2_BM, N - 1);
+      src[q] = SB + (int64_t)rg * 128 + 16 * word;
+      sstride[q] = (int64_t)N * 128;
+    }
+  }
+  auto issue = [&](int f) {   // strip f into stage f % NSTAGE
+    u4* dst = &ring[f % NSTAGE][0];
+#pragma unroll
+    for (int q = 0; q < LPT; ++q)
+      __builtin_amdgcn_global_load_lds((const void*)(src[q] + (int64_t)f * sstride[q]),
+                                       (__attribute__((address_space(3))) void*)(dst + q * O2_NT + (tid & ~63)),
+                                       16, 0, 0);
+  };
+
+  i16v arr, aii, ari;
+  double sre[16], sim[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    arr[v] = 0; aii[v] = 0; ari[v] = 0;
+    sre[v] = 0.0; sim[v] = 0.0;
+  }
+
+  const int la = 32 * wm + (lane & 31), lb = O2_BM + 32 * wn + (lane & 31), lk = lane >> 5;
+  const int sa = la & 7, sb = lb & 7;
+#pragma unroll
+  for (int f = 0; f < NSTAGE - 1; ++f)
+    if (f < NSTRIP) issue(f);
+  for (int f = 0; f < NSTRIP; ++f) {
+    if (f + NSTAGE - 2 < NSTRIP) wait_vm<LPT * (NSTAGE - 2)>();   // strip f landed (this thread's part)
+    else wait_vm<0>();
+    lds_barrier();                                                // ... and every thread's
+    if (f + NSTAGE - 1 < NSTRIP) issue(f + NSTAGE - 1);          // refills the stage read at f - 1
+    const uint32_t st = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) u4*)&ring[f % NSTAGE][0];
+    const int i = f / KT;
+    const int kt = f - i * KT;
+    if (wlive) {
+      const int nk = (kt == KT - 1 && K - kt * KS <= 32) ? 1 : 2;   // a half strip at the end
+      for (int s = 0; s < nk; ++s) {
+        const int w = 2 * s + lk;
+        i4 ar, ai, br, bi;
+        lds_read4(st + 16u * (la * 8 + (w ^ sa)), st + 16u * (la * 8 + ((4 + w) ^ sa)),
+                  st + 16u * (lb * 8 + (w ^ sb)), st + 16u * (lb * 8 + ((4 + w) ^ sb)), ar, ai, br, bi);
+        arr = mfma_i8(ar, br, arr);
+        aii = mfma_i8(ai, bi, aii);
+        ari = mfma_i8(ar, bi, ari);
+        ari = mfma_i8(ai, br, ari);
+      }
+    }
+    if (kt == KT - 1) {
+      const double m = P.m[i], im = P.inv_m[i], u = P.u[i];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        crt_fold(arr[v] - aii[v], m, im, u, sre[v]);
+        crt_fold(ari[v], m, im, u, sim[v]);
+        arr[v] = 0; aii[v] = 0; ari[v] = 0;
+      }
+    }
+  }
+
+  // epilogue in FP64 (same addend semantics as the FP64 kernels)
+  double2* __restrict__ C = d.tC ? d.tC[z] : d.C + (int64_t)z * d.sC;
+  const double bs = d.bscal ? d.bscal[z] : 1.0;
+  double2 coef[kMaxAddends];
+  const double2* X[kMaxAddends];
+#pragma unroll
+  for (int q = 0; q < kMaxAddends; ++q) {
+    coef[q] = d.add[q].coef;
+    if (d.add[q].scale_by_batch) coef[q] = cmk(coef[q].x * bs, coef[q].y * bs);
+    X[q] = d.add[q].tX ? d.add[q].tX[z] : (d.add[q].X ? d.add[q].X + (int64_t)z * d.add[q].stride : nullptr);
+  }
+  const double2 dg = d.diag_by_batch ? cmk(d.diag.x * bs, d.diag.y * bs) : d.diag;
+  if (!wlive) return;
+  const int c = n0 + lb - O2_BM;
+  const int eb = Eb[lb - O2_BM];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int rl = 32 * wm + 8 * (v >> 2) + 4 * lk + (v & 3);
+    const int r = m0 + rl;
+    if (r < M && c < N) {
+      const double sc = pow2(Ea[rl] + eb - 2 * P.kbits - 2) * P.M;
+      const double cr = (sre[v] - rint(sre[v])) * sc;
+      const double ci = (sim[v] - rint(sim[v])) * sc;
+      double2 out = cmul(d.alpha, cmk(cr, ci));
+#pragma unroll
+      for (int q = 0; q < kMaxAddends; ++q) {
+        if (X[q]) {
+          const double2 x = (d.add[q].op == OP_N) ? X[q][(int64_t)r * d.add[q].ld + c]
+                                                   : cconj(X[q][(int64_t)c * d.add[q].ld + r]);
+          out = cadd(out, cmul(coef[q], x));
+        }
+      }
+      if (r == c) out = cadd(out, dg);
+      C[(int64_t)r * d.ldc + c] = out;
+    }
+  }
+}
+
+// Modular inverse of a mod m (gcd 1), by the extended Euclidean algorithm.
+int64_t inv_mod(int64_t a, int64_t m) {
+  int64_t t = 0, nt = 1, r = m, nr = ((a % m) + m) % m;
+  while (nr != 0) {
+    const int64_t q = r / nr;
+    int64_t tmp = t - q * nt; t = nt; nt = tmp;
+    tmp = r - q * nr; r = nr; nr = tmp;
+  }
+  return t < 0 ? t + m : t;
+}
+
+}  // namespace
+
+bool o2_params(int p, int K, O2Params* out) {
+  if (p < 2 || p > kO2MaxModuli || K < 1 || K > 65536) return false;
+  // kbits(q) = largest k with 8 K 4^k < M_q = m_0 ... m_{q-1}: then |C'| <= 2 K 4^k < M / 4,
+  // so C' / M is within 1/4 of the integer the CRT sum S lands near and rint(S) is
+  // exact.  Moduli beyond those that 47-bit operands can use only widen M against
+  // C' (the FP64 sum S = C' / M mod 1 then loses log2(M / C') bits), so p is
+  // clipped to the largest count whose kbits stays <= 47.
+  auto kbits_of = [&](int q) {
+    unsigned __int128 Mx = 1;
+    for (int i = 0; i < q; ++i) Mx *= (unsigned)kModuli[i];
+    int kb = -1;
+    while (kb < 60) {
+      const unsigned __int128 lhs = ((unsigned __int128)(8 * (int64_t)K)) << (2 * (kb + 1));
+      if (!(lhs < Mx)) break;
+      ++kb;
+    }
+    return kb;
+  };
+  int q = p, kb = kbits_of(q);
+  while (kb > 47 && q > 2) kb = kbits_of(--q);
+  if (kb < 1 || kb > 47) return false;
+  O2Params P;
+  P.p = q;
+  P.kbits = kb;
+  double Md = 1.0;
+  for (int i = 0; i < q; ++i) Md *= kModuli[i];
+  for (int i = 0; i < q; ++i) {
+    const int64_t m = kModuli[i];
+    int64_t rest = 1;   // (M / m_i) mod m_i
+    for (int j = 0; j < q; ++j)
+      if (j != i) rest = rest * (kModuli[j] % m) % m;
+    P.m[i] = (double)m;
+    P.inv_m[i] = 1.0 / (double)m;
+    P.u[i] = (double)inv_mod(rest, m);
+  }
+  for (int i = q; i < kO2MaxModuli; ++i) { P.m[i] = 1.0; P.inv_m[i] = 1.0; P.u[i] = 0.0; }
+  P.M = Md;
+  *out = P;
+  return true;
+}
+
+int o2_modulus(int i) { return (i >= 0 && i < kO2MaxModuli) ? kModuli[i] : 0; }
+
+int64_t o2_res_stride(int rows, int cols, int p) {
+  return (int64_t)p * ((cols + KS - 1) / KS) * rows * 2 * KS;
+}
+
+hipError_t launch_o2_convert(const SplitDesc& sd, const O2Params& P, hipStream_t s) {
+  if (sd.rows <= 0 || sd.cols <= 0 || sd.batch <= 0) return hipSuccess;
+  if (sd.cols <= kO2FusedMaxK) {
+    const int KP = (sd.cols + KS - 1) / KS * KS;
+    const size_t lds = (size_t)kO2FusedRows * KP * sizeof(double2);
+    hipLaunchKernelGGL(o2_convert_kernel, dim3((sd.rows + kO2FusedRows - 1) / kO2FusedRows, sd.batch), dim3(NT),
+                       lds, s, sd, P);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_split_exp(sd, s);
+  if (e != hipSuccess) return e;
+  dim3 grid((sd.rows + 63) / 64, (sd.cols + KS - 1) / KS, sd.batch);
+  hipLaunchKernelGGL(o2_residue_kernel, grid, dim3(NT), 0, s, sd, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_t s) {
+  const GemmDesc& d = g.d;
+  if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
+  const int64_t total = (int64_t)((d.M + O2_BM - 1) / O2_BM) * ((d.N + O2_BN - 1) / O2_BN) * d.batch;
+  if (total > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(zgemm_o2_kernel, dim3((unsigned)total), dim3(O2_NT), 0, s, g, P);
+  return hipGetLastError();
+}
+
+}  // namespace qtx

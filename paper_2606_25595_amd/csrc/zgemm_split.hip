@@ -159,7 +159,7 @@ __global__ __launch_bounds__(NT) void split_kernel(SplitDesc sd) {
       }
     }
   }
-  uint16_t* out = sd.S + (int64_t)z * sd.s_stride + ((int64_t)kt * sd.rows + r0 + r) * NQ * KS + kq;
+  uint16_t* out = (uint16_t*)sd.S + (int64_t)z * sd.s_stride + ((int64_t)kt * sd.rows + r0 + r) * NQ * KS + kq;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     uint4 pk;
@@ -209,8 +209,8 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(SplitGemmDesc g) {
   const int M = d.M, N = d.N;
   const int KT = (d.K + KS - 1) / KS;
 
-  const u4* SA = (const u4*)(g.SA + (int64_t)z * g.sa_stride);
-  const u4* SB = (const u4*)(g.SB + (int64_t)z * g.sb_stride);
+  const u4* SA = (const u4*)((const uint16_t*)g.SA + (int64_t)z * g.sa_stride);
+  const u4* SB = (const u4*)((const uint16_t*)g.SB + (int64_t)z * g.sb_stride);
   const int32_t* EA = g.EA + (int64_t)z * g.ea_stride;
   const int32_t* EB = g.EB + (int64_t)z * g.eb_stride;
 
@@ -433,6 +433,12 @@ hipError_t launch_split(const SplitDesc& sd, int fmt, int ns, hipStream_t s) {
   QTX_SPLIT_CASE(1, 2) QTX_SPLIT_CASE(1, 3) QTX_SPLIT_CASE(1, 4) QTX_SPLIT_CASE(1, 5)
 #undef QTX_SPLIT_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_split_exp(const SplitDesc& sd, hipStream_t s) {
+  if (sd.rows <= 0 || sd.cols <= 0 || sd.batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(split_exp_kernel, dim3((sd.rows + 63) / 64, sd.batch), dim3(NT), 0, s, sd);
+  return hipGetLastError();
 }
 
 hipError_t launch_zgemm_split(const SplitGemmDesc& g, int fmt, int ns, hipStream_t s) {

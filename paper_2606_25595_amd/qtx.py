@@ -26,17 +26,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqtx_rgf.so")
 
 QTX_OK, QTX_ERR_ARG, QTX_ERR_NOMEM, QTX_ERR_HIP, QTX_ERR_UNSUPPORTED, QTX_ERR_SINGULAR, QTX_ERR_NONFINITE = range(7)
-QTX_FP64, QTX_FP32, QTX_BF16_SPLIT, QTX_FP16_SPLIT = range(4)
+QTX_FP64, QTX_FP32, QTX_BF16_SPLIT, QTX_FP16_SPLIT, QTX_INT8_OZAKI2 = range(5)
 QTX_S_IDENTITY = 1
 QTX_WANT_GREATER = 8
-PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16": QTX_FP16_SPLIT}
+PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16": QTX_FP16_SPLIT,
+              "int8": QTX_INT8_OZAKI2}
 
 EXPORTED = ("qtx_rgf_create", "qtx_rgf_solve", "qtx_rgf_destroy", "qtx_rgf_footprint", "qtx_status_str",
             "qtx_zgemm", "qtx_zinv", "qtx_rgf_observables", "qtx_rgf_profile", "qtx_rgf_profile_read",
-            "qtx_rgf_set_option", "qtx_rgf_get_stat")
+            "qtx_rgf_set_option", "qtx_rgf_get_stat", "qtx_ozaki2_bits")
 QTX_OPT_GRAPH, QTX_OPT_RESERVE_WORKSPACE = 1, 2
 QTX_STAT_GRAPH_LAUNCHES, QTX_STAT_GRAPH_CAPTURES, QTX_STAT_WORKSPACE_BYTES = 1, 2, 3
-QTX_KERNEL_GEMM, QTX_KERNEL_INV = 0, 1
+QTX_KERNEL_GEMM, QTX_KERNEL_INV, QTX_KERNEL_CONVERT = 0, 1, 2
 
 
 class QtxError(RuntimeError):
@@ -102,12 +103,25 @@ def load_library(path: str = LIB_PATH):
     lib.qtx_rgf_set_option.restype = ctypes.c_int
     lib.qtx_rgf_get_stat.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64)]
     lib.qtx_rgf_get_stat.restype = ctypes.c_int
+    lib.qtx_ozaki2_bits.argtypes = [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.qtx_ozaki2_bits.restype = ctypes.c_int
     _lib = lib
     return lib
 
 
 def status_str(code: int) -> str:
     return load_library().qtx_status_str(int(code)).decode()
+
+
+def ozaki2_bits(p: int, K: int):
+    """(moduli used, kbits) of the INT8 modular scheme asked for p moduli at
+    contraction length K (host computation, no device)."""
+    mods = (ctypes.c_int32 * max(p, 1))()
+    pu, kb = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = load_library().qtx_ozaki2_bits(int(p), int(K), mods, ctypes.byref(pu), ctypes.byref(kb))
+    if rc != QTX_OK:
+        raise QtxError(rc, "qtx_ozaki2_bits")
+    return [int(m) for m in mods[:pu.value]], int(kb.value)
 
 
 def _ptr(t):
