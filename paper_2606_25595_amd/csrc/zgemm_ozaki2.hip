@@ -225,25 +225,31 @@ __device__ inline void crt_fold(int c, double m, double im, double u, double& S)
 // of outstanding vector-memory operations.  Rows beyond M (N) load row M - 1
 // (N - 1): they only feed outputs that are never stored.
 constexpr int O2_BM = 128, O2_BN = 64, O2_NT = 512;
-constexpr int NSTAGE = 6;
-constexpr int STAGE_U4 = (O2_BM + O2_BN) * 8;   // 16-byte slots per stage (24 KB)
-constexpr int LPT = STAGE_U4 / O2_NT;           // loads per thread per strip (3)
+constexpr int SPI = 2;                          // strips per step
+constexpr int NSTAGE = 3;                       // ring stages (steps)
+constexpr int STRIP_U4 = (O2_BM + O2_BN) * 8;   // 16-byte slots per strip (24 KB)
+constexpr int STAGE_U4 = SPI * STRIP_U4;        // per stage (48 KB)
+constexpr int LPS = STRIP_U4 / O2_NT;           // copies per thread per strip (3: two of A rows, one of B rows)
+constexpr int LPT = SPI * LPS;                  // copies per thread per step (6)
+constexpr int kBufWord3 = 0x00020000;           // buffer descriptor word 3: raw 32-bit data, no swizzle
 
-// Four 16-byte LDS reads (byte addresses) that complete inside the block: the
-// compiler does not see them as LDS accesses, so it does not drain the pending
-// global->LDS loads of the other ring stages before them.
-__device__ inline void lds_read4(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, i4& r0, i4& r1, i4& r2,
-                                 i4& r3) {
-  asm volatile(
-      "ds_read_b128 %0, %4\n\t"
-      "ds_read_b128 %1, %5\n\t"
-      "ds_read_b128 %2, %6\n\t"
-      "ds_read_b128 %3, %7\n\t"
-      "s_waitcnt lgkmcnt(0)"
-      : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
-      : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
-      : "memory");
-}
+typedef __attribute__((address_space(3))) u4 lds_u4;
+typedef __attribute__((address_space(3))) double lds_f64;
+
+// Accumulators of one wave's 32 x 32 output block.
+struct O2Acc {
+  i16v arr, aii, ari;        // INT32 sums of the current modulus
+  double sre[16], sim[16];   // CRT sums (real, imaginary)
+};
+
+// Per-thread constants of the strip loop.
+struct O2Ctx {
+  int64_t off[LPS];          // byte offset (in A's or B's residues) of each of the thread's slots of a strip
+  int64_t sstride[LPS];      // bytes from one strip to the next
+  const lds_f64* cst;        // moduli, their reciprocals, the CRT factors u (LDS)
+  int tid, la, lb, lk, KT, K, NSTRIP;
+  bool wlive;
+};
 
 __device__ inline void lds_barrier() {
   asm volatile("" ::: "memory");
@@ -258,15 +264,114 @@ __device__ inline void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
-__global__ __launch_bounds__(O2_NT) void zgemm_o2_kernel(SplitGemmDesc g, O2Params P) {
+// One step s of the strip loop (s = -(NSTAGE-1) .. NSTEP-1; a step is SPI strips):
+// wait until step s's strips have landed (this thread's copies, then everyone's
+// via the barrier), start the copy of step s + NSTAGE - 1 into stage `dma` (the
+// stage step s - 1 used), then read step s's fragments from stage `rd` and feed
+// them to the matrix cores.  After the last strip of a modulus the INT32 sums
+// are folded into the CRT sums.  `rd` and `dma` are distinct restrict pointers
+// (as are the residue arrays), which gives the copies and the reads their own
+// alias scopes: the compiler's wait-count insertion then leaves the copies of
+// later steps in flight during the reads; their completion is awaited
+// explicitly.  Every thread issues exactly LPT copies per step (a step past the
+// last strip re-copies that strip into its unused half), so "step s landed" is a
+// fixed count of outstanding vector-memory operations.
+__device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u4* __restrict__ rd,
+                                                            lds_u4* __restrict__ dma, const int8_t* __restrict__ gA,
+                                                            const int8_t* __restrict__ gB, const O2Ctx& c, O2Acc& a) {
+  const int nstep = (c.NSTRIP + SPI - 1) / SPI;
+  if (s >= 0) {
+    if (s + 1 < nstep) wait_vm<LPT>();   // step s + 1 may still be pending
+    else wait_vm<0>();
+  }
+  lds_barrier();
+  const int sd = s + NSTAGE - 1;   // >= 0
+  if (sd < nstep) {
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void*)gA, 0, 0x7fffffff, kBufWord3);
+    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc((void*)gB, 0, 0x7fffffff, kBufWord3);
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) {
+      const int f = min(SPI * sd + q / LPS, c.NSTRIP - 1);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(q % LPS < LPS - 1 ? ra : rb,
+                                               (__attribute__((address_space(3))) void*)(dma + q * O2_NT + (c.tid & ~63)),
+                                               16, (int)(c.off[q % LPS] + (int64_t)f * c.sstride[q % LPS]), 0, 0, 0);
+    }
+  }
+  if (s < 0) return;
+#pragma unroll
+  for (int h = 0; h < SPI; ++h) {
+    const int f = SPI * s + h;
+    if (f >= c.NSTRIP) break;
+    const int i = f / c.KT;
+    const int kt = f - i * c.KT;
+    if (c.wlive) {
+      const lds_u4* st = rd + h * STRIP_U4;
+      const int sa = c.la & 7, sb = c.lb & 7;
+      i4 fr[8];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int w = 2 * t + c.lk;
+        fr[4 * t + 0] = __builtin_bit_cast(i4, st[c.la * 8 + (w ^ sa)]);
+        fr[4 * t + 1] = __builtin_bit_cast(i4, st[c.la * 8 + ((4 + w) ^ sa)]);
+        fr[4 * t + 2] = __builtin_bit_cast(i4, st[c.lb * 8 + (w ^ sb)]);
+        fr[4 * t + 3] = __builtin_bit_cast(i4, st[c.lb * 8 + ((4 + w) ^ sb)]);
+      }
+      a.arr = mfma_i8(fr[0], fr[2], a.arr);
+      a.aii = mfma_i8(fr[1], fr[3], a.aii);
+      a.ari = mfma_i8(fr[0], fr[3], a.ari);
+      a.ari = mfma_i8(fr[1], fr[2], a.ari);
+      if (!(kt == c.KT - 1 && c.K - kt * KS <= 32)) {   // a half strip at the end has one step
+        a.arr = mfma_i8(fr[4], fr[6], a.arr);
+        a.aii = mfma_i8(fr[5], fr[7], a.aii);
+        a.ari = mfma_i8(fr[4], fr[7], a.ari);
+        a.ari = mfma_i8(fr[5], fr[6], a.ari);
+      }
+    }
+    if (kt == c.KT - 1) {
+      const double m = c.cst[i], im = c.cst[kO2MaxModuli + i], u = c.cst[2 * kO2MaxModuli + i];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        crt_fold(a.arr[v] - a.aii[v], m, im, u, a.sre[v]);
+        crt_fold(a.ari[v], m, im, u, a.sim[v]);
+        a.arr[v] = 0; a.aii[v] = 0; a.ari[v] = 0;
+      }
+    }
+  }
+}
+
+// Persistent grid (persist = 1): one workgroup per CU; workgroup w runs on XCD
+// w % 8 and takes that XCD's tiles (a contiguous range) in rounds of the XCD's
+// workgroup count, so the workgroups sharing an L2 work on adjacent tiles of the
+// same energies in step and read each residue strip from HBM about once.
+// Otherwise one tile per workgroup.
+__global__ __launch_bounds__(O2_NT) void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
+                                                         int persist) {
   __shared__ u4 ring[NSTAGE][STAGE_U4];
   __shared__ int Ea[O2_BM], Eb[O2_BN];
+  __shared__ double cst[3 * kO2MaxModuli];
 
+  if (threadIdx.x < kO2MaxModuli) {
+    cst[threadIdx.x] = P.m[threadIdx.x];
+    cst[kO2MaxModuli + threadIdx.x] = P.inv_m[threadIdx.x];
+    cst[2 * kO2MaxModuli + threadIdx.x] = P.u[threadIdx.x];
+  }
   const GemmDesc& d = g.d;
   const int tiles_m = (d.M + O2_BM - 1) / O2_BM;
   const int tiles_n = (d.N + O2_BN - 1) / O2_BN;
   const int per = tiles_m * tiles_n;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  int first, last, step;
+  if (persist) {
+    const int nx = 8, x = blockIdx.x % nx, wpx = gridDim.x / nx;
+    const int tpx = (total_tiles + nx - 1) / nx;
+    first = x * tpx + (int)blockIdx.x / nx;
+    last = min((x + 1) * tpx, total_tiles);
+    step = wpx;
+  } else {
+    first = xcd_remap(blockIdx.x, gridDim.x);
+    last = first + 1;
+    step = 1;
+  }
+  for (int tile = first; tile < last; tile += step) {
   const int z = tile / per;
   const int t = tile - z * per;
   const int m0 = (t % tiles_m) * O2_BM;
@@ -289,77 +394,43 @@ __global__ __launch_bounds__(O2_NT) void zgemm_o2_kernel(SplitGemmDesc g, O2Para
   __syncthreads();   // also drains these loads before the counted ring loads start
 
   // Per-thread source of each of its LPT slots of a stage (the strip offset added
-  // per strip): slot c = q * 512 + tid; A rows first, then B rows.
-  const int8_t* src[LPT];
-  int64_t sstride[LPT];                     // bytes between consecutive strips
+  // per strip): slot cs = q * 512 + tid; A rows first, then B rows.
+  O2Ctx c;
 #pragma unroll
-  for (int q = 0; q < LPT; ++q) {
-    const int c = q * O2_NT + tid;
-    const int row = c >> 3, slot = c & 7;
+  for (int q = 0; q < LPS; ++q) {
+    const int cs = q * O2_NT + tid;
+    const int row = cs >> 3, slot = cs & 7;
     const int word = slot ^ (row & 7);
-    if (row < O2_BM) {
+    if (row < O2_BM) {   // q < LPS - 1: A rows
       const int rg = min(m0 + row, M - 1);
-      src[q] = SA + (int64_t)rg * 128 + 16 * word;
-      sstride[q] = (int64_t)M * 128;
+      c.off[q] = (int64_t)rg * 128 + 16 * word;
+      c.sstride[q] = (int64_t)M * 128;
     } else {
       const int rg = min(n0 + row - O2_BM, N - 1);
-      src[q] = SB + (int64_t)rg * 128 + 16 * word;
-      sstride[q] = (int64_t)N * 128;
+      c.off[q] = (int64_t)rg * 128 + 16 * word;
+      c.sstride[q] = (int64_t)N * 128;
     }
   }
-  auto issue = [&](int f) {   // strip f into stage f % NSTAGE
-    u4* dst = &ring[f % NSTAGE][0];
-#pragma unroll
-    for (int q = 0; q < LPT; ++q)
-      __builtin_amdgcn_global_load_lds((const void*)(src[q] + (int64_t)f * sstride[q]),
-                                       (__attribute__((address_space(3))) void*)(dst + q * O2_NT + (tid & ~63)),
-                                       16, 0, 0);
-  };
+  c.cst = (const lds_f64*)&cst[0];
+  c.tid = tid;
+  c.la = 32 * wm + (lane & 31);
+  c.lb = O2_BM + 32 * wn + (lane & 31);
+  c.lk = lane >> 5;
+  c.KT = KT;
+  c.K = K;
+  c.NSTRIP = NSTRIP;
+  c.wlive = wlive;
 
-  i16v arr, aii, ari;
-  double sre[16], sim[16];
+  O2Acc acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    arr[v] = 0; aii[v] = 0; ari[v] = 0;
-    sre[v] = 0.0; sim[v] = 0.0;
+    acc.arr[v] = 0; acc.aii[v] = 0; acc.ari[v] = 0;
+    acc.sre[v] = 0.0; acc.sim[v] = 0.0;
   }
-
-  const int la = 32 * wm + (lane & 31), lb = O2_BM + 32 * wn + (lane & 31), lk = lane >> 5;
-  const int sa = la & 7, sb = lb & 7;
-#pragma unroll
-  for (int f = 0; f < NSTAGE - 1; ++f)
-    if (f < NSTRIP) issue(f);
-  for (int f = 0; f < NSTRIP; ++f) {
-    if (f + NSTAGE - 2 < NSTRIP) wait_vm<LPT * (NSTAGE - 2)>();   // strip f landed (this thread's part)
-    else wait_vm<0>();
-    lds_barrier();                                                // ... and every thread's
-    if (f + NSTAGE - 1 < NSTRIP) issue(f + NSTAGE - 1);          // refills the stage read at f - 1
-    const uint32_t st = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) u4*)&ring[f % NSTAGE][0];
-    const int i = f / KT;
-    const int kt = f - i * KT;
-    if (wlive) {
-      const int nk = (kt == KT - 1 && K - kt * KS <= 32) ? 1 : 2;   // a half strip at the end
-      for (int s = 0; s < nk; ++s) {
-        const int w = 2 * s + lk;
-        i4 ar, ai, br, bi;
-        lds_read4(st + 16u * (la * 8 + (w ^ sa)), st + 16u * (la * 8 + ((4 + w) ^ sa)),
-                  st + 16u * (lb * 8 + (w ^ sb)), st + 16u * (lb * 8 + ((4 + w) ^ sb)), ar, ai, br, bi);
-        arr = mfma_i8(ar, br, arr);
-        aii = mfma_i8(ai, bi, aii);
-        ari = mfma_i8(ar, bi, ari);
-        ari = mfma_i8(ai, br, ari);
-      }
-    }
-    if (kt == KT - 1) {
-      const double m = P.m[i], im = P.inv_m[i], u = P.u[i];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        crt_fold(arr[v] - aii[v], m, im, u, sre[v]);
-        crt_fold(ari[v], m, im, u, sim[v]);
-        arr[v] = 0; aii[v] = 0; ari[v] = 0;
-      }
-    }
-  }
+  auto stage = [&](int f) { return (lds_u4*)&ring[(f + NSTAGE) % NSTAGE][0]; };   // f >= -NSTAGE
+  const int nstep = (NSTRIP + SPI - 1) / SPI;
+  for (int st = -(NSTAGE - 1); st < nstep; ++st)
+    o2_step(st, stage(st), stage(st + NSTAGE - 1), SA, SB, c, acc);
 
   // epilogue in FP64 (same addend semantics as the FP64 kernels)
   double2* __restrict__ C = d.tC ? d.tC[z] : d.C + (int64_t)z * d.sC;
@@ -373,29 +444,31 @@ __global__ __launch_bounds__(O2_NT) void zgemm_o2_kernel(SplitGemmDesc g, O2Para
     X[q] = d.add[q].tX ? d.add[q].tX[z] : (d.add[q].X ? d.add[q].X + (int64_t)z * d.add[q].stride : nullptr);
   }
   const double2 dg = d.diag_by_batch ? cmk(d.diag.x * bs, d.diag.y * bs) : d.diag;
-  if (!wlive) return;
-  const int c = n0 + lb - O2_BM;
+  const int lb = c.lb, lk = c.lk;
+  const int col = n0 + lb - O2_BM;
   const int eb = Eb[lb - O2_BM];
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int rl = 32 * wm + 8 * (v >> 2) + 4 * lk + (v & 3);
     const int r = m0 + rl;
-    if (r < M && c < N) {
+    if (wlive && r < M && col < N) {
       const double sc = pow2(Ea[rl] + eb - 2 * P.kbits - 2) * P.M;
-      const double cr = (sre[v] - rint(sre[v])) * sc;
-      const double ci = (sim[v] - rint(sim[v])) * sc;
+      const double cr = (acc.sre[v] - rint(acc.sre[v])) * sc;
+      const double ci = (acc.sim[v] - rint(acc.sim[v])) * sc;
       double2 out = cmul(d.alpha, cmk(cr, ci));
 #pragma unroll
       for (int q = 0; q < kMaxAddends; ++q) {
         if (X[q]) {
-          const double2 x = (d.add[q].op == OP_N) ? X[q][(int64_t)r * d.add[q].ld + c]
-                                                   : cconj(X[q][(int64_t)c * d.add[q].ld + r]);
+          const double2 x = (d.add[q].op == OP_N) ? X[q][(int64_t)r * d.add[q].ld + col]
+                                                   : cconj(X[q][(int64_t)col * d.add[q].ld + r]);
           out = cadd(out, cmul(coef[q], x));
         }
       }
-      if (r == c) out = cadd(out, dg);
-      C[(int64_t)r * d.ldc + c] = out;
+      if (r == col) out = cadd(out, dg);
+      C[(int64_t)r * d.ldc + col] = out;
     }
+  }
+  __syncthreads();   // Ea / Eb and the ring are reused by the next tile
   }
 }
 
@@ -480,7 +553,21 @@ hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
   const int64_t total = (int64_t)((d.M + O2_BM - 1) / O2_BM) * ((d.N + O2_BN - 1) / O2_BN) * d.batch;
   if (total > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(zgemm_o2_kernel, dim3((unsigned)total), dim3(O2_NT), 0, s, g, P);
+  if (o2_res_stride(d.M, d.K, P.p) > 0x7fffffff || o2_res_stride(d.N, d.K, P.p) > 0x7fffffff)
+    return hipErrorInvalidValue;   // per-entry residue offsets are 32-bit in the kernel
+  // one workgroup per CU (the kernel's LDS admits one) when there are more tiles
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cus[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 8;
+    cus[dev] = n;
+  }
+  const int grid_p = cus[dev] / 8 * 8;
+  const bool persist = grid_p >= 8 && total > grid_p;
+  const unsigned grid = persist ? (unsigned)grid_p : (unsigned)total;
+  hipLaunchKernelGGL(zgemm_o2_kernel, dim3(grid), dim3(O2_NT), 0, s, g, P, (int)total, persist ? 1 : 0);
   return hipGetLastError();
 }
 
