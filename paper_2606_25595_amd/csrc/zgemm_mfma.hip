@@ -236,6 +236,98 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
     }
 }
 
+// The inversion's trailing update C = X + A B with K <= BK (one operand tile,
+// A = Wp row-major M x K, B = Tp row-major K x N, the only addend X in C's own
+// layout).  It is bound by reading and rewriting X, so it is a single-tile
+// kernel without a K loop: the operand tiles are staged through LDS, then this
+// thread's X values are requested (in the registers the staging used) and arrive
+// while the MFMAs run.
+__global__ __launch_bounds__(NT) void zgemm_update_kernel(GemmDesc d) {
+  __shared__ double2 As[TILE_ELEMS];
+  __shared__ double2 Bs[TILE_ELEMS];
+  const int tiles_m = (d.M + BM - 1) / BM;
+  const int tiles_n = (d.N + BN - 1) / BN;
+  const int per = tiles_m * tiles_n;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int z = tile / per;
+  const int t = tile - z * per;
+  const int m0 = (t % tiles_m) * BM;
+  const int n0 = (t / tiles_m) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1, li = lane & 15, lk = lane >> 4;
+  const int M = d.M, N = d.N, K = d.K;
+  const double2* __restrict__ A = d.tA ? d.tA[z] : d.A + (int64_t)z * d.sA;
+  const double2* __restrict__ B = d.tB ? d.tB[z] : d.B + (int64_t)z * d.sB;
+  const double2* __restrict__ X = d.add[0].tX ? d.add[0].tX[z] : d.add[0].X + (int64_t)z * d.add[0].stride;
+  double2* __restrict__ C = d.tC ? d.tC[z] : d.C + (int64_t)z * d.sC;
+  bool rv[2], cv[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    rv[i] = m0 + 16 * (wm + 2 * i) < M;
+    cv[i] = n0 + 16 * (wn + 2 * i) < N;
+  }
+  {
+    TileLoader<BM, BK> la;
+    TileLoader<BK, BN> lb;
+    la.load(A, d.lda, m0, 0, M, K, tid);
+    lb.load(B, d.ldb, 0, n0, K, N, tid);
+    la.template store<false, MathF64>(As, RS_WIDE, tid);
+    lb.template store<false, MathF64>(Bs, RS_LONG, tid);
+  }
+  double2 x[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + 16 * (wm + 2 * i) + MathF64::row(lk, v);
+        const int c = n0 + 16 * (wn + 2 * j) + li;
+        x[i][j][v] = (rv[i] && cv[j] && r < M && c < N) ? X[(int64_t)r * d.add[0].ld + c] : cmk(0.0, 0.0);
+      }
+  __syncthreads();
+  d4 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc_re[i][j] = MathF64::zero();
+      acc_im[i][j] = MathF64::zero();
+    }
+#pragma unroll
+  for (int kk = 0; kk < BK; kk += 4) {
+    const int kr = kk + lk;
+    double2 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      a[i] = As[(16 * (wm + 2 * i) + li) * RS_WIDE + kr];
+      b[i] = Bs[kr * RS_LONG + 16 * (wn + 2 * i) + li];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        if (rv[i] && cv[j]) {
+          acc_re[i][j] = MathF64::mfma(a[i].x, b[j].x, acc_re[i][j]);
+          acc_im[i][j] = MathF64::mfma(a[i].x, b[j].y, acc_im[i][j]);
+          acc_re[i][j] = MathF64::mfma(-a[i].y, b[j].y, acc_re[i][j]);
+          acc_im[i][j] = MathF64::mfma(a[i].y, b[j].x, acc_im[i][j]);
+        }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (!(rv[i] && cv[j])) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + 16 * (wm + 2 * i) + MathF64::row(lk, v);
+        const int c = n0 + 16 * (wn + 2 * j) + li;
+        if (r < M && c < N) C[(int64_t)r * d.ldc + c] = cmk(x[i][j][v].x + acc_re[i][j][v], x[i][j][v].y + acc_im[i][j][v]);
+      }
+    }
+}
+
 }  // namespace
 
 template <int KIND, class MATH>
@@ -257,7 +349,13 @@ static hipError_t launch_zgemm_mfma(const GemmDesc& d, hipStream_t s, int kind, 
     e.opA = OP_N; e.opB = OP_N;
     launch_kind<GEMM_ELEMENTWISE, MathF64>(e, grid, block, s);
   } else if (kind == GEMM_INV_UPDATE) {
-    launch_kind<GEMM_INV_UPDATE, MathF64>(d, grid, block, s);
+    // contract of the update form: C = X + A B, op N, K <= BK, X the only addend (op N)
+    if (d.K > BK || d.opA != OP_N || d.opB != OP_N || d.alpha.x != 1.0 || d.alpha.y != 0.0 ||
+        (!d.add[0].X && !d.add[0].tX) || d.add[0].op != OP_N || d.add[0].coef.x != 1.0 || d.add[0].coef.y != 0.0 ||
+        d.add[0].scale_by_batch || d.add[1].X || d.add[1].tX || d.add[2].X || d.add[2].tX || d.diag.x != 0.0 ||
+        d.diag.y != 0.0)
+      return hipErrorInvalidValue;
+    hipLaunchKernelGGL(zgemm_update_kernel, grid, block, 0, s, d);
   } else if (fp32) {
     launch_kind<GEMM_PRODUCT, MathF32>(d, grid, block, s);
   } else {

@@ -183,6 +183,185 @@ __global__ __launch_bounds__(PT) void gje_panel_kernel(int n, int k0, double2* X
   if (tid == 0 && singular && status) status[z] = 5;   // QTX_ERR_SINGULAR
 }
 
+// ---- 32-column panel (n <= 512) --------------------------------------------
+// Same elimination as gje_panel_kernel, organised for a short pivot step:
+//  * the column loop is 8 rolled groups of 4 unrolled columns, so the current
+//    column is picked with an 8-way select and only 8 columns need the
+//    "is this the pivot column" select;
+//  * every row is updated with one formula, v <- s v - m pr, where s = 0 and
+//    m = -1/pivot for the pivot row (which turns into pr / pivot) and s = 1,
+//    m = v_k / pivot for the others; the pivot column then takes the transform
+//    entry (1/pivot, resp. -v_k / pivot);
+//  * 256 threads hold two rows each (one wave per SIMD, so the panel and the
+//    update's temporaries fit the register file);
+//  * the pivot search reduces (|re| + |im|, row) over each thread's rows, then
+//    within 16-lane groups with DPP moves; each group's winner puts its whole row
+//    in LDS next to its candidate, so after a single barrier every thread picks
+//    the best of the 16 candidates and reads the pivot row directly.
+template <int CTRL>
+__device__ inline void argmax_dpp(double& m, int& i) {
+  const int2 mb = __builtin_bit_cast(int2, m);
+  int2 ob;
+  ob.x = __builtin_amdgcn_update_dpp(0, mb.x, CTRL, 0xF, 0xF, false);
+  ob.y = __builtin_amdgcn_update_dpp(0, mb.y, CTRL, 0xF, 0xF, false);
+  const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
+  const double om = __builtin_bit_cast(double, ob);
+  if (om > m || (om == m && oi < i)) { m = om; i = oi; }
+}
+__device__ inline void argmax_row16(double& m, int& i) {
+  argmax_dpp<0xB1>(m, i);    // quad_perm [1,0,3,2]
+  argmax_dpp<0x4E>(m, i);    // quad_perm [2,3,0,1]
+  argmax_dpp<0x141>(m, i);   // row_half_mirror
+  argmax_dpp<0x140>(m, i);   // row_mirror
+}
+
+constexpr int PT32 = 256;   // threads of the 32-column panel kernel (one wave per SIMD)
+
+__global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double2* X, int64_t sX, GjeWork w,
+                                                           int32_t* status) {
+  constexpr int NB = 32, RPT = 2, NG = PT32 / 16, GW = 4;   // GW: unrolled columns per group
+  const int z = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nbw = min(NB, n - k0);
+  double2* __restrict__ Xz = X + (int64_t)z * sX;
+  int32_t* __restrict__ prow = w.prow + (int64_t)z * n;
+  int32_t* __restrict__ used = w.used + (int64_t)z * n;
+
+  __shared__ double2 cand_row[2][NG][NB];
+  __shared__ double cand_mag[2][NG];
+  __shared__ int cand_idx[2][NG];
+  __shared__ int piv_of[NB];
+
+  bool u[RPT];
+  int pivcol[RPT];
+  double2 v[RPT][NB];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int r = tid + PT32 * j;
+    u[j] = (r >= n) || (used[r] != 0);
+    pivcol[j] = -1;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) v[j][c] = (r < n && c < nbw) ? Xz[(int64_t)r * n + k0 + c] : cmk(0.0, 0.0);
+  }
+  bool singular = false;
+
+  for (int kg = 0; kg < NB / GW; ++kg) {
+#pragma unroll
+    for (int kk = 0; kk < GW; ++kk) {
+      const int k = GW * kg + kk;
+      if (k < nbw) {   // uniform
+        const int buf = k & 1;
+        double2 ck[RPT];
+        double mag = -1.0;
+        int idx = 0x7fffffff;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          ck[j] = v[j][kk];
+#pragma unroll
+          for (int g = 1; g < NB / GW; ++g)
+            if (g == kg) ck[j] = v[j][GW * g + kk];
+          if (!u[j]) {   // rows increase with j: strict > keeps the lower row on ties
+            double mg = fabs(ck[j].x) + fabs(ck[j].y);
+            if (mg != mg) mg = __builtin_huge_val();   // a NaN row is taken (its NaN propagates)
+            if (mg > mag) { mag = mg; idx = tid + PT32 * j; }
+          }
+        }
+        argmax_row16(mag, idx);
+        const int grp = tid >> 4;
+        if ((lane & 15) == 0) { cand_mag[buf][grp] = mag; cand_idx[buf][grp] = idx; }
+#pragma unroll
+        for (int j = 0; j < RPT; ++j)
+          if (idx == tid + PT32 * j) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) cand_row[buf][grp][c] = v[j][c];
+          }
+        __syncthreads();
+        // best of the NG candidates: lane l looks at candidate l % NG
+        double pm = cand_mag[buf][lane % NG];
+        int p = cand_idx[buf][lane % NG];
+        argmax_row16(pm, p);
+        // p is an unused row while k0 + k < n; pm == 0 means singular.  Defensive clamp only.
+        if ((unsigned)p >= (unsigned)n) p = 0;
+        const int pg = (p % PT32) >> 4;
+        const double2 pv = cand_row[buf][pg][k];
+        const double2 dinv = (pv.x == 0.0 && pv.y == 0.0) ? cmk(1.0, 0.0) : cinv(pv);
+        double s[RPT];
+        double2 m[RPT], newk[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          const bool isp = (tid + PT32 * j == p);
+          const double2 fd = cmul(ck[j], dinv);
+          s[j] = isp ? 0.0 : 1.0;
+          m[j] = isp ? cmk(-dinv.x, -dinv.y) : fd;
+          newk[j] = isp ? dinv : cmk(-fd.x, -fd.y);
+          if (isp) { u[j] = true; pivcol[j] = k; }
+        }
+#pragma unroll
+        for (int c8 = 0; c8 < NB; c8 += 8) {
+          double2 pr[8];   // 8 pivot-row entries at a time
+#pragma unroll
+          for (int q = 0; q < 8; ++q) pr[q] = cand_row[buf][pg][c8 + q];
+#pragma unroll
+          for (int j = 0; j < RPT; ++j)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int c = c8 + q;
+              double2 nv;
+              nv.x = fma(s[j], v[j][c].x, -fma(m[j].x, pr[q].x, -m[j].y * pr[q].y));
+              nv.y = fma(s[j], v[j][c].y, -fma(m[j].x, pr[q].y, m[j].y * pr[q].x));
+              if (c % GW == kk && c / GW == kg) nv = newk[j];
+              v[j][c] = nv;
+            }
+          asm volatile("" ::: "memory");
+        }
+        if (tid == 0) {
+          piv_of[k] = p;
+          prow[k0 + k] = p;
+        }
+        singular = singular || !(pm > 0.0);
+      }
+      asm volatile("" ::: "memory");   // one step's temporaries die here
+    }
+  }
+  __syncthreads();
+
+  // write back the panel, the shifted transform Wp and the usage flags
+  double2* __restrict__ Wp = w.Wp + (int64_t)z * n * NB;
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int r = tid + PT32 * j;
+    if (r < n) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        if (c < nbw) Xz[(int64_t)r * n + k0 + c] = v[j][c];
+        double2 wv = (c < nbw) ? v[j][c] : cmk(0.0, 0.0);
+        if (c == pivcol[j]) wv.x -= 1.0;
+        Wp[(int64_t)r * NB + c] = wv;
+      }
+      if (pivcol[j] >= 0) used[r] = 1;
+    }
+  }
+  // pivot rows of this panel (pre-update values outside the panel), panel columns
+  // zeroed; 8 loads in flight per thread before their stores
+  double2* __restrict__ Tp = w.Tp + (int64_t)z * NB * n;
+  for (int base = 0; base < NB * n; base += PT32 * 8) {
+    double2 val[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = base + PT32 * q + tid;
+      const int k = idx / n, c = idx - k * n;
+      val[q] = cmk(0.0, 0.0);
+      if (idx < NB * n && k < nbw && (c < k0 || c >= k0 + nbw)) val[q] = Xz[(int64_t)piv_of[k] * n + c];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = base + PT32 * q + tid;
+      if (idx < NB * n) Tp[idx] = val[q];
+    }
+  }
+  if (tid == 0 && singular && status) status[z] = 5;   // QTX_ERR_SINGULAR
+}
+
 __global__ void gje_reset_kernel(int n, int batch, int32_t* used) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < (int64_t)n * batch) used[i] = 0;
@@ -255,7 +434,7 @@ hipError_t launch_gje_invert(int n, double2* X, int64_t sX, double2* Out, int64_
     hipLaunchKernelGGL(gje_reset_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, batch, w.used);
   }
   for (int k0 = 0; k0 < n; k0 += nb) {
-    if (nb == 32) hipLaunchKernelGGL((gje_panel_kernel<32, 1>), dim3(batch), dim3(PT), 0, s, n, k0, X, sX, w, status);
+    if (nb == 32) hipLaunchKernelGGL(gje_panel32_kernel, dim3(batch), dim3(PT32), 0, s, n, k0, X, sX, w, status);
     else hipLaunchKernelGGL((gje_panel_kernel<16, 2>), dim3(batch), dim3(PT), 0, s, n, k0, X, sX, w, status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
