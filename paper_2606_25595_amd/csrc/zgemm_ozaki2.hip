@@ -117,60 +117,63 @@ __global__ __launch_bounds__(NT) void o2_residue_kernel(SplitDesc sd, O2Params P
 // so the 8 rows of one k fall in distinct banks), finds the row exponents, and
 // writes every (modulus, strip) block of those rows: 8 rows x 2 planes x 64 bytes
 // = 1 KB contiguous, one 16-byte store per lane of a wave (lane -> row l / 8,
-// plane (l / 4) % 2, k = 16 (l % 4) .. +15 of the strip).
+// plane (l / 4) % 2, k = 16 (l % 4) .. +15 of the strip); wave w converts strips
+// w, w + 8, ...
 constexpr int kO2FusedRows = 8;
 constexpr int kO2FusedMaxK = 512;   // 8 rows x 512 x 16 B = 64 KB of LDS
 
-__global__ __launch_bounds__(NT) void o2_convert_kernel(SplitDesc sd, O2Params P) {
+constexpr int CT = 512;   // threads of the conversion kernel (8 waves: one per row, one per strip)
+
+__global__ __launch_bounds__(CT) void o2_convert_kernel(SplitDesc sd, O2Params P) {
   extern __shared__ double2 rows_lds[];   // [RB][KP], KP = KT * 64 (zero-padded), swizzled
   constexpr int RB = kO2FusedRows;
   const int z = blockIdx.y, r0 = blockIdx.x * RB, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int K = sd.cols, KT = (K + KS - 1) / KS, KP = KT * KS, pitch = KP;
   const double2* X = sd.tX ? sd.tX[z] : sd.X + (int64_t)z * sd.stride;
-  // load (zero outside rows x K, conjugate on the way in): thread t takes row t / 32
+  // load (zero outside rows x K, conjugate on the way in): thread t takes row t / 64
   // (trans 0: rows contiguous) or t % 8 (trans 1: 8 adjacent columns of X = 128
-  // bytes), and k = its base + 32 j; all loads are issued before the LDS stores.
+  // bytes), and k = its base + 64 j; all loads are issued before the LDS stores.
   {
-    const int r = sd.trans ? (tid & 7) : (tid >> 5);
-    const int kb = sd.trans ? (tid >> 3) : (tid & 31);
+    const int r = sd.trans ? (tid & 7) : (tid >> 6);
+    const int kb = sd.trans ? (tid >> 3) : (tid & 63);
     const bool rok = r0 + r < sd.rows;
-    const int nj = KP / 32;   // <= 16
-    double2 v[kO2FusedMaxK / 32];
+    const int nj = KP / 64;   // <= 8
+    double2 v[kO2FusedMaxK / 64];
 #pragma unroll
-    for (int j = 0; j < kO2FusedMaxK / 32; ++j) {
-      const int k = kb + 32 * j;
+    for (int j = 0; j < kO2FusedMaxK / 64; ++j) {
+      const int k = kb + 64 * j;
       v[j] = cmk(0.0, 0.0);
       if (j < nj && rok && k < K)
         v[j] = sd.trans ? X[(int64_t)k * sd.ld + r0 + r] : X[(int64_t)(r0 + r) * sd.ld + k];
     }
 #pragma unroll
-    for (int j = 0; j < kO2FusedMaxK / 32; ++j) {
-      const int k = kb + 32 * j;
+    for (int j = 0; j < kO2FusedMaxK / 64; ++j) {
+      const int k = kb + 64 * j;
       if (j < nj) rows_lds[r * pitch + (k ^ r)] = sd.conj ? cconj(v[j]) : v[j];
     }
   }
   __syncthreads();
-  // row exponents: 32 threads per row
+  // row exponents: wave w reduces row w
   {
-    const int r = tid >> 5, q = tid & 31;
+    const int r = wave;
     double mx = 0.0;
-    for (int k = q; k < KP; k += 32) {
+    for (int k = lane; k < KP; k += 64) {
       const double2 v = rows_lds[r * pitch + k];   // any order: all k of the row
       mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
     }
 #pragma unroll
-    for (int o = 16; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
     int e = 0;
     if (mx > 0.0 && mx <= 1.7e308) e = ilogb(mx) + 2;   // max * 2^-e in [1/4, 1/2)
-    if (q == 0 && r0 + r < sd.rows) sd.E[(int64_t)z * sd.e_stride + r0 + r] = e;
+    if (lane == 0 && r0 + r < sd.rows) sd.E[(int64_t)z * sd.e_stride + r0 + r] = e;
   }
   __syncthreads();   // the exponents are read back below (same workgroup)
-  const int lane = tid & 63, wave = tid >> 6;
   const int r = lane >> 3, c = (lane >> 2) & 1, ks = lane & 3;
   const bool live = r0 + r < sd.rows;
   const double sc = live ? pow2(P.kbits + 1 - sd.E[(int64_t)z * sd.e_stride + r0 + r]) : 0.0;
   int8_t* out = (int8_t*)sd.S + (int64_t)z * sd.s_stride;
-  for (int kt = wave; kt < KT; kt += NT / 64) {
+  for (int kt = wave; kt < KT; kt += CT / 64) {
     double a[16];
     const double2* src = rows_lds + r * pitch;
     const int k0 = kt * KS + 16 * ks;
@@ -537,7 +540,7 @@ hipError_t launch_o2_convert(const SplitDesc& sd, const O2Params& P, hipStream_t
   if (sd.cols <= kO2FusedMaxK) {
     const int KP = (sd.cols + KS - 1) / KS * KS;
     const size_t lds = (size_t)kO2FusedRows * KP * sizeof(double2);
-    hipLaunchKernelGGL(o2_convert_kernel, dim3((sd.rows + kO2FusedRows - 1) / kO2FusedRows, sd.batch), dim3(NT),
+    hipLaunchKernelGGL(o2_convert_kernel, dim3((sd.rows + kO2FusedRows - 1) / kO2FusedRows, sd.batch), dim3(CT),
                        lds, s, sd, P);
     return hipGetLastError();
   }
