@@ -267,18 +267,23 @@ class Context:
         self.close()
 
     # -- qtx_rgf_solve
-    def solve(self, problems, prec="fp64", n_slices: int = 0, stream=None, check: bool = True,
-              prec_lesser=None, n_slices_lesser: int = -1) -> int:
+    def solve(self, problems, prec="fp64", n_slices=0, stream=None, check: bool = True,
+              prec_lesser=None, n_slices_lesser=-1) -> int:
         """prec / n_slices: scheme of the retarded-chain products; prec_lesser /
-        n_slices_lesser: scheme of the lesser-chain products (None = same)."""
+        n_slices_lesser: scheme of the lesser-chain products (None = same).  Each
+        may be one value for all problems or a list with one per problem."""
         if isinstance(problems, DeviceProblem):
             problems = [problems]
-        precs = prec if isinstance(prec, (list, tuple)) else [prec] * len(problems)
-        pl = -1 if prec_lesser is None else PREC_NAMES.get(prec_lesser, prec_lesser)
-        arr = (_Problem * len(problems))()
+        n = len(problems)
+
+        def per(x):
+            return list(x) if isinstance(x, (list, tuple)) else [x] * n
+        precs, nss, pls, nsls = per(prec), per(n_slices), per(prec_lesser), per(n_slices_lesser)
+        arr = (_Problem * n)()
         keep = []
-        for k, (dp, pr) in enumerate(zip(problems, precs)):
-            st, en = _problem_struct(dp, PREC_NAMES.get(pr, pr), n_slices, pl, n_slices_lesser)
+        for k, dp in enumerate(problems):
+            pl = -1 if pls[k] is None else PREC_NAMES.get(pls[k], pls[k])
+            st, en = _problem_struct(dp, PREC_NAMES.get(precs[k], precs[k]), nss[k], pl, nsls[k])
             arr[k] = st
             keep.append(en)
         rc = self.lib.qtx_rgf_solve(self.handle, arr, len(problems), _stream_ptr(stream))

@@ -100,3 +100,30 @@ def test_batch_mixed_precision_per_problem(ctx):
         tol = 1e-10 if q % 2 == 0 else 1e-7
         for k in KEYS:
             assert oracle.rel_fro_err(out[k], ref[k]).max() <= tol, (q, k)
+
+
+def test_batch_per_problem_scheme_lists(ctx):
+    """Every scheme field may differ per problem, the lesser-chain scheme included;
+    each problem's result equals that of solving it alone with its own scheme."""
+    import torch
+    from paper_2606_25595_amd import qtx
+    probs = mixed_problems(seed=8, count=5)
+    sch = [dict(prec="fp64"), dict(prec="int8", n_slices=11), dict(prec="int8", n_slices=10, prec_lesser="int8",
+           n_slices_lesser=11), dict(prec="bf16", n_slices=5, prec_lesser="fp64"), dict(prec="int8", n_slices=9)]
+    dps = [qtx.to_device(p) for p in probs]
+    ctx.solve(dps, prec=[x["prec"] for x in sch], n_slices=[x.get("n_slices", 0) for x in sch],
+              prec_lesser=[x.get("prec_lesser") for x in sch],
+              n_slices_lesser=[x.get("n_slices_lesser", -1) for x in sch])
+    torch.cuda.synchronize()
+    tols = [1e-10, 1e-7, 1e-6, 1e-7, 1e-5]
+    for q, (p, dp, x) in enumerate(zip(probs, dps, sch)):
+        out = dp.outputs()
+        ref = oracle.rgf_selected(p)
+        for k in KEYS:
+            assert oracle.rel_fro_err(out[k], ref[k]).max() <= tols[q], (q, k)
+        alone = qtx.to_device(p)
+        ctx.solve(alone, **x)
+        torch.cuda.synchronize()
+        ao = alone.outputs()
+        for k in KEYS:
+            assert np.array_equal(ao[k], out[k]), (q, k)

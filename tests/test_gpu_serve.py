@@ -63,6 +63,16 @@ def test_mix_equals_alone_and_matches_oracle(gpu):
             assert oracle.rel_fro_err(r.blocks[k], ref[k]).max() <= 1e-10, (r.rid, k)
         T = oracle.transmission_left(ref["GR_d"][:, 0], 2.0 * 0.5 * np.eye(r.b))
         np.testing.assert_allclose(r.T_L, T, rtol=1e-9, atol=1e-12)
+    # mixed-precision requests meet the 1e-6 bar
+    mixed = [q for q in reqs if q.precision == "mixed"][:3]
+    assert mixed
+    for r in mixed:
+        sr, sl = inputs.random_bt_scalars(r.n_b, r.energies)
+        p = inputs.BTProblem(energies=r.energies, H_d=r.blocks["H_d"], H_u=r.blocks["H_u"], H_l=r.blocks["H_l"],
+                             SR_d=inputs._diag_blocks(sr, r.b), SL_d=inputs._diag_blocks(sl, r.b))
+        ref = oracle.rgf_selected(p)
+        for k in KEYS:
+            assert oracle.rel_fro_err(r.blocks[k], ref[k]).max() <= 1e-6, (r.rid, k)
 
 
 def test_budget_bounds_admission(gpu):
