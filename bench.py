@@ -55,6 +55,25 @@ def parse_scheme(spec):
     return kw
 
 
+def autotune(ctx, skw, shapes):
+    """Autotuner pass (outside any timed region): for each INT8 scheme of `skw`
+    (retarded and lesser chain) and each (b, batch) in `shapes`, time the product
+    kernel's tile variants and keep the fastest in the context."""
+    out = {}
+    chains = [(skw["prec"], skw.get("n_slices", 0))]
+    if skw.get("prec_lesser"):
+        chains.append((skw["prec_lesser"], skw.get("n_slices_lesser", 0)))
+    for prec, ns in sorted(set(chains)):
+        if prec != "int8":
+            continue
+        for b, batch in shapes:
+            v, ms = ctx.tune(b, prec, ns, batch=batch)
+            out["%s:%d b=%d batch=%d" % (prec, ns, b, batch)] = {"variant": v, "ms_per_product": [round(t, 4) for t in ms]}
+            log("bench: autotune %s:%d b=%d batch=%d -> variant %d (%s ms)" % (prec, ns, b, batch, v,
+                                                                                 " ".join("%.3f" % t for t in ms)))
+    return out
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -154,8 +173,10 @@ def main():
                          "numpy/LAPACK FP64, %.1f s" % (len(sample), n_e // len(sample), t_cpu)}
 
     results = {}
+    tuned = {}
     for prec in args.precs.split(","):
         skw = parse_scheme(prec)
+        tuned.update(autotune(ctx, skw, [(b, n_e)]))
         log("bench: %s warmup x%d" % (prec, args.warmup))
         for _ in range(args.warmup):
             ctx.solve(dp, **skw)
@@ -245,6 +266,7 @@ def main():
                         "inversion_ms_per_step": v["inv"][0] / args.steps}
                     for p, v in results.items()},
         "fp64_energies_per_s": results["fp64"]["value"] if "fp64" in results else None,
+        "autotune": tuned,
         "algorithmic_tflops_fp64eq": (144 * (n_b - 1) + 24) * b ** 3 * n_e / (r["ms_per_step"] / 1e3) / 1e12,
     }
     print(json.dumps(line), flush=True)
@@ -285,6 +307,10 @@ def bench_batch(args):
     torch.cuda.synchronize()
     skw = parse_scheme(args.prec)
     ctx = qtx.Context(0)
+    counts = {}
+    for b, _, _ in spec:
+        counts[b] = counts.get(b, 0) + 1
+    tuned = autotune(ctx, skw, sorted(counts.items()))
     ctx.set_graph(True)
     stream = torch.cuda.Stream()
     flops = sum((144 * (nb - 1) + 24) * b ** 3 for b, nb, _ in spec)
@@ -323,7 +349,7 @@ def bench_batch(args):
             "fp64eq_tflops": flops / t / 1e12, "first_call_ms": t_first * 1e3, "status_ok": ok,
             "graph_captures": ctx.stat(qtx.QTX_STAT_GRAPH_CAPTURES),
             "graph_launches": ctx.stat(qtx.QTX_STAT_GRAPH_LAUNCHES),
-            "sampled_max_rel_err": errs, "sampled_problems": len(sample)}
+            "sampled_max_rel_err": errs, "sampled_problems": len(sample), "autotune": tuned}
     print(json.dumps(line), flush=True)
     ctx.close()
 

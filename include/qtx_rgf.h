@@ -139,7 +139,9 @@ typedef struct {
 /* Create a context on HIP device `device`.  workspace_bytes caps the device
  * workspace the context may hold (0 = automatic: up to 1/4 of the device's
  * free memory at the first solve); energies are processed in chunks that fit.
- * tune_cache_path: optional JSON file of tile choices (may be NULL).
+ * tune_cache_path: optional text file of autotuner choices (may be NULL): read
+ * here when it exists and was written for the same device kind, rewritten by
+ * qtx_rgf_tune.
  * Returns QTX_ERR_ARG for a NULL `out` or an invalid device. */
 qtx_status qtx_rgf_create(qtx_rgf_ctx* out, int device, size_t workspace_bytes,
                           const char* tune_cache_path);
@@ -165,14 +167,44 @@ qtx_status qtx_rgf_solve(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int32_t 
  *                  and replays it with one graph launch on later identical calls
  *                  (same problem structs, energies and workspace).  Needs a
  *                  non-NULL stream; with the NULL stream the solve runs eagerly.
- * Counters (qtx_rgf_get_stat): graph launches, graph captures, workspace bytes.
+ * Counters (qtx_rgf_get_stat): graph launches, graph captures, workspace bytes,
+ * autotuner records held.
  *   QTX_OPT_RESERVE_WORKSPACE  value = bytes: allocate the device workspace now
  *                  (grows only; for callers that must claim memory before other
- *                  allocators do).  Returns QTX_ERR_NOMEM if it cannot. */
-enum { QTX_OPT_GRAPH = 1, QTX_OPT_RESERVE_WORKSPACE = 2 };
-enum { QTX_STAT_GRAPH_LAUNCHES = 1, QTX_STAT_GRAPH_CAPTURES = 2, QTX_STAT_WORKSPACE_BYTES = 3 };
+ *                  allocators do).  Returns QTX_ERR_NOMEM if it cannot.
+ *   QTX_OPT_INT8_TILE_VARIANT  value = -1 (default): INT8 products take the tile
+ *                  variant the autotuner recorded for their shape, else a default
+ *                  from the shape (64 x 64 tiles three per CU when K >= 256 and
+ *                  there are >= 512 such tiles, else 64 x 64 tiles two per CU);
+ *                  value = 0 .. count-1: every INT8 product uses that variant.
+ *                  All variants give bitwise the same results. */
+enum { QTX_OPT_GRAPH = 1, QTX_OPT_RESERVE_WORKSPACE = 2, QTX_OPT_INT8_TILE_VARIANT = 3 };
+enum { QTX_STAT_GRAPH_LAUNCHES = 1, QTX_STAT_GRAPH_CAPTURES = 2, QTX_STAT_WORKSPACE_BYTES = 3,
+       QTX_STAT_TUNE_RECORDS = 4 };
 qtx_status qtx_rgf_set_option(qtx_rgf_ctx ctx, int option, int64_t value);
 qtx_status qtx_rgf_get_stat(qtx_rgf_ctx ctx, int stat, int64_t* value);
+
+/* Autotuner.  Times every tile variant of the product kernel that the scheme
+ * (prec, n_slices) uses on synthetic complex b x b x b products over `batch`
+ * entries (deterministic pseudo-random operands in [-1, 1)), 1 warm-up and 3 timed
+ * products each on hip_stream, and records the fastest for the shape (b, b, b),
+ * the batch class ceil(log2(batch)) (classes 0..9) and the modulus count used.
+ * Later products of that shape and modulus count (in qtx_rgf_solve and qtx_zgemm)
+ * take the recorded variant, from the record of the nearest batch class; cached
+ * hipGraphs are dropped.  The table is written to
+ * the context's tune_cache_path when one was given (QTX_ERR_ARG if that write
+ * fails; the record is kept).  Only the INT8 scheme has variants (5: a 128 x 64
+ * tile with one workgroup per CU, 64 x 64 tiles with two or three per CU); for
+ * the other schemes nothing is timed, *out_count = 1 and *out_variant = 0.
+ *   out_variant  chosen variant (nullable)
+ *   out_ms       ms per product (operand conversion included) of each variant,
+ *                up to max_variants entries (nullable when max_variants = 0)
+ *   out_count    number of variants (nullable)
+ * Allocates and frees three b*b*batch complex128 buffers and synchronizes
+ * hip_stream.  b in 1..1024, batch >= 1; QTX_ERR_NOMEM if the buffers do not fit. */
+qtx_status qtx_rgf_tune(qtx_rgf_ctx ctx, int32_t b, int32_t prec, int32_t n_slices, int32_t batch,
+                        void* hip_stream, int32_t* out_variant, double* out_ms, int32_t max_variants,
+                        int32_t* out_count);
 
 /* Free the context and its workspace (synchronizes the device first). */
 qtx_status qtx_rgf_destroy(qtx_rgf_ctx ctx);

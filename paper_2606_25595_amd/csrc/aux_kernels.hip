@@ -11,6 +11,20 @@ __global__ void fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
+// Deterministic pseudo-random complex values in [-1, 1) x [-1, 1) (an integer
+// hash of the index and seed; synthetic operands for timing runs).
+__device__ inline uint32_t mix32(uint32_t x) {
+  x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;
+  return x;
+}
+__global__ void fill_hash_kernel(double2* p, int64_t n, uint32_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t h = mix32((uint32_t)i ^ mix32(seed ^ (uint32_t)(i >> 32)));
+  const uint32_t g = mix32(h ^ 0x9e3779b9U);
+  p[i] = make_double2((double)(h >> 8) * (1.0 / 8388608.0) - 1.0, (double)(g >> 8) * (1.0 / 8388608.0) - 1.0);
+}
+
 // Fill the per_batch elements of batch entry z with NaN when status[z] != 0.
 __global__ void nan_fill_kernel(double2* X, int64_t per_batch, int64_t stride, const int32_t* status) {
   const int z = blockIdx.y;
@@ -101,6 +115,12 @@ __global__ __launch_bounds__(256) void observables_kernel(int b, const double2* 
 }
 
 }  // namespace
+
+hipError_t launch_fill_hash(double2* p, int64_t n, uint32_t seed, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_hash_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, seed);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;

@@ -56,6 +56,15 @@ struct GraphCacheEntry {
   hipGraphExec_t exec = nullptr;
 };
 
+// Autotuner record: the tile variant of the INT8 product kernel chosen for one
+// product shape (M, N, K), batch class and modulus count, with the measured ms
+// per variant.
+struct TuneRec {
+  int variant = 0;
+  std::vector<double> ms;
+};
+typedef std::tuple<int, int, int, int, int> TuneKey;   // M, N, K, batch class, moduli
+
 struct qtx_rgf_ctx_s {
   int device = 0;
   size_t ws_cap = 0;       // 0 = automatic
@@ -63,6 +72,8 @@ struct qtx_rgf_ctx_s {
   size_t ws_size = 0;
   qtx_status sticky = QTX_OK;
   std::string tune_path;
+  std::map<TuneKey, TuneRec> tune;
+  int o2_force = -1;       // >= 0: every INT8 product uses this tile variant
   bool profiling = false;
   bool use_graph = false;
   bool capturing = false;
@@ -283,6 +294,32 @@ SplitBufs carve_split(char*& w, int b, const Scheme& sc, int batch) {
   return sb;
 }
 
+// Batch class of the autotuner: ceil(log2(batch)), 0 .. 9 (512 and more share one).
+int batch_class(int batch) {
+  int c = 0;
+  while (c < 9 && (1 << c) < batch) ++c;
+  return c;
+}
+
+// Tile variant for an INT8 product with p moduli: the forced one, else the tuned
+// record of the shape and p at the nearest batch class, else a default from the shape: 64 x 64 tiles
+// three per CU (variant 4) for long contractions with enough tiles to fill the
+// chip three times over, else 64 x 64 tiles two per CU (variant 1), which wins
+// for short contractions and small batches (measured on MI355X over b = 128 .. 512
+// and batch 1 .. 256).
+int o2_variant_for(qtx_rgf_ctx ctx, const GemmDesc& d, int p) {
+  if (ctx->o2_force >= 0) return ctx->o2_force;
+  const int bc = batch_class(d.batch);
+  int best = -1, dist = 1 << 30;
+  for (int c = 0; c <= 9; ++c) {
+    auto it = ctx->tune.find(TuneKey(d.M, d.N, d.K, c, p));
+    if (it != ctx->tune.end() && std::abs(c - bc) < dist) { dist = std::abs(c - bc); best = it->second.variant; }
+  }
+  if (best >= 0) return best;
+  const int64_t tiles = (int64_t)((d.M + 63) / 64) * ((d.N + 63) / 64) * d.batch;
+  return (d.K >= 256 && tiles >= 512) ? 4 : 1;
+}
+
 // One batched complex block product with a precision scheme.  Elementwise (K = 0)
 // launches stay FP64.
 hipError_t run_product(qtx_rgf_ctx ctx, const GemmDesc& d, const Scheme& sc, const SplitBufs& sb, hipStream_t s) {
@@ -346,7 +383,7 @@ hipError_t run_product(qtx_rgf_ctx ctx, const GemmDesc& d, const Scheme& sc, con
     }
   }
   ProfScope ps(ctx, QTX_KERNEL_GEMM, s, core_ops, prof);
-  if (sc.o2()) return launch_zgemm_o2(g, P, s);
+  if (sc.o2()) return launch_zgemm_o2(g, P, s, o2_variant_for(ctx, d, P.p));
   return launch_zgemm_split(g, sc.fmt, sc.ns, s);
 }
 
@@ -945,6 +982,66 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
   return result;
 }
 
+// Tuning cache file: a text file, first line "qtx-tune 2 <arch> <CUs>", then one
+// line per record "o2 M N K class p variant ms_0 .. ms_{n-1}".  A file written on a
+// different device kind, or lines that do not parse, are ignored.
+std::string device_tag(int device) {
+  hipDeviceProp_t pr;
+  if (hipGetDeviceProperties(&pr, device) != hipSuccess) return "unknown 0";
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "%s %d", pr.gcnArchName, pr.multiProcessorCount);
+  for (char* c = buf; *c; ++c)
+    if (*c == ':' ) { *c = '\0'; break; }   // drop target features
+  std::string t(buf);
+  if (t.find(' ') == std::string::npos) t += " " + std::to_string(pr.multiProcessorCount);
+  return t;
+}
+
+void tune_load(qtx_rgf_ctx ctx) {
+  if (ctx->tune_path.empty()) return;
+  FILE* f = std::fopen(ctx->tune_path.c_str(), "r");
+  if (!f) return;
+  char line[1024];
+  bool ok = false;
+  const std::string tag = "qtx-tune 2 " + device_tag(ctx->device);
+  if (std::fgets(line, sizeof line, f)) {
+    std::string h(line);
+    while (!h.empty() && (h.back() == '\n' || h.back() == '\r' || h.back() == ' ')) h.pop_back();
+    ok = (h == tag);
+  }
+  while (ok && std::fgets(line, sizeof line, f)) {
+    int M, N, K, c, p, v, used = 0;
+    if (std::sscanf(line, "o2 %d %d %d %d %d %d%n", &M, &N, &K, &c, &p, &v, &used) != 6) continue;
+    if (M < 1 || N < 1 || K < 1 || c < 0 || c > 9 || p < 1 || p > kO2MaxModuli || v < 0 ||
+        v >= o2_variant_count())
+      continue;
+    TuneRec r;
+    r.variant = v;
+    const char* q = line + used;
+    double ms;
+    int n = 0;
+    while (std::sscanf(q, "%lf%n", &ms, &n) == 1) { r.ms.push_back(ms); q += n; }
+    ctx->tune[TuneKey(M, N, K, c, p)] = r;
+  }
+  std::fclose(f);
+}
+
+bool tune_save(qtx_rgf_ctx ctx) {
+  if (ctx->tune_path.empty()) return true;
+  const std::string tmp = ctx->tune_path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "qtx-tune 2 %s\n", device_tag(ctx->device).c_str());
+  for (const auto& kv : ctx->tune) {
+    std::fprintf(f, "o2 %d %d %d %d %d %d", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                 std::get<3>(kv.first), std::get<4>(kv.first), kv.second.variant);
+    for (double ms : kv.second.ms) std::fprintf(f, " %.4f", ms);
+    std::fprintf(f, "\n");
+  }
+  const bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), ctx->tune_path.c_str()) == 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -982,6 +1079,7 @@ qtx_status qtx_rgf_create(qtx_rgf_ctx* out, int device, size_t workspace_bytes, 
   ctx->device = device;
   ctx->ws_cap = workspace_bytes;
   if (tune_cache_path) ctx->tune_path = tune_cache_path;
+  tune_load(ctx);
   *out = ctx;
   return QTX_OK;
 }
@@ -997,6 +1095,15 @@ qtx_status qtx_rgf_set_option(qtx_rgf_ctx ctx, int option, int64_t value) {
       DeviceGuard guard(ctx->device);
       return ensure_ws(ctx, (size_t)value);
     }
+    case QTX_OPT_INT8_TILE_VARIANT:
+      if (value < -1 || value >= o2_variant_count()) return QTX_ERR_ARG;
+      if (ctx->o2_force != (int)value) {
+        DeviceGuard guard(ctx->device);
+        (void)hipDeviceSynchronize();
+        drop_graphs(ctx);   // captured launches carry the old choice
+      }
+      ctx->o2_force = (int)value;
+      return QTX_OK;
     default:
       return QTX_ERR_ARG;
   }
@@ -1008,6 +1115,7 @@ qtx_status qtx_rgf_get_stat(qtx_rgf_ctx ctx, int stat, int64_t* value) {
     case QTX_STAT_GRAPH_LAUNCHES: *value = ctx->graph_launches; return QTX_OK;
     case QTX_STAT_GRAPH_CAPTURES: *value = ctx->graph_captures; return QTX_OK;
     case QTX_STAT_WORKSPACE_BYTES: *value = (int64_t)ctx->ws_size; return QTX_OK;
+    case QTX_STAT_TUNE_RECORDS: *value = (int64_t)ctx->tune.size(); return QTX_OK;
     default: return QTX_ERR_ARG;
   }
 }
@@ -1122,6 +1230,85 @@ qtx_status qtx_zgemm(qtx_rgf_ctx ctx, char opA, char opB, int32_t M, int32_t N, 
   }
   QTX_TRY(run_product(ctx, d, sc, sb, (hipStream_t)hip_stream));
   return QTX_OK;
+}
+
+qtx_status qtx_rgf_tune(qtx_rgf_ctx ctx, int32_t b, int32_t prec, int32_t n_slices, int32_t batch,
+                        void* hip_stream, int32_t* out_variant, double* out_ms, int32_t max_variants,
+                        int32_t* out_count) {
+  if (!ctx) return QTX_ERR_ARG;
+  if (ctx->sticky != QTX_OK) return ctx->sticky;
+  if (b < 1 || b > 1024 || batch < 1 || max_variants < 0 || (max_variants > 0 && !out_ms)) return QTX_ERR_ARG;
+  Scheme sc;
+  if (!make_scheme(prec, n_slices, &sc)) return QTX_ERR_UNSUPPORTED;
+  if (!sc.o2()) {   // one kernel configuration: nothing to choose
+    if (out_variant) *out_variant = 0;
+    if (out_count) *out_count = 1;
+    if (max_variants > 0) out_ms[0] = 0.0;
+    return QTX_OK;
+  }
+  O2Params P;
+  if (!o2_params(sc.ns, b, &P)) return QTX_ERR_UNSUPPORTED;
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int64_t bb = (int64_t)b * b;
+  const size_t bytes = (size_t)bb * batch * sizeof(double2);
+  double2* buf[3] = {nullptr, nullptr, nullptr};
+  for (auto& p : buf)
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      for (auto& q : buf)
+        if (q) (void)hipFree(q);
+      return QTX_ERR_NOMEM;
+    }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  qtx_status st = QTX_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      launch_fill_hash(buf[0], bb * batch, 1u, s) != hipSuccess ||
+      launch_fill_hash(buf[1], bb * batch, 2u, s) != hipSuccess)
+    st = hip_fail(ctx, hipErrorUnknown);
+  const int nv = o2_variant_count();
+  std::vector<double> ms(nv, 0.0);
+  const int saved_force = ctx->o2_force;
+  const bool saved_prof = ctx->profiling;
+  ctx->profiling = false;
+  const int reps = 3;
+  for (int v = 0; v < nv && st == QTX_OK; ++v) {
+    ctx->o2_force = v;
+    auto one = [&]() {
+      return qtx_zgemm(ctx, 'N', 'N', b, b, b, 1.0, 0.0, buf[0], b, bb, buf[1], b, bb, 0.0, 0.0, buf[2], b, bb,
+                       batch, prec, n_slices, hip_stream);
+    };
+    if ((st = one()) != QTX_OK) break;   // warm-up
+    if (hipEventRecord(e0, s) != hipSuccess) { st = hip_fail(ctx, hipErrorUnknown); break; }
+    for (int r = 0; r < reps && st == QTX_OK; ++r) st = one();
+    if (st != QTX_OK) break;
+    float t = 0.0f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+      st = hip_fail(ctx, hipErrorUnknown);
+      break;
+    }
+    ms[v] = t / reps;
+  }
+  ctx->o2_force = saved_force;
+  ctx->profiling = saved_prof;
+  (void)hipStreamSynchronize(s);
+  for (auto& p : buf) (void)hipFree(p);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st != QTX_OK) return st;
+  int best = 0;
+  for (int v = 1; v < nv; ++v)
+    if (ms[v] < ms[best]) best = v;
+  TuneRec rec;
+  rec.variant = best;
+  rec.ms = ms;
+  ctx->tune[TuneKey(b, b, b, batch_class(batch), P.p)] = rec;
+  drop_graphs(ctx);   // captured launches carry the old choice
+  if (out_variant) *out_variant = best;
+  if (out_count) *out_count = nv;
+  for (int v = 0; v < nv && v < max_variants; ++v) out_ms[v] = ms[v];
+  return tune_save(ctx) ? QTX_OK : QTX_ERR_ARG;
 }
 
 qtx_status qtx_zinv(qtx_rgf_ctx ctx, int32_t n, const void* A, int64_t sA, void* Ainv, int64_t sAinv,

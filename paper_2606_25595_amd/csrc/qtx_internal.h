@@ -119,7 +119,11 @@ int o2_modulus(int i);                                      // i-th modulus (0 o
 int64_t o2_res_stride(int rows, int cols, int p);           // bytes of residues per batch entry
 // Row exponents (as launch_split_exp) and residues of one operand.
 hipError_t launch_o2_convert(const SplitDesc& sd, const O2Params& P, hipStream_t s);
-hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_t s);
+// Tile variants of the INT8 product kernel (bitwise the same results; they differ
+// in tile height, threads, LDS ring shape and workgroups per CU).
+constexpr int kO2Variants = 5;
+int o2_variant_count();
+hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_t s, int variant);
 
 // Gauss-Jordan inversion with implicit partial pivoting, batched.
 // X_z (n x n, ld n, stride sX) is overwritten; the inverse is written to Out_z.
@@ -138,6 +142,7 @@ hipError_t launch_gje_invert(int n, double2* X, int64_t sX, double2* Out, int64_
 
 // Status / NaN fill / observables helpers.
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_hash(double2* p, int64_t n, uint32_t seed, hipStream_t s);
 hipError_t launch_nan_fill_failed(double2* X, int64_t per_batch, int64_t stride, int batch,
                                   const int32_t* status, hipStream_t s);
 hipError_t launch_check_finite(const double2* X, int64_t per_batch, int64_t stride, int batch,

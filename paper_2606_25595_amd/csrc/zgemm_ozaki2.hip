@@ -213,28 +213,53 @@ __device__ inline void crt_fold(int c, double m, double im, double u, double& S)
   S = fma(r, im, S);
 }
 
-// 128 x 64 complex output tile per 512-thread workgroup (one per CU); wave w owns
-// the 32 x 32 block (w % 4, w / 4).  MFMA 32x32x32 i8 layouts: operand lane l
+// BM x 64 complex output tile per workgroup of NT = 4 BM threads; wave w owns the
+// 32 x 32 block (w % (BM / 32), w / (BM / 32)).  MFMA 32x32x32 i8 layouts: operand lane l
 // holds row (column) l % 32 and k = 16 (l / 32) .. +15 of a 32-k step; result
 // lane l, element v -> row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
 //
 // The (modulus, strip) tiles, modulus-major, stream through an NSTAGE-deep LDS
 // ring filled by direct global->LDS loads (no registers held for them), so
-// NSTAGE - 1 strips (~120 KB per CU) are in flight while one feeds the matrix
-// cores.  A stage holds the 128 A rows then the 64 B rows, 128 bytes each (two
+// NSTAGE - 1 steps of SPI strips are in flight while one feeds the matrix
+// cores.  A stage holds SPI strips, each the BM A rows then the 64 B rows, 128 bytes each (two
 // planes x 64 k); the 16-byte slot s of row r sits at slot s ^ (r % 8), which keeps
 // the fragment reads (32 rows, one slot) free of bank conflicts.  Each thread
 // issues exactly LPT loads per strip, so "strip j has landed" is a fixed count
 // of outstanding vector-memory operations.  Rows beyond M (N) load row M - 1
 // (N - 1): they only feed outputs that are never stored.
-constexpr int O2_BM = 128, O2_BN = 64, O2_NT = 512;
-constexpr int SPI = 2;                          // strips per step
-constexpr int NSTAGE = 3;                       // ring stages (steps)
-constexpr int STRIP_U4 = (O2_BM + O2_BN) * 8;   // 16-byte slots per strip (24 KB)
-constexpr int STAGE_U4 = SPI * STRIP_U4;        // per stage (48 KB)
-constexpr int LPS = STRIP_U4 / O2_NT;           // copies per thread per strip (3: two of A rows, one of B rows)
-constexpr int LPT = SPI * LPS;                  // copies per thread per step (6)
+//
+// Tile variants (the launch takes one by index; all give bitwise the same result,
+// since every output's INT32 sums and CRT fold run in the same order):
+//   0: BM = 128, 512 threads, 2 strips per step, 3 stages (144 KB of LDS, one
+//      workgroup per CU)
+//   1: BM = 64, 256 threads, 2 strips per step, 2 stages (64 KB, two per CU)
+//   2: BM = 64, 256 threads, 1 strip per step, 3 stages (48 KB, two per CU)
+//   3: as 2, three per CU (registers capped at 168 per lane; some spill)
+//   4: BM = 64, 256 threads, 1 strip per step, 2 stages (32 KB, three per CU)
+constexpr int O2_BN = 64;
 constexpr int kBufWord3 = 0x00020000;           // buffer descriptor word 3: raw 32-bit data, no swizzle
+
+template <int BM_, int NT_, int SPI_, int NSTAGE_, int WPC_>
+struct O2Cfg {
+  static constexpr int BM = BM_, NT = NT_, SPI = SPI_, NSTAGE = NSTAGE_;
+  static constexpr int STRIP_U4 = (BM + O2_BN) * 8;   // 16-byte slots per strip
+  static constexpr int STAGE_U4 = SPI * STRIP_U4;     // per stage
+  static constexpr int LPS = STRIP_U4 / NT;           // copies per thread per strip
+  static constexpr int LPS_A = BM * 8 / NT;           // of which the first LPS_A copy A rows
+  static constexpr int LPT = SPI * LPS;               // copies per thread per step
+  static constexpr int WPC = WPC_;                    // workgroups per CU (LDS / registers)
+  static constexpr int WAVES_PER_SIMD = WPC * NT / 256;
+  static_assert(NT == 4 * BM && (BM == 64 || BM == 128), "tile shape");   // one wave per 32 x 32 block
+  static_assert(STRIP_U4 % NT == 0 && (BM * 8) % NT == 0, "copy split");
+  static_assert(NSTAGE == 2 || NSTAGE == 3, "ring depth");
+  static_assert(LPT < 64, "vmcnt range");
+  static_assert(NT >= BM + O2_BN && NT >= 16, "exponent and constant fills");
+};
+typedef O2Cfg<128, 512, 2, 3, 1> O2V0;
+typedef O2Cfg<64, 256, 2, 2, 2> O2V1;
+typedef O2Cfg<64, 256, 1, 3, 2> O2V2;
+typedef O2Cfg<64, 256, 1, 3, 3> O2V3;
+typedef O2Cfg<64, 256, 1, 2, 3> O2V4;
 
 typedef __attribute__((address_space(3))) u4 lds_u4;
 typedef __attribute__((address_space(3))) double lds_f64;
@@ -246,9 +271,10 @@ struct O2Acc {
 };
 
 // Per-thread constants of the strip loop.
+template <int LPS>
 struct O2Ctx {
-  int64_t off[LPS];          // byte offset (in A's or B's residues) of each of the thread's slots of a strip
-  int64_t sstride[LPS];      // bytes from one strip to the next
+  int off[LPS];              // byte offset (in A's or B's residues) of each of the thread's slots of a strip
+  int sstride_a, sstride_b;  // bytes from one strip to the next (residue offsets are < 2^31)
   const lds_f64* cst;        // moduli, their reciprocals, the CRT factors u (LDS)
   int tid, la, lb, lk, KT, K, NSTRIP;
   bool wlive;
@@ -277,14 +303,18 @@ __device__ inline void wait_vm() {
 // alias scopes: the compiler's wait-count insertion then leaves the copies of
 // later steps in flight during the reads; their completion is awaited
 // explicitly.  Every thread issues exactly LPT copies per step (a step past the
-// last strip re-copies that strip into its unused half), so "step s landed" is a
-// fixed count of outstanding vector-memory operations.
+// last strip re-copies that strip into its unused part), so "step s landed" is a
+// fixed count of outstanding vector-memory operations: with 3 stages step s + 1
+// may still be in flight, with 2 nothing else is.
+template <class CF>
 __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u4* __restrict__ rd,
                                                             lds_u4* __restrict__ dma, const int8_t* __restrict__ gA,
-                                                            const int8_t* __restrict__ gB, const O2Ctx& c, O2Acc& a) {
+                                                            const int8_t* __restrict__ gB,
+                                                            const O2Ctx<CF::LPS>& c, O2Acc& a) {
+  constexpr int SPI = CF::SPI, NSTAGE = CF::NSTAGE, LPS = CF::LPS, LPT = CF::LPT;
   const int nstep = (c.NSTRIP + SPI - 1) / SPI;
   if (s >= 0) {
-    if (s + 1 < nstep) wait_vm<LPT>();   // step s + 1 may still be pending
+    if (NSTAGE == 3 && s + 1 < nstep) wait_vm<LPT>();   // step s + 1 may still be pending
     else wait_vm<0>();
   }
   lds_barrier();
@@ -295,9 +325,10 @@ __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
       const int f = min(SPI * sd + q / LPS, c.NSTRIP - 1);
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(q % LPS < LPS - 1 ? ra : rb,
-                                               (__attribute__((address_space(3))) void*)(dma + q * O2_NT + (c.tid & ~63)),
-                                               16, (int)(c.off[q % LPS] + (int64_t)f * c.sstride[q % LPS]), 0, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(q % LPS < CF::LPS_A ? ra : rb,
+                                               (__attribute__((address_space(3))) void*)(dma + q * CF::NT + (c.tid & ~63)),
+                                               16, c.off[q % LPS] + f * (q % LPS < CF::LPS_A ? c.sstride_a : c.sstride_b),
+                                               0, 0, 0);
     }
   }
   if (s < 0) return;
@@ -308,7 +339,7 @@ __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u
     const int i = f / c.KT;
     const int kt = f - i * c.KT;
     if (c.wlive) {
-      const lds_u4* st = rd + h * STRIP_U4;
+      const lds_u4* st = rd + h * CF::STRIP_U4;
       const int sa = c.la & 7, sb = c.lb & 7;
       i4 fr[8];
 #pragma unroll
@@ -342,14 +373,17 @@ __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u
   }
 }
 
-// Persistent grid (persist = 1): one workgroup per CU; workgroup w runs on XCD
+// Persistent grid (persist = 1): WPC workgroups per CU; workgroup w runs on XCD
 // w % 8 and takes that XCD's tiles (a contiguous range) in rounds of the XCD's
 // workgroup count, so the workgroups sharing an L2 work on adjacent tiles of the
 // same energies in step and read each residue strip from HBM about once.
 // Otherwise one tile per workgroup.
-__global__ __launch_bounds__(O2_NT) void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
-                                                         int persist) {
-  __shared__ u4 ring[NSTAGE][STAGE_U4];
+template <class CF>
+__global__ __launch_bounds__(CF::NT) __attribute__((amdgpu_waves_per_eu(CF::WAVES_PER_SIMD)))
+void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
+                                                          int persist) {
+  constexpr int O2_BM = CF::BM, O2_NT = CF::NT, NSTAGE = CF::NSTAGE, SPI = CF::SPI, LPS = CF::LPS;
+  __shared__ u4 ring[NSTAGE][CF::STAGE_U4];
   __shared__ int Ea[O2_BM], Eb[O2_BN];
   __shared__ double cst[3 * kO2MaxModuli];
 
@@ -389,31 +423,26 @@ __global__ __launch_bounds__(O2_NT) void zgemm_o2_kernel(SplitGemmDesc g, O2Para
   const int32_t* EB = g.EB + (int64_t)z * g.eb_stride;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 3, wn = wave >> 2;
+  const int wm = wave % (O2_BM / 32), wn = wave / (O2_BM / 32);
   const bool wlive = (m0 + 32 * wm < M) && (n0 + 32 * wn < N);   // wave-uniform
 
   if (tid < O2_BM) Ea[tid] = (m0 + tid < M) ? EA[m0 + tid] : 0;
   else if (tid < O2_BM + O2_BN) Eb[tid - O2_BM] = (n0 + tid - O2_BM < N) ? EB[n0 + tid - O2_BM] : 0;
   __syncthreads();   // also drains these loads before the counted ring loads start
 
-  // Per-thread source of each of its LPT slots of a stage (the strip offset added
-  // per strip): slot cs = q * 512 + tid; A rows first, then B rows.
-  O2Ctx c;
+  // Per-thread source of each of its LPS slots of a strip (the strip offset added
+  // per strip): slot cs = q * NT + tid; A rows first, then B rows.
+  O2Ctx<LPS> c;
 #pragma unroll
   for (int q = 0; q < LPS; ++q) {
     const int cs = q * O2_NT + tid;
     const int row = cs >> 3, slot = cs & 7;
     const int word = slot ^ (row & 7);
-    if (row < O2_BM) {   // q < LPS - 1: A rows
-      const int rg = min(m0 + row, M - 1);
-      c.off[q] = (int64_t)rg * 128 + 16 * word;
-      c.sstride[q] = (int64_t)M * 128;
-    } else {
-      const int rg = min(n0 + row - O2_BM, N - 1);
-      c.off[q] = (int64_t)rg * 128 + 16 * word;
-      c.sstride[q] = (int64_t)N * 128;
-    }
+    const int rg = row < O2_BM ? min(m0 + row, M - 1) : min(n0 + row - O2_BM, N - 1);   // q < LPS_A: A rows
+    c.off[q] = rg * 128 + 16 * word;
   }
+  c.sstride_a = M * 128;
+  c.sstride_b = N * 128;
   c.cst = (const lds_f64*)&cst[0];
   c.tid = tid;
   c.la = 32 * wm + (lane & 31);
@@ -433,7 +462,7 @@ __global__ __launch_bounds__(O2_NT) void zgemm_o2_kernel(SplitGemmDesc g, O2Para
   auto stage = [&](int f) { return (lds_u4*)&ring[(f + NSTAGE) % NSTAGE][0]; };   // f >= -NSTAGE
   const int nstep = (NSTRIP + SPI - 1) / SPI;
   for (int st = -(NSTAGE - 1); st < nstep; ++st)
-    o2_step(st, stage(st), stage(st + NSTAGE - 1), SA, SB, c, acc);
+    o2_step<CF>(st, stage(st), stage(st + NSTAGE - 1), SA, SB, c, acc);
 
   // epilogue in FP64 (same addend semantics as the FP64 kernels)
   double2* __restrict__ C = d.tC ? d.tC[z] : d.C + (int64_t)z * d.sC;
@@ -551,14 +580,14 @@ hipError_t launch_o2_convert(const SplitDesc& sd, const O2Params& P, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_t s) {
+namespace {
+
+template <class CF>
+hipError_t launch_o2_variant(const SplitGemmDesc& g, const O2Params& P, hipStream_t s) {
   const GemmDesc& d = g.d;
-  if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
-  const int64_t total = (int64_t)((d.M + O2_BM - 1) / O2_BM) * ((d.N + O2_BN - 1) / O2_BN) * d.batch;
+  const int64_t total = (int64_t)((d.M + CF::BM - 1) / CF::BM) * ((d.N + O2_BN - 1) / O2_BN) * d.batch;
   if (total > 0x7fffffff) return hipErrorInvalidValue;
-  if (o2_res_stride(d.M, d.K, P.p) > 0x7fffffff || o2_res_stride(d.N, d.K, P.p) > 0x7fffffff)
-    return hipErrorInvalidValue;   // per-entry residue offsets are 32-bit in the kernel
-  // one workgroup per CU (the kernel's LDS admits one) when there are more tiles
+  // WPC workgroups per CU (what the kernel's LDS and registers admit) when there are more tiles
   static int cus[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
@@ -567,11 +596,30 @@ hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_
     if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 8;
     cus[dev] = n;
   }
-  const int grid_p = cus[dev] / 8 * 8;
+  const int grid_p = cus[dev] / 8 * 8 * CF::WPC;
   const bool persist = grid_p >= 8 && total > grid_p;
   const unsigned grid = persist ? (unsigned)grid_p : (unsigned)total;
-  hipLaunchKernelGGL(zgemm_o2_kernel, dim3(grid), dim3(O2_NT), 0, s, g, P, (int)total, persist ? 1 : 0);
+  hipLaunchKernelGGL((zgemm_o2_kernel<CF>), dim3(grid), dim3(CF::NT), 0, s, g, P, (int)total, persist ? 1 : 0);
   return hipGetLastError();
+}
+
+}  // namespace
+
+int o2_variant_count() { return kO2Variants; }
+
+hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_t s, int variant) {
+  const GemmDesc& d = g.d;
+  if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
+  if (o2_res_stride(d.M, d.K, P.p) > 0x7fffffff || o2_res_stride(d.N, d.K, P.p) > 0x7fffffff)
+    return hipErrorInvalidValue;   // per-entry residue offsets are 32-bit in the kernel
+  switch (variant) {
+    case 0: return launch_o2_variant<O2V0>(g, P, s);
+    case 1: return launch_o2_variant<O2V1>(g, P, s);
+    case 2: return launch_o2_variant<O2V2>(g, P, s);
+    case 3: return launch_o2_variant<O2V3>(g, P, s);
+    case 4: return launch_o2_variant<O2V4>(g, P, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace qtx

@@ -34,9 +34,9 @@ PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16"
 
 EXPORTED = ("qtx_rgf_create", "qtx_rgf_solve", "qtx_rgf_destroy", "qtx_rgf_footprint", "qtx_status_str",
             "qtx_zgemm", "qtx_zinv", "qtx_rgf_observables", "qtx_rgf_profile", "qtx_rgf_profile_read",
-            "qtx_rgf_set_option", "qtx_rgf_get_stat", "qtx_ozaki2_bits")
-QTX_OPT_GRAPH, QTX_OPT_RESERVE_WORKSPACE = 1, 2
-QTX_STAT_GRAPH_LAUNCHES, QTX_STAT_GRAPH_CAPTURES, QTX_STAT_WORKSPACE_BYTES = 1, 2, 3
+            "qtx_rgf_set_option", "qtx_rgf_get_stat", "qtx_ozaki2_bits", "qtx_rgf_tune")
+QTX_OPT_GRAPH, QTX_OPT_RESERVE_WORKSPACE, QTX_OPT_INT8_TILE_VARIANT = 1, 2, 3
+QTX_STAT_GRAPH_LAUNCHES, QTX_STAT_GRAPH_CAPTURES, QTX_STAT_WORKSPACE_BYTES, QTX_STAT_TUNE_RECORDS = 1, 2, 3, 4
 QTX_KERNEL_GEMM, QTX_KERNEL_INV, QTX_KERNEL_CONVERT = 0, 1, 2
 
 
@@ -105,6 +105,9 @@ def load_library(path: str = LIB_PATH):
     lib.qtx_rgf_get_stat.restype = ctypes.c_int
     lib.qtx_ozaki2_bits.argtypes = [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.qtx_ozaki2_bits.restype = ctypes.c_int
+    lib.qtx_rgf_tune.argtypes = [vp, i32, i32, i32, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), i32,
+                                 ctypes.POINTER(i32)]
+    lib.qtx_rgf_tune.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -352,6 +355,25 @@ class Context:
         rc = self.lib.qtx_rgf_set_option(self.handle, QTX_OPT_RESERVE_WORKSPACE, int(nbytes))
         if rc != QTX_OK:
             raise QtxError(rc, "qtx_rgf_set_option(reserve)")
+
+    def set_int8_tile_variant(self, variant: int = -1):
+        """-1: the autotuner's choice per shape; 0.. : force one tile variant."""
+        rc = self.lib.qtx_rgf_set_option(self.handle, QTX_OPT_INT8_TILE_VARIANT, int(variant))
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_rgf_set_option(int8 tile variant)")
+
+    # -- qtx_rgf_tune
+    def tune(self, b: int, prec="int8", n_slices: int = 0, batch: int = 1, stream=None):
+        """Time the product kernel's tile variants for b x b x b products over
+        `batch` entries; returns (chosen variant, [ms per product of each variant])."""
+        v = ctypes.c_int32()
+        cnt = ctypes.c_int32()
+        ms = (ctypes.c_double * 8)()
+        rc = self.lib.qtx_rgf_tune(self.handle, int(b), PREC_NAMES.get(prec, prec), int(n_slices), int(batch),
+                                   _stream_ptr(stream), ctypes.byref(v), ms, 8, ctypes.byref(cnt))
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_rgf_tune")
+        return v.value, [ms[i] for i in range(cnt.value)]
 
     def stat(self, which: int) -> int:
         v = ctypes.c_int64()

@@ -1,0 +1,151 @@
+"""INT8 product tile variants and the autotuner: every variant gives bitwise the
+same product (the same exact INT32 sums and the same CRT fold order), the tuner
+records a choice per shape, writes and re-reads its cache file, and a solve after
+tuning equals the solve before it."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_25595_amd import inputs
+
+pytestmark = pytest.mark.gpu
+N_VARIANTS = 5      # tile variants of the INT8 product kernel
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_25595_amd import qtx
+    c = qtx.Context(0)
+    yield c
+    c.close()
+
+
+def rand_c(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("M,N,K,batch", [(416, 416, 416, 3), (200, 150, 300, 2), (33, 97, 70, 4), (64, 64, 64, 1),
+                                         (130, 70, 600, 1)])
+@pytest.mark.parametrize("ops", ["NN", "NC", "CN", "CC"])
+@pytest.mark.parametrize("p", [6, 11])
+def test_variants_bitwise_equal(ctx, M, N, K, batch, ops, p):
+    import torch
+    rng = np.random.default_rng(M * 7 + N * 3 + K + p)
+    A = rand_c(rng, batch, *((M, K) if ops[0] == "N" else (K, M)))
+    B = rand_c(rng, batch, *((K, N) if ops[1] == "N" else (N, K)))
+    C0 = rand_c(rng, batch, M, N)
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    outs = []
+    try:
+        for v in range(N_VARIANTS):
+            ctx.set_int8_tile_variant(v)
+            C = torch.from_numpy(C0).cuda()
+            ctx.zgemm(At, Bt, C, opA=ops[0], opB=ops[1], alpha=-1.0, beta=1.0, prec="int8", n_slices=p)
+            torch.cuda.synchronize()
+            outs.append(C.cpu().numpy())
+    finally:
+        ctx.set_int8_tile_variant(-1)
+    for v in range(1, N_VARIANTS):
+        assert np.array_equal(outs[v].view(np.float64), outs[0].view(np.float64)), v
+    # and the common result is the product to the scheme's accuracy
+    opa = A if ops[0] == "N" else np.conj(np.swapaxes(A, 1, 2))
+    opb = B if ops[1] == "N" else np.conj(np.swapaxes(B, 1, 2))
+    ref = C0 - opa @ opb
+    from paper_2606_25595_amd import qtx
+    kbits = qtx.ozaki2_bits(p, K)[1]
+    bound = 8 * 2.0 ** -kbits * K * np.abs(opa).max() * np.abs(opb).max()
+    assert np.abs(outs[0] - ref).max() <= bound
+
+
+def test_tune_records_and_cache(tmp_path):
+    import torch
+    from paper_2606_25595_amd import qtx
+    path = str(tmp_path / "tune.txt")
+    c = qtx.Context(0, tune_cache=path)
+    try:
+        assert c.stat(qtx.QTX_STAT_TUNE_RECORDS) == 0
+        v, ms = c.tune(96, "int8", 8, batch=16)
+        assert 0 <= v < N_VARIANTS and len(ms) == N_VARIANTS
+        assert all(t > 0 for t in ms) and ms[v] == min(ms)
+        v2, _ = c.tune(96, "int8", 8, batch=200)          # another batch class: a second record
+        assert c.stat(qtx.QTX_STAT_TUNE_RECORDS) == 2
+        v, _ = c.tune(96, "int8", 8, batch=16)             # the same key again: replaced, not added
+        assert c.stat(qtx.QTX_STAT_TUNE_RECORDS) == 2
+        v3, _ = c.tune(96, "int8", 9, batch=16)            # another modulus count: a third record
+        assert c.stat(qtx.QTX_STAT_TUNE_RECORDS) == 3
+        assert c.tune(96, "fp64") == (0, [0.0])           # one configuration: nothing recorded
+        assert c.stat(qtx.QTX_STAT_TUNE_RECORDS) == 3
+    finally:
+        c.close()
+    lines = open(path).read().splitlines()
+    assert lines[0].startswith("qtx-tune 2 ")
+    recs = sorted(l.split()[:7] for l in lines[1:])
+    assert recs == sorted([["o2", "96", "96", "96", "4", "8", str(v)], ["o2", "96", "96", "96", "8", "8", str(v2)],
+                           ["o2", "96", "96", "96", "4", "9", str(v3)]])
+    c2 = qtx.Context(0, tune_cache=path)
+    try:
+        assert c2.stat(qtx.QTX_STAT_TUNE_RECORDS) == 3
+    finally:
+        c2.close()
+
+
+def test_bad_cache_file_is_ignored(tmp_path):
+    from paper_2606_25595_amd import qtx
+    path = tmp_path / "bad.txt"
+    path.write_text("qtx-tune 2 some-other-device 7\no2 96 96 96 4 8 1 1.0 2.0 3.0\n")
+    c = qtx.Context(0, tune_cache=str(path))
+    try:
+        assert c.stat(qtx.QTX_STAT_TUNE_RECORDS) == 0
+    finally:
+        c.close()
+    path.write_text("garbage\n\x00\x01 o2 x y\n")
+    c = qtx.Context(0, tune_cache=str(path))
+    try:
+        assert c.stat(qtx.QTX_STAT_TUNE_RECORDS) == 0
+    finally:
+        c.close()
+
+
+def test_tune_rejects_bad_arguments(ctx):
+    from paper_2606_25595_amd import qtx
+    for args in [(0, "int8", 8, 1), (1025, "int8", 8, 1), (64, "int8", 8, 0)]:
+        with pytest.raises(qtx.QtxError):
+            ctx.tune(*args[:3], batch=args[3])
+    with pytest.raises(qtx.QtxError):
+        ctx.tune(64, "int8", 1, batch=1)                   # too few moduli
+    with pytest.raises(qtx.QtxError):
+        ctx.set_int8_tile_variant(N_VARIANTS)
+
+
+def test_solve_unchanged_by_tuning():
+    import torch
+    from paper_2606_25595_amd import qtx
+    p = inputs.random_bt_problem(4, 72, np.array([-0.5, 0.3, 1.1]), seed=21)
+    c = qtx.Context(0)
+    try:
+        dp = qtx.to_device(p)
+        c.solve(dp, prec="int8", n_slices=10, prec_lesser="int8", n_slices_lesser=11)
+        torch.cuda.synchronize()
+        before = dp.outputs()
+        # force each variant, then the tuned choice: the outputs do not move
+        for v in list(range(N_VARIANTS)) + [-1]:
+            if v < 0:
+                c.set_int8_tile_variant(-1)
+                c.tune(72, "int8", 10, batch=3)
+                c.tune(72, "int8", 11, batch=3)
+            else:
+                c.set_int8_tile_variant(v)
+            dp2 = qtx.to_device(p)
+            c.solve(dp2, prec="int8", n_slices=10, prec_lesser="int8", n_slices_lesser=11)
+            torch.cuda.synchronize()
+            after = dp2.outputs()
+            for k in before:
+                assert np.array_equal(before[k], after[k]), (v, k)
+        ref = oracle.rgf_selected(p)
+        for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u"):
+            assert oracle.rel_fro_err(before[k], ref[k]).max() <= 1e-6
+    finally:
+        c.close()
