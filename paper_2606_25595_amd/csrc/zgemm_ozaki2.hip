@@ -112,31 +112,34 @@ __global__ __launch_bounds__(NT) void o2_residue_kernel(SplitDesc sd, O2Params P
   }
 }
 
-// Single-pass conversion for K <= kO2FusedMaxK: one workgroup holds RB = 8 rows of
-// S = op(X) over all of K in LDS (coalesced loads; element (r, k) at r KP + (k ^ r),
-// so the 8 rows of one k fall in distinct banks), finds the row exponents, and
-// writes every (modulus, strip) block of those rows: 8 rows x 2 planes x 64 bytes
-// = 1 KB contiguous, one 16-byte store per lane of a wave (lane -> row l / 8,
-// plane (l / 4) % 2, k = 16 (l % 4) .. +15 of the strip); wave w converts strips
-// w, w + 8, ...
-constexpr int kO2FusedRows = 8;
-constexpr int kO2FusedMaxK = 512;   // 8 rows x 512 x 16 B = 64 KB of LDS
+// Single-pass conversion for K <= kO2FusedMaxK: one workgroup of RB waves holds RB
+// rows of S = op(X) over all of K in LDS (coalesced loads; element (r, k) at
+// r KP + (k ^ r), so the rows of one k fall in distinct banks), finds the row
+// exponents (wave w reduces row w), and writes every (modulus, strip) block of its
+// rows: RB rows x 2 planes x 64 bytes contiguous, 2 RB bytes per lane of a wave
+// (lane -> row l / (64 / RB), plane, 2 RB consecutive k of the strip); wave w
+// converts strips w, w + RB, ...
+constexpr int kO2FusedMaxK = 512;   // RB rows x 512 x 16 B of LDS (64 KB at RB = 8)
+constexpr int kO2ConvRows = 4;      // rows per conversion workgroup (4: five workgroups per CU at K = 512;
+                                    // faster than 8 or 2 on MI355X for both load orders)
 
-constexpr int CT = 512;   // threads of the conversion kernel (8 waves: one per row, one per strip)
-
-__global__ __launch_bounds__(CT) void o2_convert_kernel(SplitDesc sd, O2Params P) {
+template <int RB>
+__global__ __launch_bounds__(64 * RB) void o2_convert_kernel(SplitDesc sd, O2Params P) {
+  static_assert(RB == 2 || RB == 4 || RB == 8, "rows per workgroup");
+  constexpr int CT = 64 * RB;          // threads
+  constexpr int LPR = 64 / RB;         // lanes per row in the residue phase
+  constexpr int VPL = 2 * RB;          // values (bytes) per lane and strip
   extern __shared__ double2 rows_lds[];   // [RB][KP], KP = KT * 64 (zero-padded), swizzled
-  constexpr int RB = kO2FusedRows;
   const int z = blockIdx.y, r0 = blockIdx.x * RB, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int K = sd.cols, KT = (K + KS - 1) / KS, KP = KT * KS, pitch = KP;
   const double2* X = sd.tX ? sd.tX[z] : sd.X + (int64_t)z * sd.stride;
   // load (zero outside rows x K, conjugate on the way in): thread t takes row t / 64
-  // (trans 0: rows contiguous) or t % 8 (trans 1: 8 adjacent columns of X = 128
-  // bytes), and k = its base + 64 j; all loads are issued before the LDS stores.
+  // (trans 0: rows contiguous) or t % RB (trans 1: RB adjacent columns of X), and
+  // k = its base + 64 j; all loads are issued before the LDS stores.
   {
-    const int r = sd.trans ? (tid & 7) : (tid >> 6);
-    const int kb = sd.trans ? (tid >> 3) : (tid & 63);
+    const int r = sd.trans ? (tid % RB) : (tid >> 6);
+    const int kb = sd.trans ? (tid / RB) : (tid & 63);
     const bool rok = r0 + r < sd.rows;
     const int nj = KP / 64;   // <= 8
     double2 v[kO2FusedMaxK / 64];
@@ -169,31 +172,43 @@ __global__ __launch_bounds__(CT) void o2_convert_kernel(SplitDesc sd, O2Params P
     if (lane == 0 && r0 + r < sd.rows) sd.E[(int64_t)z * sd.e_stride + r0 + r] = e;
   }
   __syncthreads();   // the exponents are read back below (same workgroup)
-  const int r = lane >> 3, c = (lane >> 2) & 1, ks = lane & 3;
+  const int r = lane / LPR, c = (lane / (LPR / 2)) & 1, ks = lane % (LPR / 2);
   const bool live = r0 + r < sd.rows;
   const double sc = live ? pow2(P.kbits + 1 - sd.E[(int64_t)z * sd.e_stride + r0 + r]) : 0.0;
   int8_t* out = (int8_t*)sd.S + (int64_t)z * sd.s_stride;
-  for (int kt = wave; kt < KT; kt += CT / 64) {
-    double a[16];
+  for (int kt = wave; kt < KT; kt += RB) {
+    double a[VPL];
     const double2* src = rows_lds + r * pitch;
-    const int k0 = kt * KS + 16 * ks;
+    const int k0 = kt * KS + VPL * ks;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < VPL; ++j) {
       const double2 v = src[(k0 + j) ^ r];
       a[j] = rint((c ? v.y : v.x) * sc);
     }
     for (int i = 0; i < P.p; ++i) {
       const double m = P.m[i], im = P.inv_m[i];
-      uint32_t w[4] = {0u, 0u, 0u, 0u};
+      uint32_t w[VPL / 4];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
+      for (int q = 0; q < VPL / 4; ++q) w[q] = 0u;
+#pragma unroll
+      for (int j = 0; j < VPL; ++j) {
         const double q = rint(a[j] * im);
         const int rr = (int)fma(-q, m, a[j]);
         w[j >> 2] |= ((uint32_t)rr & 0xffu) << (8 * (j & 3));
       }
       if (live) {
-        u4 pk = {w[0], w[1], w[2], w[3]};
-        *(u4*)(out + ((((int64_t)i * KT + kt) * sd.rows + r0 + r) * 2 + c) * KS + 16 * ks) = pk;
+        int8_t* dst = out + ((((int64_t)i * KT + kt) * sd.rows + r0 + r) * 2 + c) * KS + VPL * ks;
+        if constexpr (VPL == 16) {
+          u4 pk = {w[0], w[1], w[2], w[3]};
+          *(u4*)dst = pk;
+        } else if constexpr (VPL == 8) {
+          uint2 pk;
+          pk.x = w[0];
+          pk.y = w[1];
+          *(uint2*)dst = pk;
+        } else {
+          *(uint32_t*)dst = w[0];
+        }
       }
     }
   }
@@ -567,10 +582,10 @@ int64_t o2_res_stride(int rows, int cols, int p) {
 hipError_t launch_o2_convert(const SplitDesc& sd, const O2Params& P, hipStream_t s) {
   if (sd.rows <= 0 || sd.cols <= 0 || sd.batch <= 0) return hipSuccess;
   if (sd.cols <= kO2FusedMaxK) {
+    constexpr int RB = kO2ConvRows;
     const int KP = (sd.cols + KS - 1) / KS * KS;
-    const size_t lds = (size_t)kO2FusedRows * KP * sizeof(double2);
-    hipLaunchKernelGGL(o2_convert_kernel, dim3((sd.rows + kO2FusedRows - 1) / kO2FusedRows, sd.batch), dim3(CT),
-                       lds, s, sd, P);
+    const size_t lds = (size_t)RB * KP * sizeof(double2);
+    hipLaunchKernelGGL(o2_convert_kernel<RB>, dim3((sd.rows + RB - 1) / RB, sd.batch), dim3(64 * RB), lds, s, sd, P);
     return hipGetLastError();
   }
   hipError_t e = launch_split_exp(sd, s);
