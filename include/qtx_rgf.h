@@ -177,8 +177,18 @@ qtx_status qtx_rgf_solve(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int32_t 
  *                  from the shape (64 x 64 tiles three per CU when K >= 256 and
  *                  there are >= 512 such tiles, else 64 x 64 tiles two per CU);
  *                  value = 0 .. count-1: every INT8 product uses that variant.
- *                  All variants give bitwise the same results. */
-enum { QTX_OPT_GRAPH = 1, QTX_OPT_RESERVE_WORKSPACE = 2, QTX_OPT_INT8_TILE_VARIANT = 3 };
+ *                  All variants give bitwise the same results.
+ *   QTX_OPT_OVERLAP  value != 0: during each forward inversion, the two
+ *                  lesser-recurrence products that do not need the new inverse run
+ *                  on an internal side stream (one per block-size lane, default
+ *                  priority) that forks from and joins back into the solve's
+ *                  stream; value = 0 (default): everything runs on the solve's
+ *                  stream.  The results are bitwise the same either way.  Solves
+ *                  captured into a hipGraph (QTX_OPT_GRAPH) never use the side
+ *                  stream.  Off by default: at 256 energies of b = 416 the
+ *                  persistent product kernels occupy every CU, so the overlap only
+ *                  adds contention (measured 2% slower). */
+enum { QTX_OPT_GRAPH = 1, QTX_OPT_RESERVE_WORKSPACE = 2, QTX_OPT_INT8_TILE_VARIANT = 3, QTX_OPT_OVERLAP = 4 };
 enum { QTX_STAT_GRAPH_LAUNCHES = 1, QTX_STAT_GRAPH_CAPTURES = 2, QTX_STAT_WORKSPACE_BYTES = 3,
        QTX_STAT_TUNE_RECORDS = 4 };
 qtx_status qtx_rgf_set_option(qtx_rgf_ctx ctx, int option, int64_t value);

@@ -74,6 +74,7 @@ struct qtx_rgf_ctx_s {
   std::string tune_path;
   std::map<TuneKey, TuneRec> tune;
   int o2_force = -1;       // >= 0: every INT8 product uses this tile variant
+  bool overlap = false;    // run independent products on a side stream during inversions
   bool profiling = false;
   bool use_graph = false;
   bool capturing = false;
@@ -86,6 +87,9 @@ struct qtx_rgf_ctx_s {
   // auxiliary streams (default priority) and fork/join events for parallel batches
   std::vector<hipStream_t> aux;
   std::vector<hipEvent_t> fork_ev, join_ev;
+  // per lane: a side stream for products that overlap the inversion, and its fork/join events
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> side_fork, side_join;
   std::vector<GraphCacheEntry> graphs;
   int64_t graph_launches = 0, graph_captures = 0;
 };
@@ -178,6 +182,20 @@ qtx_status ensure_aux(qtx_rgf_ctx ctx, size_t n) {
     ctx->aux.push_back(st);
     ctx->fork_ev.push_back(a);
     ctx->join_ev.push_back(b);
+  }
+  return QTX_OK;
+}
+
+qtx_status ensure_side(qtx_rgf_ctx ctx, size_t n) {
+  while (ctx->side.size() < n) {
+    hipStream_t st;
+    hipEvent_t a, b;
+    QTX_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    QTX_TRY(hipEventCreateWithFlags(&a, hipEventDisableTiming));
+    QTX_TRY(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+    ctx->side.push_back(st);
+    ctx->side_fork.push_back(a);
+    ctx->side_join.push_back(b);
   }
   return QTX_OK;
 }
@@ -458,7 +476,7 @@ BatchKey key_of(const qtx_rgf_problem& p) {
 size_t batch_ws_bytes(const BatchKey& k, int Z) {
   const size_t blk = align_up((size_t)Z * k.b * k.b * sizeof(double2));
   return blk * (1 + kTemps + 2) + align_up(gje_work_bytes(k.b, Z)) + align_up((size_t)Z * sizeof(int32_t)) +
-         split_pair_bytes(k.b, larger_split(k.r, k.l), Z) + 1024;
+         split_pair_bytes(k.b, larger_split(k.r, k.l), Z) + split_pair_bytes(k.b, k.l, Z) + 1024;
 }
 
 size_t per_entry_bytes(const BatchKey& k) { return batch_ws_bytes(k, 1); }
@@ -514,6 +532,8 @@ EntryData entry_data_layout(int Z) {
 struct Run {
   qtx_rgf_ctx ctx;
   hipStream_t s = nullptr;
+  hipStream_t side = nullptr;          // launch pass: stream for products that overlap the inversion
+  hipEvent_t side_fork = nullptr, side_join = nullptr;
   Batch* B = nullptr;
   bool dry = true;
   std::map<TabKey, TabVal> tabs;
@@ -621,6 +641,7 @@ struct Gemm {
   const double* energies;   // device, per entry
   Scheme sc;
   SplitBufs sb;
+  bool on_side = false;     // launch on the run's side stream
 
   // C = alpha * op(A) op(B) + addends (+ diag * E_z I), over the first Z entries
   hipError_t go(int Z, int opA, Mat A, int opB, Mat B, Mat C, double2 alpha, std::initializer_list<Addend> adds,
@@ -645,7 +666,7 @@ struct Gemm {
     d.diag_by_batch = 1;
     d.bscal = energies;
     d.batch = Z;
-    return run_product(run->ctx, d, sc, sb, run->s);
+    return run_product(run->ctx, d, sc, sb, on_side ? run->side : run->s);
   }
 };
 
@@ -658,6 +679,7 @@ struct BatchWs {
   GjeWork gw;
   int32_t* st = nullptr;
   SplitBufs sb;
+  SplitBufs sb_side;   // converted operands of the products on the side stream
   // per-entry data (inside the table area)
   const double* en = nullptr;
   int32_t* const* ust = nullptr;
@@ -675,6 +697,7 @@ BatchWs carve_batch(char* w, const BatchKey& k, int Z) {
   L.gw = gje_carve(w, k.b, Z); w += align_up(gje_work_bytes(k.b, Z));
   L.st = (int32_t*)w; w += align_up((size_t)Z * sizeof(int32_t));
   L.sb = carve_split(w, k.b, larger_split(k.r, k.l), Z);
+  L.sb_side = carve_split(w, k.b, k.l, Z);
   return L;
 }
 
@@ -690,6 +713,7 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
   const bool dry = R.dry;
   Gemm g{&R, b, W.en, k.r, W.sb};     // retarded chain
   Gemm gl{&R, b, W.en, k.l, W.sb};    // lesser / greater chain
+  Gemm gl_side{&R, b, W.en, k.l, W.sb_side, true};   // lesser chain on the side stream
   const double2 one = cmk(1, 0), mone = cmk(-1, 0), zero = cmk(0, 0);
   auto ws = [&](double2* p) { Mat m; m.p = p; m.stride = bb; return m; };
 
@@ -741,18 +765,40 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
       QTX_TRY(g.go(Z, OP_N, ws(W.Tm[0]), OP_N, U, ws(W.X), cmk(-sL * sU, 0), {aH, aS, aO}, dg));
     }
     const Mat xi = R.get(A_GRD, 0, i, 0);
+    // The first lesser recurrence's Y' = L' xl_{i-1} and Q = B_i + Y' L'^H do not
+    // need x_i: with a side stream they run there while x_i is inverted (the
+    // inversion leaves most matrix cores idle), else before the inversion.  The
+    // side stream forks after everything they read is enqueued and joins before Q
+    // is used; it owns its own converted-operand buffers.
+    const bool side = !dry && R.side != nullptr && !ctx->capturing && Z > 0 && i > 0;
+    if (i > 0) {
+      const Rhs& r = rhs[0];
+      const Mat Bi = R.get(r.S, 0, i, 0);
+      if (side) {
+        QTX_TRY(hipEventRecord(R.side_fork, s));
+        QTX_TRY(hipStreamWaitEvent(R.side, R.side_fork, 0));
+      }
+      const Gemm& G = side ? gl_side : gl;
+      QTX_TRY(G.go(Z, OP_N, L, OP_N, R.get(r.Gd, 0, i, -1), ws(W.Tm[1]), one, {}));
+      QTX_TRY(G.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one, {addend_of(Bi, one)}));
+      if (side) QTX_TRY(hipEventRecord(R.side_join, R.side));
+    }
     if (!dry && Z > 0) {
       ProfScope ps(ctx, QTX_KERNEL_INV, s, 8.0 * (double)b * b * b * Z, true);
       QTX_TRY(launch_gje_invert(b, W.X, bb, (double2*)xi.p, xi.stride, Z, W.gw, W.st, s, (double2* const*)xi.tab));
     }
-    for (const Rhs& r : rhs) {
+    if (side) QTX_TRY(hipStreamWaitEvent(s, R.side_join, 0));
+    for (size_t q = 0; q < rhs.size(); ++q) {
+      const Rhs& r = rhs[q];
       const Mat Bi = R.get(r.S, 0, i, 0);
       if (i == 0) {
         QTX_TRY(gl.go(Z, OP_N, xi, OP_N, Bi, ws(W.Tm[2]), one, {}));
       } else {
-        // Y' = L' xl_{i-1};  Q = B_i + Y' L'^H;  Z = x_i Q
-        QTX_TRY(gl.go(Z, OP_N, L, OP_N, R.get(r.Gd, 0, i, -1), ws(W.Tm[1]), one, {}));
-        QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one, {addend_of(Bi, one)}));
+        // Y' = L' xl_{i-1};  Q = B_i + Y' L'^H  (done above for the first recurrence);  Z = x_i Q
+        if (q > 0) {
+          QTX_TRY(gl.go(Z, OP_N, L, OP_N, R.get(r.Gd, 0, i, -1), ws(W.Tm[1]), one, {}));
+          QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one, {addend_of(Bi, one)}));
+        }
         QTX_TRY(gl.go(Z, OP_N, xi, OP_N, ws(W.Tm[3]), ws(W.Tm[2]), one, {}));
       }
       // xl_i = Z x_i^H
@@ -923,6 +969,11 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
   }
   if (replay) return QTX_OK;
   if (n_lanes > 1) QTX_TRYS(ensure_aux(ctx, n_lanes));
+  // The side stream is used in eager solves only: a captured solve runs every
+  // product on its lane's stream (a capture that forked the side stream from a lane
+  // stream at every forward step ended in a segmentation fault inside the runtime).
+  const bool use_side = ctx->overlap && !capture;
+  if (use_side) QTX_TRYS(ensure_side(ctx, n_lanes));
   if (capture) {
     QTX_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     ctx->capturing = true;
@@ -942,6 +993,11 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
       Run& R = runs[bi];
       R.dry = false;
       R.s = ls;
+      if (use_side) {
+        R.side = ctx->side[l];
+        R.side_fork = ctx->side_fork[l];
+        R.side_join = ctx->side_join[l];
+      }
       R.dev = dev_tab + batches[bi].tab_off;
       const int Z = (int)R.B->ent.size();
       BatchWs W = carve_batch((char*)ctx->ws + lane_off[l], R.B->key, Z);
@@ -1095,6 +1151,14 @@ qtx_status qtx_rgf_set_option(qtx_rgf_ctx ctx, int option, int64_t value) {
       DeviceGuard guard(ctx->device);
       return ensure_ws(ctx, (size_t)value);
     }
+    case QTX_OPT_OVERLAP:
+      if (ctx->overlap != (value != 0)) {
+        DeviceGuard guard(ctx->device);
+        (void)hipDeviceSynchronize();
+        drop_graphs(ctx);   // captured launches carry the old stream structure
+      }
+      ctx->overlap = value != 0;
+      return QTX_OK;
     case QTX_OPT_INT8_TILE_VARIANT:
       if (value < -1 || value >= o2_variant_count()) return QTX_ERR_ARG;
       if (ctx->o2_force != (int)value) {
@@ -1165,6 +1229,11 @@ qtx_status qtx_rgf_destroy(qtx_rgf_ctx ctx) {
       (void)hipStreamDestroy(ctx->aux[i]);
       (void)hipEventDestroy(ctx->fork_ev[i]);
       (void)hipEventDestroy(ctx->join_ev[i]);
+    }
+    for (size_t i = 0; i < ctx->side.size(); ++i) {
+      (void)hipStreamDestroy(ctx->side[i]);
+      (void)hipEventDestroy(ctx->side_fork[i]);
+      (void)hipEventDestroy(ctx->side_join[i]);
     }
   }
   delete ctx;
