@@ -359,7 +359,7 @@ def bench_serve(args):
     N_E in 16..128, FP64 or mixed with probability 1/2, seed 1000 + id), continuous
     batching by HBM footprint, p50/p99 latency of completed requests."""
     import torch
-    from paper_2606_25595_amd.serve import GpuExecutor, Server, request_stream
+    from paper_2606_25595_amd.serve import PRECISIONS, GpuExecutor, Server, request_stream
     free, total = torch.cuda.mem_get_info()
     budget = int(free * 0.55)
     reqs = request_stream(rate=args.rate, duration=args.duration, seed=0)
@@ -371,7 +371,11 @@ def bench_serve(args):
     ex.close()
     line = {"metric": "served RGF energy points/sec with p50/p99 request latency",
             "value": rep["energy_points_per_s"], "unit": "energy points/s", "n_gpus": 1,
-            "higher_is_better": True, "dtype": "f64 / f64+bf16:5", "data": "synthetic",
+            "higher_is_better": True, "data": "synthetic",
+            "dtype": " / ".join("f64" if x["prec"] == "fp64" else
+                                "f64+%s:%d/%s:%d" % (x["prec"], x.get("n_slices", 0), x.get("prec_lesser", x["prec"]),
+                                                     x.get("n_slices_lesser", x.get("n_slices", 0)))
+                                for x in PRECISIONS.values()),
             "config": {"workload": "serve: Poisson %.1f/s for %.1f s, b 128..512, n_b 8..48, N_E 16..128"
                                    % (args.rate, args.duration)},
             "p50_latency_s": rep["p50_latency_s"], "p99_latency_s": rep["p99_latency_s"], "report": rep}
