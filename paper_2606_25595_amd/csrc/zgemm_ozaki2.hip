@@ -251,6 +251,9 @@ __device__ inline void crt_fold(int c, double m, double im, double u, double& S)
 //   2: BM = 64, 256 threads, 1 strip per step, 3 stages (48 KB, two per CU)
 //   3: as 2, three per CU (registers capped at 168 per lane; some spill)
 //   4: BM = 64, 256 threads, 1 strip per step, 2 stages (32 KB, three per CU)
+//   5, 6: variants 4 and 1 with one tile per workgroup instead of persistent
+//      workgroups (the hardware then keeps a window of consecutive tiles -- the
+//      same energies on one XCD -- in flight, in place of rounds that drift apart)
 constexpr int O2_BN = 64;
 constexpr int kBufWord3 = 0x00020000;           // buffer descriptor word 3: raw 32-bit data, no swizzle
 
@@ -598,7 +601,7 @@ hipError_t launch_o2_convert(const SplitDesc& sd, const O2Params& P, hipStream_t
 namespace {
 
 template <class CF>
-hipError_t launch_o2_variant(const SplitGemmDesc& g, const O2Params& P, hipStream_t s) {
+hipError_t launch_o2_variant(const SplitGemmDesc& g, const O2Params& P, hipStream_t s, bool allow_persist) {
   const GemmDesc& d = g.d;
   const int64_t total = (int64_t)((d.M + CF::BM - 1) / CF::BM) * ((d.N + O2_BN - 1) / O2_BN) * d.batch;
   if (total > 0x7fffffff) return hipErrorInvalidValue;
@@ -612,7 +615,7 @@ hipError_t launch_o2_variant(const SplitGemmDesc& g, const O2Params& P, hipStrea
     cus[dev] = n;
   }
   const int grid_p = cus[dev] / 8 * 8 * CF::WPC;
-  const bool persist = grid_p >= 8 && total > grid_p;
+  const bool persist = allow_persist && grid_p >= 8 && total > grid_p;
   const unsigned grid = persist ? (unsigned)grid_p : (unsigned)total;
   hipLaunchKernelGGL((zgemm_o2_kernel<CF>), dim3(grid), dim3(CF::NT), 0, s, g, P, (int)total, persist ? 1 : 0);
   return hipGetLastError();
@@ -628,11 +631,13 @@ hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_
   if (o2_res_stride(d.M, d.K, P.p) > 0x7fffffff || o2_res_stride(d.N, d.K, P.p) > 0x7fffffff)
     return hipErrorInvalidValue;   // per-entry residue offsets are 32-bit in the kernel
   switch (variant) {
-    case 0: return launch_o2_variant<O2V0>(g, P, s);
-    case 1: return launch_o2_variant<O2V1>(g, P, s);
-    case 2: return launch_o2_variant<O2V2>(g, P, s);
-    case 3: return launch_o2_variant<O2V3>(g, P, s);
-    case 4: return launch_o2_variant<O2V4>(g, P, s);
+    case 0: return launch_o2_variant<O2V0>(g, P, s, true);
+    case 1: return launch_o2_variant<O2V1>(g, P, s, true);
+    case 2: return launch_o2_variant<O2V2>(g, P, s, true);
+    case 3: return launch_o2_variant<O2V3>(g, P, s, true);
+    case 4: return launch_o2_variant<O2V4>(g, P, s, true);
+    case 5: return launch_o2_variant<O2V4>(g, P, s, false);
+    case 6: return launch_o2_variant<O2V1>(g, P, s, false);
     default: return hipErrorInvalidValue;
   }
 }
