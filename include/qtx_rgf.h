@@ -98,11 +98,16 @@ enum {
  *   SR_d [n_e][n_b][b][b]   retarded self-energy, diagonal blocks (required).
  *   SR_u/SR_l [n_e][n_b-1][b][b]  off-diagonal blocks of Sigma^R, or NULL (= 0).
  *   SL_d [n_e][n_b][b][b]   lesser self-energy, diagonal blocks (required).
- *   SL_u/SL_l  must be NULL in this build (block-diagonal Sigma^<), else
- *              QTX_ERR_UNSUPPORTED.
- *   SG_d  greater self-energy diagonal blocks (required with QTX_WANT_GREATER).
+ *   SL_u [n_e][n_b-1][b][b] = Sigma^<_{i,i+1} for a BT Sigma^<, or NULL
+ *              (block-diagonal Sigma^<).  SL_l must be NULL (else
+ *              QTX_ERR_UNSUPPORTED): the lower blocks are -(SL_u)^H.
+ *   SG_d, SG_u  greater self-energy, same layout (SG_d required with
+ *              QTX_WANT_GREATER; SG_u without that flag is QTX_ERR_ARG); SG_l
+ *              must be NULL.
  *   Sigma^< and Sigma^> must be skew-Hermitian (as lesser/greater functions
- *   are): the backward pass uses that symmetry for one of its products.
+ *   are): the recurrences use that symmetry to evaluate a term and its
+ *   conjugate transpose with one product (the cross terms of a BT Sigma^<
+ *   cost one more product per forward step and two per backward step).
  * Outputs (device, caller-allocated, written entirely):
  *   GR_d [n_e][n_b][b][b], GR_u [n_e][n_b-1][b][b] = G^R_{i,i+1},
  *   GR_l [n_e][n_b-1][b][b] = G^R_{i+1,i},

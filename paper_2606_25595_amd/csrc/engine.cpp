@@ -428,7 +428,10 @@ bool valid_problem(const qtx_rgf_problem* p) {
 }
 
 qtx_status check_supported(const qtx_rgf_problem* p) {
-  if (p->SL_u || p->SL_l || p->SG_u || p->SG_l) return QTX_ERR_UNSUPPORTED;   // BT Sigma^<, Sigma^>
+  // BT Sigma^< / Sigma^> come as their upper blocks only: the lower blocks of a
+  // skew-Hermitian matrix are -(upper)^H and are never read.
+  if (p->SL_l || p->SG_l) return QTX_ERR_UNSUPPORTED;
+  if (p->SG_u && !(p->flags & QTX_WANT_GREATER)) return QTX_ERR_ARG;
   Scheme sc;
   if (!make_scheme(p->prec, p->n_slices, &sc)) return QTX_ERR_UNSUPPORTED;
   if (p->prec_lesser >= 0 && !make_scheme(p->prec_lesser, p->n_slices_lesser, &sc)) return QTX_ERR_UNSUPPORTED;
@@ -444,7 +447,8 @@ constexpr int kTemps = 6;
 enum Arr {
   A_HD, A_HU, A_HL, A_SD, A_SU, A_SL,               // per problem, [n_b] / [n_b-1] blocks
   A_SRD, A_SLD, A_SGD, A_GRD, A_GLD, A_GGD,         // per energy, [n_b] blocks
-  A_SRU, A_SRL, A_GRU, A_GRL, A_GLU, A_GGU          // per energy, [n_b-1] blocks
+  A_SRU, A_SRL, A_GRU, A_GRL, A_GLU, A_GGU,         // per energy, [n_b-1] blocks
+  A_SLU, A_SGU
 };
 
 struct Entry {
@@ -457,8 +461,10 @@ struct BatchKey {
   int b = 0;
   Scheme r, l;
   bool s_id = true, greater = false, coupled = false;
+  bool l_bt = false, g_bt = false;   // Sigma^< / Sigma^> with off-diagonal blocks
   bool operator==(const BatchKey& o) const {
-    return b == o.b && r == o.r && l == o.l && s_id == o.s_id && greater == o.greater && coupled == o.coupled;
+    return b == o.b && r == o.r && l == o.l && s_id == o.s_id && greater == o.greater && coupled == o.coupled &&
+           l_bt == o.l_bt && g_bt == o.g_bt;
   }
 };
 
@@ -469,6 +475,8 @@ BatchKey key_of(const qtx_rgf_problem& p) {
   k.s_id = (p.flags & QTX_S_IDENTITY) != 0;
   k.greater = (p.flags & QTX_WANT_GREATER) != 0;
   k.coupled = !k.s_id || p.SR_u || p.SR_l;
+  k.l_bt = p.n_b > 1 && p.SL_u != nullptr;
+  k.g_bt = k.greater && p.n_b > 1 && p.SG_u != nullptr;
   return k;
 }
 
@@ -579,6 +587,8 @@ struct Run {
       case A_GRL: base = p.GR_l; idx = e * nu + j; break;
       case A_GLU: base = p.GL_u; idx = e * nu + j; break;
       case A_GGU: base = p.GG_u; idx = e * nu + j; break;
+      case A_SLU: base = p.SL_u; idx = e * nu + j; break;
+      case A_SGU: base = p.SG_u; idx = e * nu + j; break;
     }
     if (!base) return nullptr;
     return (const double2*)base + idx * bb;
@@ -719,9 +729,10 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
 
   if (!dry) QTX_TRY(launch_fill_i32(W.st, 0, Zall, s));
 
-  struct Rhs { int S, Gd, Gu; };
-  std::vector<Rhs> rhs{{A_SLD, A_GLD, A_GLU}};
-  if (k.greater) rhs.push_back({A_SGD, A_GGD, A_GGU});
+  // Right-hand sides: Sigma^< (and Sigma^>), with their upper blocks when BT.
+  struct Rhs { int S, SU, Gd, Gu; };
+  std::vector<Rhs> rhs{{A_SLD, k.l_bt ? A_SLU : -1, A_GLD, A_GLU}};
+  if (k.greater) rhs.push_back({A_SGD, k.g_bt ? A_SGU : -1, A_GGD, A_GGU});
 
   // The coupling operands: U_i = E S_{i,i+1} - H_{i,i+1} - Sigma^R_{i,i+1}(E) and the
   // same for L_i.  With S = I and no Sigma^R coupling they are -H_u, -H_l: the
@@ -771,16 +782,25 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
     // side stream forks after everything they read is enqueued and joins before Q
     // is used; it owns its own converted-operand buffers.
     const bool side = !dry && R.side != nullptr && !ctx->capturing && Z > 0 && i > 0;
-    if (i > 0) {
-      const Rhs& r = rhs[0];
+    // Q_i = B_i + L xl_{i-1} L^H - BL_{i-1} x_{i-1}^H L^H - L x_{i-1} BU_{i-1}.  With
+    // L = sL L' and BL = -BU^H (skew-Hermitian right-hand side) the two cross terms are
+    // -sL V + sL V^H with V = T' BU_{i-1}, T' = L' x_{i-1} (still in Tm[0]).
+    auto lesser_q = [&](const Gemm& G, const Rhs& r) -> hipError_t {
       const Mat Bi = R.get(r.S, 0, i, 0);
+      hipError_t e = G.go(Z, OP_N, L, OP_N, R.get(r.Gd, 0, i, -1), ws(W.Tm[1]), one, {});
+      if (e != hipSuccess) return e;
+      if (r.SU < 0) return G.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one, {addend_of(Bi, one)});
+      e = G.go(Z, OP_N, ws(W.Tm[0]), OP_N, R.get(r.SU, 0, i, -1), ws(W.Tm[4]), one, {});
+      if (e != hipSuccess) return e;
+      return G.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one,
+                  {addend_of(Bi, one), addend_of(ws(W.Tm[4]), cmk(-sL, 0)), addend_of(ws(W.Tm[4]), cmk(sL, 0), OP_C)});
+    };
+    if (i > 0) {
       if (side) {
         QTX_TRY(hipEventRecord(R.side_fork, s));
         QTX_TRY(hipStreamWaitEvent(R.side, R.side_fork, 0));
       }
-      const Gemm& G = side ? gl_side : gl;
-      QTX_TRY(G.go(Z, OP_N, L, OP_N, R.get(r.Gd, 0, i, -1), ws(W.Tm[1]), one, {}));
-      QTX_TRY(G.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one, {addend_of(Bi, one)}));
+      QTX_TRY(lesser_q(side ? gl_side : gl, rhs[0]));
       if (side) QTX_TRY(hipEventRecord(R.side_join, R.side));
     }
     if (!dry && Z > 0) {
@@ -794,11 +814,8 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
       if (i == 0) {
         QTX_TRY(gl.go(Z, OP_N, xi, OP_N, Bi, ws(W.Tm[2]), one, {}));
       } else {
-        // Y' = L' xl_{i-1};  Q = B_i + Y' L'^H  (done above for the first recurrence);  Z = x_i Q
-        if (q > 0) {
-          QTX_TRY(gl.go(Z, OP_N, L, OP_N, R.get(r.Gd, 0, i, -1), ws(W.Tm[1]), one, {}));
-          QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one, {addend_of(Bi, one)}));
-        }
+        // Q_i (done above for the first recurrence);  Z = x_i Q
+        if (q > 0) QTX_TRY(lesser_q(gl, r));
         QTX_TRY(gl.go(Z, OP_N, xi, OP_N, ws(W.Tm[3]), ws(W.Tm[2]), one, {}));
       }
       // xl_i = Z x_i^H
@@ -820,20 +837,32 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
     QTX_TRY(g.go(Z, OP_N, L, OP_N, xi, Rp, one, {}));                           // R' = L' x_i
     QTX_TRY(g.go(Z, OP_N, Pp, OP_N, Gn, GRu, cmk(-sU, 0), {}));                 // G_{i,i+1}
     QTX_TRY(g.go(Z, OP_N, Gn, OP_N, Rp, GRl, cmk(-sL, 0), {}));                 // G_{i+1,i}
-    QTX_TRY(g.go(Z, OP_N, GRu, OP_N, Rp, xi, cmk(-sL, 0), {addend_of(xi, one)}));   // G_ii (in place)
     QTX_TRY(gl.go(Z, OP_N, GRu, OP_N, L, Wp, one, {}));                         // W' = G_{i,i+1} L'
+    // The lesser blocks (x_i is still unchanged here: G_ii overwrites it below).
+    //   G<_{i,i+1} = -P G<_{i+1} - xl L^H G_{i+1}^H + x BU G_{i+1}^H
+    //   G<_ii = xl + P G<_{i+1} P^H - W xl - xl L^H G_{i,i+1}^H + G_{i,i+1} BL x^H + x BU G_{i,i+1}^H
+    // With P = sU P', W = sL W', L = sL L' and the skew-Hermitian xl and BL = -BU^H:
+    //   Y = -sL W' xl + x BU G_{i,i+1}^H,  Z = -sL xl L'^H + x BU,
+    //   G<_{i,i+1} = Z G_{i+1}^H - sU V',  G<_ii = xl + V' P'^H + Y - Y^H,  V' = P' G<_{i+1}.
     for (const Rhs& r : rhs) {
       const Mat xl = R.get(r.Gd, 1, kk, 0);
       const Mat Gln = R.get(r.Gd, 1, kk, 1);
-      QTX_TRY(gl.go(Z, OP_N, Pp, OP_N, Gln, Vp, one, {}));                      // V' = P' G<_{i+1}
-      QTX_TRY(gl.go(Z, OP_N, Wp, OP_N, xl, Yp, one, {}));                       // Y' = W' xl_i
-      QTX_TRY(gl.go(Z, OP_N, xl, OP_C, L, Zp, one, {}));                        // Z' = xl_i L'^H
-      // G<_{i,i+1} = -sU V' - sL Z' G_{i+1}^H
-      QTX_TRY(gl.go(Z, OP_N, Zp, OP_C, Gn, R.get(r.Gu, 1, kk, 0), cmk(-sL, 0), {addend_of(Vp, cmk(-sU, 0))}));
-      // G<_ii = xl_i + V' P'^H - sL Y' + sL Y'^H   (in place)
-      QTX_TRY(gl.go(Z, OP_N, Vp, OP_C, Pp, xl, one,
-                    {addend_of(xl, one), addend_of(Yp, cmk(-sL, 0)), addend_of(Yp, cmk(sL, 0), OP_C)}));
+      const double2 msl = cmk(-sL, 0);
+      if (r.SU >= 0) {
+        QTX_TRY(gl.go(Z, OP_N, xi, OP_N, R.get(r.SU, 1, kk, 0), Zp, one, {}));   // K' = x_i BU_i
+        QTX_TRY(gl.go(Z, OP_N, Zp, OP_C, GRu, Yp, one, {}));                      // K' G_{i,i+1}^H
+        QTX_TRY(gl.go(Z, OP_N, Wp, OP_N, xl, Yp, msl, {addend_of(Yp, one)}));     // Y
+        QTX_TRY(gl.go(Z, OP_N, xl, OP_C, L, Zp, msl, {addend_of(Zp, one)}));      // Z
+      } else {
+        QTX_TRY(gl.go(Z, OP_N, Wp, OP_N, xl, Yp, msl, {}));                       // Y = -sL W' xl_i
+        QTX_TRY(gl.go(Z, OP_N, xl, OP_C, L, Zp, msl, {}));                        // Z = -sL xl_i L'^H
+      }
+      QTX_TRY(gl.go(Z, OP_N, Pp, OP_N, Gln, Vp, one, {}));                        // V' = P' G<_{i+1}
+      QTX_TRY(gl.go(Z, OP_N, Zp, OP_C, Gn, R.get(r.Gu, 1, kk, 0), one, {addend_of(Vp, cmk(-sU, 0))}));
+      QTX_TRY(gl.go(Z, OP_N, Vp, OP_C, Pp, xl, one,                               // G<_ii (in place)
+                    {addend_of(xl, one), addend_of(Yp, one), addend_of(Yp, cmk(-1, 0), OP_C)}));
     }
+    QTX_TRY(g.go(Z, OP_N, GRu, OP_N, Rp, xi, cmk(-sL, 0), {addend_of(xi, one)}));   // G_ii (in place)
   }
   // ------------------------------------------------------------ status
   // Non-finite values propagate into the first blocks: check those; then every

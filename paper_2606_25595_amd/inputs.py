@@ -128,12 +128,21 @@ def _diag_blocks(scal: np.ndarray, b: int) -> np.ndarray:
 
 def random_bt_problem(n_b: int, b: int, energies, seed: int = 0, eta: float = 1e-3,
                       gamma: float = 0.5, mu_L: float = 0.1, mu_R: float = -0.1, kT: float = 0.025,
-                      with_greater: bool = False, coupling_var: float = 0.5) -> BTProblem:
+                      with_greater: bool = False, coupling_var: float = 0.5,
+                      bt_sigma: float = 0.0) -> BTProblem:
     """The synthetic device used throughout: random Hermitian BT H, S = I,
     Sigma^R_ii = -i(eta + gamma_i) I with gamma_i = gamma on the first and last block,
     Sigma^< = -f_i(E) (Sigma^R - Sigma^R^H) with f_i the Fermi function at mu_i,
     mu_i linear from mu_L (block 1) to mu_R (block n_b), temperature kT.
     Sigma^> = Sigma^< + Sigma^R - Sigma^A when requested.
+
+    bt_sigma = c > 0 makes every self-energy BT: Sigma^R = -i(eta + gamma_i + K) with K
+    the Hermitian BT matrix of diagonal blocks 2c I and upper blocks K_i = c X_i / |X_i|_F
+    (X_i circular complex normal, drawn from PCG64([seed, 1])), which is positive
+    semidefinite, so the anti-Hermitian part of M stays >= eta.  The off-diagonal
+    blocks of Sigma^< take the mean occupation of the two blocks they couple, which
+    keeps Sigma^< skew-Hermitian: Sigma^<_{i,i+1} = 2i fbar_i K_i,
+    Sigma^<_{i+1,i} = 2i fbar_i K_i^H, Sigma^>_{i,i+1} = 2i (fbar_i - 1) K_i.
     """
     energies = np.atleast_1d(np.asarray(energies, dtype=np.float64))
     H_d, H_u, H_l = random_hamiltonian(n_b, b, seed, coupling_var)
@@ -141,6 +150,9 @@ def random_bt_problem(n_b: int, b: int, energies, seed: int = 0, eta: float = 1e
     gam[0] += gamma
     gam[-1] += gamma
     broad = eta + gam                                   # [n_b]
+    bt = bt_sigma > 0 and n_b > 1
+    if bt:
+        broad = broad + 2.0 * bt_sigma
     mu = np.linspace(mu_L, mu_R, n_b)
     f = fermi(energies[:, None], mu[None, :], kT)        # [n_e][n_b]
     sr = np.broadcast_to(-1j * broad[None, :], (energies.size, n_b))
@@ -155,6 +167,24 @@ def random_bt_problem(n_b: int, b: int, energies, seed: int = 0, eta: float = 1e
     if with_greater:
         # Sigma^> = Sigma^< + Sigma^R - Sigma^A = 2i f broad - 2i broad
         prob.SG_d = _diag_blocks(2j * (f - 1.0) * broad[None, :], b)
+    if bt:
+        rng = np.random.default_rng([seed, 1])
+        K = np.empty((n_b - 1, b, b), dtype=np.complex128)
+        for i in range(n_b - 1):
+            R = rng.standard_normal((b, b))
+            J = rng.standard_normal((b, b))
+            X = R + 1j * J
+            K[i] = bt_sigma * X / np.linalg.norm(X)
+        KH = np.conj(np.transpose(K, (0, 2, 1)))
+        fbar = 0.5 * (f[:, :-1] + f[:, 1:])               # [n_e][n_b-1]
+        n_e = energies.size
+        prob.SR_u = np.ascontiguousarray(np.broadcast_to(-1j * K, (n_e,) + K.shape))
+        prob.SR_l = np.ascontiguousarray(np.broadcast_to(-1j * KH, (n_e,) + K.shape))
+        prob.SL_u = 2j * fbar[:, :, None, None] * K[None]
+        prob.SL_l = 2j * fbar[:, :, None, None] * KH[None]
+        if with_greater:
+            prob.SG_u = 2j * (fbar[:, :, None, None] - 1.0) * K[None]
+            prob.SG_l = 2j * (fbar[:, :, None, None] - 1.0) * KH[None]
     return prob
 
 

@@ -163,7 +163,9 @@ class DeviceProblem:
     S_l: object = None
     SR_u: object = None
     SR_l: object = None
+    SL_u: object = None
     SG_d: object = None
+    SG_u: object = None
     GG_d: object = None
     GG_u: object = None
 
@@ -191,13 +193,15 @@ class DeviceProblem:
 
 def to_device(p, device="cuda", greater: Optional[bool] = None) -> DeviceProblem:
     """Copy a host problem (paper_2606_25595_amd.inputs.BTProblem) to the device
-    and allocate its outputs (uninitialised)."""
+    and allocate its outputs (uninitialised).  A BT Sigma^< / Sigma^> travels as its
+    upper blocks only (SL_u / SG_u): the library takes the lower blocks as
+    -(upper)^H, so SL_l / SG_l are not copied."""
     import torch
 
     def dev(a):
         if a is None:
             return None
-        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to(device)
+        return torch.from_numpy(np.require(a, dtype=np.complex128, requirements=["C", "W"])).to(device)
 
     n_e, n_b, b = p.n_e, p.n_b, p.b
     if greater is None:
@@ -210,9 +214,11 @@ def to_device(p, device="cuda", greater: Optional[bool] = None) -> DeviceProblem
         GR_l=torch.empty((n_e, max(n_b - 1, 0), b, b), **kw), GL_d=torch.empty((n_e, n_b, b, b), **kw),
         GL_u=torch.empty((n_e, max(n_b - 1, 0), b, b), **kw),
         status=torch.full((n_e,), -1, dtype=torch.int32, device=device),
-        S_d=dev(p.S_d), S_u=dev(p.S_u), S_l=dev(p.S_l), SR_u=dev(p.SR_u), SR_l=dev(p.SR_l))
+        S_d=dev(p.S_d), S_u=dev(p.S_u), S_l=dev(p.S_l), SR_u=dev(p.SR_u), SR_l=dev(p.SR_l),
+        SL_u=dev(p.SL_u))
     if greater:
         dp.SG_d = dev(p.SG_d)
+        dp.SG_u = dev(p.SG_u)
         dp.GG_d = torch.empty((n_e, n_b, b, b), **kw)
         dp.GG_u = torch.empty((n_e, max(n_b - 1, 0), b, b), **kw)
     return dp
@@ -231,7 +237,7 @@ def _problem_struct(dp: DeviceProblem, prec: int, n_slices: int, prec_lesser: in
     st.flags = flags
     en = np.ascontiguousarray(dp.energies, dtype=np.float64)
     st.energies = en.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    for name in ("H_d", "H_u", "H_l", "S_d", "S_u", "S_l", "SR_d", "SR_u", "SR_l", "SL_d", "SG_d",
+    for name in ("H_d", "H_u", "H_l", "S_d", "S_u", "S_l", "SR_d", "SR_u", "SR_l", "SL_d", "SL_u", "SG_d", "SG_u",
                  "GR_d", "GR_u", "GR_l", "GL_d", "GL_u", "GG_d", "GG_u", "status"):
         t = getattr(dp, name)
         if t is not None and t.numel() == 0:

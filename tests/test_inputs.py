@@ -42,3 +42,33 @@ def test_fermi_limits():
     assert inputs.fermi(-100.0, 0.0, 0.025) == 1.0
     assert inputs.fermi(100.0, 0.0, 0.025) < 1e-300 or inputs.fermi(100.0, 0.0, 0.025) == 0.0
     assert abs(inputs.fermi(0.1, 0.1, 0.025) - 0.5) < 1e-15
+
+
+def test_bt_self_energies_skew_hermitian_and_dissipative():
+    """bt_sigma: Sigma^< is skew-Hermitian with -i Sigma^< >= 0, Sigma^> = Sigma^< +
+    Sigma^R - Sigma^A, and the anti-Hermitian part of Sigma^R is <= -eta (so that
+    M keeps sigma_min >= eta), all checked on the assembled dense matrices."""
+    import numpy as np
+    from paper_2606_25595_amd import inputs
+
+    def dense(D, U, L):
+        n, b = D.shape[0], D.shape[1]
+        M = np.zeros((n * b, n * b), complex)
+        for i in range(n):
+            M[i * b:(i + 1) * b, i * b:(i + 1) * b] = D[i]
+        for i in range(n - 1):
+            M[i * b:(i + 1) * b, (i + 1) * b:(i + 2) * b] = U[i]
+            M[(i + 1) * b:(i + 2) * b, i * b:(i + 1) * b] = L[i]
+        return M
+
+    eta = 1e-3
+    p = inputs.random_bt_problem(4, 5, np.array([-0.3, 0.05, 0.6]), seed=2, eta=eta, with_greater=True,
+                                 bt_sigma=0.2)
+    for e in range(p.n_e):
+        SL = dense(p.SL_d[e], p.SL_u[e], p.SL_l[e])
+        SR = dense(p.SR_d[e], p.SR_u[e], p.SR_l[e])
+        SG = dense(p.SG_d[e], p.SG_u[e], p.SG_l[e])
+        assert np.allclose(SL, -SL.conj().T, atol=1e-15)
+        assert np.linalg.eigvalsh(-1j * SL).min() >= -1e-14
+        assert np.allclose(SG, SL + SR - SR.conj().T, atol=1e-15)
+        assert np.linalg.eigvalsh(-(SR - SR.conj().T) / 2j).min() >= eta - 1e-13
