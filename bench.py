@@ -116,9 +116,12 @@ def main():
                          "<retarded>/<lesser>")
     ap.add_argument("--cpu-energies", type=int, default=8, help="energies in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="realistic", choices=["realistic", "batch", "serve"],
-                    help="realistic (default, the headline line) | batch (512 uneven problems, one graph "
-                         "launch) | serve (Poisson arrivals, continuous batching, p50/p99)")
+    ap.add_argument("--workload", default="realistic", choices=["realistic", "hard", "kappa", "batch", "serve"],
+                    help="realistic (default, the headline line) | hard (the realistic shapes at eta = 1e-6, "
+                         "condition numbers up to ~5e6) | kappa (error against the exact condition number, "
+                         "n_b=8, b=128, eta 1e-3..1e-6) | batch (512 uneven problems, one graph launch) | "
+                         "serve (Poisson arrivals, continuous batching, p50/p99)")
+    ap.add_argument("--eta", type=float, default=None, help="realistic/hard: broadening (default 1e-3 / 1e-6)")
     ap.add_argument("--problems", type=int, default=512, help="batch workload: number of problems")
     ap.add_argument("--rate", type=float, default=200.0, help="serve workload: arrivals per second")
     ap.add_argument("--duration", type=float, default=10.0, help="serve workload: arrival window (s)")
@@ -138,12 +141,16 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "kappa":
+        return bench_kappa(args)
 
     cfg = inputs.CONFIGS["realistic"]
     n_b, b, n_e = cfg["n_b"], cfg["b"], cfg["n_e"]
+    eta = args.eta if args.eta is not None else (1e-6 if args.workload == "hard" else 1e-3)
+    gamma, mu_L, kT = 0.5, 0.1, 0.025
     grid = np.linspace(-2.0, 2.0, n_e)
-    log("bench: building realistic workload n_b=%d b=%d n_e=%d on the device" % (n_b, b, n_e))
-    d = inputs.device_random_problem(n_b, b, grid, seed=0)
+    log("bench: building realistic workload n_b=%d b=%d n_e=%d eta=%g on the device" % (n_b, b, n_e, eta))
+    d = inputs.device_random_problem(n_b, b, grid, seed=0, eta=eta)
     kw = dict(dtype=torch.complex128, device="cuda")
     dp = qtx.DeviceProblem(energies=d["energies"], H_d=d["H_d"], H_u=d["H_u"], H_l=d["H_l"], SR_d=d["SR_d"],
                            SL_d=d["SL_d"], GR_d=torch.empty((n_e, n_b, b, b), **kw),
@@ -152,6 +159,9 @@ def main():
                            status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"))
     ctx = qtx.Context(0)
     sample = list(range(0, n_e, max(1, n_e // args.cpu_energies)))[: args.cpu_energies]
+    gamma_L = 2.0 * gamma * np.eye(b, dtype=np.complex128)
+    f_L = inputs.fermi(grid, mu_L, kT)
+    kappa = None
 
     # ---- CPU oracle on the sample (also the parity reference for the sampled outputs)
     ref = None
@@ -163,11 +173,14 @@ def main():
             threads = max([t.get("num_threads", 1) for t in threadpool_info() if t.get("user_api") == "blas"] or [1])
         except Exception:
             threads = os.cpu_count() or 1
-        p_s = inputs.config_problem("realistic", energy_index=sample)
+        p_s = inputs.config_problem("realistic", energy_index=sample, eta=eta)
         log("bench: oracle on %d sampled energies (%d BLAS threads)" % (len(sample), threads))
         t0 = time.perf_counter()
         ref = oracle.rgf_selected(p_s)
         t_cpu = time.perf_counter() - t0
+        ref["T_L"] = oracle.transmission_left(ref["GR_d"][:, 0], p_s.gamma_L)
+        ref["j_L"] = oracle.contact_current_left(ref["GR_d"][:, 0], ref["GL_d"][:, 0], p_s.gamma_L, p_s.f_L)
+        kappa = kappa_bounds(p_s, ref, eta) if args.workload == "hard" else None
         cpu = {"value": len(sample) / t_cpu, "unit": "energy points/s", "cores": int(threads), "kind": "oracle",
                "sample": "%d of the 256 energies (every %dth) of the realistic workload, block recurrences in "
                          "numpy/LAPACK FP64, %.1f s" % (len(sample), n_e // len(sample), t_cpu)}
@@ -204,6 +217,12 @@ def main():
             for key in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u"):
                 got = getattr(dp, key)[sample].cpu().numpy()
                 errs[key] = float(oracle.rel_fro_err(got, ref[key]).max())
+            # observables from the library's own kernel on the GPU outputs; error relative
+            # to the largest magnitude over the sample
+            T, j = ctx.observables(dp, gamma_L, f_L)
+            for key, got in (("T_L", T), ("j_L", j)):
+                g = got.cpu().numpy()[sample]
+                errs[key] = float(np.abs(g - ref[key]).max() / max(np.abs(ref[key]).max(), 1e-300))
         results[prec] = dict(ms_per_step=ms_step, value=n_e / (ms_step / 1e3), status_ok=bool(np.all(st == 0)),
                              gemm=(g_ms, g_n, g_fl), inv=(i_ms, i_n, i_fl), conv=(c_ms, c_n, c_by), errs=errs)
         log("bench: %s %.1f ms/step, %.1f energies/s, product kernel avg %.3f ms x%d, conversion %.1f ms/step, "
@@ -244,8 +263,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if best == "fp64" else "f64+" + best.replace(":", "x"),
         "data": "synthetic",
-        "config": {"workload": "realistic selected RGF solve: n_b=32 blocks, b=416, N_E=256 energies in [-2,2], "
-                               "complex128, S=I, random Hermitian H (seed 0), eta=1e-3, gamma=0.5",
+        "config": {"workload": "%sselected RGF solve: n_b=32 blocks, b=416, N_E=256 energies in [-2,2], "
+                               "complex128, S=I, random Hermitian H (seed 0), eta=%g, gamma=0.5"
+                               % ("realistic " if args.workload == "realistic" else "hard (ill-conditioned) ", eta),
                    "precision": best, "energies_per_step": n_e},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": (achieved / peak) if achieved else None, "traffic": traffic,
@@ -269,8 +289,131 @@ def main():
         "autotune": tuned,
         "algorithmic_tflops_fp64eq": (144 * (n_b - 1) + 24) * b ** 3 * n_e / (r["ms_per_step"] / 1e3) / 1e12,
     }
+    if kappa is not None:
+        line["kappa_sampled"] = kappa
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def _spec_norm(mv, rmv, n, iters=40, seed=0):
+    """Largest singular value of the operator x -> mv(x) by power iteration on
+    rmv(mv(.)) (a lower bound that converges from below)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x /= np.linalg.norm(x)
+    s = 0.0
+    for _ in range(iters):
+        y = rmv(mv(x))
+        s = np.sqrt(np.linalg.norm(y))
+        x = y / np.linalg.norm(y)
+    return float(s)
+
+
+def kappa_bounds(p, ref, eta):
+    """Bounds on the 2-norm condition number of M(E) = E - H - Sigma^R at the
+    sampled energies: sigma_min(M) >= eta (the anti-Hermitian part of M is at
+    least eta), so kappa <= ||M|| / eta; and ||M^-1|| >= max_i ||G^R_ii||, so
+    kappa >= ||M|| max_i ||G^R_ii||.  Norms by power iteration."""
+    import numpy as np
+    n_b, b = p.n_b, p.b
+    lo, hi = [], []
+    for k in range(p.n_e):
+        E = p.energies[k]
+        D = [E * np.eye(b) - p.H_d[i] - p.SR_d[k, i] for i in range(n_b)]
+        U = [-p.H_u[i] for i in range(n_b - 1)]
+        L = [-p.H_l[i] for i in range(n_b - 1)]
+
+        def mv(x, D=D, U=U, L=L, adj=False):
+            X = x.reshape(n_b, b)
+            Y = np.empty_like(X)
+            for i in range(n_b):
+                y = (D[i].conj().T if adj else D[i]) @ X[i]
+                if i + 1 < n_b:
+                    y = y + ((L[i].conj().T if adj else U[i]) @ X[i + 1])
+                if i > 0:
+                    y = y + ((U[i - 1].conj().T if adj else L[i - 1]) @ X[i - 1])
+                Y[i] = y
+            return Y.reshape(-1)
+        nM = _spec_norm(mv, lambda x: mv(x, adj=True), n_b * b)
+        g = max(_spec_norm(lambda x, G=G: G @ x, lambda x, G=G: G.conj().T @ x, b, iters=30)
+                for G in ref["GR_d"][k])
+        lo.append(nM * g)
+        hi.append(nM / eta)
+    return {"lower_max": max(lo), "lower_min": min(lo), "upper": max(hi),
+            "note": "kappa_2(M) per sampled energy lies in [||M|| max_i ||G^R_ii||, ||M||/eta]"}
+
+
+def bench_kappa(args):
+    """Error of each scheme against the exact 2-norm condition number of M(E)
+    (singular values of the dense matrix), as the paper relates emulation error to
+    conditioning.  The synthetic device with n_b = 8, b = 128 (N = 1024) is closed
+    (no contact broadening, gamma = 0), so that sigma_min(M) is set by eta alone at
+    an eigenvalue of H: 4 energies are eigenvalues of H (kappa ~ ||M|| / eta) and 4
+    lie on the grid linspace(-1.9, 1.9, 4), for eta = 1e-2 ... 1e-7.  Reference: the
+    FP64 oracle's block recurrences."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2606_25595_amd import inputs, qtx
+    n_b, b = 8, 128
+    H_d, H_u, H_l = inputs.random_hamiltonian(n_b, b, 0)
+    Hd = np.zeros((n_b * b, n_b * b), complex)
+    for i in range(n_b):
+        Hd[i * b:(i + 1) * b, i * b:(i + 1) * b] = H_d[i]
+        if i + 1 < n_b:
+            Hd[i * b:(i + 1) * b, (i + 1) * b:(i + 2) * b] = H_u[i]
+            Hd[(i + 1) * b:(i + 2) * b, i * b:(i + 1) * b] = H_l[i]
+    lam = np.linalg.eigvalsh(Hd)
+    on = np.array([lam[np.argmin(np.abs(lam - x))] for x in np.linspace(-1.5, 1.5, 4)])
+    grid = np.concatenate([on, np.linspace(-1.9, 1.9, 4)])
+    n_e = grid.size
+    precs = args.precs.split(",")
+    ctx = qtx.Context(0)
+    rows = []
+    for eta in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7):
+        p = inputs.random_bt_problem(n_b, b, grid, seed=0, eta=eta, gamma=0.0)
+        ref = oracle.rgf_selected(p)
+        kap = np.array([(lambda s: s[0] / s[-1])(np.linalg.svd(oracle.assemble_dense(p, e)[0], compute_uv=False))
+                        for e in range(n_e)])
+        kap_s = np.array([max(np.linalg.cond(S) for S in oracle.schur_complements(p, e)) for e in range(n_e)])
+        dp = qtx.to_device(p)
+        for prec in precs:
+            ctx.solve(dp, **parse_scheme(prec))
+            torch.cuda.synchronize()
+            out = dp.outputs()
+            for e in range(n_e):
+                err = {k: float(oracle.rel_fro_err(out[k][e], ref[k][e]).max())
+                       for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")}
+                rows.append({"eta": eta, "E": float(grid[e]), "on_eigenvalue": bool(e < 4), "kappa": float(kap[e]),
+                             "kappa_schur": float(kap_s[e]), "scheme": prec, "err": err})
+        log("bench kappa: eta=%g kappa(M) %.2e .. %.2e, max_i kappa(S_i) %.2e .. %.2e" % (
+            eta, kap.min(), kap.max(), kap_s.min(), kap_s.max()))
+    ctx.close()
+    # error envelope per scheme and decade of kappa(M), then of max_i kappa(S_i)
+    def envelope(kkey):
+        table = {}
+        for r in rows:
+            dec = int(np.floor(np.log10(r[kkey])))
+            key = "%s|1e%d" % (r["scheme"], dec)
+            t = table.setdefault(key, {"scheme": r["scheme"], "decade": "1e%d" % dec, "n": 0,
+                                       "max_err_GR": 0.0, "max_err_GL": 0.0})
+            t["n"] += 1
+            t["max_err_GR"] = max(t["max_err_GR"], r["err"]["GR_d"], r["err"]["GR_u"], r["err"]["GR_l"])
+            t["max_err_GL"] = max(t["max_err_GL"], r["err"]["GL_d"], r["err"]["GL_u"])
+        env = sorted(table.values(), key=lambda t: (t["scheme"], float(t["decade"])))
+        for t in env:
+            log("bench kappa: %-18s %s~%-5s (%2d points): G^R %.2e  G^< %.2e" % (
+                t["scheme"], kkey, t["decade"], t["n"], t["max_err_GR"], t["max_err_GL"]))
+        return env
+    env = envelope("kappa")
+    env_s = envelope("kappa_schur")
+    line = {"metric": "max relative error per block type against the exact condition number of M(E)",
+            "unit": "relative Frobenius error", "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": "kappa: closed device n_b=8, b=128, 4 energies on eigenvalues of H + 4 on "
+                                   "linspace(-1.9,1.9,4), eta in {1e-2..1e-7}, gamma=0, seed 0"},
+            "envelope_kappa_M": env, "envelope_kappa_schur": env_s, "points": rows}
+    print(json.dumps(line), flush=True)
 
 
 def bench_batch(args):

@@ -17,5 +17,5 @@ Parity is pinned (tests/test_oracle_*.py) by closed forms of a uniform chain
 and a uniform strip, exact rational brute force on tiny systems, and the
 structural invariants of lesser/greater/retarded functions.
 """
-from .rgf_oracle import dense_selected, rgf_selected, assemble_dense, OUTPUT_KEYS  # noqa: F401
+from .rgf_oracle import dense_selected, rgf_selected, assemble_dense, schur_complements, OUTPUT_KEYS  # noqa: F401
 from .observables import transmission_left, contact_current_left, bond_currents, rel_fro_err  # noqa: F401

@@ -211,6 +211,20 @@ def _rgf_one(A, U, L, rhs_list):
     return GRd, GRu, GRl, outs
 
 
+def schur_complements(p, e):
+    """The forward Schur complements of M(E_e) in block order (block Gaussian
+    elimination, Section IV-A): S_0 = A_0, S_i = A_i - L_{i-1} S_{i-1}^-1 U_{i-1}.
+    S_i is the Schur complement of the leading i-block submatrix in the leading
+    (i+1)-block submatrix, so S_i^-1 is the last diagonal block of that
+    submatrix's inverse; these are the matrices the recurrences invert, and their
+    condition numbers (not only that of M) set the rounding error of the method."""
+    A, U, L = _system_blocks(p, e)
+    S = [A[0]]
+    for i in range(1, len(A)):
+        S.append(A[i] - L[i - 1] @ np.linalg.inv(S[i - 1]) @ U[i - 1])
+    return S
+
+
 def rgf_selected(p, energy_index=None):
     """Selected blocks by the block recurrences (see _rgf_one), per energy."""
     idx = list(range(p.n_e) if energy_index is None else energy_index)

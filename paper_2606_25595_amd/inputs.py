@@ -195,14 +195,16 @@ CONFIGS = {
 }
 
 
-def config_problem(name: str, energy_index=None, seed: int = 0) -> BTProblem:
+def config_problem(name: str, energy_index=None, seed: int = 0, eta: float = 1e-3) -> BTProblem:
     """A named workload with the uniform energy grid linspace(-2, 2, n_e).
-    `energy_index` selects a subset of the grid (the device is the same)."""
+    `energy_index` selects a subset of the grid (the device is the same);
+    `eta` is the broadening of every block (1e-3 in the named workloads, 1e-6 in
+    their ill-conditioned "hard" variants)."""
     c = CONFIGS[name]
     grid = np.linspace(-2.0, 2.0, c["n_e"])
     if energy_index is not None:
         grid = grid[np.asarray(energy_index)]
-    return random_bt_problem(c["n_b"], c["b"], grid, seed=seed)
+    return random_bt_problem(c["n_b"], c["b"], grid, seed=seed, eta=eta)
 
 
 # --------------------------------------------------------------------------

@@ -278,3 +278,28 @@ def test_rgf_realistic_workload_sampled(ctx):
     out = {k: getattr(dp, k)[sample].cpu().numpy() for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")}
     worst = check_blocks(out, ref)
     print("realistic sampled worst rel err:", worst)
+
+
+# ----------------------------------------------------------------- ill-conditioned ("hard") inputs
+
+@pytest.mark.parametrize("eta", [1e-3, 1e-6])
+def test_rgf_fp64_error_scales_with_schur_conditioning(ctx, eta):
+    """Closed device (no contact broadening) at an eigenvalue of H and off it: the
+    FP64 error of G^R stays within 100 eps kappa, kappa the largest condition number
+    of the Schur complements the recurrences invert (Eq. 6 sets the kappa eps scale;
+    kappa(M) alone under-estimates it where a leading submatrix is near resonance)."""
+    n_b, b = 6, 64
+    H_d, H_u, H_l = inputs.random_hamiltonian(n_b, b, 0)
+    p0 = inputs.random_bt_problem(n_b, b, np.array([0.0]), seed=0, eta=eta, gamma=0.0)
+    lam = np.linalg.eigvalsh(0.5 * ((lambda M: M + M.conj().T)(-oracle.assemble_dense(p0, 0)[0])))
+    E = np.array([lam[np.argmin(np.abs(lam - 0.4))], -1.3])
+    p = inputs.random_bt_problem(n_b, b, E, seed=0, eta=eta, gamma=0.0)
+    _, out = solve_gpu(ctx, p)
+    assert np.all(out["status"] == 0)
+    ref = oracle.rgf_selected(p)
+    eps = np.finfo(np.float64).eps
+    for e in range(p.n_e):
+        kap = max(np.linalg.cond(S) for S in oracle.schur_complements(p, e))
+        for k in ("GR_d", "GR_u", "GR_l"):
+            err = oracle.rel_fro_err(out[k][e], ref[k][e]).max()
+            assert err <= 100 * eps * kap, (k, e, err, kap)

@@ -333,3 +333,21 @@ def test_dense_and_rgf_agree_on_tiny_workload():
         assert oracle.rel_fro_err(r[key], d[key]).max() < 1e-11
     for key in ("GL_d", "GL_u"):
         assert oracle.rel_fro_err(r[key], d[key]).max() < 1e-10
+
+
+@pytest.mark.parametrize("bt_sigma", [0.0, 0.05])
+def test_schur_complements_are_leading_submatrix_inverses(bt_sigma):
+    """Each forward Schur complement S_i inverts to the last diagonal block of the
+    inverse of the leading (i+1)-block submatrix of M (dense inverse, LAPACK), so
+    the last one inverts to G^R_nn; the first is A_0 itself."""
+    p = inputs.random_bt_problem(5, 7, np.array([-0.8, 0.45]), seed=17, bt_sigma=bt_sigma)
+    b = p.b
+    for e in range(p.n_e):
+        M = oracle.assemble_dense(p, e)[0]
+        S = oracle.schur_complements(p, e)
+        assert len(S) == p.n_b
+        np.testing.assert_array_equal(S[0], M[:b, :b])
+        for i in range(p.n_b):
+            k = (i + 1) * b
+            lead_inv = np.linalg.inv(M[:k, :k])
+            np.testing.assert_allclose(np.linalg.inv(S[i]), lead_inv[k - b:k, k - b:k], rtol=0, atol=1e-12)
