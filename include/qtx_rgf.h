@@ -192,8 +192,16 @@ qtx_status qtx_rgf_solve(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int32_t 
  *                  captured into a hipGraph (QTX_OPT_GRAPH) never use the side
  *                  stream.  Off by default: at 256 energies of b = 416 the
  *                  persistent product kernels occupy every CU, so the overlap only
- *                  adds contention (measured 2% slower). */
-enum { QTX_OPT_GRAPH = 1, QTX_OPT_RESERVE_WORKSPACE = 2, QTX_OPT_INT8_TILE_VARIANT = 3, QTX_OPT_OVERLAP = 4 };
+ *                  adds contention (measured 2% slower).
+ *   QTX_OPT_LANE_SPLIT  value = k in 1..8 (default 1): the energies of each group of
+ *                  one block size and scheme are split (alternately) into k parts
+ *                  that run as independent batches on k internal streams (default
+ *                  priority) forking from and joining back into the solve's stream,
+ *                  so that one part's inversions and operand conversions overlap the
+ *                  other parts' products.  Results are bitwise the same for any k;
+ *                  the workspace is the same in total. */
+enum { QTX_OPT_GRAPH = 1, QTX_OPT_RESERVE_WORKSPACE = 2, QTX_OPT_INT8_TILE_VARIANT = 3, QTX_OPT_OVERLAP = 4,
+       QTX_OPT_LANE_SPLIT = 5 };
 enum { QTX_STAT_GRAPH_LAUNCHES = 1, QTX_STAT_GRAPH_CAPTURES = 2, QTX_STAT_WORKSPACE_BYTES = 3,
        QTX_STAT_TUNE_RECORDS = 4 };
 qtx_status qtx_rgf_set_option(qtx_rgf_ctx ctx, int option, int64_t value);

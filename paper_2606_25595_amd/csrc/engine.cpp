@@ -75,6 +75,7 @@ struct qtx_rgf_ctx_s {
   std::map<TuneKey, TuneRec> tune;
   int o2_force = -1;       // >= 0: every INT8 product uses this tile variant
   bool overlap = false;    // run independent products on a side stream during inversions
+  int lane_split = 1;      // stream lanes each batch group is split over
   bool profiling = false;
   bool use_graph = false;
   bool capturing = false;
@@ -343,7 +344,10 @@ int o2_variant_for(qtx_rgf_ctx ctx, const GemmDesc& d, int p) {
 hipError_t run_product(qtx_rgf_ctx ctx, const GemmDesc& d, const Scheme& sc, const SplitBufs& sb, hipStream_t s) {
   // per-launch timers: the matrix-core kernel (its own operations) and the operand
   // conversion passes (their algorithmic bytes) separately
-  const double mnk = 2.0 * d.M * d.N * d.K * d.batch;
+  // a skew-Hermitian result needs only its elements r <= c (the split scheme
+  // computes them all)
+  const bool half = d.skew && !sc.split();
+  const double mnk = 2.0 * (half ? 0.5 * d.M * (d.M + 1.0) : (double)d.M * d.N) * d.K * d.batch;
   double core_ops = 4.0 * mnk;   // FP64 / FP32: four real products
   if (sc.split()) core_ops = 4.0 * (sc.ns * (sc.ns + 1) / 2) * mnk;
   const bool prof = d.K > 0;
@@ -653,9 +657,10 @@ struct Gemm {
   SplitBufs sb;
   bool on_side = false;     // launch on the run's side stream
 
-  // C = alpha * op(A) op(B) + addends (+ diag * E_z I), over the first Z entries
+  // C = alpha * op(A) op(B) + addends (+ diag * E_z I), over the first Z entries;
+  // skew: the result is skew-Hermitian (only r <= c computed, mirrored)
   hipError_t go(int Z, int opA, Mat A, int opB, Mat B, Mat C, double2 alpha, std::initializer_list<Addend> adds,
-                double2 diag = cmk(0, 0), int K = -1) const {
+                double2 diag = cmk(0, 0), int K = -1, bool skew = false) const {
     if (run->dry || Z <= 0) return hipSuccess;
     GemmDesc d;
     d.M = b; d.N = b; d.K = (K < 0) ? b : K;
@@ -676,6 +681,7 @@ struct Gemm {
     d.diag_by_batch = 1;
     d.bscal = energies;
     d.batch = Z;
+    d.skew = skew ? 1 : 0;
     return run_product(run->ctx, d, sc, sb, on_side ? run->side : run->s);
   }
 };
@@ -789,11 +795,12 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
       const Mat Bi = R.get(r.S, 0, i, 0);
       hipError_t e = G.go(Z, OP_N, L, OP_N, R.get(r.Gd, 0, i, -1), ws(W.Tm[1]), one, {});
       if (e != hipSuccess) return e;
-      if (r.SU < 0) return G.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one, {addend_of(Bi, one)});
+      if (r.SU < 0) return G.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one, {addend_of(Bi, one)}, zero, -1, true);
       e = G.go(Z, OP_N, ws(W.Tm[0]), OP_N, R.get(r.SU, 0, i, -1), ws(W.Tm[4]), one, {});
       if (e != hipSuccess) return e;
       return G.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one,
-                  {addend_of(Bi, one), addend_of(ws(W.Tm[4]), cmk(-sL, 0)), addend_of(ws(W.Tm[4]), cmk(sL, 0), OP_C)});
+                  {addend_of(Bi, one), addend_of(ws(W.Tm[4]), cmk(-sL, 0)), addend_of(ws(W.Tm[4]), cmk(sL, 0), OP_C)},
+                  zero, -1, true);
     };
     if (i > 0) {
       if (side) {
@@ -818,8 +825,8 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
         if (q > 0) QTX_TRY(lesser_q(gl, r));
         QTX_TRY(gl.go(Z, OP_N, xi, OP_N, ws(W.Tm[3]), ws(W.Tm[2]), one, {}));
       }
-      // xl_i = Z x_i^H
-      QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[2]), OP_C, xi, R.get(r.Gd, 0, i, 0), one, {}));
+      // xl_i = Z x_i^H (skew-Hermitian)
+      QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[2]), OP_C, xi, R.get(r.Gd, 0, i, 0), one, {}, zero, -1, true));
     }
   }
   // ------------------------------------------------------------ backward (i = n_b - 2 - kk per entry)
@@ -860,7 +867,7 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
       QTX_TRY(gl.go(Z, OP_N, Pp, OP_N, Gln, Vp, one, {}));                        // V' = P' G<_{i+1}
       QTX_TRY(gl.go(Z, OP_N, Zp, OP_C, Gn, R.get(r.Gu, 1, kk, 0), one, {addend_of(Vp, cmk(-sU, 0))}));
       QTX_TRY(gl.go(Z, OP_N, Vp, OP_C, Pp, xl, one,                               // G<_ii (in place)
-                    {addend_of(xl, one), addend_of(Yp, one), addend_of(Yp, cmk(-1, 0), OP_C)}));
+                    {addend_of(xl, one), addend_of(Yp, one), addend_of(Yp, cmk(-1, 0), OP_C)}, zero, -1, true));
     }
     QTX_TRY(g.go(Z, OP_N, GRu, OP_N, Rp, xi, cmk(-sL, 0), {addend_of(xi, one)}));   // G_ii (in place)
   }
@@ -895,15 +902,31 @@ struct Hasher {
 
 // Plan, upload and run (or capture / replay) a full solve.
 qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs, hipStream_t s) {
-  // 1. group entries by batch key; each group becomes one or more batches (chunks)
+  // 1. group entries by batch key, split each group over lane_split stream lanes
+  //    (alternate entries, so that the parts carry the same mix of n_b); each part
+  //    becomes one or more batches (chunks) on its own lane
   std::vector<BatchKey> keys;
   std::vector<std::vector<Entry>> groups;
-  for (int q = 0; q < n_probs; ++q) {
-    const BatchKey k = key_of(probs[q]);
-    size_t g = 0;
-    while (g < keys.size() && !(keys[g] == k)) ++g;
-    if (g == keys.size()) { keys.push_back(k); groups.emplace_back(); }
-    for (int e = 0; e < probs[q].n_e; ++e) groups[g].push_back({&probs[q], e});
+  {
+    std::vector<BatchKey> gkeys;
+    std::vector<std::vector<Entry>> gents;
+    for (int q = 0; q < n_probs; ++q) {
+      const BatchKey k = key_of(probs[q]);
+      size_t g = 0;
+      while (g < gkeys.size() && !(gkeys[g] == k)) ++g;
+      if (g == gkeys.size()) { gkeys.push_back(k); gents.emplace_back(); }
+      for (int e = 0; e < probs[q].n_e; ++e) gents[g].push_back({&probs[q], e});
+    }
+    for (size_t g = 0; g < gkeys.size(); ++g) {
+      auto& ent = gents[g];
+      std::stable_sort(ent.begin(), ent.end(), [](const Entry& a, const Entry& b) { return a.p->n_b > b.p->n_b; });
+      const size_t parts = std::min<size_t>((size_t)std::max(1, ctx->lane_split), ent.size());
+      for (size_t j = 0; j < parts; ++j) {
+        keys.push_back(gkeys[g]);
+        groups.emplace_back();
+        for (size_t z = j; z < ent.size(); z += parts) groups.back().push_back(ent[z]);
+      }
+    }
   }
   size_t total_need = 0;
   for (size_t g = 0; g < keys.size(); ++g) total_need += per_entry_bytes(keys[g]) * groups[g].size();
@@ -1187,6 +1210,15 @@ qtx_status qtx_rgf_set_option(qtx_rgf_ctx ctx, int option, int64_t value) {
         drop_graphs(ctx);   // captured launches carry the old stream structure
       }
       ctx->overlap = value != 0;
+      return QTX_OK;
+    case QTX_OPT_LANE_SPLIT:
+      if (value < 1 || value > 8) return QTX_ERR_ARG;
+      if (ctx->lane_split != (int)value) {
+        DeviceGuard guard(ctx->device);
+        (void)hipDeviceSynchronize();
+        drop_graphs(ctx);   // captured launches carry the old stream structure
+      }
+      ctx->lane_split = (int)value;
       return QTX_OK;
     case QTX_OPT_INT8_TILE_VARIANT:
       if (value < -1 || value >= o2_variant_count()) return QTX_ERR_ARG;

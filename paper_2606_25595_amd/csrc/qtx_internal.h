@@ -60,6 +60,12 @@ struct GemmDesc {
   int diag_by_batch = 0;
   const double* bscal = nullptr;   // per-batch real scalars (the energies), device
   int batch = 1;
+  // skew = 1: the caller guarantees that C_z is skew-Hermitian (M == N, every addend
+  // skew-Hermitian, diag purely imaginary).  The FP64, FP32 and INT8 kernels then
+  // compute only the elements r <= c, write each r < c element also at (c, r) as
+  // -conj, and store the diagonal with its real part set to zero; the other schemes
+  // compute every element.
+  int skew = 0;
 };
 
 // Precision schemes of the complex block products.

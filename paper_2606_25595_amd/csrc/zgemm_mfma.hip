@@ -114,6 +114,8 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
   const int t = tile - z * per;
   const int m0 = (t % tiles_m) * BM;
   const int n0 = (t / tiles_m) * BN;
+  const bool skew = d.skew != 0;
+  if (skew && m0 >= n0 + BN) return;   // strictly below the diagonal: written as mirror images
 
   const double2* __restrict__ A = d.tA ? d.tA[z] : d.A + (int64_t)z * d.sA;
   const double2* __restrict__ B = d.tB ? d.tB[z] : d.B + (int64_t)z * d.sB;
@@ -124,13 +126,16 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
   const int wm = wave & 1, wn = wave >> 1;
   const int M = d.M, N = d.N, K = d.K;
 
-  // this wave's blocks: rows m0 + 16*(wm + 2i), columns n0 + 16*(wn + 2j)
-  bool rv[2], cv[2];
+  // this wave's blocks: rows m0 + 16*(wm + 2i), columns n0 + 16*(wn + 2j); a block
+  // is live if it lies in C (and, for a skew-Hermitian C, touches r <= c)
+  bool live[2][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    rv[i] = m0 + 16 * (wm + 2 * i) < M;
-    cv[i] = n0 + 16 * (wn + 2 * i) < N;
-  }
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int rb = m0 + 16 * (wm + 2 * i), cb = n0 + 16 * (wn + 2 * j);
+      live[i][j] = rb < M && cb < N && !(skew && rb >= cb + 16);
+    }
 
   acc_t acc_re[2][2], acc_im[2][2];
 #pragma unroll
@@ -179,22 +184,22 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          if (rv[i] && cv[j]) acc_re[i][j] = MATH::mfma(a[i].x, b[j].x, acc_re[i][j]);
+          if (live[i][j]) acc_re[i][j] = MATH::mfma(a[i].x, b[j].x, acc_re[i][j]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          if (rv[i] && cv[j]) acc_im[i][j] = MATH::mfma(a[i].x, b[j].y, acc_im[i][j]);
+          if (live[i][j]) acc_im[i][j] = MATH::mfma(a[i].x, b[j].y, acc_im[i][j]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          if (rv[i] && cv[j]) acc_re[i][j] = MATH::mfma(na[i], b[j].y, acc_re[i][j]);
+          if (live[i][j]) acc_re[i][j] = MATH::mfma(na[i], b[j].y, acc_re[i][j]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          if (rv[i] && cv[j]) acc_im[i][j] = MATH::mfma(a[i].y, b[j].x, acc_im[i][j]);
+          if (live[i][j]) acc_im[i][j] = MATH::mfma(a[i].y, b[j].x, acc_im[i][j]);
     }
   }
 
@@ -214,12 +219,12 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      if (!(rv[i] && cv[j])) continue;
+      if (!live[i][j]) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = m0 + 16 * (wm + 2 * i) + MATH::row(lk, v);
         const int c = n0 + 16 * (wn + 2 * j) + li;
-        if (r < M && c < N) {
+        if (r < M && c < N && !(skew && r > c)) {
           double2 out = cmul(d.alpha, cmk((double)acc_re[i][j][v], (double)acc_im[i][j][v]));
 #pragma unroll
           for (int q = 0; q < kMaxAddends; ++q) {
@@ -230,7 +235,11 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
             }
           }
           if (r == c) out = cadd(out, dg);
+          // a skew-Hermitian diagonal is imaginary: its rounding-level real part is
+          // dropped (left in, the lesser recurrences amplify it coherently)
+          if (skew && r == c) out.x = 0.0;
           C[(int64_t)r * d.ldc + c] = out;
+          if (skew && r < c) C[(int64_t)c * d.ldc + r] = cmk(-out.x, out.y);
         }
       }
     }
@@ -340,6 +349,7 @@ static void launch_kind(const GemmDesc& d, dim3 grid, dim3 block, hipStream_t s)
 
 static hipError_t launch_zgemm_mfma(const GemmDesc& d, hipStream_t s, int kind, bool fp32) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
+  if (d.skew && d.M != d.N) return hipErrorInvalidValue;
   const int tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
   const int64_t total = (int64_t)tiles * d.batch;
   if (total > 0x7fffffff) return hipErrorInvalidValue;
@@ -349,6 +359,7 @@ static hipError_t launch_zgemm_mfma(const GemmDesc& d, hipStream_t s, int kind, 
     e.opA = OP_N; e.opB = OP_N;
     launch_kind<GEMM_ELEMENTWISE, MathF64>(e, grid, block, s);
   } else if (kind == GEMM_INV_UPDATE) {
+    if (d.skew) return hipErrorInvalidValue;
     // contract of the update form: C = X + A B, op N, K <= BK, X the only addend (op N)
     if (d.K > BK || d.opA != OP_N || d.opB != OP_N || d.alpha.x != 1.0 || d.alpha.y != 0.0 ||
         (!d.add[0].X && !d.add[0].tX) || d.add[0].op != OP_N || d.add[0].coef.x != 1.0 || d.add[0].coef.y != 0.0 ||

@@ -431,6 +431,8 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
   const int t = tile - z * per;
   const int m0 = (t % tiles_m) * O2_BM;
   const int n0 = (t / tiles_m) * O2_BN;
+  const bool skew = d.skew != 0;
+  if (skew && m0 >= n0 + O2_BN) continue;   // strictly below the diagonal (workgroup-uniform)
   const int M = d.M, N = d.N, K = d.K;
   const int KT = (K + KS - 1) / KS;
   const int NSTRIP = P.p * KT;                  // (modulus, strip) pairs, modulus-major
@@ -442,7 +444,8 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % (O2_BM / 32), wn = wave / (O2_BM / 32);
-  const bool wlive = (m0 + 32 * wm < M) && (n0 + 32 * wn < N);   // wave-uniform
+  const bool wlive = (m0 + 32 * wm < M) && (n0 + 32 * wn < N) &&
+                     !(skew && m0 + 32 * wm >= n0 + 32 * wn + 32);   // wave-uniform
 
   if (tid < O2_BM) Ea[tid] = (m0 + tid < M) ? EA[m0 + tid] : 0;
   else if (tid < O2_BM + O2_BN) Eb[tid - O2_BM] = (n0 + tid - O2_BM < N) ? EB[n0 + tid - O2_BM] : 0;
@@ -501,7 +504,7 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
   for (int v = 0; v < 16; ++v) {
     const int rl = 32 * wm + 8 * (v >> 2) + 4 * lk + (v & 3);
     const int r = m0 + rl;
-    if (wlive && r < M && col < N) {
+    if (wlive && r < M && col < N && !(skew && r > col)) {
       const double sc = pow2(Ea[rl] + eb - 2 * P.kbits - 2) * P.M;
       const double cr = (acc.sre[v] - rint(acc.sre[v])) * sc;
       const double ci = (acc.sim[v] - rint(acc.sim[v])) * sc;
@@ -515,7 +518,9 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
         }
       }
       if (r == col) out = cadd(out, dg);
+      if (skew && r == col) out.x = 0.0;   // a skew-Hermitian diagonal is imaginary
       C[(int64_t)r * d.ldc + col] = out;
+      if (skew && r < col) C[(int64_t)col * d.ldc + r] = cmk(-out.x, out.y);
     }
   }
   __syncthreads();   // Ea / Eb and the ring are reused by the next tile
@@ -628,14 +633,18 @@ int o2_variant_count() { return kO2Variants; }
 hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_t s, int variant) {
   const GemmDesc& d = g.d;
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
+  if (d.skew && d.M != d.N) return hipErrorInvalidValue;
   if (o2_res_stride(d.M, d.K, P.p) > 0x7fffffff || o2_res_stride(d.N, d.K, P.p) > 0x7fffffff)
     return hipErrorInvalidValue;   // per-entry residue offsets are 32-bit in the kernel
+  // A skew-Hermitian result skips the tiles below the diagonal, which would leave
+  // persistent rounds unbalanced: such products always run one tile per workgroup.
+  const bool persist = !d.skew;
   switch (variant) {
-    case 0: return launch_o2_variant<O2V0>(g, P, s, true);
-    case 1: return launch_o2_variant<O2V1>(g, P, s, true);
-    case 2: return launch_o2_variant<O2V2>(g, P, s, true);
-    case 3: return launch_o2_variant<O2V3>(g, P, s, true);
-    case 4: return launch_o2_variant<O2V4>(g, P, s, true);
+    case 0: return launch_o2_variant<O2V0>(g, P, s, persist);
+    case 1: return launch_o2_variant<O2V1>(g, P, s, persist);
+    case 2: return launch_o2_variant<O2V2>(g, P, s, persist);
+    case 3: return launch_o2_variant<O2V3>(g, P, s, persist);
+    case 4: return launch_o2_variant<O2V4>(g, P, s, persist);
     case 5: return launch_o2_variant<O2V4>(g, P, s, false);
     case 6: return launch_o2_variant<O2V1>(g, P, s, false);
     default: return hipErrorInvalidValue;

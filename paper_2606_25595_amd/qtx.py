@@ -35,7 +35,7 @@ PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16"
 EXPORTED = ("qtx_rgf_create", "qtx_rgf_solve", "qtx_rgf_destroy", "qtx_rgf_footprint", "qtx_status_str",
             "qtx_zgemm", "qtx_zinv", "qtx_rgf_observables", "qtx_rgf_profile", "qtx_rgf_profile_read",
             "qtx_rgf_set_option", "qtx_rgf_get_stat", "qtx_ozaki2_bits", "qtx_rgf_tune")
-QTX_OPT_GRAPH, QTX_OPT_RESERVE_WORKSPACE, QTX_OPT_INT8_TILE_VARIANT, QTX_OPT_OVERLAP = 1, 2, 3, 4
+QTX_OPT_GRAPH, QTX_OPT_RESERVE_WORKSPACE, QTX_OPT_INT8_TILE_VARIANT, QTX_OPT_OVERLAP, QTX_OPT_LANE_SPLIT = 1, 2, 3, 4, 5
 QTX_STAT_GRAPH_LAUNCHES, QTX_STAT_GRAPH_CAPTURES, QTX_STAT_WORKSPACE_BYTES, QTX_STAT_TUNE_RECORDS = 1, 2, 3, 4
 QTX_KERNEL_GEMM, QTX_KERNEL_INV, QTX_KERNEL_CONVERT = 0, 1, 2
 
@@ -367,6 +367,12 @@ class Context:
         rc = self.lib.qtx_rgf_set_option(self.handle, QTX_OPT_OVERLAP, 1 if enable else 0)
         if rc != QTX_OK:
             raise QtxError(rc, "qtx_rgf_set_option(overlap)")
+
+    def set_lane_split(self, parts: int = 1):
+        """QTX_OPT_LANE_SPLIT: run each batch group as `parts` batches on parallel streams."""
+        rc = self.lib.qtx_rgf_set_option(self.handle, QTX_OPT_LANE_SPLIT, int(parts))
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_rgf_set_option(LANE_SPLIT)")
 
     def set_int8_tile_variant(self, variant: int = -1):
         """-1: the autotuner's choice per shape; 0.. : force one tile variant."""

@@ -127,3 +127,33 @@ def test_batch_per_problem_scheme_lists(ctx):
         ao = alone.outputs()
         for k in KEYS:
             assert np.array_equal(ao[k], out[k]), (q, k)
+
+
+@pytest.mark.parametrize("prec,ns", [("fp64", 0), ("int8", 10)])
+def test_lane_split_bitwise_equal(ctx, prec, ns):
+    """QTX_OPT_LANE_SPLIT runs each group's energies as k batches on k streams; every
+    output is bitwise the same as with one lane, also under graph capture."""
+    import torch
+    from paper_2606_25595_amd import qtx
+    probs = mixed_problems(seed=3, count=7)
+    ref = [qtx.to_device(p) for p in probs]
+    ctx.solve(ref, prec=prec, n_slices=ns)
+    torch.cuda.synchronize()
+    ref_out = [dp.outputs() for dp in ref]
+    try:
+        for k, graph in ((2, False), (3, False), (2, True)):
+            ctx.set_lane_split(k)
+            ctx.set_graph(graph)
+            dps = [qtx.to_device(p) for p in probs]
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                for _ in range(2 if graph else 1):
+                    ctx.solve(dps, prec=prec, n_slices=ns, stream=stream)
+                stream.synchronize()
+            for dp, r in zip(dps, ref_out):
+                out = dp.outputs()
+                for key in KEYS:
+                    assert np.array_equal(out[key], r[key]), (k, graph, key)
+    finally:
+        ctx.set_lane_split(1)
+        ctx.set_graph(False)

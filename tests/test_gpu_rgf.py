@@ -303,3 +303,23 @@ def test_rgf_fp64_error_scales_with_schur_conditioning(ctx, eta):
         for k in ("GR_d", "GR_u", "GR_l"):
             err = oracle.rel_fro_err(out[k][e], ref[k][e]).max()
             assert err <= 100 * eps * kap, (k, e, err, kap)
+
+
+@pytest.mark.parametrize("prec,ns", [("fp64", 0), ("fp32", 0), ("int8", 11), ("bf16", 3)])
+def test_rgf_lesser_diagonal_blocks_skew_hermitian(ctx, prec, ns):
+    """The products whose results are skew-Hermitian (Q_i, x^<_i, G^<_ii) compute
+    only r <= c and mirror the rest, so G^<_ii and G^>_ii come out exactly
+    skew-Hermitian (bitwise) in the FP64, FP32 and INT8 schemes (the split scheme
+    computes every element); all schemes stay within their error against the oracle."""
+    p = inputs.random_bt_problem(5, 70, np.linspace(-1.7, 1.3, 3), seed=41, with_greater=True, bt_sigma=0.03)
+    _, out = solve_gpu(ctx, p, prec=prec, n_slices=ns)
+    for k in ("GL_d", "GG_d"):
+        X = out[k]
+        if prec != "bf16":
+            iu = np.triu_indices(X.shape[-1], 1)
+            assert np.array_equal(X[..., iu[1], iu[0]], -np.conj(X[..., iu[0], iu[1]])), k
+            assert np.all(np.diagonal(X, axis1=-2, axis2=-1).real == 0.0), k
+    ref = oracle.rgf_selected(p)
+    tol = {"fp64": 1e-10, "fp32": 5e-2, "int8": 1e-6, "bf16": 1e-2}[prec]
+    for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u", "GG_d", "GG_u"):
+        assert oracle.rel_fro_err(out[k], ref[k]).max() <= tol, k
