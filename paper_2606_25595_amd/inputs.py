@@ -31,7 +31,7 @@ import numpy as np
 __all__ = [
     "BTProblem", "fermi", "random_hamiltonian", "random_bt_problem",
     "config_problem", "uniform_chain", "uniform_strip", "chain_lead_lambda",
-    "CONFIGS", "bt_from_dense",
+    "CONFIGS", "bt_from_dense", "WProblem", "random_w_problem", "w_base_matrices", "w_scalars",
 ]
 
 
@@ -351,3 +351,104 @@ def device_random_problem(n_b: int, b: int, energies, seed: int = 0, device="cud
         return torch.from_numpy(np.ascontiguousarray(a)).to(device)
     return dict(energies=energies, H_d=dev(H_d), H_u=dev(H_u), H_l=dev(H_l),
                 SR_d=diag_blocks_device(sr, b, device), SL_d=diag_blocks_device(sl, b, device))
+
+
+# --------------------------------------------------------------------------
+# Screened Coulomb (W) system inputs (the W row of Table I)
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class WProblem:
+    """Inputs of M = I - V P^R(E), B^<> = V P^<>(E) V^H (Table I, W row).
+    V_d [n_b][b][b], V_u [n_b-1][b][b] (Hermitian BT Coulomb matrix, V_l = V_u^H);
+    PR_d/u/l, PL_d/u/l, PG_d/u/l: [n_e][n_b or n_b-1][b][b] polarizations (BT)."""
+    energies: np.ndarray
+    V_d: np.ndarray
+    V_u: np.ndarray
+    PR_d: np.ndarray
+    PR_u: np.ndarray
+    PR_l: np.ndarray
+    PL_d: np.ndarray
+    PL_u: np.ndarray
+    PL_l: np.ndarray
+    PG_d: Optional[np.ndarray] = None
+    PG_u: Optional[np.ndarray] = None
+    PG_l: Optional[np.ndarray] = None
+
+    @property
+    def n_b(self) -> int:
+        return int(self.V_d.shape[0])
+
+    @property
+    def b(self) -> int:
+        return int(self.V_d.shape[1])
+
+    @property
+    def n_e(self) -> int:
+        return int(self.energies.shape[0])
+
+
+def w_base_matrices(n_b: int, b: int, seed: int, v_coupling: float = 0.3, c_k: float = 0.5):
+    """Energy-independent parts of the synthetic W system, from PCG64([seed, 2]):
+    V_ii = I + (X + X^H) / (4 sqrt(2b)) (Hermitian), V_{i,i+1} = v_coupling Y / sqrt(2b)
+    (Y circular complex normal with E|y|^2 = 2, so E|v|^2 = v_coupling^2 / b);
+    P0: a general complex BT matrix with entries of variance 1/b (blocks d, u, l);
+    K: the Hermitian positive semidefinite BT matrix of diagonal blocks 2 c_k I and
+    upper blocks c_k Z / |Z|_F.  Draw order: X_i, Y_i, P0 d, u, l, Z_i (R then J each)."""
+    rng = np.random.default_rng([seed, 2])
+
+    def cn(*shape):
+        return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    nu = max(n_b - 1, 0)
+    V_d = np.empty((n_b, b, b), np.complex128)
+    for i in range(n_b):
+        X = cn(b, b)
+        V_d[i] = np.eye(b) + (X + X.conj().T) / (4.0 * math.sqrt(2.0 * b))
+    V_u = np.empty((nu, b, b), np.complex128)
+    for i in range(nu):
+        V_u[i] = v_coupling * cn(b, b) / math.sqrt(2.0 * b)
+    P0_d = cn(n_b, b, b) / math.sqrt(2.0 * b)
+    P0_u = cn(nu, b, b) / math.sqrt(2.0 * b)
+    P0_l = cn(nu, b, b) / math.sqrt(2.0 * b)
+    K_d = np.broadcast_to(2.0 * c_k * np.eye(b), (n_b, b, b)).astype(np.complex128)
+    K_u = np.empty((nu, b, b), np.complex128)
+    for i in range(nu):
+        Z = cn(b, b)
+        K_u[i] = c_k * Z / np.linalg.norm(Z)
+    return V_d, V_u, (P0_d, P0_u, P0_l), (K_d, K_u)
+
+
+def w_scalars(energies, p_scale: float = 0.3, g_scale: float = 0.2, mu: float = 0.0, kT: float = 0.1):
+    """Per-energy scalars of the polarization: P^R(E) = a(E) P0 - i g(E) K with
+    a(E) = p_scale e^{iE} / (1 + E^2), g(E) = g_scale / (1 + E^2); occupation f(E)
+    (Fermi function at mu, temperature kT) for P^< = -f (P^R - P^A)."""
+    E = np.atleast_1d(np.asarray(energies, dtype=np.float64))
+    a = p_scale * np.exp(1j * E) / (1.0 + E * E)
+    g = g_scale / (1.0 + E * E)
+    return a, g, fermi(E, mu, kT)
+
+
+def random_w_problem(n_b: int, b: int, energies, seed: int = 0, with_greater: bool = False, **kw) -> WProblem:
+    """Synthetic W system on the host (w_base_matrices, w_scalars):
+    P^R = a P0 - i g K;  P^< = -f (P^R - P^A);  P^> = P^< + P^R - P^A.
+    With ||V P^R|| well below 1, M = I - V P^R is well conditioned, as the W
+    systems are (Section IV-A)."""
+    E = np.atleast_1d(np.asarray(energies, dtype=np.float64))
+    V_d, V_u, (P0_d, P0_u, P0_l), (K_d, K_u) = w_base_matrices(n_b, b, seed)
+    a, g, f = w_scalars(E, **kw)
+    K_l = np.conj(np.transpose(K_u, (0, 2, 1)))
+    A = a[:, None, None, None]
+    Gm = g[:, None, None, None]
+    PR_d = A * P0_d[None] - 1j * Gm * K_d[None]
+    PR_u = A * P0_u[None] - 1j * Gm * K_u[None]
+    PR_l = A * P0_l[None] - 1j * Gm * K_l[None]
+    H = lambda X: np.conj(np.swapaxes(X, -1, -2))
+    D_d = PR_d - H(PR_d)                 # (P^R - P^A) blocks
+    D_u = PR_u - H(PR_l)
+    D_l = PR_l - H(PR_u)
+    F = f[:, None, None, None]
+    w = WProblem(energies=E, V_d=V_d, V_u=V_u, PR_d=PR_d, PR_u=PR_u, PR_l=PR_l,
+                 PL_d=-F * D_d, PL_u=-F * D_u, PL_l=-F * D_l)
+    if with_greater:
+        w.PG_d, w.PG_u, w.PG_l = (1.0 - F) * D_d, (1.0 - F) * D_u, (1.0 - F) * D_l
+    return w
