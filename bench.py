@@ -116,10 +116,11 @@ def main():
                          "<retarded>/<lesser>")
     ap.add_argument("--cpu-energies", type=int, default=8, help="energies in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="realistic", choices=["realistic", "hard", "kappa", "batch", "serve"],
+    ap.add_argument("--workload", default="realistic", choices=["realistic", "hard", "kappa", "w", "batch", "serve"],
                     help="realistic (default, the headline line) | hard (the realistic shapes at eta = 1e-6, "
                          "condition numbers up to ~5e6) | kappa (error against the exact condition number, "
-                         "n_b=8, b=128, eta 1e-3..1e-6) | batch (512 uneven problems, one graph launch) | "
+                         "n_b=8, b=128, eta 1e-3..1e-6) | w (screened Coulomb system: assembly + solve, n_b=16, "
+                         "b=256, 128 energies) | batch (512 uneven problems, one graph launch) | "
                          "serve (Poisson arrivals, continuous batching, p50/p99)")
     ap.add_argument("--eta", type=float, default=None, help="realistic/hard: broadening (default 1e-3 / 1e-6)")
     ap.add_argument("--problems", type=int, default=512, help="batch workload: number of problems")
@@ -143,6 +144,8 @@ def main():
         return bench_serve(args)
     if args.workload == "kappa":
         return bench_kappa(args)
+    if args.workload == "w":
+        return bench_w(args)
 
     cfg = inputs.CONFIGS["realistic"]
     n_b, b, n_e = cfg["n_b"], cfg["b"], cfg["n_e"]
@@ -413,6 +416,85 @@ def bench_kappa(args):
             "config": {"workload": "kappa: closed device n_b=8, b=128, 4 energies on eigenvalues of H + 4 on "
                                    "linspace(-1.9,1.9,4), eta in {1e-2..1e-7}, gamma=0, seed 0"},
             "envelope_kappa_M": env, "envelope_kappa_schur": env_s, "points": rows}
+    print(json.dumps(line), flush=True)
+
+
+def bench_w(args):
+    """Screened Coulomb (W) system, the W row of Table I: per step, qtx_w_assemble
+    (BT blocks of V P^R and V P^< V^H) and qtx_rgf_solve of the assembled system, for
+    n_b = 16 blocks of b = 256 at 128 energies in [-2, 2].  V, P0 and K come from
+    inputs.w_base_matrices (seed 0); the per-energy P^R = a(E) P0 - i g(E) K and
+    P^< = -f (P^R - P^A) are built on the device.  Errors on 4 sampled energies
+    against the FP64 oracle (dense assembly, block recurrences) on the same inputs."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2606_25595_amd import inputs, qtx
+    n_b, b, n_e = 16, 256, 128
+    E = np.linspace(-2.0, 2.0, n_e)
+    V_d, V_u, (P0_d, P0_u, P0_l), (K_d, K_u) = inputs.w_base_matrices(n_b, b, 0)
+    a, g, f = inputs.w_scalars(E)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    A = dev(a).view(-1, 1, 1, 1)
+    G = dev(g.astype(np.complex128)).view(-1, 1, 1, 1)
+    F = dev(f.astype(np.complex128)).view(-1, 1, 1, 1)
+    K_l = np.conj(np.transpose(K_u, (0, 2, 1)))
+    PR = [A * dev(P)[None] - 1j * G * dev(Kx)[None] for P, Kx in ((P0_d, K_d), (P0_u, K_u), (P0_l, K_l))]
+    Hh = lambda X: X.conj().transpose(-1, -2)
+    PL_d = -F * (PR[0] - Hh(PR[0]))
+    PL_u = -F * (PR[1] - Hh(PR[2]))
+    dw = qtx.DeviceW(n_e=n_e, V_d=dev(V_d), V_u=dev(V_u), PR_d=PR[0].contiguous(), PR_u=PR[1].contiguous(),
+                     PR_l=PR[2].contiguous(), PL_d=PL_d.contiguous(), PL_u=PL_u.contiguous())
+    torch.cuda.synchronize()
+    sample = [0, 43, 85, 127]
+    log("bench w: oracle on %d sampled energies" % len(sample))
+    host = lambda t: t[sample].cpu().numpy()
+    w_s = inputs.WProblem(energies=E[sample], V_d=V_d, V_u=V_u, PR_d=host(dw.PR_d), PR_u=host(dw.PR_u),
+                          PR_l=host(dw.PR_l), PL_d=host(dw.PL_d), PL_u=host(dw.PL_u),
+                          PL_l=-np.conj(np.swapaxes(host(dw.PL_u), -1, -2)))
+    t0 = time.perf_counter()
+    ref = oracle.w_selected(w_s, "rgf")
+    t_cpu = time.perf_counter() - t0
+    ctx = qtx.Context(0)
+    results = {}
+    for spec in args.precs.split(","):
+        asm_prec, _, solve_spec = spec.partition("+")      # "<assembly scheme>+<solve scheme>"
+        akw = parse_scheme(asm_prec)
+        skw = parse_scheme(solve_spec or asm_prec)
+        autotune(ctx, skw, [(b, n_e)])
+        autotune(ctx, akw, [(b, n_e)])
+
+        def step():
+            asm = ctx.w_assemble(dw, prec=akw["prec"], n_slices=akw.get("n_slices", 0))
+            dp = ctx.w_problem(dw, asm)
+            ctx.solve(dp, **skw)
+            return dp
+        for _ in range(args.warmup):
+            dp = step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dp = step()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        out = {k: getattr(dp, k)[sample].cpu().numpy() for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")}
+        errs = {k: float(oracle.rel_fro_err(out[k], ref[k]).max()) for k in out}
+        results[spec] = {"energies_per_s": n_e / t, "ms_per_step": t * 1e3, "max_rel_err": errs,
+                         "status_ok": bool((dp.status == 0).all().item())}
+        log("bench w: %s %.1f ms/step, %.1f energies/s, err %s" % (spec, t * 1e3, n_e / t, errs))
+        del dp
+    ctx.close()
+    ok = [k for k, v in results.items() if v["status_ok"] and max(v["max_rel_err"].values()) <= TOL_MIXED]
+    best = max(ok or list(results), key=lambda k: results[k]["energies_per_s"])
+    line = {"metric": "W-system energy points/sec (assembly + selected solve) at rel err <= 1e-6",
+            "value": results[best]["energies_per_s"], "unit": "energy points/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": results[best]["ms_per_step"], "higher_is_better": True,
+            "dtype": "f64" if best == "fp64" else "f64+" + best, "data": "synthetic",
+            "config": {"workload": "w: screened Coulomb system, n_b=16, b=256, 128 energies in [-2,2], seed 0",
+                       "precision": best},
+            "schemes": results,
+            "cpu_baseline": {"value": len(sample) / t_cpu, "unit": "energy points/s", "kind": "oracle",
+                             "sample": "%d energies, dense assembly + block recurrences, %.1f s" % (len(sample), t_cpu)}}
     print(json.dumps(line), flush=True)
 
 

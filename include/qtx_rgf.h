@@ -250,6 +250,35 @@ const char* qtx_status_str(qtx_status s);
  * (p in 2..16, K in 1..65536, kbits >= 1). */
 qtx_status qtx_ozaki2_bits(int32_t p, int32_t K, int32_t* moduli, int32_t* p_used, int32_t* kbits);
 
+/* Screened Coulomb (W) system, the W row of Table I: per energy
+ *     M(E) = I - V P^R(E),   B^<>(E) = V P^<>(E) V^H,   W^<> = M^-1 B^<> M^-H,
+ * with V the Coulomb matrix (Hermitian, BT, energy independent) and P the
+ * polarization (BT).  The products of BT matrices are wider than BT; the system
+ * solved is the BT one the paper states (Section II-A: only the BT entries are
+ * needed), so this call returns the BT blocks of V P^R and of V P^<> V^H.  The
+ * W system is then qtx_rgf_solve on energies 1, S = I, H = 0 (zero blocks),
+ * Sigma^R := BT(V P^R) (SR_d/u/l = VPR_d/u/l) and Sigma^< := BT(V P^< V^H)
+ * (SL_d/u = BL_d/u), Sigma^> likewise: its G^R outputs are the BT blocks of
+ * M^-1 and its G^<> outputs those of W^<>.
+ * Inputs (device):
+ *   V_d [n_b][b][b], V_u [n_b-1][b][b] = V_{i,i+1}; V_{i+1,i} = V_u^H is implied.
+ *   PR_d [n_e][n_b][b][b], PR_u / PR_l [n_e][n_b-1][b][b]  P^R blocks.
+ *   PL_d, PL_u  P^< diagonal and upper blocks (P^< skew-Hermitian: the lower
+ *               blocks are -(PL_u)^H).  PG_d, PG_u  P^> likewise, or both NULL.
+ * Outputs (device, caller-allocated, written entirely):
+ *   VPR_d [n_e][n_b][b][b], VPR_u / VPR_l [n_e][n_b-1][b][b]: BT blocks of V P^R.
+ *   BL_d, BL_u (and BG_d, BG_u with PG_*): diagonal and upper BT blocks of
+ *   V P^<> V^H (skew-Hermitian: lower = -(upper)^H).
+ * prec / n_slices: scheme of the block products (qtx_prec), as in qtx_zgemm.
+ * Energies are processed in chunks that fit the context's workspace budget
+ * (four blocks per energy plus converted operands).  Limits: n_b >= 1,
+ * 1 <= b <= 1024, n_e >= 1; u/l pointers may be NULL when n_b = 1. */
+qtx_status qtx_w_assemble(qtx_rgf_ctx ctx, int32_t n_b, int32_t b, int32_t n_e, int32_t prec, int32_t n_slices,
+                          const void* V_d, const void* V_u, const void* PR_d, const void* PR_u, const void* PR_l,
+                          const void* PL_d, const void* PL_u, const void* PG_d, const void* PG_u,
+                          void* VPR_d, void* VPR_u, void* VPR_l, void* BL_d, void* BL_u, void* BG_d, void* BG_u,
+                          void* hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Kernel-level entry points (the building blocks of qtx_rgf_solve), exposed
  * so each can be checked in isolation.

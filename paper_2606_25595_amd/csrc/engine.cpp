@@ -1441,6 +1441,118 @@ qtx_status qtx_rgf_tune(qtx_rgf_ctx ctx, int32_t b, int32_t prec, int32_t n_slic
   return tune_save(ctx) ? QTX_OK : QTX_ERR_ARG;
 }
 
+// ---------------------------------------------------------------- screened Coulomb (W) system
+// BT blocks of V P^R and of V P^<> V^H (the W row of Table I), batched over energies.
+// V is Hermitian BT (V_{i+1,i} = V_u[i]^H); P^<> is skew-Hermitian BT
+// (P_{i+1,i} = -P_u[i]^H).  Row i of Y = V P^< needs Y_{i,i-1}, Y_ii, Y_{i,i+1},
+// Y_{i,i+2}; B_ij = sum_k Y_ik (V_jk)^H for j = i, i+1.
+qtx_status qtx_w_assemble(qtx_rgf_ctx ctx, int32_t n_b, int32_t b, int32_t n_e, int32_t prec, int32_t n_slices,
+                          const void* V_d, const void* V_u, const void* PR_d, const void* PR_u, const void* PR_l,
+                          const void* PL_d, const void* PL_u, const void* PG_d, const void* PG_u, void* VPR_d,
+                          void* VPR_u, void* VPR_l, void* BL_d, void* BL_u, void* BG_d, void* BG_u,
+                          void* hip_stream) {
+  if (!ctx) return QTX_ERR_ARG;
+  if (ctx->sticky != QTX_OK) return ctx->sticky;
+  if (n_b < 1 || b < 1 || b > 1024 || n_e < 1) return QTX_ERR_ARG;
+  if (!V_d || !PR_d || !PL_d || !VPR_d || !BL_d) return QTX_ERR_ARG;
+  if (n_b > 1 && (!V_u || !PR_u || !PR_l || !PL_u || !VPR_u || !VPR_l || !BL_u)) return QTX_ERR_ARG;
+  const bool greater = PG_d != nullptr;
+  if (greater != (BG_d != nullptr)) return QTX_ERR_ARG;
+  if (greater && n_b > 1 && (!PG_u || !BG_u)) return QTX_ERR_ARG;
+  Scheme sc;
+  if (!make_scheme(prec, n_slices, &sc)) return QTX_ERR_UNSUPPORTED;
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int64_t bb = (int64_t)b * b;
+  const int64_t sd = (int64_t)n_b * bb, su = (int64_t)(n_b - 1) * bb;   // per-energy strides
+  // workspace: four Y blocks per energy and the converted operands of one product
+  const size_t per_e = 4 * align_up((size_t)bb * sizeof(double2)) + split_pair_bytes(b, sc, 1) + 1024;
+  const size_t budget = std::max(ws_budget(ctx), per_e + 4096);
+  const int ec = (int)std::max<size_t>(1, std::min<size_t>((size_t)n_e, (budget - 4096) / per_e));
+  const size_t blk = align_up((size_t)ec * bb * sizeof(double2));
+  QTX_TRYS(ensure_ws(ctx, 4 * blk + split_pair_bytes(b, sc, ec) + 4096));
+  char* w = (char*)ctx->ws;
+  double2* Y[4];
+  for (int q = 0; q < 4; ++q) { Y[q] = (double2*)w; w += blk; }
+  const SplitBufs sb = carve_split(w, b, sc, ec);
+  const double2 one = cmk(1, 0), mone = cmk(-1, 0);
+  auto cpt = [](const void* p) { return (const double2*)p; };
+  for (int e0 = 0; e0 < n_e; e0 += ec) {
+    const int Z = std::min(ec, n_e - e0);
+    // C = alpha op(A) op(B) (+ C); A / B: (pointer, per-energy stride; stride 0 = V, shared)
+    auto prod = [&](int opA, const double2* A, int64_t sA, int opB, const double2* B, int64_t sB, double2* C,
+                    int64_t sC, double2 alpha, bool acc) -> hipError_t {
+      GemmDesc d;
+      d.M = b; d.N = b; d.K = b;
+      d.opA = opA; d.opB = opB;
+      d.A = A; d.lda = b; d.sA = sA;
+      d.B = B; d.ldb = b; d.sB = sB;
+      d.C = C; d.ldc = b; d.sC = sC;
+      d.alpha = alpha;
+      if (acc) { d.add[0].X = C; d.add[0].ld = b; d.add[0].stride = sC; d.add[0].coef = one; }
+      d.batch = Z;
+      return run_product(ctx, d, sc, sb, s);
+    };
+    // per-energy block k of an array with per-energy stride st, offset to this chunk
+    auto at = [&](const void* base, int64_t st, int k) { return cpt(base) + e0 * st + (int64_t)k * bb; };
+    auto atw = [&](void* base, int64_t st, int k) { return (double2*)base + e0 * st + (int64_t)k * bb; };
+    auto vd = [&](int k) { return cpt(V_d) + (int64_t)k * bb; };
+    auto vu = [&](int k) { return cpt(V_u) + (int64_t)k * bb; };
+    // ---- BT(V P^R)
+    for (int i = 0; i < n_b; ++i) {
+      double2* C = atw(VPR_d, sd, i);
+      QTX_TRY(prod(OP_N, vd(i), 0, OP_N, at(PR_d, sd, i), sd, C, sd, one, false));
+      if (i > 0) QTX_TRY(prod(OP_C, vu(i - 1), 0, OP_N, at(PR_u, su, i - 1), su, C, sd, one, true));
+      if (i + 1 < n_b) QTX_TRY(prod(OP_N, vu(i), 0, OP_N, at(PR_l, su, i), su, C, sd, one, true));
+    }
+    for (int i = 0; i + 1 < n_b; ++i) {
+      double2* C = atw(VPR_u, su, i);
+      QTX_TRY(prod(OP_N, vd(i), 0, OP_N, at(PR_u, su, i), su, C, su, one, false));
+      QTX_TRY(prod(OP_N, vu(i), 0, OP_N, at(PR_d, sd, i + 1), sd, C, su, one, true));
+      C = atw(VPR_l, su, i);
+      QTX_TRY(prod(OP_C, vu(i), 0, OP_N, at(PR_d, sd, i), sd, C, su, one, false));
+      QTX_TRY(prod(OP_N, vd(i + 1), 0, OP_N, at(PR_l, su, i), su, C, su, one, true));
+    }
+    // ---- BT(V P V^H) for P^< and P^>
+    for (int r = 0; r < (greater ? 2 : 1); ++r) {
+      const void* Pd = r ? PG_d : PL_d;
+      const void* Pu = r ? PG_u : PL_u;
+      void* Bd = r ? BG_d : BL_d;
+      void* Bu = r ? BG_u : BL_u;
+      for (int i = 0; i < n_b; ++i) {
+        const bool lo = i > 0, hi = i + 1 < n_b, hi2 = i + 2 < n_b;
+        double2 *Ym = Y[0], *Y0 = Y[1], *Yp = Y[2], *Yq = Y[3];
+        const int64_t sy = bb;
+        if (lo) {   // Y_{i,i-1} = V_u[i-1]^H P_{i-1,i-1} - V_ii P_u[i-1]^H
+          QTX_TRY(prod(OP_C, vu(i - 1), 0, OP_N, at(Pd, sd, i - 1), sd, Ym, sy, one, false));
+          QTX_TRY(prod(OP_N, vd(i), 0, OP_C, at(Pu, su, i - 1), su, Ym, sy, mone, true));
+        }
+        // Y_ii = V_u[i-1]^H P_u[i-1] + V_ii P_ii - V_u[i] P_u[i]^H
+        QTX_TRY(prod(OP_N, vd(i), 0, OP_N, at(Pd, sd, i), sd, Y0, sy, one, false));
+        if (lo) QTX_TRY(prod(OP_C, vu(i - 1), 0, OP_N, at(Pu, su, i - 1), su, Y0, sy, one, true));
+        if (hi) QTX_TRY(prod(OP_N, vu(i), 0, OP_C, at(Pu, su, i), su, Y0, sy, mone, true));
+        if (hi) {   // Y_{i,i+1} = V_ii P_u[i] + V_u[i] P_{i+1,i+1}
+          QTX_TRY(prod(OP_N, vd(i), 0, OP_N, at(Pu, su, i), su, Yp, sy, one, false));
+          QTX_TRY(prod(OP_N, vu(i), 0, OP_N, at(Pd, sd, i + 1), sd, Yp, sy, one, true));
+        }
+        if (hi2) QTX_TRY(prod(OP_N, vu(i), 0, OP_N, at(Pu, su, i + 1), su, Yq, sy, one, false));   // Y_{i,i+2}
+        // B_ii = Y_{i,i-1} V_u[i-1] + Y_ii V_ii^H + Y_{i,i+1} V_u[i]^H
+        double2* C = atw(Bd, sd, i);
+        QTX_TRY(prod(OP_N, Y0, sy, OP_C, vd(i), 0, C, sd, one, false));
+        if (lo) QTX_TRY(prod(OP_N, Ym, sy, OP_N, vu(i - 1), 0, C, sd, one, true));
+        if (hi) QTX_TRY(prod(OP_N, Yp, sy, OP_C, vu(i), 0, C, sd, one, true));
+        if (hi) {   // B_{i,i+1} = Y_ii V_u[i] + Y_{i,i+1} V_{i+1,i+1}^H + Y_{i,i+2} V_u[i+1]^H
+          C = atw(Bu, su, i);
+          QTX_TRY(prod(OP_N, Y0, sy, OP_N, vu(i), 0, C, su, one, false));
+          QTX_TRY(prod(OP_N, Yp, sy, OP_C, vd(i + 1), 0, C, su, one, true));
+          if (hi2) QTX_TRY(prod(OP_N, Yq, sy, OP_C, vu(i + 1), 0, C, su, one, true));
+        }
+      }
+    }
+  }
+  return QTX_OK;
+}
+
 qtx_status qtx_zinv(qtx_rgf_ctx ctx, int32_t n, const void* A, int64_t sA, void* Ainv, int64_t sAinv,
                     int32_t batch, int32_t* status, void* hip_stream) {
   if (!ctx) return QTX_ERR_ARG;

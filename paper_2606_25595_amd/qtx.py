@@ -34,7 +34,7 @@ PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16"
 
 EXPORTED = ("qtx_rgf_create", "qtx_rgf_solve", "qtx_rgf_destroy", "qtx_rgf_footprint", "qtx_status_str",
             "qtx_zgemm", "qtx_zinv", "qtx_rgf_observables", "qtx_rgf_profile", "qtx_rgf_profile_read",
-            "qtx_rgf_set_option", "qtx_rgf_get_stat", "qtx_ozaki2_bits", "qtx_rgf_tune")
+            "qtx_rgf_set_option", "qtx_rgf_get_stat", "qtx_ozaki2_bits", "qtx_rgf_tune", "qtx_w_assemble")
 QTX_OPT_GRAPH, QTX_OPT_RESERVE_WORKSPACE, QTX_OPT_INT8_TILE_VARIANT, QTX_OPT_OVERLAP, QTX_OPT_LANE_SPLIT = 1, 2, 3, 4, 5
 QTX_STAT_GRAPH_LAUNCHES, QTX_STAT_GRAPH_CAPTURES, QTX_STAT_WORKSPACE_BYTES, QTX_STAT_TUNE_RECORDS = 1, 2, 3, 4
 QTX_KERNEL_GEMM, QTX_KERNEL_INV, QTX_KERNEL_CONVERT = 0, 1, 2
@@ -108,6 +108,8 @@ def load_library(path: str = LIB_PATH):
     lib.qtx_rgf_tune.argtypes = [vp, i32, i32, i32, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), i32,
                                  ctypes.POINTER(i32)]
     lib.qtx_rgf_tune.restype = ctypes.c_int
+    lib.qtx_w_assemble.argtypes = [vp, i32, i32, i32, i32, i32] + [vp] * 16
+    lib.qtx_w_assemble.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -224,6 +226,45 @@ def to_device(p, device="cuda", greater: Optional[bool] = None) -> DeviceProblem
     return dp
 
 
+@dataclasses.dataclass
+class DeviceW:
+    """Device tensors of a screened Coulomb (W) system (paper_2606_25595_amd.inputs.WProblem)."""
+    n_e: int
+    V_d: object
+    V_u: object
+    PR_d: object
+    PR_u: object
+    PR_l: object
+    PL_d: object
+    PL_u: object
+    PG_d: object = None
+    PG_u: object = None
+
+    @property
+    def n_b(self):
+        return int(self.V_d.shape[0])
+
+    @property
+    def b(self):
+        return int(self.V_d.shape[1])
+
+
+def w_to_device(w, device="cuda", greater: Optional[bool] = None) -> DeviceW:
+    """Copy a WProblem to the device.  P^<> travel as diagonal and upper blocks
+    (the library takes the lower blocks as -(upper)^H)."""
+    import torch
+
+    def dev(a):
+        if a is None:
+            return None
+        return torch.from_numpy(np.require(a, dtype=np.complex128, requirements=["C", "W"])).to(device)
+    if greater is None:
+        greater = w.PG_d is not None
+    return DeviceW(n_e=w.n_e, V_d=dev(w.V_d), V_u=dev(w.V_u), PR_d=dev(w.PR_d), PR_u=dev(w.PR_u),
+                   PR_l=dev(w.PR_l), PL_d=dev(w.PL_d), PL_u=dev(w.PL_u),
+                   PG_d=dev(w.PG_d) if greater else None, PG_u=dev(w.PG_u) if greater else None)
+
+
 def _problem_struct(dp: DeviceProblem, prec: int, n_slices: int, prec_lesser: int = -1, n_slices_lesser: int = -1):
     st = _Problem()
     st.n_b, st.b, st.n_e = dp.n_b, dp.b, dp.n_e
@@ -274,6 +315,60 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+    # -- screened Coulomb system
+    def w_assemble(self, dw: DeviceW, prec="fp64", n_slices=0, stream=None, check: bool = True):
+        """qtx_w_assemble: BT blocks of V P^R and V P^<> V^H (dict of device tensors
+        VPR_d/u/l, BL_d/u, and BG_d/u when P^> is given)."""
+        import torch
+        n_e, n_b, b = dw.n_e, dw.n_b, dw.b
+        kw = dict(dtype=torch.complex128, device=dw.V_d.device)
+        nu = max(n_b - 1, 0)
+        out = {"VPR_d": torch.empty((n_e, n_b, b, b), **kw), "VPR_u": torch.empty((n_e, nu, b, b), **kw),
+               "VPR_l": torch.empty((n_e, nu, b, b), **kw), "BL_d": torch.empty((n_e, n_b, b, b), **kw),
+               "BL_u": torch.empty((n_e, nu, b, b), **kw)}
+        if dw.PG_d is not None:
+            out["BG_d"] = torch.empty((n_e, n_b, b, b), **kw)
+            out["BG_u"] = torch.empty((n_e, nu, b, b), **kw)
+        p = lambda t: _ptr(t if (t is not None and t.numel()) else None)
+        rc = self.lib.qtx_w_assemble(self.handle, n_b, b, n_e, PREC_NAMES.get(prec, prec), int(n_slices),
+                                     p(dw.V_d), p(dw.V_u), p(dw.PR_d), p(dw.PR_u), p(dw.PR_l), p(dw.PL_d),
+                                     p(dw.PL_u), p(dw.PG_d), p(dw.PG_u), p(out["VPR_d"]), p(out["VPR_u"]),
+                                     p(out["VPR_l"]), p(out["BL_d"]), p(out["BL_u"]), p(out.get("BG_d")),
+                                     p(out.get("BG_u")), _stream_ptr(stream))
+        if check and rc != QTX_OK:
+            raise QtxError(rc, "qtx_w_assemble")
+        return out if check else rc
+
+    def w_problem(self, dw: DeviceW, asm) -> DeviceProblem:
+        """The W system as a DeviceProblem for qtx_rgf_solve: energies 1, S = I,
+        H = 0, Sigma^R = BT(V P^R), Sigma^<> = BT(V P^<> V^H); outputs allocated."""
+        import torch
+        n_e, n_b, b = dw.n_e, dw.n_b, dw.b
+        kw = dict(dtype=torch.complex128, device=dw.V_d.device)
+        nu = max(n_b - 1, 0)
+        z = torch.zeros((n_b, b, b), **kw)
+        zu = torch.zeros((nu, b, b), **kw)
+        dp = DeviceProblem(
+            energies=np.ones(n_e), H_d=z, H_u=zu, H_l=zu, SR_d=asm["VPR_d"], SL_d=asm["BL_d"],
+            GR_d=torch.empty((n_e, n_b, b, b), **kw), GR_u=torch.empty((n_e, nu, b, b), **kw),
+            GR_l=torch.empty((n_e, nu, b, b), **kw), GL_d=torch.empty((n_e, n_b, b, b), **kw),
+            GL_u=torch.empty((n_e, nu, b, b), **kw),
+            status=torch.full((n_e,), -1, dtype=torch.int32, device=dw.V_d.device),
+            SR_u=asm["VPR_u"], SR_l=asm["VPR_l"], SL_u=asm["BL_u"])
+        if "BG_d" in asm:
+            dp.SG_d, dp.SG_u = asm["BG_d"], asm["BG_u"]
+            dp.GG_d = torch.empty((n_e, n_b, b, b), **kw)
+            dp.GG_u = torch.empty((n_e, nu, b, b), **kw)
+        return dp
+
+    def w_solve(self, dw: DeviceW, prec="fp64", n_slices=0, stream=None, **kw) -> DeviceProblem:
+        """Assemble the W system (qtx_w_assemble, FP64 products) and solve it
+        (qtx_rgf_solve with the given schemes); returns the solved DeviceProblem."""
+        asm = self.w_assemble(dw, stream=stream)
+        dp = self.w_problem(dw, asm)
+        self.solve(dp, prec=prec, n_slices=n_slices, stream=stream, **kw)
+        return dp
 
     # -- qtx_rgf_solve
     def solve(self, problems, prec="fp64", n_slices=0, stream=None, check: bool = True,
