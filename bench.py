@@ -116,11 +116,12 @@ def main():
                          "<retarded>/<lesser>")
     ap.add_argument("--cpu-energies", type=int, default=8, help="energies in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="realistic", choices=["realistic", "hard", "kappa", "w", "batch", "serve"],
+    ap.add_argument("--workload", default="realistic", choices=["realistic", "hard", "kappa", "w", "fpx", "batch", "serve"],
                     help="realistic (default, the headline line) | hard (the realistic shapes at eta = 1e-6, "
                          "condition numbers up to ~5e6) | kappa (error against the exact condition number, "
                          "n_b=8, b=128, eta 1e-3..1e-6) | w (screened Coulomb system: assembly + solve, n_b=16, "
-                         "b=256, 128 energies) | batch (512 uneven problems, one graph launch) | "
+                         "b=256, 128 energies) | fpx (FPX storage codec GB/s on G^R blocks) | batch (512 uneven "
+                         "problems, one graph launch) | "
                          "serve (Poisson arrivals, continuous batching, p50/p99)")
     ap.add_argument("--eta", type=float, default=None, help="realistic/hard: broadening (default 1e-3 / 1e-6)")
     ap.add_argument("--problems", type=int, default=512, help="batch workload: number of problems")
@@ -146,6 +147,8 @@ def main():
         return bench_kappa(args)
     if args.workload == "w":
         return bench_w(args)
+    if args.workload == "fpx":
+        return bench_fpx(args)
 
     cfg = inputs.CONFIGS["realistic"]
     n_b, b, n_e = cfg["n_b"], cfg["b"], cfg["n_e"]
@@ -495,6 +498,64 @@ def bench_w(args):
             "schemes": results,
             "cpu_baseline": {"value": len(sample) / t_cpu, "unit": "energy points/s", "kind": "oracle",
                              "sample": "%d energies, dense assembly + block recurrences, %.1f s" % (len(sample), t_cpu)}}
+    print(json.dumps(line), flush=True)
+
+
+def bench_fpx(args):
+    """FPX storage codec (Section V-A): encode and decode of the diagonal G^R blocks
+    of 64 energies of the realistic workload's shape (64 x 32 x 416 x 416 complex128,
+    5.67 GB, values of a synthetic spread over the FP32 range), for every X.  HBM
+    roofline: algorithmic bytes = 8 read + X/8 written per value (encode), the
+    reverse for decode; each launch timed by HIP events on its stream.  The oracle
+    checks a sample bitwise."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2606_25595_amd import qtx
+    n_vals = 64 * 32 * 416 * 416 * 2
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    x = torch.randn(n_vals, dtype=torch.float64, device="cuda", generator=g)
+    x.mul_(torch.pow(10.0, torch.randint(-30, 30, (n_vals,), device="cuda", generator=g).double()))
+    ctx = qtx.Context(0)
+    rows = {}
+    y = torch.empty_like(x)
+    for bits in (16, 24, 32, 40, 48, 56):
+        enc = torch.empty(n_vals * bits // 8, dtype=torch.uint8, device="cuda")
+        ctx.fpx_encode(x, bits, out=enc)
+        ctx.fpx_decode(enc, bits, n_vals, out=y)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        te = td = 0.0
+        for _ in range(args.steps):
+            ev[0].record()
+            ctx.fpx_encode(x, bits, out=enc)
+            ev[1].record()
+            ctx.fpx_decode(enc, bits, n_vals, out=y)
+            ev[2].record()
+            torch.cuda.synchronize()
+            te += ev[0].elapsed_time(ev[1]) / args.steps
+            td += ev[1].elapsed_time(ev[2]) / args.steps
+        nbytes = n_vals * (8 + bits // 8)
+        ok_e = np.array_equal(enc[: 8 * 4096 * bits // 8].cpu().numpy(),
+                              oracle.fpx_encode(x[: 8 * 4096].cpu().numpy(), bits))
+        rows[bits] = {"encode_ms": te, "decode_ms": td, "encode_GBps": nbytes / te / 1e6,
+                      "decode_GBps": nbytes / td / 1e6, "sample_bitwise_ok": bool(ok_e),
+                      "max_rel_roundtrip": float(((y - x).abs() / x.abs()).max().item())}
+        log("bench fpx: X=%d encode %.3f ms (%.0f GB/s), decode %.3f ms (%.0f GB/s), sample ok %s, "
+            "max rel round trip %.2e" % (bits, te, rows[bits]["encode_GBps"], td, rows[bits]["decode_GBps"], ok_e,
+                                         rows[bits]["max_rel_roundtrip"]))
+        del enc
+    ctx.close()
+    best = max(rows, key=lambda k: rows[k]["encode_GBps"])
+    line = {"metric": "FPX codec HBM throughput (encode + decode of complex128 blocks)", "unit": "GB/s",
+            "value": min(min(r["encode_GBps"], r["decode_GBps"]) for r in rows.values()), "n_gpus": 1,
+            "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": "fpx: 64 x 32 blocks of 416 x 416 complex128 (5.67 GB of FP64)"},
+            "roofline": {"bound": "hbm", "peak": 8000.0, "unit": "GB/s",
+                         "achieved": rows[best]["encode_GBps"], "frac": rows[best]["encode_GBps"] / 8000.0,
+                         "kernel": "fpx_encode_kernel<%d>" % best},
+            "formats": rows}
     print(json.dumps(line), flush=True)
 
 

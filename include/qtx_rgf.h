@@ -279,6 +279,21 @@ qtx_status qtx_w_assemble(qtx_rgf_ctx ctx, int32_t n_b, int32_t b, int32_t n_e, 
                           void* VPR_d, void* VPR_u, void* VPR_l, void* BL_d, void* BL_u, void* BG_d, void* BG_u,
                           void* hip_stream);
 
+/* FPX storage formats (Section V-A): X-bit byte-aligned floating point, X in
+ * {16, 24, 32, 40, 48, 56}, with 1 sign bit, FP32's 8-bit exponent and bias (127)
+ * and X - 9 significand bits; FP64 values are rounded to nearest, ties to even
+ * (IEEE-754), with FP32's range: subnormals below 2^-126, magnitudes that round to
+ * 2^128 or more become infinite, NaN stays NaN (sign kept, payload not).  FPX32 is
+ * IEEE FP32 bitwise; FPX16 has the bfloat16 layout.  Element i occupies bytes
+ * [i X/8, (i+1) X/8) of the byte stream, little-endian.
+ * qtx_fpx_encode: x [n] doubles (device) -> out [n X/8] bytes (device).
+ * qtx_fpx_decode: in [n X/8] bytes (device) -> y [n] doubles (device), exact.
+ * A complex128 array of k elements is n = 2k doubles.  Both pointers must be
+ * 8-byte aligned and must not overlap; n = 0 does nothing.  QTX_ERR_ARG for an
+ * unsupported bits value, n < 0, NULL or misaligned pointers (nothing enqueued). */
+qtx_status qtx_fpx_encode(qtx_rgf_ctx ctx, int32_t bits, int64_t n, const double* x, void* out, void* hip_stream);
+qtx_status qtx_fpx_decode(qtx_rgf_ctx ctx, int32_t bits, int64_t n, const void* in, double* y, void* hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Kernel-level entry points (the building blocks of qtx_rgf_solve), exposed
  * so each can be checked in isolation.

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqtx_rgf.so")
-SOURCES = ["zgemm_mfma.hip", "zgemm_split.hip", "zgemm_ozaki2.hip", "zgje.hip", "aux_kernels.hip", "engine.cpp"]
+SOURCES = ["zgemm_mfma.hip", "zgemm_split.hip", "zgemm_ozaki2.hip", "zgje.hip", "aux_kernels.hip", "fpx.hip",
+           "engine.cpp"]
 ARCH = "gfx950"
 # No packed-FP32 instructions anywhere (they are generated from plain float code otherwise).
 HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

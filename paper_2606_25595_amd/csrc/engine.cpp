@@ -1553,6 +1553,29 @@ qtx_status qtx_w_assemble(qtx_rgf_ctx ctx, int32_t n_b, int32_t b, int32_t n_e, 
   return QTX_OK;
 }
 
+// ---------------------------------------------------------------- FPX storage codec
+namespace {
+qtx_status fpx_call(qtx_rgf_ctx ctx, bool encode, int32_t bits, int64_t n, const void* src, void* dst,
+                    void* hip_stream) {
+  if (!ctx) return QTX_ERR_ARG;
+  if (ctx->sticky != QTX_OK) return ctx->sticky;
+  if (!fpx_supported(bits) || n < 0) return QTX_ERR_ARG;
+  if (n == 0) return QTX_OK;
+  if (!src || !dst || ((uintptr_t)src & 7) || ((uintptr_t)dst & 7)) return QTX_ERR_ARG;
+  DeviceGuard guard(ctx->device);
+  QTX_TRY(launch_fpx(encode, bits, n, src, dst, (hipStream_t)hip_stream));
+  return QTX_OK;
+}
+}  // namespace
+
+qtx_status qtx_fpx_encode(qtx_rgf_ctx ctx, int32_t bits, int64_t n, const double* x, void* out, void* hip_stream) {
+  return fpx_call(ctx, true, bits, n, x, out, hip_stream);
+}
+
+qtx_status qtx_fpx_decode(qtx_rgf_ctx ctx, int32_t bits, int64_t n, const void* in, double* y, void* hip_stream) {
+  return fpx_call(ctx, false, bits, n, in, y, hip_stream);
+}
+
 qtx_status qtx_zinv(qtx_rgf_ctx ctx, int32_t n, const void* A, int64_t sA, void* Ainv, int64_t sAinv,
                     int32_t batch, int32_t* status, void* hip_stream) {
   if (!ctx) return QTX_ERR_ARG;

@@ -146,6 +146,11 @@ hipError_t launch_gje_invert(int n, double2* X, int64_t sX, double2* Out, int64_
                              const GjeWork& w, int32_t* status, hipStream_t s,
                              double2* const* tOut = nullptr);
 
+// FPX storage codec: FP64 <-> X-bit floats (X in 16..56, multiples of 8), encode
+// reads n doubles and writes n X / 8 bytes, decode the reverse.
+bool fpx_supported(int bits);
+hipError_t launch_fpx(bool encode, int bits, int64_t n, const void* src, void* dst, hipStream_t s);
+
 // Status / NaN fill / observables helpers.
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_hash(double2* p, int64_t n, uint32_t seed, hipStream_t s);

@@ -34,7 +34,8 @@ PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16"
 
 EXPORTED = ("qtx_rgf_create", "qtx_rgf_solve", "qtx_rgf_destroy", "qtx_rgf_footprint", "qtx_status_str",
             "qtx_zgemm", "qtx_zinv", "qtx_rgf_observables", "qtx_rgf_profile", "qtx_rgf_profile_read",
-            "qtx_rgf_set_option", "qtx_rgf_get_stat", "qtx_ozaki2_bits", "qtx_rgf_tune", "qtx_w_assemble")
+            "qtx_rgf_set_option", "qtx_rgf_get_stat", "qtx_ozaki2_bits", "qtx_rgf_tune", "qtx_w_assemble",
+            "qtx_fpx_encode", "qtx_fpx_decode")
 QTX_OPT_GRAPH, QTX_OPT_RESERVE_WORKSPACE, QTX_OPT_INT8_TILE_VARIANT, QTX_OPT_OVERLAP, QTX_OPT_LANE_SPLIT = 1, 2, 3, 4, 5
 QTX_STAT_GRAPH_LAUNCHES, QTX_STAT_GRAPH_CAPTURES, QTX_STAT_WORKSPACE_BYTES, QTX_STAT_TUNE_RECORDS = 1, 2, 3, 4
 QTX_KERNEL_GEMM, QTX_KERNEL_INV, QTX_KERNEL_CONVERT = 0, 1, 2
@@ -110,6 +111,9 @@ def load_library(path: str = LIB_PATH):
     lib.qtx_rgf_tune.restype = ctypes.c_int
     lib.qtx_w_assemble.argtypes = [vp, i32, i32, i32, i32, i32] + [vp] * 16
     lib.qtx_w_assemble.restype = ctypes.c_int
+    for name in ("qtx_fpx_encode", "qtx_fpx_decode"):
+        getattr(lib, name).argtypes = [vp, i32, i64, vp, vp, vp]
+        getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -315,6 +319,32 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+    # -- FPX storage codec
+    def fpx_encode(self, x, bits: int, out=None, stream=None):
+        """qtx_fpx_encode of a float64 / complex128 device tensor; returns the uint8 codes."""
+        import torch
+        xd = torch.view_as_real(x) if x.is_complex() else x
+        assert xd.dtype == torch.float64 and xd.is_contiguous()
+        n = xd.numel()
+        if out is None:
+            out = torch.empty(n * bits // 8, dtype=torch.uint8, device=x.device)
+        rc = self.lib.qtx_fpx_encode(self.handle, int(bits), n, _ptr(xd) if n else None, _ptr(out) if n else None,
+                                     _stream_ptr(stream))
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_fpx_encode")
+        return out
+
+    def fpx_decode(self, data, bits: int, n: int, out=None, stream=None):
+        """qtx_fpx_decode of n values from a uint8 device tensor; returns float64."""
+        import torch
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=data.device)
+        rc = self.lib.qtx_fpx_decode(self.handle, int(bits), int(n), _ptr(data) if n else None,
+                                     _ptr(out) if n else None, _stream_ptr(stream))
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_fpx_decode")
+        return out
 
     # -- screened Coulomb system
     def w_assemble(self, dw: DeviceW, prec="fp64", n_slices=0, stream=None, check: bool = True):

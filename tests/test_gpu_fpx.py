@@ -1,0 +1,76 @@
+"""GPU parity of the FPX storage codec (Section V-A) against the oracle: encoded
+bytes and decoded values bitwise equal (integer / byte work), for every X, over
+the whole FP32 range with subnormals, overflow, ties and specials, and ragged
+lengths (groups of 8 elements with a partial last group)."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_25595_amd import qtx
+    c = qtx.Context(0)
+    yield c
+    c.close()
+
+
+def values(bits, n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(n) * 10.0 ** rng.integers(-48, 41, n)
+    m = bits - 9
+    special = [0.0, -0.0, np.inf, -np.inf, np.nan, 2.0 ** -126, 2.0 ** (-126 - m), 2.0 ** (-127 - m),
+               3 * 2.0 ** (-127 - m), 1 + 2.0 ** -(m + 1), 1 + 3 * 2.0 ** -(m + 1), 2.0 ** 128,
+               (2 - 2.0 ** -(m + 1)) * 2.0 ** 127, (2 - 2.0 ** -(m + 2)) * 2.0 ** 127, 5e-324, -1e-310]
+    x[: len(special)] = special
+    return x
+
+
+@pytest.mark.parametrize("bits", [16, 24, 32, 40, 48, 56])
+@pytest.mark.parametrize("n", [1, 7, 8, 9, 1000, 65541])
+def test_fpx_encode_decode_bitwise(ctx, bits, n):
+    import torch
+    x = values(bits, max(n, 16), bits * 7 + n)[:n]
+    xd = torch.from_numpy(x).cuda()
+    enc = ctx.fpx_encode(xd, bits)
+    torch.cuda.synchronize()
+    ref = oracle.fpx_encode(x, bits)
+    assert np.array_equal(enc.cpu().numpy(), ref)
+    dec = ctx.fpx_decode(torch.from_numpy(ref).cuda(), bits, n).cpu().numpy()
+    want = oracle.fpx_decode(ref, bits, n)
+    nan = np.isnan(want)
+    assert np.array_equal(np.isnan(dec), nan)
+    assert np.array_equal(dec[~nan], want[~nan])
+    assert np.array_equal(np.signbit(dec[~nan]), np.signbit(want[~nan]))
+
+
+def test_fpx_complex_blocks_roundtrip(ctx):
+    """A complex128 block array travels as 2k doubles; FPX32 round trip equals the
+    FP32 rounding of each part."""
+    import torch
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((3, 40, 40)) + 1j * rng.standard_normal((3, 40, 40))
+    t = torch.from_numpy(G).cuda()
+    enc = ctx.fpx_encode(t, 32)
+    back = ctx.fpx_decode(enc, 32, 2 * G.size).cpu().numpy().view(np.complex128).reshape(G.shape)
+    ref = G.real.astype(np.float32) + 1j * G.imag.astype(np.float32)
+    assert np.array_equal(back, ref)
+
+
+def test_fpx_argument_errors(ctx):
+    import torch
+    from paper_2606_25595_amd import qtx
+    x = torch.zeros(16, dtype=torch.float64, device="cuda")
+    out = torch.empty(16 * 8, dtype=torch.uint8, device="cuda")
+    lib = ctx.lib
+    assert lib.qtx_fpx_encode(ctx.handle, 12, 16, x.data_ptr(), out.data_ptr(), None) == qtx.QTX_ERR_ARG
+    assert lib.qtx_fpx_encode(ctx.handle, 32, -1, x.data_ptr(), out.data_ptr(), None) == qtx.QTX_ERR_ARG
+    assert lib.qtx_fpx_encode(ctx.handle, 32, 16, x.data_ptr(), out.data_ptr() + 4, None) == qtx.QTX_ERR_ARG
+    assert lib.qtx_fpx_decode(ctx.handle, 32, 16, None, x.data_ptr(), None) == qtx.QTX_ERR_ARG
+    assert lib.qtx_fpx_encode(ctx.handle, 32, 0, None, None, None) == qtx.QTX_OK
