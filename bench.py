@@ -7,9 +7,12 @@ random Hermitian H, eta = 1e-3, contact broadening gamma = 0.5) at all 256
 energies of linspace(-2, 2, 256) -- forward and backward passes for G^R and
 G^< with every block inversion, inputs resident in HBM.  The metric is energy
 points per second.  Precision schemes: fp64 (reference) and the mixed schemes
-of the complex block products; `value` is the fastest scheme whose sampled
-per-block error against the FP64 oracle is <= 1e-6 (the FP64 path always
-qualifies), and every scheme's rate and error is reported beside it.
+of the complex block products; `value` is the fastest scheme whose per-block
+error against the FP64 oracle on sampled energies is <= 1e-6 and whose error
+against the FP64 GPU run over all energies (diagonal G^R and G^< blocks, T_L,
+j_L) is <= 1e-6 as well (the FP64 path always qualifies; it is itself checked
+against the oracle on the sample), and every scheme's rate and error is reported
+beside it.
 
 Also reported:
   roofline     the dominant kernel (the b x b x b complex block products),
@@ -111,7 +114,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precs", default="fp64,fp32,bf16:5,int8:11,int8:10/int8:11",
+    ap.add_argument("--precs", default="fp64,fp32,bf16:5,int8:11,int8:10/int8:11,int8:10/int8:10",
                     help="comma list of schemes: fp64 | fp32 | bf16:NS | fp16:NS | int8:P (P moduli) | "
                          "<retarded>/<lesser>")
     ap.add_argument("--cpu-energies", type=int, default=8, help="energies in the oracle's timed sample")
@@ -193,6 +196,25 @@ def main():
 
     results = {}
     tuned = {}
+    full_ref = None   # the FP64 run's G^R_ii, G^<_ii, T_L, j_L for every energy (device copies)
+
+    def full_errors(T, j):
+        """Max relative Frobenius error per (energy, diagonal block) of G^R and G^< over
+        all energies, against the FP64 GPU run, and T_L / j_L relative to their largest
+        magnitude; chunked over energies on the device."""
+        out = {}
+        for key in ("GR_d", "GL_d"):
+            X, R = getattr(dp, key), full_ref[key]
+            worst = 0.0
+            for e0 in range(0, n_e, 16):
+                d = (X[e0:e0 + 16] - R[e0:e0 + 16]).abs().pow(2).sum((-1, -2)).sqrt()
+                nr = R[e0:e0 + 16].abs().pow(2).sum((-1, -2)).sqrt()
+                worst = max(worst, float((d / nr.clamp_min(1e-300)).max().item()))
+            out[key] = worst
+        for key, got in (("T_L", T), ("j_L", j)):
+            ref_t = full_ref[key]
+            out[key] = float(((got - ref_t).abs().max() / ref_t.abs().max().clamp_min(1e-300)).item())
+        return out
     for prec in args.precs.split(","):
         skw = parse_scheme(prec)
         tuned.update(autotune(ctx, skw, [(b, n_e)]))
@@ -229,11 +251,22 @@ def main():
             for key, got in (("T_L", T), ("j_L", j)):
                 g = got.cpu().numpy()[sample]
                 errs[key] = float(np.abs(g - ref[key]).max() / max(np.abs(ref[key]).max(), 1e-300))
+        errs_full = None
+        if prec == "fp64" and full_ref is None:
+            need = 2 * dp.GR_d.numel() * 16
+            if torch.cuda.mem_get_info()[0] > need + (16 << 30):
+                T, j = ctx.observables(dp, gamma_L, f_L)
+                full_ref = {"GR_d": dp.GR_d.clone(), "GL_d": dp.GL_d.clone(), "T_L": T.clone(), "j_L": j.clone()}
+        elif full_ref is not None:
+            errs_full = full_errors(*ctx.observables(dp, gamma_L, f_L))
         results[prec] = dict(ms_per_step=ms_step, value=n_e / (ms_step / 1e3), status_ok=bool(np.all(st == 0)),
-                             gemm=(g_ms, g_n, g_fl), inv=(i_ms, i_n, i_fl), conv=(c_ms, c_n, c_by), errs=errs)
+                             gemm=(g_ms, g_n, g_fl), inv=(i_ms, i_n, i_fl), conv=(c_ms, c_n, c_by), errs=errs,
+                             errs_full=errs_full)
         log("bench: %s %.1f ms/step, %.1f energies/s, product kernel avg %.3f ms x%d, conversion %.1f ms/step, "
-            "inv avg %.3f ms x%d, err %s" % (prec, ms_step, n_e / (ms_step / 1e3), g_ms / max(g_n, 1), g_n,
-                                             c_ms / args.steps, i_ms / max(i_n, 1), i_n, errs))
+            "inv avg %.3f ms x%d, err %s, all-energy err vs fp64 %s" % (
+                prec, ms_step, n_e / (ms_step / 1e3), g_ms / max(g_n, 1), g_n, c_ms / args.steps,
+                i_ms / max(i_n, 1), i_n, errs, errs_full))
+    full_ref = None
 
     # headline: fastest scheme meeting the error bar (FP64 always qualifies)
     def qualifies(p):
@@ -242,7 +275,10 @@ def main():
             return False
         if p == "fp64":
             return True
-        return r["errs"] is not None and max(r["errs"].values()) <= TOL_MIXED
+        if r["errs"] is None or max(r["errs"].values()) > TOL_MIXED:
+            return False
+        # where the FP64 run's outputs could be kept, every energy's diagonal blocks too
+        return r["errs_full"] is None or max(r["errs_full"].values()) <= TOL_MIXED
     # without the oracle (--no-cpu) no mixed scheme qualifies: report the fastest one that ran
     cands = [p for p in results if qualifies(p)] or [p for p in results if results[p]["status_ok"]] or list(results)
     best = max(cands, key=lambda p: results[p]["value"])
@@ -281,6 +317,7 @@ def main():
                      "launches": g_n},
         "cpu_baseline": cpu,
         "schemes": {p: {"energies_per_s": v["value"], "ms_per_step": v["ms_per_step"], "max_rel_err": v["errs"],
+                        "max_rel_err_all_energies_vs_fp64": v["errs_full"],
                         "status_ok": v["status_ok"],
                         "products_tflops_fp64eq": gemm_fp64eq * args.steps / ((v["gemm"][0] + v["conv"][0]) / 1e3)
                         / 1e12 if v["gemm"][1] else None,
