@@ -130,7 +130,13 @@ __global__ __launch_bounds__(64 * RB) void o2_convert_kernel(SplitDesc sd, O2Par
   constexpr int LPR = 64 / RB;         // lanes per row in the residue phase
   constexpr int VPL = 2 * RB;          // values (bytes) per lane and strip
   extern __shared__ double2 rows_lds[];   // [RB][KP], KP = KT * 64 (zero-padded), swizzled
-  const int z = blockIdx.y, r0 = blockIdx.x * RB, tid = threadIdx.x;
+  // 1-D grid over (entry, row group), remapped so that each XCD takes a contiguous run of
+  // row groups of one entry: with trans = 1 a group is RB adjacent columns (RB * 16 bytes
+  // of each source row), and its neighbours then read the rest of the same cache lines
+  // through the same L2 instead of fetching them again into another XCD's.
+  const int gx = (sd.rows + RB - 1) / RB;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int z = lb / gx, r0 = (lb - z * gx) * RB, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int K = sd.cols, KT = (K + KS - 1) / KS, KP = KT * KS, pitch = KP;
   const double2* X = sd.tX ? sd.tX[z] : sd.X + (int64_t)z * sd.stride;
@@ -593,7 +599,9 @@ hipError_t launch_o2_convert(const SplitDesc& sd, const O2Params& P, hipStream_t
     constexpr int RB = kO2ConvRows;
     const int KP = (sd.cols + KS - 1) / KS * KS;
     const size_t lds = (size_t)RB * KP * sizeof(double2);
-    hipLaunchKernelGGL(o2_convert_kernel<RB>, dim3((sd.rows + RB - 1) / RB, sd.batch), dim3(64 * RB), lds, s, sd, P);
+    const int64_t blocks = (int64_t)((sd.rows + RB - 1) / RB) * sd.batch;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(o2_convert_kernel<RB>, dim3((unsigned)blocks), dim3(64 * RB), lds, s, sd, P);
     return hipGetLastError();
   }
   hipError_t e = launch_split_exp(sd, s);
