@@ -83,7 +83,9 @@ def test_zgemm_shared_operand_and_k0(ctx):
 
 # ----------------------------------------------------------------- inversion kernel
 
-@pytest.mark.parametrize("n", [1, 2, 7, 31, 32, 33, 64, 100, 416, 512, 513, 1000])
+# 32-column panels go in pairs for n <= 512: n = 40, 65, 96, 130, 300 and 448 cover a pair
+# with a partial second panel, a pair plus a single panel, and several pairs.
+@pytest.mark.parametrize("n", [1, 2, 7, 31, 32, 33, 40, 64, 65, 96, 100, 130, 300, 416, 448, 512, 513, 1000])
 def test_zinv_random(ctx, n):
     import torch
     rng = np.random.default_rng(n)
@@ -118,11 +120,12 @@ def test_zinv_forced_pivoting(ctx):
     assert rel(out.cpu().numpy()[0], np.linalg.inv(A)) < 1e-12
 
 
-def test_zinv_singular_is_flagged(ctx):
+@pytest.mark.parametrize("n,col", [(20, 5), (100, 40)])
+def test_zinv_singular_is_flagged(ctx, n, col):
     import torch
     rng = np.random.default_rng(2)
-    A = crand(rng, 3, 20, 20)
-    A[1, :, 5] = 0.0                                    # a zero column: exactly singular
+    A = crand(rng, 3, n, n)
+    A[1, :, col] = 0.0                                  # a zero column: exactly singular
     dA = torch.from_numpy(A).cuda()
     out = torch.empty_like(dA)
     st = torch.zeros(3, dtype=torch.int32, device="cuda")
@@ -131,7 +134,8 @@ def test_zinv_singular_is_flagged(ctx):
     X = out.cpu().numpy()
     assert s[0] == 0 and s[1] == 5 and s[2] == 0
     assert np.all(np.isnan(X[1]))
-    assert rel(X[0], np.linalg.inv(A[0])) < 1e-12 and rel(X[2], np.linalg.inv(A[2])) < 1e-12
+    for z in (0, 2):
+        assert rel(X[z], np.linalg.inv(A[z])) <= 200 * np.linalg.cond(A[z]) * 2.2e-16
 
 
 # ----------------------------------------------------------------- full solve
