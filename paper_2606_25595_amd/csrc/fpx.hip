@@ -2,12 +2,11 @@
 // X in {16, 24, 32, 40, 48, 56}, with FP32's 8-bit exponent and bias and X - 9
 // significand bits, rounded to nearest even (IEEE-754); X = 32 is IEEE FP32.
 //
-// HBM-bound elementwise passes.  One thread takes a group of 8 consecutive
-// elements: 64 bytes of FP64 on one side and exactly X bytes (X / 8 whole 64-bit
-// words, since X is a multiple of 8) of codes on the other, so the packed side is
-// written and read with aligned 8-byte accesses; a partial last group is written
-// byte by byte.  Element i's code sits in bits [X i, X (i + 1)) of the little-endian
-// byte stream.
+// HBM-bound elementwise passes.  A group of 8 consecutive values is exactly X bytes
+// (X / 8 whole 64-bit words, since X is a multiple of 8) of codes, so the packed side
+// is read and written in aligned 8-byte words; a partial last tile is written byte by
+// byte.  Element i's code sits in bits [X i, X (i + 1)) of the little-endian byte
+// stream.
 #include "qtx_internal.h"
 
 namespace qtx {
@@ -67,32 +66,55 @@ __device__ inline double fpx_value(uint64_t c) {
   return __longlong_as_double(bits | (sign << 63));
 }
 
+// One workgroup of 256 threads converts a tile of 2048 consecutive values: 16 KB of
+// FP64 and 256 X bytes of codes.  Both sides go through LDS so that every global load
+// and store is contiguous across the wave (16-byte FP64 loads / stores, 8-byte code
+// words); thread t packs or unpacks group t (values 8t .. 8t + 7) in LDS, reading its
+// FP64 values in a rotated order to spread the LDS banks.
+constexpr int kTile = 2048;
+
 template <int X>
 __global__ __launch_bounds__(256) void fpx_encode_kernel(int64_t n, const double* __restrict__ x,
                                                           uint8_t* __restrict__ out) {
-  constexpr int W = X / 8;   // 64-bit words per group of 8 elements
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i0 = g * 8;
-  if (i0 >= n) return;
-  const int cnt = (n - i0 >= 8) ? 8 : (int)(n - i0);
+  constexpr int W = X / 8;   // 64-bit words per group of 8 values
+  __shared__ __align__(16) double vin[kTile];
+  __shared__ uint64_t wout[256 * W];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  const int cnt = (n - base >= kTile) ? kTile : (int)(n - base);   // values in this tile
+  if (cnt == kTile && ((uintptr_t)x & 15) == 0) {   // 16-byte loads need 16-byte alignment
+    const double2* src = (const double2*)(x + base);
+#pragma unroll
+    for (int q = 0; q < kTile / 512; ++q) ((double2*)vin)[t + 256 * q] = src[t + 256 * q];
+  } else {
+    for (int e = t; e < kTile; e += 256) vin[e] = (e < cnt) ? x[base + e] : 0.0;
+  }
+  __syncthreads();
   uint64_t w[W];
 #pragma unroll
   for (int k = 0; k < W; ++k) w[k] = 0;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const uint64_t c = (j < cnt) ? fpx_code<X>(x[i0 + j]) : 0;
-    const int bit = j * X, word = bit / 64, s = bit % 64;
-    w[word] |= c << s;
-    if (s + X > 64) w[word + 1] |= c >> (64 - s);
-  }
-  uint8_t* dst = out + g * X;
-  if (cnt == 8) {
-    uint64_t* d = (uint64_t*)dst;
+  for (int jj = 0; jj < 8; ++jj) {
+    const int j = (jj + t) & 7;
+    const uint64_t c = fpx_code<X>(vin[8 * t + j]);
+    // place value j's code at bits [j X, (j + 1) X) of the group
 #pragma unroll
-    for (int k = 0; k < W; ++k) d[k] = w[k];
+    for (int k = 0; k < W; ++k) {
+      const int lo = 64 * k - j * X;                    // bit of the code at the word's bit 0
+      if (lo >= X || lo <= -64) continue;
+      w[k] |= (lo >= 0) ? (c >> lo) : (c << (-lo));
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < W; ++k) wout[t * W + k] = w[k];
+  __syncthreads();
+  const int64_t obase = base / 8 * X;                   // byte offset of the tile's codes
+  const int nbytes = cnt * (X / 8);
+  uint8_t* dst = out + obase;
+  if (nbytes % 8 == 0) {
+    for (int q = t; q < nbytes / 8; q += 256) ((uint64_t*)dst)[q] = wout[q];
   } else {
-    const int nbytes = cnt * (X / 8);
-    for (int k = 0; k < nbytes; ++k) dst[k] = (uint8_t)(w[k / 8] >> (8 * (k % 8)));
+    for (int q = t; q < nbytes; q += 256) dst[q] = (uint8_t)(wout[q / 8] >> (8 * (q % 8)));
   }
 }
 
@@ -101,36 +123,48 @@ __global__ __launch_bounds__(256) void fpx_decode_kernel(int64_t n, const uint8_
                                                           double* __restrict__ y) {
   constexpr int W = X / 8;
   constexpr uint64_t kMask = (1ull << X) - 1;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t i0 = g * 8;
-  if (i0 >= n) return;
-  const int cnt = (n - i0 >= 8) ? 8 : (int)(n - i0);
-  const uint8_t* src = in + g * X;
-  uint64_t w[W + 1];
-  w[W] = 0;
-  if (cnt == 8) {
-    const uint64_t* s = (const uint64_t*)src;
-#pragma unroll
-    for (int k = 0; k < W; ++k) w[k] = s[k];
+  __shared__ uint64_t win[256 * W + 1];
+  __shared__ __align__(16) double vout[kTile];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  const int cnt = (n - base >= kTile) ? kTile : (int)(n - base);
+  const int nbytes = cnt * (X / 8);
+  const uint8_t* src = in + base / 8 * X;
+  if (nbytes % 8 == 0) {
+    for (int q = t; q < nbytes / 8; q += 256) win[q] = ((const uint64_t*)src)[q];
   } else {
-#pragma unroll
-    for (int k = 0; k < W; ++k) w[k] = 0;
-    const int nbytes = cnt * (X / 8);
-    for (int k = 0; k < nbytes; ++k) w[k / 8] |= (uint64_t)src[k] << (8 * (k % 8));
+    for (int q = t; q < 256 * W; q += 256) win[q] = 0;
+    __syncthreads();
+    for (int q = t; q < nbytes; q += 256) atomicOr((unsigned long long*)&win[q / 8], (unsigned long long)src[q] << (8 * (q % 8)));
   }
+  __syncthreads();
+  uint64_t w[W + 1];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int bit = j * X, word = bit / 64, s = bit % 64;
-    uint64_t c = w[word] >> s;
-    if (s + X > 64) c |= w[word + 1] << (64 - s);
-    if (j < cnt) y[i0 + j] = fpx_value<X>(c & kMask);
+  for (int k = 0; k < W; ++k) w[k] = win[t * W + k];
+  w[W] = 0;
+#pragma unroll
+  for (int jj = 0; jj < 8; ++jj) {
+    const int j = (jj + t) & 7;
+    const int bit = j * X, word = bit / 64, sh = bit % 64;
+    uint64_t c = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+      if (k == word) c = (w[k] >> sh) | (sh ? (w[k + 1] << (64 - sh)) : 0);
+    vout[8 * t + j] = fpx_value<X>(c & kMask);
+  }
+  __syncthreads();
+  if (cnt == kTile && ((uintptr_t)y & 15) == 0) {
+    double2* dst = (double2*)(y + base);
+#pragma unroll
+    for (int q = 0; q < kTile / 512; ++q) dst[t + 256 * q] = ((const double2*)vout)[t + 256 * q];
+  } else {
+    for (int e = t; e < cnt; e += 256) y[base + e] = vout[e];
   }
 }
 
 template <int X>
 hipError_t launch_x(bool enc, int64_t n, const void* a, void* b, hipStream_t s) {
-  const int64_t groups = (n + 7) / 8;
-  const int64_t blocks = (groups + 255) / 256;
+  const int64_t blocks = (n + kTile - 1) / kTile;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   if (enc) hipLaunchKernelGGL(fpx_encode_kernel<X>, dim3((unsigned)blocks), dim3(256), 0, s, n, (const double*)a, (uint8_t*)b);
   else hipLaunchKernelGGL(fpx_decode_kernel<X>, dim3((unsigned)blocks), dim3(256), 0, s, n, (const uint8_t*)a, (double*)b);
