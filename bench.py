@@ -117,7 +117,7 @@ def main():
     ap.add_argument("--precs", default="fp64,fp32,bf16:5,int8:11,int8:10/int8:11,int8:10/int8:10",
                     help="comma list of schemes: fp64 | fp32 | bf16:NS | fp16:NS | int8:P (P moduli) | "
                          "<retarded>/<lesser>")
-    ap.add_argument("--cpu-energies", type=int, default=8, help="energies in the oracle's timed sample")
+    ap.add_argument("--cpu-energies", type=int, default=16, help="energies in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="realistic", choices=["realistic", "hard", "kappa", "w", "fpx", "batch", "serve"],
                     help="realistic (default, the headline line) | hard (the realistic shapes at eta = 1e-6, "
