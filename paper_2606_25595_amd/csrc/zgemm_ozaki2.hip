@@ -224,6 +224,18 @@ __device__ inline i16v mfma_i8(i4 a, i4 b, i16v c) {
   return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
 }
 
+// Negate 16 packed int8 values (residues in [-127, 127], so -x fits): per byte,
+// (0x80 - (x & 0x7f)) ^ (~x & 0x80); the subtraction never borrows across bytes.
+__device__ inline i4 neg_i8x16(i4 x) {
+  i4 r;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t u = (uint32_t)x[q];
+    r[q] = (int)((0x80808080u - (u & 0x7f7f7f7fu)) ^ (~u & 0x80808080u));
+  }
+  return r;
+}
+
 // S += ((c u) mod m) / m.  |c| < 2^31 and u < 2^8, so c u is exact in FP64; its
 // quotient by m is never within 1/(2m) of a half-integer (m odd), so q is exact and
 // so is the remainder.
@@ -273,6 +285,7 @@ struct O2Cfg {
   static constexpr int LPT = SPI * LPS;               // copies per thread per step
   static constexpr int WPC = WPC_;                    // workgroups per CU (LDS / registers)
   static constexpr int WAVES_PER_SIMD = WPC * NT / 256;
+  static constexpr bool TWO_ACC = WPC >= 3;            // O2Acc layout
   static_assert(NT == 4 * BM && (BM == 64 || BM == 128), "tile shape");   // one wave per 32 x 32 block
   static_assert(STRIP_U4 % NT == 0 && (BM * 8) % NT == 0, "copy split");
   static_assert(NSTAGE == 2 || NSTAGE == 3, "ring depth");
@@ -288,10 +301,40 @@ typedef O2Cfg<64, 256, 1, 2, 3> O2V4;
 typedef __attribute__((address_space(3))) u4 lds_u4;
 typedef __attribute__((address_space(3))) double lds_f64;
 
-// Accumulators of one wave's 32 x 32 output block.
-struct O2Acc {
-  i16v arr, aii, ari;        // INT32 sums of the current modulus
+// Accumulators of one wave's 32 x 32 output block.  INT32 sums of the current modulus:
+// with TWO, re = rr - ii in one accumulator (the imaginary B fragment negated in
+// registers, 16 fewer VGPRs: the variants with three workgroups per CU, whose registers
+// are capped, then spill less) and im = ri + ir; else rr, ii and ri + ir apart (no
+// negation work).  The INT32 sums, and so the results, are the same either way.
+template <bool TWO>
+struct O2Acc;
+template <>
+struct O2Acc<true> {
+  i16v are, aim;
   double sre[16], sim[16];   // CRT sums (real, imaginary)
+  __device__ inline void clear(int v) { are[v] = 0; aim[v] = 0; }
+  __device__ inline int re(int v) const { return are[v]; }
+  __device__ inline int im(int v) const { return aim[v]; }
+  __device__ inline void step(i4 ar, i4 ai, i4 br, i4 bi) {
+    are = mfma_i8(ar, br, are);
+    aim = mfma_i8(ar, bi, aim);
+    are = mfma_i8(ai, neg_i8x16(bi), are);
+    aim = mfma_i8(ai, br, aim);
+  }
+};
+template <>
+struct O2Acc<false> {
+  i16v arr, aii, ari;
+  double sre[16], sim[16];
+  __device__ inline void clear(int v) { arr[v] = 0; aii[v] = 0; ari[v] = 0; }
+  __device__ inline int re(int v) const { return arr[v] - aii[v]; }
+  __device__ inline int im(int v) const { return ari[v]; }
+  __device__ inline void step(i4 ar, i4 ai, i4 br, i4 bi) {
+    arr = mfma_i8(ar, br, arr);
+    aii = mfma_i8(ai, bi, aii);
+    ari = mfma_i8(ar, bi, ari);
+    ari = mfma_i8(ai, br, ari);
+  }
 };
 
 // Per-thread constants of the strip loop.
@@ -334,7 +377,7 @@ template <class CF>
 __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u4* __restrict__ rd,
                                                             lds_u4* __restrict__ dma, const int8_t* __restrict__ gA,
                                                             const int8_t* __restrict__ gB,
-                                                            const O2Ctx<CF::LPS>& c, O2Acc& a) {
+                                                            const O2Ctx<CF::LPS>& c, O2Acc<CF::TWO_ACC>& a) {
   constexpr int SPI = CF::SPI, NSTAGE = CF::NSTAGE, LPS = CF::LPS, LPT = CF::LPT;
   const int nstep = (c.NSTRIP + SPI - 1) / SPI;
   if (s >= 0) {
@@ -374,24 +417,18 @@ __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u
         fr[4 * t + 2] = __builtin_bit_cast(i4, st[c.lb * 8 + (w ^ sb)]);
         fr[4 * t + 3] = __builtin_bit_cast(i4, st[c.lb * 8 + ((4 + w) ^ sb)]);
       }
-      a.arr = mfma_i8(fr[0], fr[2], a.arr);
-      a.aii = mfma_i8(fr[1], fr[3], a.aii);
-      a.ari = mfma_i8(fr[0], fr[3], a.ari);
-      a.ari = mfma_i8(fr[1], fr[2], a.ari);
+      a.step(fr[0], fr[1], fr[2], fr[3]);
       if (!(kt == c.KT - 1 && c.K - kt * KS <= 32)) {   // a half strip at the end has one step
-        a.arr = mfma_i8(fr[4], fr[6], a.arr);
-        a.aii = mfma_i8(fr[5], fr[7], a.aii);
-        a.ari = mfma_i8(fr[4], fr[7], a.ari);
-        a.ari = mfma_i8(fr[5], fr[6], a.ari);
+        a.step(fr[4], fr[5], fr[6], fr[7]);
       }
     }
     if (kt == c.KT - 1) {
       const double m = c.cst[i], im = c.cst[kO2MaxModuli + i], u = c.cst[2 * kO2MaxModuli + i];
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        crt_fold(a.arr[v] - a.aii[v], m, im, u, a.sre[v]);
-        crt_fold(a.ari[v], m, im, u, a.sim[v]);
-        a.arr[v] = 0; a.aii[v] = 0; a.ari[v] = 0;
+        crt_fold(a.re(v), m, im, u, a.sre[v]);
+        crt_fold(a.im(v), m, im, u, a.sim[v]);
+        a.clear(v);
       }
     }
   }
@@ -480,10 +517,10 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
   c.NSTRIP = NSTRIP;
   c.wlive = wlive;
 
-  O2Acc acc;
+  O2Acc<CF::TWO_ACC> acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
-    acc.arr[v] = 0; acc.aii[v] = 0; acc.ari[v] = 0;
+    acc.clear(v);
     acc.sre[v] = 0.0; acc.sim[v] = 0.0;
   }
   auto stage = [&](int f) { return (lds_u4*)&ring[(f + NSTAGE) % NSTAGE][0]; };   // f >= -NSTAGE
