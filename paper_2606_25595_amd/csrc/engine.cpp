@@ -296,17 +296,30 @@ Scheme larger_split(const Scheme& a, const Scheme& b) {
   return operand_bytes(64, 64, b, 1) > operand_bytes(64, 64, a, 1) ? b : a;
 }
 
+// Converted-operand slots: 0 and 1 take a product's A and B by default; a batch also
+// has kKeepSlots more, where an operand converted for one product is kept for a later
+// product of the same scheme that uses it on the same side.
+constexpr int kKeepSlots = 3;
 struct SplitBufs {
-  void* S[2] = {nullptr, nullptr};
-  int32_t* E[2] = {nullptr, nullptr};
+  void* S[2 + kKeepSlots] = {};
+  int32_t* E[2 + kKeepSlots] = {};
 };
 
-size_t split_pair_bytes(int b, const Scheme& sc, int batch) { return 2 * operand_bytes(b, b, sc, batch); }
+// Which slots a product converts its operands into, and whether an operand is already
+// there (then it is not converted again).  Ignored by the unsliced schemes.
+struct ConvUse {
+  int a = 0, b = 1;
+  bool have_a = false, have_b = false;
+};
 
-SplitBufs carve_split(char*& w, int b, const Scheme& sc, int batch) {
+size_t split_pair_bytes(int b, const Scheme& sc, int batch, int slots = 2) {
+  return slots * operand_bytes(b, b, sc, batch);
+}
+
+SplitBufs carve_split(char*& w, int b, const Scheme& sc, int batch, int slots = 2) {
   SplitBufs sb;
   if (!sc.sliced()) return sb;
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < slots; ++q) {
     sb.S[q] = w; w += align_up(operand_digit_bytes(b, b, sc) * batch);
     sb.E[q] = (int32_t*)w; w += align_up((size_t)split_exp_stride(b, b) * sizeof(int32_t) * batch);
   }
@@ -341,7 +354,8 @@ int o2_variant_for(qtx_rgf_ctx ctx, const GemmDesc& d, int p) {
 
 // One batched complex block product with a precision scheme.  Elementwise (K = 0)
 // launches stay FP64.
-hipError_t run_product(qtx_rgf_ctx ctx, const GemmDesc& d, const Scheme& sc, const SplitBufs& sb, hipStream_t s) {
+hipError_t run_product(qtx_rgf_ctx ctx, const GemmDesc& d, const Scheme& sc, const SplitBufs& sb, hipStream_t s,
+                       ConvUse use = ConvUse()) {
   // per-launch timers: the matrix-core kernel (its own operations) and the operand
   // conversion passes (their algorithmic bytes) separately
   // a skew-Hermitian result needs only its elements r <= c (the split scheme
@@ -371,7 +385,7 @@ hipError_t run_product(qtx_rgf_ctx ctx, const GemmDesc& d, const Scheme& sc, con
   sa.tX = d.tA; sa.X = d.A; sa.ld = d.lda; sa.stride = d.sA;
   sa.rows = d.M; sa.cols = d.K;
   sa.trans = (d.opA == OP_C); sa.conj = (d.opA == OP_C);
-  sa.S = sb.S[0]; sa.E = sb.E[0];
+  sa.S = sb.S[use.a]; sa.E = sb.E[use.a];
   sa.s_stride = stride(d.M);
   sa.e_stride = split_exp_stride(d.M, d.K);
   sa.batch = shA ? 1 : d.batch;
@@ -379,7 +393,7 @@ hipError_t run_product(qtx_rgf_ctx ctx, const GemmDesc& d, const Scheme& sc, con
   sbd.tX = d.tB; sbd.X = d.B; sbd.ld = d.ldb; sbd.stride = d.sB;
   sbd.rows = d.N; sbd.cols = d.K;
   sbd.trans = (d.opB == OP_N); sbd.conj = (d.opB == OP_C);
-  sbd.S = sb.S[1]; sbd.E = sb.E[1];
+  sbd.S = sb.S[use.b]; sbd.E = sb.E[use.b];
   sbd.s_stride = stride(d.N);
   sbd.e_stride = split_exp_stride(d.N, d.K);
   sbd.batch = shB ? 1 : d.batch;
@@ -391,17 +405,17 @@ hipError_t run_product(qtx_rgf_ctx ctx, const GemmDesc& d, const Scheme& sc, con
   g.EB = sbd.E; g.eb_stride = shB ? 0 : sbd.e_stride;
   // conversion bytes: read the operand, write digits / residues and exponents
   const double conv_bytes =
-      (double)sa.batch * ((double)d.M * d.K * 16.0 + (double)operand_digit_bytes(d.M, d.K, sc)) +
-      (double)sbd.batch * ((double)d.N * d.K * 16.0 + (double)operand_digit_bytes(d.N, d.K, sc));
+      (use.have_a ? 0.0 : (double)sa.batch * ((double)d.M * d.K * 16.0 + (double)operand_digit_bytes(d.M, d.K, sc))) +
+      (use.have_b ? 0.0 : (double)sbd.batch * ((double)d.N * d.K * 16.0 + (double)operand_digit_bytes(d.N, d.K, sc)));
   hipError_t e;
-  {
+  if (!use.have_a || !use.have_b) {
     ProfScope ps(ctx, QTX_KERNEL_CONVERT, s, conv_bytes, prof);
     if (sc.o2()) {
-      if ((e = launch_o2_convert(sa, P, s)) != hipSuccess) return e;
-      if ((e = launch_o2_convert(sbd, P, s)) != hipSuccess) return e;
+      if (!use.have_a && (e = launch_o2_convert(sa, P, s)) != hipSuccess) return e;
+      if (!use.have_b && (e = launch_o2_convert(sbd, P, s)) != hipSuccess) return e;
     } else {
-      if ((e = launch_split(sa, sc.fmt, sc.ns, s)) != hipSuccess) return e;
-      if ((e = launch_split(sbd, sc.fmt, sc.ns, s)) != hipSuccess) return e;
+      if (!use.have_a && (e = launch_split(sa, sc.fmt, sc.ns, s)) != hipSuccess) return e;
+      if (!use.have_b && (e = launch_split(sbd, sc.fmt, sc.ns, s)) != hipSuccess) return e;
     }
   }
   ProfScope ps(ctx, QTX_KERNEL_GEMM, s, core_ops, prof);
@@ -488,7 +502,7 @@ BatchKey key_of(const qtx_rgf_problem& p) {
 size_t batch_ws_bytes(const BatchKey& k, int Z) {
   const size_t blk = align_up((size_t)Z * k.b * k.b * sizeof(double2));
   return blk * (1 + kTemps + 2) + align_up(gje_work_bytes(k.b, Z)) + align_up((size_t)Z * sizeof(int32_t)) +
-         split_pair_bytes(k.b, larger_split(k.r, k.l), Z) + split_pair_bytes(k.b, k.l, Z) + 1024;
+         split_pair_bytes(k.b, larger_split(k.r, k.l), Z, 2 + kKeepSlots) + split_pair_bytes(k.b, k.l, Z) + 1024;
 }
 
 size_t per_entry_bytes(const BatchKey& k) { return batch_ws_bytes(k, 1); }
@@ -660,7 +674,7 @@ struct Gemm {
   // C = alpha * op(A) op(B) + addends (+ diag * E_z I), over the first Z entries;
   // skew: the result is skew-Hermitian (only r <= c computed, mirrored)
   hipError_t go(int Z, int opA, Mat A, int opB, Mat B, Mat C, double2 alpha, std::initializer_list<Addend> adds,
-                double2 diag = cmk(0, 0), int K = -1, bool skew = false) const {
+                double2 diag = cmk(0, 0), int K = -1, bool skew = false, ConvUse use = ConvUse()) const {
     if (run->dry || Z <= 0) return hipSuccess;
     GemmDesc d;
     d.M = b; d.N = b; d.K = (K < 0) ? b : K;
@@ -682,7 +696,7 @@ struct Gemm {
     d.bscal = energies;
     d.batch = Z;
     d.skew = skew ? 1 : 0;
-    return run_product(run->ctx, d, sc, sb, on_side ? run->side : run->s);
+    return run_product(run->ctx, d, sc, sb, on_side ? run->side : run->s, use);
   }
 };
 
@@ -712,7 +726,7 @@ BatchWs carve_batch(char* w, const BatchKey& k, int Z) {
   L.Lw = (double2*)w; w += blk;
   L.gw = gje_carve(w, k.b, Z); w += align_up(gje_work_bytes(k.b, Z));
   L.st = (int32_t*)w; w += align_up((size_t)Z * sizeof(int32_t));
-  L.sb = carve_split(w, k.b, larger_split(k.r, k.l), Z);
+  L.sb = carve_split(w, k.b, larger_split(k.r, k.l), Z, 2 + kKeepSlots);
   L.sb_side = carve_split(w, k.b, k.l, Z);
   return L;
 }
@@ -840,11 +854,20 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
     const Mat Gn = R.get(A_GRD, 1, kk, 1);
     const Mat GRu = R.get(A_GRU, 1, kk, 0);
     const Mat GRl = R.get(A_GRL, 1, kk, 0);
+    // Converted operands kept for a second use (slots 2..4): P' as A of G_{i,i+1} and V',
+    // R' as B of G_{i+1,i} and G_ii, G_{i,i+1} as A of W' and G_ii; across the two chains
+    // only when they use the same scheme.
+    const bool same = k.r == k.l;
+    ConvUse keepP, keepR, keepG, useP, useRG;
+    keepP.a = 2;
+    keepR.b = 3;
+    if (same) { keepG.a = 4; useP.a = 2; useP.have_a = true; useRG.a = 4; useRG.have_a = true; }
+    useRG.b = 3; useRG.have_b = true;
     QTX_TRY(g.go(Z, OP_N, xi, OP_N, U, Pp, one, {}));                           // P' = x_i U'
     QTX_TRY(g.go(Z, OP_N, L, OP_N, xi, Rp, one, {}));                           // R' = L' x_i
-    QTX_TRY(g.go(Z, OP_N, Pp, OP_N, Gn, GRu, cmk(-sU, 0), {}));                 // G_{i,i+1}
-    QTX_TRY(g.go(Z, OP_N, Gn, OP_N, Rp, GRl, cmk(-sL, 0), {}));                 // G_{i+1,i}
-    QTX_TRY(gl.go(Z, OP_N, GRu, OP_N, L, Wp, one, {}));                         // W' = G_{i,i+1} L'
+    QTX_TRY(g.go(Z, OP_N, Pp, OP_N, Gn, GRu, cmk(-sU, 0), {}, zero, -1, false, keepP));   // G_{i,i+1}
+    QTX_TRY(g.go(Z, OP_N, Gn, OP_N, Rp, GRl, cmk(-sL, 0), {}, zero, -1, false, keepR));   // G_{i+1,i}
+    QTX_TRY(gl.go(Z, OP_N, GRu, OP_N, L, Wp, one, {}, zero, -1, false, keepG));          // W' = G_{i,i+1} L'
     // The lesser blocks (x_i is still unchanged here: G_ii overwrites it below).
     //   G<_{i,i+1} = -P G<_{i+1} - xl L^H G_{i+1}^H + x BU G_{i+1}^H
     //   G<_ii = xl + P G<_{i+1} P^H - W xl - xl L^H G_{i,i+1}^H + G_{i,i+1} BL x^H + x BU G_{i,i+1}^H
@@ -864,12 +887,12 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
         QTX_TRY(gl.go(Z, OP_N, Wp, OP_N, xl, Yp, msl, {}));                       // Y = -sL W' xl_i
         QTX_TRY(gl.go(Z, OP_N, xl, OP_C, L, Zp, msl, {}));                        // Z = -sL xl_i L'^H
       }
-      QTX_TRY(gl.go(Z, OP_N, Pp, OP_N, Gln, Vp, one, {}));                        // V' = P' G<_{i+1}
+      QTX_TRY(gl.go(Z, OP_N, Pp, OP_N, Gln, Vp, one, {}, zero, -1, false, useP));   // V' = P' G<_{i+1}
       QTX_TRY(gl.go(Z, OP_N, Zp, OP_C, Gn, R.get(r.Gu, 1, kk, 0), one, {addend_of(Vp, cmk(-sU, 0))}));
       QTX_TRY(gl.go(Z, OP_N, Vp, OP_C, Pp, xl, one,                               // G<_ii (in place)
                     {addend_of(xl, one), addend_of(Yp, one), addend_of(Yp, cmk(-1, 0), OP_C)}, zero, -1, true));
     }
-    QTX_TRY(g.go(Z, OP_N, GRu, OP_N, Rp, xi, cmk(-sL, 0), {addend_of(xi, one)}));   // G_ii (in place)
+    QTX_TRY(g.go(Z, OP_N, GRu, OP_N, Rp, xi, cmk(-sL, 0), {addend_of(xi, one)}, zero, -1, false, useRG));   // G_ii
   }
   // ------------------------------------------------------------ status
   // Non-finite values propagate into the first blocks: check those; then every
