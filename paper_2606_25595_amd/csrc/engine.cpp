@@ -299,7 +299,7 @@ Scheme larger_split(const Scheme& a, const Scheme& b) {
 // Converted-operand slots: 0 and 1 take a product's A and B by default; a batch also
 // has kKeepSlots more, where an operand converted for one product is kept for a later
 // product of the same scheme that uses it on the same side.
-constexpr int kKeepSlots = 3;
+constexpr int kKeepSlots = 4;
 struct SplitBufs {
   void* S[2 + kKeepSlots] = {};
   int32_t* E[2 + kKeepSlots] = {};
@@ -310,6 +310,7 @@ struct SplitBufs {
 struct ConvUse {
   int a = 0, b = 1;
   bool have_a = false, have_b = false;
+  bool conj_b = false;   // INT8 only: op(B) = X^H and slot b holds X converted as a left operand
 };
 
 size_t split_pair_bytes(int b, const Scheme& sc, int batch, int slots = 2) {
@@ -397,8 +398,10 @@ hipError_t run_product(qtx_rgf_ctx ctx, const GemmDesc& d, const Scheme& sc, con
   sbd.s_stride = stride(d.N);
   sbd.e_stride = split_exp_stride(d.N, d.K);
   sbd.batch = shB ? 1 : d.batch;
+  if (use.conj_b && (!sc.o2() || !use.have_b || d.opB != OP_C)) return hipErrorInvalidValue;
   SplitGemmDesc g;
   g.d = d;
+  g.conj_b = use.conj_b ? 1 : 0;
   g.SA = sa.S; g.sa_stride = shA ? 0 : sa.s_stride;
   g.SB = sbd.S; g.sb_stride = shB ? 0 : sbd.s_stride;
   g.EA = sa.E; g.ea_stride = shA ? 0 : sa.e_stride;
@@ -829,18 +832,25 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
       QTX_TRY(launch_gje_invert(b, W.X, bb, (double2*)xi.p, xi.stride, Z, W.gw, W.st, s, (double2* const*)xi.tab));
     }
     if (side) QTX_TRY(hipStreamWaitEvent(s, R.side_join, 0));
+    // x_i is converted once (slot 2) as the left operand of Z = x_i Q for every right-hand
+    // side; with the INT8 scheme the same residues, imaginary part negated, are the right
+    // operand x_i^H of x^<_i = Z x_i^H.
+    ConvUse xA, xH;
+    xA.a = 2;
+    if (k.l.o2()) { xH.b = 2; xH.have_b = true; xH.conj_b = true; }
     for (size_t q = 0; q < rhs.size(); ++q) {
       const Rhs& r = rhs[q];
       const Mat Bi = R.get(r.S, 0, i, 0);
       if (i == 0) {
-        QTX_TRY(gl.go(Z, OP_N, xi, OP_N, Bi, ws(W.Tm[2]), one, {}));
+        QTX_TRY(gl.go(Z, OP_N, xi, OP_N, Bi, ws(W.Tm[2]), one, {}, zero, -1, false, xA));
       } else {
         // Q_i (done above for the first recurrence);  Z = x_i Q
         if (q > 0) QTX_TRY(lesser_q(gl, r));
-        QTX_TRY(gl.go(Z, OP_N, xi, OP_N, ws(W.Tm[3]), ws(W.Tm[2]), one, {}));
+        QTX_TRY(gl.go(Z, OP_N, xi, OP_N, ws(W.Tm[3]), ws(W.Tm[2]), one, {}, zero, -1, false, xA));
       }
+      xA.have_a = true;
       // xl_i = Z x_i^H (skew-Hermitian)
-      QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[2]), OP_C, xi, R.get(r.Gd, 0, i, 0), one, {}, zero, -1, true));
+      QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[2]), OP_C, xi, R.get(r.Gd, 0, i, 0), one, {}, zero, -1, true, xH));
     }
   }
   // ------------------------------------------------------------ backward (i = n_b - 2 - kk per entry)
@@ -854,15 +864,22 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
     const Mat Gn = R.get(A_GRD, 1, kk, 1);
     const Mat GRu = R.get(A_GRU, 1, kk, 0);
     const Mat GRl = R.get(A_GRL, 1, kk, 0);
-    // Converted operands kept for a second use (slots 2..4): P' as A of G_{i,i+1} and V',
+    // Converted operands kept for a second use (slots 2..5): P' as A of G_{i,i+1} and V',
     // R' as B of G_{i+1,i} and G_ii, G_{i,i+1} as A of W' and G_ii; across the two chains
-    // only when they use the same scheme.
+    // only when they use the same scheme.  With the INT8 scheme the left-operand residues
+    // of G_{i+1,i+1} and P' also serve, imaginary part negated, as the right operands
+    // G_{i+1,i+1}^H of G<_{i,i+1} and P'^H of G<_ii.
     const bool same = k.r == k.l;
-    ConvUse keepP, keepR, keepG, useP, useRG;
+    ConvUse keepP, keepR, keepG, useP, useRG, gnH, pH;
     keepP.a = 2;
+    keepR.a = 5;
     keepR.b = 3;
     if (same) { keepG.a = 4; useP.a = 2; useP.have_a = true; useRG.a = 4; useRG.have_a = true; }
     useRG.b = 3; useRG.have_b = true;
+    if (same && k.l.o2()) {
+      gnH.b = 5; gnH.have_b = true; gnH.conj_b = true;
+      pH.b = 2; pH.have_b = true; pH.conj_b = true;
+    }
     QTX_TRY(g.go(Z, OP_N, xi, OP_N, U, Pp, one, {}));                           // P' = x_i U'
     QTX_TRY(g.go(Z, OP_N, L, OP_N, xi, Rp, one, {}));                           // R' = L' x_i
     QTX_TRY(g.go(Z, OP_N, Pp, OP_N, Gn, GRu, cmk(-sU, 0), {}, zero, -1, false, keepP));   // G_{i,i+1}
@@ -888,9 +905,10 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
         QTX_TRY(gl.go(Z, OP_N, xl, OP_C, L, Zp, msl, {}));                        // Z = -sL xl_i L'^H
       }
       QTX_TRY(gl.go(Z, OP_N, Pp, OP_N, Gln, Vp, one, {}, zero, -1, false, useP));   // V' = P' G<_{i+1}
-      QTX_TRY(gl.go(Z, OP_N, Zp, OP_C, Gn, R.get(r.Gu, 1, kk, 0), one, {addend_of(Vp, cmk(-sU, 0))}));
+      QTX_TRY(gl.go(Z, OP_N, Zp, OP_C, Gn, R.get(r.Gu, 1, kk, 0), one, {addend_of(Vp, cmk(-sU, 0))}, zero, -1, false,
+                    gnH));
       QTX_TRY(gl.go(Z, OP_N, Vp, OP_C, Pp, xl, one,                               // G<_ii (in place)
-                    {addend_of(xl, one), addend_of(Yp, one), addend_of(Yp, cmk(-1, 0), OP_C)}, zero, -1, true));
+                    {addend_of(xl, one), addend_of(Yp, one), addend_of(Yp, cmk(-1, 0), OP_C)}, zero, -1, true, pH));
     }
     QTX_TRY(g.go(Z, OP_N, GRu, OP_N, Rp, xi, cmk(-sL, 0), {addend_of(xi, one)}, zero, -1, false, useRG));   // G_ii
   }

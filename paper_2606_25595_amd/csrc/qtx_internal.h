@@ -95,6 +95,10 @@ struct SplitGemmDesc {
   const void* SB = nullptr; int64_t sb_stride = 0;   // rows = N
   const int32_t* EA = nullptr; int64_t ea_stride = 0;
   const int32_t* EB = nullptr; int64_t eb_stride = 0;
+  // INT8 scheme: SB / EB hold the conversion of the matrix X whose conjugate transpose
+  // op(B) is, made for X as a left operand (same rows, exponents and layout); the
+  // product negates its imaginary residues (exactly the right-operand conversion of X^H).
+  int conj_b = 0;
 };
 bool split_supported(int fmt, int ns);                    // fmt 0 = FP16, 1 = BF16
 size_t split_bytes(int rows, int cols, int ns, int batch);

@@ -321,6 +321,13 @@ struct O2Acc<true> {
     are = mfma_i8(ai, neg_i8x16(bi), are);
     aim = mfma_i8(ai, br, aim);
   }
+  // the same with B conjugated (bi -> -bi): the negation moves to the other product
+  __device__ inline void step_conj(i4 ar, i4 ai, i4 br, i4 bi) {
+    are = mfma_i8(ar, br, are);
+    aim = mfma_i8(ar, neg_i8x16(bi), aim);
+    are = mfma_i8(ai, bi, are);
+    aim = mfma_i8(ai, br, aim);
+  }
 };
 template <>
 struct O2Acc<false> {
@@ -335,6 +342,7 @@ struct O2Acc<false> {
     ari = mfma_i8(ar, bi, ari);
     ari = mfma_i8(ai, br, ari);
   }
+  __device__ inline void step_conj(i4 ar, i4 ai, i4 br, i4 bi) { step(ar, ai, br, neg_i8x16(bi)); }
 };
 
 // Per-thread constants of the strip loop.
@@ -373,7 +381,7 @@ __device__ inline void wait_vm() {
 // last strip re-copies that strip into its unused part), so "step s landed" is a
 // fixed count of outstanding vector-memory operations: with 3 stages step s + 1
 // may still be in flight, with 2 nothing else is.
-template <class CF>
+template <class CF, bool CONJB>
 __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u4* __restrict__ rd,
                                                             lds_u4* __restrict__ dma, const int8_t* __restrict__ gA,
                                                             const int8_t* __restrict__ gB,
@@ -417,9 +425,11 @@ __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u
         fr[4 * t + 2] = __builtin_bit_cast(i4, st[c.lb * 8 + (w ^ sb)]);
         fr[4 * t + 3] = __builtin_bit_cast(i4, st[c.lb * 8 + ((4 + w) ^ sb)]);
       }
-      a.step(fr[0], fr[1], fr[2], fr[3]);
+      if (CONJB) a.step_conj(fr[0], fr[1], fr[2], fr[3]);
+      else a.step(fr[0], fr[1], fr[2], fr[3]);
       if (!(kt == c.KT - 1 && c.K - kt * KS <= 32)) {   // a half strip at the end has one step
-        a.step(fr[4], fr[5], fr[6], fr[7]);
+        if (CONJB) a.step_conj(fr[4], fr[5], fr[6], fr[7]);
+        else a.step(fr[4], fr[5], fr[6], fr[7]);
       }
     }
     if (kt == c.KT - 1) {
@@ -439,7 +449,7 @@ __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u
 // workgroup count, so the workgroups sharing an L2 work on adjacent tiles of the
 // same energies in step and read each residue strip from HBM about once.
 // Otherwise one tile per workgroup.
-template <class CF>
+template <class CF, bool CONJB>
 __global__ __launch_bounds__(CF::NT) __attribute__((amdgpu_waves_per_eu(CF::WAVES_PER_SIMD)))
 void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
                                                           int persist) {
@@ -526,7 +536,7 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
   auto stage = [&](int f) { return (lds_u4*)&ring[(f + NSTAGE) % NSTAGE][0]; };   // f >= -NSTAGE
   const int nstep = (NSTRIP + SPI - 1) / SPI;
   for (int st = -(NSTAGE - 1); st < nstep; ++st)
-    o2_step<CF>(st, stage(st), stage(st + NSTAGE - 1), SA, SB, c, acc);
+    o2_step<CF, CONJB>(st, stage(st), stage(st + NSTAGE - 1), SA, SB, c, acc);
 
   // epilogue in FP64 (same addend semantics as the FP64 kernels)
   double2* __restrict__ C = d.tC ? d.tC[z] : d.C + (int64_t)z * d.sC;
@@ -667,7 +677,9 @@ hipError_t launch_o2_variant(const SplitGemmDesc& g, const O2Params& P, hipStrea
   const int grid_p = cus[dev] / 8 * 8 * CF::WPC;
   const bool persist = allow_persist && grid_p >= 8 && total > grid_p;
   const unsigned grid = persist ? (unsigned)grid_p : (unsigned)total;
-  hipLaunchKernelGGL((zgemm_o2_kernel<CF>), dim3(grid), dim3(CF::NT), 0, s, g, P, (int)total, persist ? 1 : 0);
+  // CONJB: the imaginary B fragments are negated in registers (SplitGemmDesc::conj_b)
+  if (g.conj_b) hipLaunchKernelGGL((zgemm_o2_kernel<CF, true>), dim3(grid), dim3(CF::NT), 0, s, g, P, (int)total, persist ? 1 : 0);
+  else hipLaunchKernelGGL((zgemm_o2_kernel<CF, false>), dim3(grid), dim3(CF::NT), 0, s, g, P, (int)total, persist ? 1 : 0);
   return hipGetLastError();
 }
 
