@@ -87,7 +87,8 @@ typedef enum {
 
 enum {
   QTX_S_IDENTITY = 1u,      /* S = I: S_d/S_u/S_l are ignored                        */
-  QTX_WANT_GREATER = 8u     /* also compute G^> from Sigma^> (SG_*)                   */
+  QTX_WANT_GREATER = 8u,    /* also compute G^> from Sigma^> (SG_*)                   */
+  QTX_SPLIT_CHAIN = 16u     /* solve each energy as two half-chains (see below)        */
 };
 
 /* One BT problem: one device (H, S) and n_e energies.
@@ -121,6 +122,20 @@ enum {
  * lesser/greater recurrences use (prec_lesser, n_slices_lesser).  The lesser
  * chain is the more sensitive one, as the paper chooses slice counts per
  * motif (Section V-B, Table IV).
+ * QTX_SPLIT_CHAIN (spatially parallel solve of one energy; Section II-A solves
+ *   Eq. 2 for the selected blocks only, and the work it cites on parallel quadratic
+ *   selected inversion splits the BT chain): each energy with n_b >= 3 runs as two
+ *   half-chains in the same launches, a top half over blocks 0 .. c-1 and a bottom
+ *   half that eliminates from block n_b-1 upwards, c = (n_b - 1) / 2.  The bottom
+ *   half's last step, at the separator block c, also takes the top half's coupling
+ *   terms, so its inverse is G^R_cc and its lesser block G^<_cc; both halves then
+ *   run the backward recurrence outwards from c.  The sequential step count per
+ *   energy drops from 2 n_b - 1 to about n_b + 1 at the same operation count: it
+ *   lowers the latency of a solve with few energies and changes nothing for a
+ *   large batch, which already fills the GPU.  Results agree with the unsplit
+ *   solve to rounding.  Requires block-diagonal Sigma^< / Sigma^> (SL_u and SG_u
+ *   NULL, else QTX_ERR_UNSUPPORTED); the workspace per energy doubles
+ *   (qtx_rgf_footprint).  n_b <= 2 ignores the flag.
  * Limits: 1 <= b <= 1024, n_b >= 1, n_e >= 1. */
 typedef struct {
   int32_t n_b, b, n_e;
@@ -128,7 +143,7 @@ typedef struct {
   int32_t n_slices;        /* split modes: slices per operand, 0 = default (2)  */
   int32_t prec_lesser;     /* qtx_prec of the lesser/greater-chain products,    */
   int32_t n_slices_lesser; /*   -1 = same as prec / n_slices                    */
-  uint32_t flags;          /* QTX_S_IDENTITY | QTX_WANT_GREATER                  */
+  uint32_t flags;          /* QTX_S_IDENTITY | QTX_WANT_GREATER | QTX_SPLIT_CHAIN */
   const double* energies;  /* host                                              */
   const void *H_d, *H_u, *H_l;
   const void *S_d, *S_u, *S_l;

@@ -71,6 +71,41 @@ __global__ void nan_fill_entries_kernel(double2* const* t, const int64_t* counts
     Xz[i] = cmk(nan, nan);
 }
 
+// Top half of a split energy (part[z] >= 0) takes its bottom half's failure.  Only
+// top halves are written and only bottom halves are read.
+__global__ void status_merge_kernel(int32_t* st, const int32_t* part, int n) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z < n && part[z] >= 0 && st[z] == 0) st[z] = st[part[z]];
+}
+
+// X <- -X^H in place for each b x b block t[m]: one workgroup per pair of 32 x 32
+// tiles (ti <= tj), both staged in LDS before either is written.
+__global__ __launch_bounds__(256) void neg_ctrans_kernel(double2* const* t, int b, int count) {
+  __shared__ double2 ta[32][33], tb[32][33];
+  const int nt = (b + 31) / 32;
+  int q = blockIdx.x, ti = 0;
+  while (q >= nt - ti) { q -= nt - ti; ++ti; }
+  const int tj = ti + q;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int m = blockIdx.y; m < count; m += gridDim.y) {
+    double2* X = t[m];
+    for (int k = ty; k < 32; k += 8) {
+      int r = ti * 32 + k, c = tj * 32 + tx;
+      if (r < b && c < b) ta[k][tx] = X[(int64_t)r * b + c];
+      r = tj * 32 + k; c = ti * 32 + tx;
+      if (r < b && c < b) tb[k][tx] = X[(int64_t)r * b + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+      int r = ti * 32 + k, c = tj * 32 + tx;
+      if (r < b && c < b) { const double2 v = tb[tx][k]; X[(int64_t)r * b + c] = cmk(-v.x, v.y); }
+      r = tj * 32 + k; c = ti * 32 + tx;
+      if (r < b && c < b) { const double2 v = ta[tx][k]; X[(int64_t)r * b + c] = cmk(-v.x, v.y); }
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void scatter_status_kernel(const int32_t* st, int32_t* const* dst, int n) {
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z < n && dst[z]) *dst[z] = st[z];
@@ -159,6 +194,20 @@ hipError_t launch_nan_fill_entries(double2* const* t, const int64_t* counts, int
                                    hipStream_t s) {
   if (batch <= 0) return hipSuccess;
   hipLaunchKernelGGL(nan_fill_entries_kernel, dim3(256, batch), dim3(256), 0, s, t, counts, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_status_merge(int32_t* st, const int32_t* part, int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(status_merge_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, st, part, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_neg_ctrans_entries(double2* const* t, int b, int count, hipStream_t s) {
+  if (count <= 0 || b <= 0) return hipSuccess;
+  const int nt = (b + 31) / 32;
+  const int gy = count < 65535 ? count : 65535;
+  hipLaunchKernelGGL(neg_ctrans_kernel, dim3((unsigned)(nt * (nt + 1) / 2), gy), dim3(256), 0, s, t, b, count);
   return hipGetLastError();
 }
 

@@ -456,7 +456,10 @@ qtx_status check_supported(const qtx_rgf_problem* p) {
   Scheme sc;
   if (!make_scheme(p->prec, p->n_slices, &sc)) return QTX_ERR_UNSUPPORTED;
   if (p->prec_lesser >= 0 && !make_scheme(p->prec_lesser, p->n_slices_lesser, &sc)) return QTX_ERR_UNSUPPORTED;
-  if (p->flags & ~(uint32_t)(QTX_S_IDENTITY | QTX_WANT_GREATER)) return QTX_ERR_ARG;
+  if (p->flags & ~(uint32_t)(QTX_S_IDENTITY | QTX_WANT_GREATER | QTX_SPLIT_CHAIN)) return QTX_ERR_ARG;
+  // The bottom half of a split chain reads the system block-reversed, where a BT
+  // Sigma^< would enter as the conjugate transposes of its upper blocks.
+  if ((p->flags & QTX_SPLIT_CHAIN) && (p->SL_u || p->SG_u)) return QTX_ERR_UNSUPPORTED;
   return QTX_OK;
 }
 
@@ -472,9 +475,19 @@ enum Arr {
   A_SLU, A_SGU
 };
 
+// One chain of the recurrences.  An energy is one entry, or two with QTX_SPLIT_CHAIN:
+// the top half (blocks 0 .. c-1, forward steps 0 .. c-1, backward from block c) and the
+// bottom half, which runs the same recurrences on the block-reversed system
+// (logical block j = physical n_b - 1 - j) from block n_b - 1 up to the separator c,
+// where it adds the top half's coupling terms before inverting (its last x is G_cc).
 struct Entry {
   const qtx_rgf_problem* p;
   int e;
+  int nf = 0;         // forward steps
+  int nbk = 0;        // backward steps + 1 (backward from logical block nbk - 1)
+  bool rev = false;   // bottom half: logical block j is physical block n_b - 1 - j
+  int c = 0;          // separator block of a split energy
+  int part = -1;      // top half: index of its bottom half in the batch
 };
 
 // The common properties of a batch's entries.
@@ -512,17 +525,21 @@ size_t per_entry_bytes(const BatchKey& k) { return batch_ws_bytes(k, 1); }
 
 struct Batch {
   BatchKey key;
-  std::vector<Entry> ent;     // sorted by n_b, descending
-  int max_nb = 0;
+  std::vector<Entry> ent;     // sorted by (nf, nbk, rev), descending
+  int max_nf = 0, max_nbk = 0;
+  bool split = false;         // holds split energies
   int lane = 0;               // stream lane (batches of one lane run in order)
   size_t ws_off = 0;          // workspace region (bytes from the workspace start)
   size_t tab_off = 0;         // table area (bytes from the table block start)
 };
 
 // A pointer table request: array, indexing mode, step, block offset.
-// mode 0: forward step i -> block i + delta (active prefix of step i)
-// mode 1: backward step k -> block n_b - 2 - k + delta (active prefix of step k)
-// mode 2: block delta of every entry, always a table (status handling)
+// mode 0: forward step i -> logical block i + delta (active prefix of step i)
+// mode 1: backward step k -> logical block nbk - 2 - k + delta (active prefix of step k)
+// mode 2: logical block delta of every entry, always a table (status handling)
+// mode 3: bottom halves that reach their separator c at forward step `step` ->
+//         physical block c - 1 + delta (the top half's last forward block)
+// mode 4: every physical upper block c .. n_b - 2 of every bottom half
 struct TabKey {
   int arr, mode, step, delta;
   bool operator<(const TabKey& o) const {
@@ -545,7 +562,7 @@ struct Mat {
 
 // Per-entry data at the head of a batch's table area.
 struct EntryData {
-  size_t en, ust, cnt_d, cnt_u, end;
+  size_t en, ust, cnt_d, cnt_u, part, end;
 };
 EntryData entry_data_layout(int Z) {
   EntryData d;
@@ -553,7 +570,8 @@ EntryData entry_data_layout(int Z) {
   d.ust = align_up(d.en + (size_t)Z * sizeof(double));
   d.cnt_d = align_up(d.ust + (size_t)Z * sizeof(void*));
   d.cnt_u = align_up(d.cnt_d + (size_t)Z * sizeof(int64_t));
-  d.end = align_up(d.cnt_u + (size_t)Z * sizeof(int64_t));
+  d.part = align_up(d.cnt_u + (size_t)Z * sizeof(int64_t));
+  d.end = align_up(d.part + (size_t)Z * sizeof(int32_t));
   return d;
 }
 
@@ -570,22 +588,47 @@ struct Run {
   char* dev = nullptr;             // its device copy (launch pass)
   int64_t bb = 0;
 
-  int nb_of(int z) const { return B->ent[z].p->n_b; }
   int active_fwd(int i) const {
     int n = 0;
-    while (n < (int)B->ent.size() && nb_of(n) > i) ++n;
+    while (n < (int)B->ent.size() && B->ent[n].nf > i) ++n;
     return n;
   }
   int active_bwd(int k) const {
     int n = 0;
-    while (n < (int)B->ent.size() && nb_of(n) - 2 >= k) ++n;
+    while (n < (int)B->ent.size() && B->ent[n].nbk - 2 >= k) ++n;
     return n;
   }
+  // Bottom halves whose last forward step is i: entries [*lo, *hi) (a contiguous run,
+  // by the sort order).
+  void merge_range(int i, int* lo, int* hi) const {
+    *lo = *hi = 0;
+    const int n = (int)B->ent.size();
+    int z = 0;
+    while (z < n && !(B->ent[z].rev && B->ent[z].nf == i + 1)) ++z;
+    *lo = z;
+    while (z < n && B->ent[z].rev && B->ent[z].nf == i + 1) ++z;
+    *hi = z;
+  }
 
-  // Base pointer of array a for entry z at block j (nullptr for an absent array).
-  const double2* ptr(int a, int z, int j) const {
+  // Base pointer of array a for entry z at logical block j (nullptr for an absent
+  // array).  For a bottom half the logical system is the block-reversed one: its
+  // diagonal block j is physical n_b - 1 - j and its upper (lower) coupling j is the
+  // physical lower (upper) block n_b - 2 - j.  Its G^</G^> upper blocks are written
+  // to the physical upper slot n_b - 2 - j as the logical block and transformed
+  // afterwards (mode 4).
+  const double2* ptr(int a, int z, int j, bool physical = false) const {
     const qtx_rgf_problem& p = *B->ent[z].p;
     const int64_t e = B->ent[z].e;
+    if (B->ent[z].rev && !physical) {
+      static const int swap[][2] = {{A_HU, A_HL}, {A_SU, A_SL}, {A_SRU, A_SRL}, {A_GRU, A_GRL}};
+      bool diag = true;
+      for (const auto& sw : swap) {
+        if (a == sw[0]) { a = sw[1]; diag = false; break; }
+        if (a == sw[1]) { a = sw[0]; diag = false; break; }
+      }
+      if (a == A_GLU || a == A_GGU || a == A_SLU || a == A_SGU) diag = false;
+      j = diag ? p.n_b - 1 - j : p.n_b - 2 - j;
+    }
     const int64_t nd = p.n_b, nu = (int64_t)p.n_b - 1;
     const void* base = nullptr;
     int64_t idx = 0;
@@ -619,16 +662,27 @@ struct Run {
     const TabKey key{a, mode, step, delta};
     auto it = tabs.find(key);
     if (it == tabs.end()) {
-      const int Z = mode == 0 ? active_fwd(step) : (mode == 1 ? active_bwd(step) : (int)B->ent.size());
-      std::vector<const double2*> v(Z);
-      bool any_null = false;
-      for (int z = 0; z < Z; ++z) {
-        const int j = mode == 0 ? step + delta : (mode == 1 ? nb_of(z) - 2 - step + delta : delta);
-        v[z] = ptr(a, z, j);
-        any_null |= (v[z] == nullptr);
+      std::vector<const double2*> v;
+      if (mode == 3) {
+        int lo, hi;
+        merge_range(step, &lo, &hi);
+        for (int z = lo; z < hi; ++z) v.push_back(ptr(a, z, B->ent[z].c - 1 + delta, true));
+      } else if (mode == 4) {
+        for (int z = 0; z < (int)B->ent.size(); ++z)
+          if (B->ent[z].rev)
+            for (int j = B->ent[z].c; j <= B->ent[z].p->n_b - 2; ++j) v.push_back(ptr(a, z, j, true));
+      } else {
+        const int Z = mode == 0 ? active_fwd(step) : (mode == 1 ? active_bwd(step) : (int)B->ent.size());
+        for (int z = 0; z < Z; ++z) {
+          const int j = mode == 0 ? step + delta : (mode == 1 ? B->ent[z].nbk - 2 - step + delta : delta);
+          v.push_back(ptr(a, z, j));
+        }
       }
+      const int Z = (int)v.size();
+      bool any_null = false;
+      for (int z = 0; z < Z; ++z) any_null |= (v[z] == nullptr);
       TabVal tv;
-      bool affine = mode != 2 && Z > 0 && !any_null;
+      bool affine = mode != 2 && mode != 4 && Z > 0 && !any_null;
       int64_t stride = 0;
       if (affine && Z > 1) {
         stride = v[1] - v[0];
@@ -718,6 +772,7 @@ struct BatchWs {
   int32_t* const* ust = nullptr;
   const int64_t* cnt_d = nullptr;
   const int64_t* cnt_u = nullptr;
+  const int32_t* part = nullptr;
 };
 
 BatchWs carve_batch(char* w, const BatchKey& k, int Z) {
@@ -783,8 +838,16 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
   };
 
   // ------------------------------------------------------------ forward
-  for (int i = 0; i < B.max_nb; ++i) {
+  // Operand at entry z0 of a per-entry workspace array.
+  auto ws_at = [&](double2* p, int z0) { Mat m; m.p = p ? p + (int64_t)z0 * bb : nullptr; m.stride = bb; return m; };
+  for (int i = 0; i < B.max_nf; ++i) {
     const int Z = R.active_fwd(i);
+    // Bottom halves that reach their separator at this step: [mlo, mhi).
+    int mlo = 0, mhi = 0;
+    if (B.split) R.merge_range(i, &mlo, &mhi);
+    const int Zm = mhi - mlo;
+    Gemm gm = g, glm = gl;   // products over the merge range (per-entry energies from mlo)
+    if (W.en) { gm.energies = W.en + mlo; glm.energies = W.en + mlo; }
     // A_i = E S_ii - H_ii - Sigma^R_ii(E) as epilogue addends
     const Addend aH = addend_of(R.get(A_HD, 0, i, 0), mone);
     const Addend aS = addend_of(R.get(A_SRD, 0, i, 0), mone);
@@ -804,7 +867,7 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
     // inversion leaves most matrix cores idle), else before the inversion.  The
     // side stream forks after everything they read is enqueued and joins before Q
     // is used; it owns its own converted-operand buffers.
-    const bool side = !dry && R.side != nullptr && !ctx->capturing && Z > 0 && i > 0;
+    const bool side = !dry && R.side != nullptr && !ctx->capturing && Z > 0 && i > 0 && Zm == 0;
     // Q_i = B_i + L xl_{i-1} L^H - BL_{i-1} x_{i-1}^H L^H - L x_{i-1} BU_{i-1}.  With
     // L = sL L' and BL = -BU^H (skew-Hermitian right-hand side) the two cross terms are
     // -sL V + sL V^H with V = T' BU_{i-1}, T' = L' x_{i-1} (still in Tm[0]).
@@ -827,6 +890,39 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
       QTX_TRY(lesser_q(side ? gl_side : gl, rhs[0]));
       if (side) QTX_TRY(hipEventRecord(R.side_join, R.side));
     }
+    // Separator of split energies: the bottom half's X = A_c - A_{c,c+1} g_{c+1} A_{c+1,c}
+    // and Q = B_c + A_{c,c+1} g<_{c+1} A_{c,c+1}^H get the top half's terms
+    // - A_{c,c-1} x_{c-1} A_{c-1,c} and + A_{c,c-1} xl_{c-1} A_{c,c-1}^H (physical
+    // couplings of block c - 1; x, xl of the top half), so that its x_c is G_cc and its
+    // xl_c is G<_cc.  Greater: the top term goes to Tm[5] and is added to its Q below.
+    if (Zm > 0) {
+      Mat Um, Lm;
+      double sUm = -1.0, sLm = -1.0;
+      if (!k.coupled) {
+        Um = R.get(A_HU, 3, i, 0);
+        Lm = R.get(A_HL, 3, i, 0);
+      } else {
+        const Mat SUm = k.s_id ? Mat{} : R.get(A_SU, 3, i, 0);
+        const Mat SLm = k.s_id ? Mat{} : R.get(A_SL, 3, i, 0);
+        Um = ws_at(W.Tm[0], mlo);
+        Lm = ws_at(W.Tm[1], mlo);
+        QTX_TRY(gm.go(Zm, OP_N, Mat{}, OP_N, Mat{}, Um, zero,
+                      {addend_of(SUm, one, OP_N, 1), addend_of(R.get(A_HU, 3, i, 0), mone),
+                       addend_of(R.get(A_SRU, 3, i, 0), mone)}, zero, 0));
+        QTX_TRY(gm.go(Zm, OP_N, Mat{}, OP_N, Mat{}, Lm, zero,
+                      {addend_of(SLm, one, OP_N, 1), addend_of(R.get(A_HL, 3, i, 0), mone),
+                       addend_of(R.get(A_SRL, 3, i, 0), mone)}, zero, 0));
+        sUm = sLm = 1.0;
+      }
+      const Mat Xm = ws_at(W.X, mlo), T4 = ws_at(W.Tm[4], mlo), T5 = ws_at(W.Tm[5], mlo);
+      QTX_TRY(gm.go(Zm, OP_N, Lm, OP_N, R.get(A_GRD, 3, i, 0), T5, one, {}));
+      QTX_TRY(gm.go(Zm, OP_N, T5, OP_N, Um, Xm, cmk(-sLm * sUm, 0), {addend_of(Xm, one)}));
+      for (size_t q = 0; q < rhs.size(); ++q) {
+        QTX_TRY(glm.go(Zm, OP_N, Lm, OP_N, R.get(rhs[q].Gd, 3, i, 0), T4, one, {}));
+        const Mat Qm = q == 0 ? ws_at(W.Tm[3], mlo) : T5;
+        QTX_TRY(glm.go(Zm, OP_N, T4, OP_C, Lm, Qm, one, {addend_of(q == 0 ? Qm : Mat{}, one)}, zero, -1, true));
+      }
+    }
     if (!dry && Z > 0) {
       ProfScope ps(ctx, QTX_KERNEL_INV, s, 8.0 * (double)b * b * b * Z, true);
       QTX_TRY(launch_gje_invert(b, W.X, bb, (double2*)xi.p, xi.stride, Z, W.gw, W.st, s, (double2* const*)xi.tab));
@@ -845,7 +941,14 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
         QTX_TRY(gl.go(Z, OP_N, xi, OP_N, Bi, ws(W.Tm[2]), one, {}, zero, -1, false, xA));
       } else {
         // Q_i (done above for the first recurrence);  Z = x_i Q
-        if (q > 0) QTX_TRY(lesser_q(gl, r));
+        if (q > 0) {
+          QTX_TRY(lesser_q(gl, r));
+          if (Zm > 0) {
+            const Mat Qm = ws_at(W.Tm[3], mlo);
+            QTX_TRY(glm.go(Zm, OP_N, Mat{}, OP_N, Mat{}, Qm, zero,
+                           {addend_of(Qm, one), addend_of(ws_at(W.Tm[5], mlo), one)}, zero, 0));
+          }
+        }
         QTX_TRY(gl.go(Z, OP_N, xi, OP_N, ws(W.Tm[3]), ws(W.Tm[2]), one, {}, zero, -1, false, xA));
       }
       xA.have_a = true;
@@ -856,7 +959,7 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
   // ------------------------------------------------------------ backward (i = n_b - 2 - kk per entry)
   const Mat Pp = ws(W.Tm[0]), Rp = ws(W.Tm[1]), Vp = ws(W.Tm[2]), Wp = ws(W.Tm[3]), Yp = ws(W.Tm[4]),
             Zp = ws(W.Tm[5]);
-  for (int kk = 0; kk + 2 <= B.max_nb; ++kk) {
+  for (int kk = 0; kk + 2 <= B.max_nbk; ++kk) {
     const int Z = R.active_bwd(kk);
     if (Z == 0) break;
     QTX_TRY(coupling(Z, 1, kk, 0));
@@ -912,15 +1015,32 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
     }
     QTX_TRY(g.go(Z, OP_N, GRu, OP_N, Rp, xi, cmk(-sL, 0), {addend_of(xi, one)}, zero, -1, false, useRG));   // G_ii
   }
+  // The bottom halves wrote their logical G^<_{i,i+1} (physical G^<_{j+1,j}) into the
+  // physical upper slot j: the upper block is its negated conjugate transpose
+  // (G^< is skew-Hermitian).
+  if (B.split) {
+    int nfix = 0;
+    for (const Entry& en : B.ent)
+      if (en.rev) nfix += en.p->n_b - 1 - en.c;
+    for (const Rhs& r : rhs) {
+      const Mat m = R.get(r.Gu, 4, 0, 0);
+      if (!dry && nfix > 0) QTX_TRY(launch_neg_ctrans_entries((double2* const*)m.tab, b, nfix, s));
+    }
+  }
   // ------------------------------------------------------------ status
   // Non-finite values propagate into the first blocks: check those; then every
-  // output of a failed entry is NaN-filled and the status is scattered out.
+  // output of a failed entry is NaN-filled and the status is scattered out.  A split
+  // energy's status is its top half's, after taking the bottom half's failure (the
+  // top half fills and reports the whole energy): a singular pivot in either half
+  // first, then non-finite values.
+  if (B.split && !dry) QTX_TRY(launch_status_merge(W.st, W.part, Zall, s));
   std::vector<int> first{A_GRD};
   for (const Rhs& r : rhs) first.push_back(r.Gd);
   for (int a : first) {
     const Mat m = R.get(a, 2, 0, 0);
     if (!dry) QTX_TRY(launch_check_finite_entries(m.tab, bb, Zall, W.st, s));
   }
+  if (B.split && !dry) QTX_TRY(launch_status_merge(W.st, W.part, Zall, s));
   std::vector<std::pair<int, bool>> outs{{A_GRD, true}, {A_GRU, false}, {A_GRL, false}};
   for (const Rhs& r : rhs) { outs.push_back({r.Gd, true}); outs.push_back({r.Gu, false}); }
   for (auto& o : outs) {
@@ -942,25 +1062,48 @@ struct Hasher {
 };
 
 // Plan, upload and run (or capture / replay) a full solve.
+// The separator block of a split chain of n_b >= 3 blocks: the top half runs
+// c forward steps and the bottom half n_b - c, so the bottom half reaches the
+// separator no earlier than the top half's last step.
+int split_point(int n_b) { return (n_b - 1) / 2; }
+
+// The entries of one energy: one chain, or the two halves of a split chain.
+std::vector<Entry> entries_of(const qtx_rgf_problem& p, int e) {
+  Entry a;
+  a.p = &p;
+  a.e = e;
+  if (!(p.flags & QTX_SPLIT_CHAIN) || p.n_b < 3) {
+    a.nf = a.nbk = p.n_b;
+    return {a};
+  }
+  const int c = split_point(p.n_b);
+  Entry t = a, bt = a;
+  t.nf = c; t.nbk = c + 1; t.c = c;
+  bt.nf = bt.nbk = p.n_b - c; bt.rev = true; bt.c = c;
+  return {t, bt};
+}
+
 qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs, hipStream_t s) {
-  // 1. group entries by batch key, split each group over lane_split stream lanes
-  //    (alternate entries, so that the parts carry the same mix of n_b); each part
-  //    becomes one or more batches (chunks) on its own lane
+  // 1. group energies by batch key, split each group over lane_split stream lanes
+  //    (alternate energies, so that the parts carry the same mix of n_b); each part
+  //    becomes one or more batches (chunks) on its own lane.  The two halves of a
+  //    split energy stay in one batch.
+  using Unit = std::vector<Entry>;
   std::vector<BatchKey> keys;
-  std::vector<std::vector<Entry>> groups;
+  std::vector<std::vector<Unit>> groups;
   {
     std::vector<BatchKey> gkeys;
-    std::vector<std::vector<Entry>> gents;
+    std::vector<std::vector<Unit>> gents;
     for (int q = 0; q < n_probs; ++q) {
       const BatchKey k = key_of(probs[q]);
       size_t g = 0;
       while (g < gkeys.size() && !(gkeys[g] == k)) ++g;
       if (g == gkeys.size()) { gkeys.push_back(k); gents.emplace_back(); }
-      for (int e = 0; e < probs[q].n_e; ++e) gents[g].push_back({&probs[q], e});
+      for (int e = 0; e < probs[q].n_e; ++e) gents[g].push_back(entries_of(probs[q], e));
     }
     for (size_t g = 0; g < gkeys.size(); ++g) {
       auto& ent = gents[g];
-      std::stable_sort(ent.begin(), ent.end(), [](const Entry& a, const Entry& b) { return a.p->n_b > b.p->n_b; });
+      std::stable_sort(ent.begin(), ent.end(), [](const Unit& a, const Unit& b) { return a[0].p->n_b > b[0].p->n_b; });
       const size_t parts = std::min<size_t>((size_t)std::max(1, ctx->lane_split), ent.size());
       for (size_t j = 0; j < parts; ++j) {
         keys.push_back(gkeys[g]);
@@ -970,24 +1113,43 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
     }
   }
   size_t total_need = 0;
-  for (size_t g = 0; g < keys.size(); ++g) total_need += per_entry_bytes(keys[g]) * groups[g].size();
+  for (size_t g = 0; g < keys.size(); ++g)
+    for (const Unit& u : groups[g]) total_need += per_entry_bytes(keys[g]) * u.size();
   const size_t budget = ws_budget(ctx);
   std::vector<Batch> batches;
   std::vector<size_t> lane_bytes;
   for (size_t g = 0; g < keys.size(); ++g) {
-    auto& ent = groups[g];
-    std::stable_sort(ent.begin(), ent.end(), [](const Entry& a, const Entry& b) { return a.p->n_b > b.p->n_b; });
+    auto& units = groups[g];
     const size_t per = per_entry_bytes(keys[g]);
-    const double share = total_need > budget ? (double)(per * ent.size()) / (double)total_need : 1.0;
-    size_t chunk = ent.size();
+    size_t n_ent = 0;
+    for (const Unit& u : units) n_ent += u.size();
+    const double share = total_need > budget ? (double)(per * n_ent) / (double)total_need : 1.0;
+    size_t chunk = n_ent;
     if (total_need > budget) chunk = std::max<size_t>(1, (size_t)(share * (double)budget) / per);
-    chunk = std::min(chunk, ent.size());
     size_t lane_need = 0;
-    for (size_t c0 = 0; c0 < ent.size(); c0 += chunk) {
+    for (size_t u0 = 0; u0 < units.size();) {
       Batch B;
       B.key = keys[g];
-      B.ent.assign(ent.begin() + c0, ent.begin() + std::min(ent.size(), c0 + chunk));
-      B.max_nb = B.ent.front().p->n_b;
+      size_t u1 = u0;
+      while (u1 < units.size() && (B.ent.empty() || B.ent.size() + units[u1].size() <= chunk)) {
+        B.ent.insert(B.ent.end(), units[u1].begin(), units[u1].end());
+        ++u1;
+      }
+      u0 = u1;
+      // Sort by (nf, nbk, rev) descending: the entries active at a forward step and
+      // at a backward step are prefixes (nbk is nf or nf + 1), and the bottom halves
+      // that reach their separator at one step are a contiguous run.
+      std::stable_sort(B.ent.begin(), B.ent.end(), [](const Entry& a, const Entry& b) {
+        return std::make_tuple(a.nf, a.nbk, a.rev) > std::make_tuple(b.nf, b.nbk, b.rev);
+      });
+      for (size_t z = 0; z < B.ent.size(); ++z) {
+        B.max_nf = std::max(B.max_nf, B.ent[z].nf);
+        B.max_nbk = std::max(B.max_nbk, B.ent[z].nbk);
+        if (!B.ent[z].rev) continue;
+        B.split = true;
+        for (size_t y = 0; y < B.ent.size(); ++y)
+          if (!B.ent[y].rev && B.ent[y].p == B.ent[z].p && B.ent[y].e == B.ent[z].e) B.ent[y].part = (int)z;
+      }
       B.lane = (int)g;
       lane_need = std::max(lane_need, batch_ws_bytes(B.key, (int)B.ent.size()));
       batches.push_back(std::move(B));
@@ -1010,12 +1172,15 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
     for (int z = 0; z < Z; ++z) {
       const Entry& en = R.B->ent[z];
       const double E = en.p->energies[en.e];
-      int32_t* us = en.p->status ? en.p->status + en.e : nullptr;
-      const int64_t cd = (int64_t)en.p->n_b * R.bb, cu = (int64_t)(en.p->n_b - 1) * R.bb;
+      // a bottom half neither reports nor fills: its top half does both for the energy
+      int32_t* us = en.p->status && !en.rev ? en.p->status + en.e : nullptr;
+      const int64_t cd = en.rev ? 0 : (int64_t)en.p->n_b * R.bb, cu = en.rev ? 0 : (int64_t)(en.p->n_b - 1) * R.bb;
+      const int32_t part = en.part;
       std::memcpy(R.host.data() + ed.en + z * sizeof(double), &E, sizeof(double));
       std::memcpy(R.host.data() + ed.ust + z * sizeof(void*), &us, sizeof(void*));
       std::memcpy(R.host.data() + ed.cnt_d + z * sizeof(int64_t), &cd, sizeof(int64_t));
       std::memcpy(R.host.data() + ed.cnt_u + z * sizeof(int64_t), &cu, sizeof(int64_t));
+      std::memcpy(R.host.data() + ed.part + z * sizeof(int32_t), &part, sizeof(int32_t));
     }
     BatchWs W;
     qtx_status st = run_batch(R, W);
@@ -1099,6 +1264,7 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
       W.ust = (int32_t* const*)(R.dev + ed.ust);
       W.cnt_d = (const int64_t*)(R.dev + ed.cnt_d);
       W.cnt_u = (const int64_t*)(R.dev + ed.cnt_u);
+      W.part = (const int32_t*)(R.dev + ed.part);
       result = run_batch(R, W);
     }
     if (n_lanes > 1 && result == QTX_OK) {
@@ -1344,7 +1510,8 @@ qtx_status qtx_rgf_destroy(qtx_rgf_ctx ctx) {
 
 size_t qtx_rgf_footprint(const qtx_rgf_problem* p) {
   if (!valid_problem(p) || check_supported(p) != QTX_OK) return 0;
-  return per_entry_bytes(key_of(*p));
+  const size_t chains = ((p->flags & QTX_SPLIT_CHAIN) && p->n_b >= 3) ? 2 : 1;
+  return chains * per_entry_bytes(key_of(*p));
 }
 
 qtx_status qtx_rgf_solve(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int32_t n_probs, void* hip_stream) {

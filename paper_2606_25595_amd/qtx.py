@@ -29,6 +29,7 @@ QTX_OK, QTX_ERR_ARG, QTX_ERR_NOMEM, QTX_ERR_HIP, QTX_ERR_UNSUPPORTED, QTX_ERR_SI
 QTX_FP64, QTX_FP32, QTX_BF16_SPLIT, QTX_FP16_SPLIT, QTX_INT8_OZAKI2 = range(5)
 QTX_S_IDENTITY = 1
 QTX_WANT_GREATER = 8
+QTX_SPLIT_CHAIN = 16
 PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16": QTX_FP16_SPLIT,
               "int8": QTX_INT8_OZAKI2}
 
@@ -174,6 +175,7 @@ class DeviceProblem:
     SG_u: object = None
     GG_d: object = None
     GG_u: object = None
+    split: bool = False     # QTX_SPLIT_CHAIN: two half-chains per energy
 
     @property
     def n_b(self):
@@ -279,6 +281,8 @@ def _problem_struct(dp: DeviceProblem, prec: int, n_slices: int, prec_lesser: in
         flags |= QTX_S_IDENTITY
     if dp.GG_d is not None:
         flags |= QTX_WANT_GREATER
+    if dp.split:
+        flags |= QTX_SPLIT_CHAIN
     st.flags = flags
     en = np.ascontiguousarray(dp.energies, dtype=np.float64)
     st.energies = en.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
