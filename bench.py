@@ -119,14 +119,19 @@ def main():
                          "<retarded>/<lesser>")
     ap.add_argument("--cpu-energies", type=int, default=16, help="energies in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="realistic", choices=["realistic", "hard", "kappa", "w", "fpx", "batch", "serve"],
+    ap.add_argument("--workload", default="realistic", choices=["realistic", "hard", "kappa", "w", "fpx", "batch", "serve", "latency"],
                     help="realistic (default, the headline line) | hard (the realistic shapes at eta = 1e-6, "
                          "condition numbers up to ~5e6) | kappa (error against the exact condition number, "
                          "n_b=8, b=128, eta 1e-3..1e-6) | w (screened Coulomb system: assembly + solve, n_b=16, "
                          "b=256, 128 energies) | fpx (FPX storage codec GB/s on G^R blocks) | batch (512 uneven "
                          "problems, one graph launch) | "
                          "serve (Poisson arrivals, continuous batching, p50/p99)")
+    ap.add_argument("--split", action="store_true",
+                    help="realistic/hard/serve: two half-chains per energy (QTX_SPLIT_CHAIN)")
     ap.add_argument("--eta", type=float, default=None, help="realistic/hard: broadening (default 1e-3 / 1e-6)")
+    ap.add_argument("--latency-ne", default="1,2,4,8,16,32", help="latency workload: energy counts")
+    ap.add_argument("--latency-precs", default="fp64,int8:10/int8:10", help="latency workload: schemes")
+    ap.add_argument("--latency-split", default="0,1", help="latency workload: 0 = one chain, 1 = split")
     ap.add_argument("--problems", type=int, default=512, help="batch workload: number of problems")
     ap.add_argument("--rate", type=float, default=200.0, help="serve workload: arrivals per second")
     ap.add_argument("--duration", type=float, default=10.0, help="serve workload: arrival window (s)")
@@ -152,6 +157,8 @@ def main():
         return bench_w(args)
     if args.workload == "fpx":
         return bench_fpx(args)
+    if args.workload == "latency":
+        return bench_latency(args)
 
     cfg = inputs.CONFIGS["realistic"]
     n_b, b, n_e = cfg["n_b"], cfg["b"], cfg["n_e"]
@@ -165,7 +172,7 @@ def main():
                            SL_d=d["SL_d"], GR_d=torch.empty((n_e, n_b, b, b), **kw),
                            GR_u=torch.empty((n_e, n_b - 1, b, b), **kw), GR_l=torch.empty((n_e, n_b - 1, b, b), **kw),
                            GL_d=torch.empty((n_e, n_b, b, b), **kw), GL_u=torch.empty((n_e, n_b - 1, b, b), **kw),
-                           status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"))
+                           status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"), split=args.split)
     ctx = qtx.Context(0)
     sample = list(range(0, n_e, max(1, n_e // args.cpu_energies)))[: args.cpu_energies]
     gamma_L = 2.0 * gamma * np.eye(b, dtype=np.complex128)
@@ -308,7 +315,7 @@ def main():
         "config": {"workload": "%sselected RGF solve: n_b=32 blocks, b=416, N_E=256 energies in [-2,2], "
                                "complex128, S=I, random Hermitian H (seed 0), eta=%g, gamma=0.5"
                                % ("realistic " if args.workload == "realistic" else "hard (ill-conditioned) ", eta),
-                   "precision": best, "energies_per_step": n_e},
+                   "precision": best, "energies_per_step": n_e, "split_chain": bool(args.split)},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": (achieved / peak) if achieved else None, "traffic": traffic,
                      "kernel": "%s: matrix-core kernel of the complex b x b x b block products (%s scheme); "
@@ -596,6 +603,98 @@ def bench_fpx(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_latency(args):
+    """Latency of solves with few energies on the realistic device (n_b = 32,
+    b = 416, eta = 1e-3, seed 0): one chain per energy against the two-sided split
+    (QTX_SPLIT_CHAIN), FP64 and INT8 10/10, n_e in {1, 2, 4, 8, 16, 32} energies
+    spread over [-2, 2], eager and hipGraph replay.  Each configuration: 2 warmup
+    solves, then `reps` solves timed one by one (host clock, synchronised);
+    p50 and max.  The split and unsplit outputs are compared (max relative
+    Frobenius difference over the diagonal blocks of G^R and G^<)."""
+    import numpy as np
+    import torch
+    from paper_2606_25595_amd import inputs, qtx
+    n_b, b = 32, 416
+    grid = np.linspace(-2.0, 2.0, 256)
+    ctx = qtx.Context(0)
+    stream = torch.cuda.Stream()
+    rows = []
+    precs = args.latency_precs.split(",")
+    kw = dict(dtype=torch.complex128, device="cuda")
+    for n_e in [int(x) for x in args.latency_ne.split(",")]:
+        E = grid[np.linspace(0, 255, n_e + 2).astype(int)[1:-1]]
+        d = inputs.device_random_problem(n_b, b, E, seed=0, eta=1e-3)
+        outs = {}
+        for split in [bool(int(x)) for x in args.latency_split.split(",")]:
+            dp = qtx.DeviceProblem(energies=d["energies"], H_d=d["H_d"], H_u=d["H_u"], H_l=d["H_l"],
+                                   SR_d=d["SR_d"], SL_d=d["SL_d"], GR_d=torch.empty((n_e, n_b, b, b), **kw),
+                                   GR_u=torch.empty((n_e, n_b - 1, b, b), **kw),
+                                   GR_l=torch.empty((n_e, n_b - 1, b, b), **kw),
+                                   GL_d=torch.empty((n_e, n_b, b, b), **kw),
+                                   GL_u=torch.empty((n_e, n_b - 1, b, b), **kw),
+                                   status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"), split=split)
+            for prec in precs:
+                skw = parse_scheme(prec)
+                for graph in (False, True):
+                    if graph and n_e > 8:
+                        continue
+                    ctx.set_graph(graph)
+                    reps = 12 if n_e <= 4 else 6
+                    ts = []
+                    with torch.cuda.stream(stream):
+                        for k in range(2 + reps):
+                            torch.cuda.synchronize()
+                            t0 = time.perf_counter()
+                            ctx.solve(dp, stream=stream, **skw)
+                            stream.synchronize()
+                            if k >= 2:
+                                ts.append(time.perf_counter() - t0)
+                    ctx.set_graph(False)
+                    ts = np.array(ts) * 1e3
+                    ok = bool((dp.status == 0).all().item())
+                    row = {"n_e": n_e, "split": split, "prec": prec, "graph": graph, "p50_ms": float(np.median(ts)),
+                           "max_ms": float(ts.max()), "energies_per_s": n_e / float(np.median(ts)) * 1e3,
+                           "status_ok": ok}
+                    if not graph:
+                        outs[(split, prec)] = (dp.GR_d.clone(), dp.GL_d.clone())
+                    rows.append(row)
+                    log("bench latency: n_e=%d %s %s %s p50 %.1f ms max %.1f ms (%.1f energies/s)%s"
+                        % (n_e, "split" if split else "chain", prec, "graph" if graph else "eager",
+                           row["p50_ms"], row["max_ms"], row["energies_per_s"], "" if ok else " STATUS FAIL"))
+            del dp
+        for prec in precs:
+            if (False, prec) not in outs or (True, prec) not in outs:
+                continue
+            a, s_ = outs[(False, prec)], outs[(True, prec)]
+            diff = 0.0
+            for x, y in zip(a, s_):
+                dn = (x - y).abs().pow(2).sum((-1, -2)).sqrt()
+                nr = x.abs().pow(2).sum((-1, -2)).sqrt().clamp_min(1e-300)
+                diff = max(diff, float((dn / nr).max().item()))
+            for r in rows:
+                if r["n_e"] == n_e and r["prec"] == prec:
+                    r["split_vs_chain_max_rel"] = diff
+            log("bench latency: n_e=%d %s split vs chain max rel diff %.2e" % (n_e, prec, diff))
+        del d, outs
+        torch.cuda.empty_cache()
+    ctx.close()
+    best = {}
+    for r in rows:
+        key = (r["n_e"], r["split"], r["prec"])
+        if key not in best or r["p50_ms"] < best[key]["p50_ms"]:
+            best[key] = r
+    n0 = min(r["n_e"] for r in rows)
+    head = best.get((n0, True, precs[0])) or best.get((n0, False, precs[0]))
+    line = {"metric": "selected-solve latency (p50) at %d energies, %s" % (n0, precs[0]), "value": head["p50_ms"],
+            "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "latency: realistic device n_b=32, b=416, eta=1e-3, %s energies"
+                                   % args.latency_ne, "split_chain": head["split"]},
+            "speedup_split": {"%d:%s" % (n, pr): best[(n, False, pr)]["p50_ms"] / best[(n, True, pr)]["p50_ms"]
+                              for (n, sp, pr) in best if sp and (n, False, pr) in best},
+            "rows": rows}
+    print(json.dumps(line), flush=True)
+
+
 def bench_batch(args):
     """Batching workload: independent problems with b in {128, 256, 384, 512} and
     n_b in {16, 24, 32}, one energy each (E uniform in [-2, 2]), random devices
@@ -688,7 +787,7 @@ def bench_serve(args):
     reqs = request_stream(rate=args.rate, duration=args.duration, seed=0)
     log("bench serve: %d requests over %.1f s at %.1f/s, budget %.1f GB" % (len(reqs), args.duration, args.rate,
                                                                            budget / 1e9))
-    ex = GpuExecutor(n_slots=3, workspace_per_slot=int(free * 0.08))
+    ex = GpuExecutor(n_slots=3, workspace_per_slot=int(free * 0.08), split=args.split)
     srv = Server(ex, hbm_budget=budget, chunk_energies=16, max_pending=512)
     rep = srv.run(reqs, time_limit=args.time_limit)
     ex.close()
@@ -700,7 +799,7 @@ def bench_serve(args):
                                                      x.get("n_slices_lesser", x.get("n_slices", 0)))
                                 for x in PRECISIONS.values()),
             "config": {"workload": "serve: Poisson %.1f/s for %.1f s, b 128..512, n_b 8..48, N_E 16..128"
-                                   % (args.rate, args.duration)},
+                                   % (args.rate, args.duration), "split_chain": bool(args.split)},
             "p50_latency_s": rep["p50_latency_s"], "p99_latency_s": rep["p99_latency_s"], "report": rep}
     print(json.dumps(line), flush=True)
 

@@ -254,12 +254,16 @@ class Server:
 class GpuExecutor:
     """Device state and launches for Server on one GPU."""
 
-    def __init__(self, n_slots: int = 3, device: int = 0, workspace_per_slot: int = 0):
+    def __init__(self, n_slots: int = 3, device: int = 0, workspace_per_slot: int = 0, split: bool = False):
         import torch
         from . import qtx
         self.torch = torch
         self.qtx = qtx
         self.n_slots = n_slots
+        # solve every energy as two half-chains (QTX_SPLIT_CHAIN): about half the
+        # sequential steps per launch, the same results to rounding, twice the
+        # library workspace per energy
+        self.split = split
         self.device = device
         self.ctx = [qtx.Context(device, workspace_bytes=workspace_per_slot) for _ in range(n_slots)]
         if workspace_per_slot:
@@ -314,7 +318,7 @@ class GpuExecutor:
             GR_d=torch.empty((n_e, n_b, b, b), **kw), GR_u=torch.empty((n_e, n_b - 1, b, b), **kw),
             GR_l=torch.empty((n_e, n_b - 1, b, b), **kw), GL_d=torch.empty((n_e, n_b, b, b), **kw),
             GL_u=torch.empty((n_e, n_b - 1, b, b), **kw),
-            status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"))
+            status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"), split=self.split)
         c.handle = dp
 
     def launch(self, slot: int, chunks: List[Chunk]):

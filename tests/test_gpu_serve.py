@@ -81,3 +81,25 @@ def test_budget_bounds_admission(gpu):
     srv, rep = run_server(reqs, budget=one_chunk)                 # roughly one chunk at a time
     assert rep["completed"] == len(reqs)
     assert srv.peak_used <= one_chunk
+
+
+def test_split_chains_in_serving_match_oracle(gpu):
+    """The executor's split option (two half-chains per energy) serves the same
+    requests with FP64 results at the oracle's bar."""
+    reqs = [r for r in small_stream(seed=11, n_max=8)]
+    ex = GpuExecutor(n_slots=2, workspace_per_slot=1 << 30, split=True)
+    try:
+        srv = Server(ex, hbm_budget=1 << 31, chunk_energies=4)
+        rep = srv.run(reqs)
+    finally:
+        ex.close()
+    assert rep["completed"] == len(reqs)
+    for r in reqs:
+        assert np.all(r.status == 0)
+        sr, sl = inputs.random_bt_scalars(r.n_b, r.energies)
+        p = inputs.BTProblem(energies=r.energies, H_d=r.blocks["H_d"], H_u=r.blocks["H_u"], H_l=r.blocks["H_l"],
+                             SR_d=inputs._diag_blocks(sr, r.b), SL_d=inputs._diag_blocks(sl, r.b))
+        ref = oracle.rgf_selected(p)
+        tol = 1e-10 if r.precision == "fp64" else 1e-6
+        for k in KEYS:
+            assert oracle.rel_fro_err(r.blocks[k], ref[k]).max() <= tol, (r.rid, k)
