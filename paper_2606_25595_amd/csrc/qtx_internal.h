@@ -11,8 +11,10 @@ namespace qtx {
 __host__ __device__ inline double2 cmk(double re, double im) { double2 r; r.x = re; r.y = im; return r; }
 __host__ __device__ inline double2 cadd(double2 a, double2 b) { return cmk(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline double2 csub(double2 a, double2 b) { return cmk(a.x - b.x, a.y - b.y); }
+// Explicit FMAs: with contraction left to the compiler, two instantiations of
+// one kernel may fuse different products and round differently.
 __host__ __device__ inline double2 cmul(double2 a, double2 b) {
-  return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return cmk(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
 __host__ __device__ inline double2 cconj(double2 a) { return cmk(a.x, -a.y); }
 __host__ __device__ inline double2 cinv(double2 a) {

@@ -8,7 +8,12 @@
 // Tiling: a 256-thread workgroup computes a 64 x 64 complex tile of C.  Each of
 // its four waves owns four 16 x 16 MFMA blocks, interleaved (wave (wm, wn) takes
 // row blocks wm, wm+2 and column blocks wn, wn+2), with separate real and
-// imaginary accumulators: 8 independent MFMA chains per wave.  Blocks that lie
+// imaginary accumulators: 8 independent MFMA chains per wave.  A launch whose
+// 64 x 64 tiles would give fewer than two workgroups per CU (one or a few
+// 416 x 416 products) uses 32 x 32 tiles instead, one 16 x 16 block per wave:
+// four times the workgroups for the same work.  Every output element is
+// accumulated in the same K order by either tile size, so the results are
+// bitwise the same.  Blocks that lie
 // entirely outside C are skipped (wave-uniform), and the interleaving spreads
 // such blocks of an edge tile evenly over the waves (b = 416 is 6.5 tiles).
 // K advances 32 complex elements per step.  Operand tiles are copied to LDS in
@@ -71,16 +76,18 @@ __device__ inline int xcd_remap(int pid, int total) {
 
 // One operand tile in its natural layout: ROWS x COLS elements of a row-major
 // source (leading dimension ld), rows [r0, r0+ROWS) bounded by nrows, columns
-// [c0, c0+COLS) bounded by ncols; zero outside.  2048 elements, 8 per thread:
-// element e = tid + 256 j, so each wave loads and stores contiguous 1 KB runs
-// (coalesced global reads, conflict-free LDS writes).
+// [c0, c0+COLS) bounded by ncols; zero outside.  EPT elements per thread
+// (8 for a 64 x 32 tile, 4 for 32 x 32): element e = tid + 256 j, so each wave
+// loads and stores contiguous 1 KB runs (coalesced global reads, conflict-free
+// LDS writes).
 template <int ROWS, int COLS>
 struct TileLoader {
-  double2 v[8];
+  static constexpr int EPT = ROWS * COLS / NT;
+  double2 v[EPT];
   __device__ inline void load(const double2* __restrict__ src, int64_t ld, int r0, int c0, int nrows, int ncols,
                               int tid) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < EPT; ++j) {
       const int e = tid + NT * j;
       const int r = r0 + e / COLS, c = c0 + e % COLS;
       v[j] = (r < nrows && c < ncols) ? src[(int64_t)r * ld + c] : cmk(0.0, 0.0);
@@ -89,7 +96,7 @@ struct TileLoader {
   template <bool CONJ, class MATH, class L>
   __device__ inline void store(L* lds, int rs, int tid) const {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < EPT; ++j) {
       const int e = tid + NT * j;
       lds[(e / COLS) * rs + e % COLS] = MATH::cvt(CONJ ? cconj(v[j]) : v[j]);
     }
@@ -99,10 +106,14 @@ struct TileLoader {
 // KIND only separates kernel symbols by use (block products of the solve, the
 // inversion's trailing update, elementwise assembly with K = 0) so profilers
 // report them apart; the code is the same.
-template <int OPA, int OPB, int KIND, class MATH>
+template <int OPA, int OPB, int KIND, class MATH, int TM>
 __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
   typedef typename MATH::lds_t lds_t;
   typedef typename MATH::acc_t acc_t;
+  // TM x TM output tile; each wave owns NW x NW blocks of 16 x 16
+  constexpr int BM = TM, BN = TM, NW = TM / 32;
+  constexpr int RS_LONG = TM + 1;
+  constexpr int TILE_ELEMS = (BM * RS_WIDE > BK * RS_LONG) ? BM * RS_WIDE : BK * RS_LONG;
   __shared__ lds_t As[TILE_ELEMS];
   __shared__ lds_t Bs[TILE_ELEMS];
 
@@ -128,20 +139,20 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
 
   // this wave's blocks: rows m0 + 16*(wm + 2i), columns n0 + 16*(wn + 2j); a block
   // is live if it lies in C (and, for a skew-Hermitian C, touches r <= c)
-  bool live[2][2];
+  bool live[NW][NW];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NW; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NW; ++j) {
       const int rb = m0 + 16 * (wm + 2 * i), cb = n0 + 16 * (wn + 2 * j);
       live[i][j] = rb < M && cb < N && !(skew && rb >= cb + 16);
     }
 
-  acc_t acc_re[2][2], acc_im[2][2];
+  acc_t acc_re[NW][NW], acc_im[NW][NW];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NW; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NW; ++j) {
       acc_re[i][j] = MATH::zero();
       acc_im[i][j] = MATH::zero();
     }
@@ -169,36 +180,37 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + lk;
-      lds_t a[2], b[2];
+      lds_t a[NW], b[NW];
+      decltype(a[0].y) na[NW];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < NW; ++i) {
         const int m = 16 * (wm + 2 * i) + li;
         a[i] = (OPA == OP_N) ? As[m * RS_WIDE + kr] : As[kr * RS_LONG + m];
         const int n = 16 * (wn + 2 * i) + li;
         b[i] = (OPB == OP_N) ? Bs[kr * RS_LONG + n] : Bs[n * RS_WIDE + kr];
+        na[i] = -a[i].y;
       }
-      const decltype(a[0].y) na[2] = {-a[0].y, -a[1].y};
       // Four product kinds over the (up to) 4 blocks: a chain is revisited only
       // after 8 MFMAs.  Skipped blocks are wave-uniform.
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < NW; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NW; ++j)
           if (live[i][j]) acc_re[i][j] = MATH::mfma(a[i].x, b[j].x, acc_re[i][j]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < NW; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NW; ++j)
           if (live[i][j]) acc_im[i][j] = MATH::mfma(a[i].x, b[j].y, acc_im[i][j]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < NW; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NW; ++j)
           if (live[i][j]) acc_re[i][j] = MATH::mfma(na[i], b[j].y, acc_re[i][j]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < NW; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NW; ++j)
           if (live[i][j]) acc_im[i][j] = MATH::mfma(a[i].y, b[j].x, acc_im[i][j]);
     }
   }
@@ -216,9 +228,9 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
   }
   const double2 dg = d.diag_by_batch ? cmk(d.diag.x * bs, d.diag.y * bs) : d.diag;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NW; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NW; ++j) {
       if (!live[i][j]) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -339,25 +351,38 @@ __global__ __launch_bounds__(NT) void zgemm_update_kernel(GemmDesc d) {
 
 }  // namespace
 
+template <int KIND, class MATH, int TM>
+static void launch_kind_tm(const GemmDesc& d, hipStream_t s) {
+  const int64_t total = (int64_t)((d.M + TM - 1) / TM) * ((d.N + TM - 1) / TM) * d.batch;
+  dim3 grid((unsigned)total), block(NT);
+  if (d.opA == OP_N && d.opB == OP_N) hipLaunchKernelGGL((zgemm_mfma_kernel<OP_N, OP_N, KIND, MATH, TM>), grid, block, 0, s, d);
+  else if (d.opA == OP_N) hipLaunchKernelGGL((zgemm_mfma_kernel<OP_N, OP_C, KIND, MATH, TM>), grid, block, 0, s, d);
+  else if (d.opB == OP_N) hipLaunchKernelGGL((zgemm_mfma_kernel<OP_C, OP_N, KIND, MATH, TM>), grid, block, 0, s, d);
+  else hipLaunchKernelGGL((zgemm_mfma_kernel<OP_C, OP_C, KIND, MATH, TM>), grid, block, 0, s, d);
+}
+
+// 64 x 64 tiles, or 32 x 32 when the 64 x 64 tiles of the launch would give fewer
+// than two workgroups per CU of the MI355X (256 CUs).
+constexpr int64_t kSmallTileBelow = 512;
 template <int KIND, class MATH>
-static void launch_kind(const GemmDesc& d, dim3 grid, dim3 block, hipStream_t s) {
-  if (d.opA == OP_N && d.opB == OP_N) hipLaunchKernelGGL((zgemm_mfma_kernel<OP_N, OP_N, KIND, MATH>), grid, block, 0, s, d);
-  else if (d.opA == OP_N) hipLaunchKernelGGL((zgemm_mfma_kernel<OP_N, OP_C, KIND, MATH>), grid, block, 0, s, d);
-  else if (d.opB == OP_N) hipLaunchKernelGGL((zgemm_mfma_kernel<OP_C, OP_N, KIND, MATH>), grid, block, 0, s, d);
-  else hipLaunchKernelGGL((zgemm_mfma_kernel<OP_C, OP_C, KIND, MATH>), grid, block, 0, s, d);
+static void launch_kind(const GemmDesc& d, hipStream_t s) {
+  const int64_t tiles64 = (int64_t)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * d.batch;
+  if (tiles64 < kSmallTileBelow) launch_kind_tm<KIND, MATH, 32>(d, s);
+  else launch_kind_tm<KIND, MATH, 64>(d, s);
 }
 
 static hipError_t launch_zgemm_mfma(const GemmDesc& d, hipStream_t s, int kind, bool fp32) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
   if (d.skew && d.M != d.N) return hipErrorInvalidValue;
-  const int tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
-  const int64_t total = (int64_t)tiles * d.batch;
+  // the 32 x 32 tiling has 4x the tiles of the 64 x 64 one
+  const int64_t total = (int64_t)((d.M + 31) / 32) * ((d.N + 31) / 32) * d.batch;
   if (total > 0x7fffffff) return hipErrorInvalidValue;
-  dim3 grid((unsigned)total), block(NT);
+  const int tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
+  dim3 grid((unsigned)((int64_t)tiles * d.batch)), block(NT);
   if (d.K == 0) {
     GemmDesc e = d;
     e.opA = OP_N; e.opB = OP_N;
-    launch_kind<GEMM_ELEMENTWISE, MathF64>(e, grid, block, s);
+    launch_kind<GEMM_ELEMENTWISE, MathF64>(e, s);
   } else if (kind == GEMM_INV_UPDATE) {
     if (d.skew) return hipErrorInvalidValue;
     // contract of the update form: C = X + A B, op N, K <= BK, X the only addend (op N)
@@ -368,9 +393,9 @@ static hipError_t launch_zgemm_mfma(const GemmDesc& d, hipStream_t s, int kind, 
       return hipErrorInvalidValue;
     hipLaunchKernelGGL(zgemm_update_kernel, grid, block, 0, s, d);
   } else if (fp32) {
-    launch_kind<GEMM_PRODUCT, MathF32>(d, grid, block, s);
+    launch_kind<GEMM_PRODUCT, MathF32>(d, s);
   } else {
-    launch_kind<GEMM_PRODUCT, MathF64>(d, grid, block, s);
+    launch_kind<GEMM_PRODUCT, MathF64>(d, s);
   }
   return hipGetLastError();
 }

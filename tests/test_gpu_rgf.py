@@ -81,10 +81,36 @@ def test_zgemm_shared_operand_and_k0(ctx):
     assert rel(C.cpu().numpy(), A @ B) < 1e-14
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("opA,opB", [("N", "N"), ("C", "N"), ("N", "C"), ("C", "C")])
+@pytest.mark.parametrize("M,N,K,big", [(416, 416, 416, 12), (70, 45, 129, 300)])
+def test_zgemm_small_and_large_tiles_bitwise(ctx, prec, opA, opB, M, N, K, big):
+    """A launch with few 64 x 64 tiles uses 32 x 32 tiles; every element is summed
+    in the same K order by both, so one product alone equals the same product
+    inside a batch large enough for 64 x 64 tiles, bit for bit."""
+    import torch
+    rng = np.random.default_rng(M + N + K)
+    A = crand(rng, 1, *((M, K) if opA == "N" else (K, M)))
+    B = crand(rng, 1, *((K, N) if opB == "N" else (N, K)))
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    one = torch.zeros(1, M, N, dtype=torch.complex128, device="cuda")
+    ctx.zgemm(dA, dB, one, opA=opA, opB=opB, alpha=0.75 + 0.5j, prec=prec)
+    many = torch.zeros(big, M, N, dtype=torch.complex128, device="cuda")
+    ctx.zgemm(dA.expand(big, -1, -1).contiguous(), dB.expand(big, -1, -1).contiguous(), many, opA=opA, opB=opB,
+              alpha=0.75 + 0.5j, prec=prec)
+    got1, gotn = one.cpu().numpy(), many.cpu().numpy()
+    for z in (0, big // 2, big - 1):
+        assert np.array_equal(got1[0], gotn[z])
+    opa = A if opA == "N" else np.conj(np.transpose(A, (0, 2, 1)))
+    opb = B if opB == "N" else np.conj(np.transpose(B, (0, 2, 1)))
+    tol = 1e-14 if prec == "fp64" else 1e-6
+    assert rel(got1, (0.75 + 0.5j) * (opa @ opb)) < tol
+
+
 # ----------------------------------------------------------------- inversion kernel
 
-# 32-column panels go in pairs for n <= 512: n = 40, 65, 96, 130, 300 and 448 cover a pair
-# with a partial second panel, a pair plus a single panel, and several pairs.
+# n = 40, 65, 96, 130, 300 and 448 end in a partial 32-column panel or cover several
+# full ones; 513 and 1000 use the 16-column panel.
 @pytest.mark.parametrize("n", [1, 2, 7, 31, 32, 33, 40, 64, 65, 96, 100, 130, 300, 416, 448, 512, 513, 1000])
 def test_zinv_random(ctx, n):
     import torch
