@@ -53,9 +53,9 @@ def check(out, ref, tol=TOL, keys=KEYS):
 
 # n_b = 1, 2 ignore the flag; 3 is the smallest split (separator 1); odd and even n_b
 # put the separator at the middle or one block above it; b spans one to several
-# 64-wide tiles with ragged tails.
+# 64-wide tiles with ragged tails, and b = 520 takes the inversion's 16-column panels.
 @pytest.mark.parametrize("n_b,b,n_e", [(1, 8, 2), (2, 24, 2), (3, 16, 2), (4, 33, 3), (5, 64, 2), (8, 40, 3),
-                                       (13, 65, 2), (6, 130, 1)])
+                                       (13, 65, 2), (6, 130, 1), (3, 520, 1)])
 def test_split_matches_oracle(ctx, n_b, b, n_e):
     p = inputs.random_bt_problem(n_b, b, np.linspace(-1.8, 1.6, n_e), seed=700 + n_b * 10 + b)
     _, out = solve(ctx, p)
