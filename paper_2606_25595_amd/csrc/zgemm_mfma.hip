@@ -9,9 +9,9 @@
 // its four waves owns four 16 x 16 MFMA blocks, interleaved (wave (wm, wn) takes
 // row blocks wm, wm+2 and column blocks wn, wn+2), with separate real and
 // imaginary accumulators: 8 independent MFMA chains per wave.  A launch whose
-// 64 x 64 tiles would give fewer than two workgroups per CU (one or a few
-// 416 x 416 products) uses 32 x 32 tiles instead, one 16 x 16 block per wave:
-// four times the workgroups for the same work.  Every output element is
+// 64 x 64 tiling pads C by more than 8% or gives few workgroups per CU uses
+// 32 x 32 tiles instead, one 16 x 16 block per wave (four times the workgroups,
+// less padding at b = 416).  Every output element is
 // accumulated in the same K order by either tile size, so the results are
 // bitwise the same.  Blocks that lie
 // entirely outside C are skipped (wave-uniform), and the interleaving spreads
@@ -361,13 +361,17 @@ static void launch_kind_tm(const GemmDesc& d, hipStream_t s) {
   else hipLaunchKernelGGL((zgemm_mfma_kernel<OP_C, OP_C, KIND, MATH, TM>), grid, block, 0, s, d);
 }
 
-// 64 x 64 tiles, or 32 x 32 when the 64 x 64 tiles of the launch would give fewer
-// than two workgroups per CU of the MI355X (256 CUs).
-constexpr int64_t kSmallTileBelow = 512;
+// 64 x 64 tiles, or 32 x 32 when the 64 x 64 tiling pads C by more than 8% (its edge
+// tiles leave matrix cores idle: b = 416 is 6.5 tiles of 64 but 13 of 32; measured at
+// 256 products of 416^3, 2.385 ms with 32 x 32 tiles against 2.621 ms) or when the
+// launch has fewer than 4096 of them (16 per CU of the MI355X: at 8 to 64 energies of
+// b = 416 the smaller tiles were 10% faster, at one energy 25%).
+constexpr int64_t kSmallTileBelow = 4096;
 template <int KIND, class MATH>
 static void launch_kind(const GemmDesc& d, hipStream_t s) {
-  const int64_t tiles64 = (int64_t)((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN) * d.batch;
-  if (tiles64 < kSmallTileBelow) launch_kind_tm<KIND, MATH, 32>(d, s);
+  const int64_t tm64 = (d.M + 63) / 64, tn64 = (d.N + 63) / 64, tm32 = (d.M + 31) / 32, tn32 = (d.N + 31) / 32;
+  const int64_t area64 = tm64 * tn64 * 4096, area32 = tm32 * tn32 * 1024;
+  if (tm64 * tn64 * d.batch < kSmallTileBelow || 100 * area64 > 108 * area32) launch_kind_tm<KIND, MATH, 32>(d, s);
   else launch_kind_tm<KIND, MATH, 64>(d, s);
 }
 
