@@ -272,6 +272,10 @@ __device__ inline void crt_fold(int c, double m, double im, double u, double& S)
 //   5, 6: variants 4 and 1 with one tile per workgroup instead of persistent
 //      workgroups (the hardware then keeps a window of consecutive tiles -- the
 //      same energies on one XCD -- in flight, in place of rounds that drift apart)
+//   7: BM = 32, 128 threads (two waves), 1 strip per step, 2 stages (24 KB, six per
+//      CU): 32 x 64 tiles, which cover b = 416 (13 x 32) without padding rows and
+//      give twice the workgroups of a 64 x 64 tiling, for about 1.4x the operand
+//      strips per output
 constexpr int O2_BN = 64;
 constexpr int kBufWord3 = 0x00020000;           // buffer descriptor word 3: raw 32-bit data, no swizzle
 
@@ -286,7 +290,7 @@ struct O2Cfg {
   static constexpr int WPC = WPC_;                    // workgroups per CU (LDS / registers)
   static constexpr int WAVES_PER_SIMD = WPC * NT / 256;
   static constexpr bool TWO_ACC = WPC >= 3;            // O2Acc layout
-  static_assert(NT == 4 * BM && (BM == 64 || BM == 128), "tile shape");   // one wave per 32 x 32 block
+  static_assert(NT == 4 * BM && (BM == 32 || BM == 64 || BM == 128), "tile shape");   // one wave per 32 x 32 block
   static_assert(STRIP_U4 % NT == 0 && (BM * 8) % NT == 0, "copy split");
   static_assert(NSTAGE == 2 || NSTAGE == 3, "ring depth");
   static_assert(LPT < 64, "vmcnt range");
@@ -297,6 +301,7 @@ typedef O2Cfg<64, 256, 2, 2, 2> O2V1;
 typedef O2Cfg<64, 256, 1, 3, 2> O2V2;
 typedef O2Cfg<64, 256, 1, 3, 3> O2V3;
 typedef O2Cfg<64, 256, 1, 2, 3> O2V4;
+typedef O2Cfg<32, 128, 1, 2, 6> O2V7;
 
 typedef __attribute__((address_space(3))) u4 lds_u4;
 typedef __attribute__((address_space(3))) double lds_f64;
@@ -704,6 +709,7 @@ hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_
     case 4: return launch_o2_variant<O2V4>(g, P, s, persist);
     case 5: return launch_o2_variant<O2V4>(g, P, s, false);
     case 6: return launch_o2_variant<O2V1>(g, P, s, false);
+    case 7: return launch_o2_variant<O2V7>(g, P, s, persist);
     default: return hipErrorInvalidValue;
   }
 }

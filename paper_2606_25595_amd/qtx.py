@@ -515,9 +515,9 @@ class Context:
         `batch` entries; returns (chosen variant, [ms per product of each variant])."""
         v = ctypes.c_int32()
         cnt = ctypes.c_int32()
-        ms = (ctypes.c_double * 8)()
+        ms = (ctypes.c_double * 16)()
         rc = self.lib.qtx_rgf_tune(self.handle, int(b), PREC_NAMES.get(prec, prec), int(n_slices), int(batch),
-                                   _stream_ptr(stream), ctypes.byref(v), ms, 8, ctypes.byref(cnt))
+                                   _stream_ptr(stream), ctypes.byref(v), ms, 16, ctypes.byref(cnt))
         if rc != QTX_OK:
             raise QtxError(rc, "qtx_rgf_tune")
         return v.value, [ms[i] for i in range(cnt.value)]
