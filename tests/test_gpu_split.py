@@ -190,3 +190,34 @@ def test_split_rejects_bt_sigma_lesser_and_doubles_footprint(ctx):
     f1 = ctx.footprint(dq)
     dq.split = True
     assert ctx.footprint(dq) == 2 * f1 > 0
+
+
+@pytest.mark.parametrize("prec,ns", [("fp64", 0), ("int8", 10)])
+def test_split_with_lanes_and_overlap_bitwise(ctx, prec, ns):
+    """Stream lanes (energies dealt to parallel streams, halves of one energy kept
+    together) and the side-stream overlap of the first lesser products (off at a
+    separator step) leave the split solve's results unchanged, bit for bit."""
+    import torch
+    from paper_2606_25595_amd import qtx
+    p = inputs.random_bt_problem(9, 48, np.linspace(-1.6, 1.4, 5), seed=79, with_greater=True)
+    keys = KEYS + ("GG_d", "GG_u")
+
+    def run():
+        dp = qtx.to_device(p)
+        dp.split = True
+        ctx.solve(dp, prec=prec, n_slices=ns)
+        torch.cuda.synchronize()
+        return dp.outputs()
+    base = run()
+    try:
+        for lanes, overlap in ((2, False), (3, False), (1, True), (2, True)):
+            ctx.set_lane_split(lanes)
+            ctx.set_overlap(overlap)
+            got = run()
+            for k in keys:
+                assert np.array_equal(got[k], base[k]), (lanes, overlap, k)
+    finally:
+        ctx.set_lane_split(1)
+        ctx.set_overlap(False)
+    if prec == "fp64":
+        check(base, oracle.rgf_selected(p), keys=keys)
