@@ -259,11 +259,17 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
 
 // The inversion's trailing update C = X + A B with K <= BK (one operand tile,
 // A = Wp row-major M x K, B = Tp row-major K x N, the only addend X in C's own
-// layout).  It is bound by reading and rewriting X, so it is a single-tile
+// layout), in TM x TM tiles chosen as for the products (the sums and the final
+// addition are the same for both, so are the results).  It is bound by reading and rewriting X, so it is a single-tile
 // kernel without a K loop: the operand tiles are staged through LDS, then this
 // thread's X values are requested (in the registers the staging used) and arrive
 // while the MFMAs run.
+template <int TM>
 __global__ __launch_bounds__(NT) void zgemm_update_kernel(GemmDesc d) {
+  // TM x TM output tile; each wave owns NW x NW blocks of 16 x 16
+  constexpr int BM = TM, BN = TM, NW = TM / 32;
+  constexpr int RS_LONG = TM + 1;
+  constexpr int TILE_ELEMS = (BM * RS_WIDE > BK * RS_LONG) ? BM * RS_WIDE : BK * RS_LONG;
   __shared__ double2 As[TILE_ELEMS];
   __shared__ double2 Bs[TILE_ELEMS];
   const int tiles_m = (d.M + BM - 1) / BM;
@@ -281,9 +287,9 @@ __global__ __launch_bounds__(NT) void zgemm_update_kernel(GemmDesc d) {
   const double2* __restrict__ B = d.tB ? d.tB[z] : d.B + (int64_t)z * d.sB;
   const double2* __restrict__ X = d.add[0].tX ? d.add[0].tX[z] : d.add[0].X + (int64_t)z * d.add[0].stride;
   double2* __restrict__ C = d.tC ? d.tC[z] : d.C + (int64_t)z * d.sC;
-  bool rv[2], cv[2];
+  bool rv[NW], cv[NW];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < NW; ++i) {
     rv[i] = m0 + 16 * (wm + 2 * i) < M;
     cv[i] = n0 + 16 * (wn + 2 * i) < N;
   }
@@ -295,11 +301,11 @@ __global__ __launch_bounds__(NT) void zgemm_update_kernel(GemmDesc d) {
     la.template store<false, MathF64>(As, RS_WIDE, tid);
     lb.template store<false, MathF64>(Bs, RS_LONG, tid);
   }
-  double2 x[2][2][4];
+  double2 x[NW][NW][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NW; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NW; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = m0 + 16 * (wm + 2 * i) + MathF64::row(lk, v);
@@ -307,27 +313,27 @@ __global__ __launch_bounds__(NT) void zgemm_update_kernel(GemmDesc d) {
         x[i][j][v] = (rv[i] && cv[j] && r < M && c < N) ? X[(int64_t)r * d.add[0].ld + c] : cmk(0.0, 0.0);
       }
   __syncthreads();
-  d4 acc_re[2][2], acc_im[2][2];
+  d4 acc_re[NW][NW], acc_im[NW][NW];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NW; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NW; ++j) {
       acc_re[i][j] = MathF64::zero();
       acc_im[i][j] = MathF64::zero();
     }
 #pragma unroll
   for (int kk = 0; kk < BK; kk += 4) {
     const int kr = kk + lk;
-    double2 a[2], b[2];
+    double2 a[NW], b[NW];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NW; ++i) {
       a[i] = As[(16 * (wm + 2 * i) + li) * RS_WIDE + kr];
       b[i] = Bs[kr * RS_LONG + 16 * (wn + 2 * i) + li];
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NW; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NW; ++j)
         if (rv[i] && cv[j]) {
           acc_re[i][j] = MathF64::mfma(a[i].x, b[j].x, acc_re[i][j]);
           acc_im[i][j] = MathF64::mfma(a[i].x, b[j].y, acc_im[i][j]);
@@ -336,9 +342,9 @@ __global__ __launch_bounds__(NT) void zgemm_update_kernel(GemmDesc d) {
         }
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NW; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NW; ++j) {
       if (!(rv[i] && cv[j])) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -367,11 +373,14 @@ static void launch_kind_tm(const GemmDesc& d, hipStream_t s) {
 // launch has fewer than 4096 of them (16 per CU of the MI355X: at 8 to 64 energies of
 // b = 416 the smaller tiles were 10% faster, at one energy 25%).
 constexpr int64_t kSmallTileBelow = 4096;
-template <int KIND, class MATH>
-static void launch_kind(const GemmDesc& d, hipStream_t s) {
+static bool small_tiles(const GemmDesc& d) {
   const int64_t tm64 = (d.M + 63) / 64, tn64 = (d.N + 63) / 64, tm32 = (d.M + 31) / 32, tn32 = (d.N + 31) / 32;
   const int64_t area64 = tm64 * tn64 * 4096, area32 = tm32 * tn32 * 1024;
-  if (tm64 * tn64 * d.batch < kSmallTileBelow || 100 * area64 > 108 * area32) launch_kind_tm<KIND, MATH, 32>(d, s);
+  return tm64 * tn64 * d.batch < kSmallTileBelow || 100 * area64 > 108 * area32;
+}
+template <int KIND, class MATH>
+static void launch_kind(const GemmDesc& d, hipStream_t s) {
+  if (small_tiles(d)) launch_kind_tm<KIND, MATH, 32>(d, s);
   else launch_kind_tm<KIND, MATH, 64>(d, s);
 }
 
@@ -395,7 +404,12 @@ static hipError_t launch_zgemm_mfma(const GemmDesc& d, hipStream_t s, int kind, 
         d.add[0].scale_by_batch || d.add[1].X || d.add[1].tX || d.add[2].X || d.add[2].tX || d.diag.x != 0.0 ||
         d.diag.y != 0.0)
       return hipErrorInvalidValue;
-    hipLaunchKernelGGL(zgemm_update_kernel, grid, block, 0, s, d);
+    if (small_tiles(d)) {
+      const int64_t t32 = (int64_t)((d.M + 31) / 32) * ((d.N + 31) / 32) * d.batch;
+      hipLaunchKernelGGL(zgemm_update_kernel<32>, dim3((unsigned)t32), block, 0, s, d);
+    } else {
+      hipLaunchKernelGGL(zgemm_update_kernel<64>, grid, block, 0, s, d);
+    }
   } else if (fp32) {
     launch_kind<GEMM_PRODUCT, MathF32>(d, s);
   } else {
