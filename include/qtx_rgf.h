@@ -133,9 +133,10 @@ enum {
  *   energy drops from 2 n_b - 1 to about n_b + 1 at the same operation count: it
  *   lowers the latency of a solve with few energies and changes nothing for a
  *   large batch, which already fills the GPU.  Results agree with the unsplit
- *   solve to rounding.  Requires block-diagonal Sigma^< / Sigma^> (SL_u and SG_u
- *   NULL, else QTX_ERR_UNSUPPORTED); the workspace per energy doubles
- *   (qtx_rgf_footprint).  n_b <= 2 ignores the flag.
+ *   solve to rounding.  With a BT Sigma^< / Sigma^> the bottom half reads the
+ *   blocks -(SL_u)^H (copied by the library into a context buffer of its own,
+ *   (n_b - 1 - c) blocks per energy and right-hand side).  The workspace per
+ *   energy doubles (qtx_rgf_footprint).  n_b <= 2 ignores the flag.
  * Limits: 1 <= b <= 1024, n_b >= 1, n_e >= 1. */
 typedef struct {
   int32_t n_b, b, n_e;

@@ -106,6 +106,30 @@ __global__ __launch_bounds__(256) void neg_ctrans_kernel(double2* const* t, int 
   }
 }
 
+// dst[m] = -src[m]^H for `count` b x b blocks: one workgroup per 32 x 32 tile of dst,
+// the source tile staged in LDS.
+__global__ __launch_bounds__(256) void neg_ctrans_copy_kernel(const double2* const* src, double2* const* dst, int b,
+                                                              int count) {
+  __shared__ double2 tl[32][33];
+  const int nt = (b + 31) / 32;
+  const int ti = blockIdx.x % nt, tj = blockIdx.x / nt;   // dst tile (ti, tj) <- src tile (tj, ti)
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int m = blockIdx.y; m < count; m += gridDim.y) {
+    const double2* S = src[m];
+    double2* D = dst[m];
+    for (int k = ty; k < 32; k += 8) {
+      const int r = tj * 32 + k, c = ti * 32 + tx;
+      if (r < b && c < b) tl[k][tx] = S[(int64_t)r * b + c];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+      const int r = ti * 32 + k, c = tj * 32 + tx;
+      if (r < b && c < b) { const double2 v = tl[tx][k]; D[(int64_t)r * b + c] = cmk(-v.x, v.y); }
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void scatter_status_kernel(const int32_t* st, int32_t* const* dst, int n) {
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z < n && dst[z]) *dst[z] = st[z];
@@ -208,6 +232,14 @@ hipError_t launch_neg_ctrans_entries(double2* const* t, int b, int count, hipStr
   const int nt = (b + 31) / 32;
   const int gy = count < 65535 ? count : 65535;
   hipLaunchKernelGGL(neg_ctrans_kernel, dim3((unsigned)(nt * (nt + 1) / 2), gy), dim3(256), 0, s, t, b, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_neg_ctrans_copy(const double2* const* src, double2* const* dst, int b, int count, hipStream_t s) {
+  if (count <= 0 || b <= 0) return hipSuccess;
+  const int nt = (b + 31) / 32;
+  const int gy = count < 65535 ? count : 65535;
+  hipLaunchKernelGGL(neg_ctrans_copy_kernel, dim3((unsigned)(nt * nt), gy), dim3(256), 0, s, src, dst, b, count);
   return hipGetLastError();
 }
 

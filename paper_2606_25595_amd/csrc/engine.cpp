@@ -93,6 +93,9 @@ struct qtx_rgf_ctx_s {
   std::vector<hipEvent_t> side_fork, side_join;
   std::vector<GraphCacheEntry> graphs;
   int64_t graph_launches = 0, graph_captures = 0;
+  // split solves with a BT Sigma^< / Sigma^>: the bottom halves' upper blocks -(SL_u)^H
+  void* rbt = nullptr;
+  size_t rbt_size = 0;
 };
 
 namespace {
@@ -154,6 +157,27 @@ qtx_status ensure_ws(qtx_rgf_ctx ctx, size_t bytes) {
   }
   ctx->ws = p;
   ctx->ws_size = bytes;
+  return QTX_OK;
+}
+
+// Room for the bottom halves' reversed BT right-hand-side blocks (same growth rule as
+// the workspace).
+qtx_status ensure_rbt(qtx_rgf_ctx ctx, size_t bytes) {
+  if (bytes <= ctx->rbt_size) return QTX_OK;
+  QTX_TRY(hipDeviceSynchronize());
+  drop_graphs(ctx);
+  if (ctx->rbt) {
+    QTX_TRY(hipFree(ctx->rbt));
+    ctx->rbt = nullptr;
+    ctx->rbt_size = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return QTX_ERR_NOMEM;
+  }
+  ctx->rbt = p;
+  ctx->rbt_size = bytes;
   return QTX_OK;
 }
 
@@ -457,9 +481,6 @@ qtx_status check_supported(const qtx_rgf_problem* p) {
   if (!make_scheme(p->prec, p->n_slices, &sc)) return QTX_ERR_UNSUPPORTED;
   if (p->prec_lesser >= 0 && !make_scheme(p->prec_lesser, p->n_slices_lesser, &sc)) return QTX_ERR_UNSUPPORTED;
   if (p->flags & ~(uint32_t)(QTX_S_IDENTITY | QTX_WANT_GREATER | QTX_SPLIT_CHAIN)) return QTX_ERR_ARG;
-  // The bottom half of a split chain reads the system block-reversed, where a BT
-  // Sigma^< would enter as the conjugate transposes of its upper blocks.
-  if ((p->flags & QTX_SPLIT_CHAIN) && (p->SL_u || p->SG_u)) return QTX_ERR_UNSUPPORTED;
   return QTX_OK;
 }
 
@@ -472,7 +493,8 @@ enum Arr {
   A_HD, A_HU, A_HL, A_SD, A_SU, A_SL,               // per problem, [n_b] / [n_b-1] blocks
   A_SRD, A_SLD, A_SGD, A_GRD, A_GLD, A_GGD,         // per energy, [n_b] blocks
   A_SRU, A_SRL, A_GRU, A_GRL, A_GLU, A_GGU,         // per energy, [n_b-1] blocks
-  A_SLU, A_SGU
+  A_SLU, A_SGU,
+  A_RBL, A_RBG                                      // bottom halves: -(SL_u)^H, -(SG_u)^H (context buffer)
 };
 
 // One chain of the recurrences.  An energy is one entry, or two with QTX_SPLIT_CHAIN:
@@ -488,6 +510,8 @@ struct Entry {
   bool rev = false;   // bottom half: logical block j is physical block n_b - 1 - j
   int c = 0;          // separator block of a split energy
   int part = -1;      // top half: index of its bottom half in the batch
+  int64_t rbt_l = -1, rbt_g = -1;   // bottom half with a BT Sigma^< / Sigma^>: element offsets
+                                    // of its -(SL_u)^H / -(SG_u)^H copies (blocks c .. n_b - 2)
 };
 
 // The common properties of a batch's entries.
@@ -626,7 +650,10 @@ struct Run {
         if (a == sw[0]) { a = sw[1]; diag = false; break; }
         if (a == sw[1]) { a = sw[0]; diag = false; break; }
       }
-      if (a == A_GLU || a == A_GGU || a == A_SLU || a == A_SGU) diag = false;
+      // the reversed system's upper Sigma^<> blocks are the physical lower ones, -(upper)^H
+      if (a == A_SLU) a = A_RBL;
+      if (a == A_SGU) a = A_RBG;
+      if (a == A_GLU || a == A_GGU || a == A_RBL || a == A_RBG) diag = false;
       j = diag ? p.n_b - 1 - j : p.n_b - 2 - j;
     }
     const int64_t nd = p.n_b, nu = (int64_t)p.n_b - 1;
@@ -653,6 +680,12 @@ struct Run {
       case A_GGU: base = p.GG_u; idx = e * nu + j; break;
       case A_SLU: base = p.SL_u; idx = e * nu + j; break;
       case A_SGU: base = p.SG_u; idx = e * nu + j; break;
+      case A_RBL:
+      case A_RBG: {
+        const int64_t o = a == A_RBL ? B->ent[z].rbt_l : B->ent[z].rbt_g;
+        if (o < 0 || !ctx->rbt) return nullptr;
+        return (const double2*)ctx->rbt + o + (int64_t)(j - B->ent[z].c) * bb;
+      }
     }
     if (!base) return nullptr;
     return (const double2*)base + idx * bb;
@@ -812,6 +845,21 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
   std::vector<Rhs> rhs{{A_SLD, k.l_bt ? A_SLU : -1, A_GLD, A_GLU}};
   if (k.greater) rhs.push_back({A_SGD, k.g_bt ? A_SGU : -1, A_GGD, A_GGU});
 
+  // Bottom halves with a BT right-hand side read it block-reversed: their upper blocks
+  // are the physical lower ones, -(SL_u)^H, copied once per solve (mode 4 lists the
+  // physical blocks c .. n_b - 2 of every bottom half).
+  if (B.split) {
+    int nfix = 0;
+    for (const Entry& en : B.ent)
+      if (en.rev) nfix += en.p->n_b - 1 - en.c;
+    for (const Rhs& r : rhs) {
+      if (r.SU < 0) continue;
+      const Mat src = R.get(r.SU, 4, 0, 0);
+      const Mat dst = R.get(r.SU == A_SLU ? A_RBL : A_RBG, 4, 0, 0);
+      if (!dry && nfix > 0) QTX_TRY(launch_neg_ctrans_copy(src.tab, (double2* const*)dst.tab, b, nfix, s));
+    }
+  }
+
   // The coupling operands: U_i = E S_{i,i+1} - H_{i,i+1} - Sigma^R_{i,i+1}(E) and the
   // same for L_i.  With S = I and no Sigma^R coupling they are -H_u, -H_l: the
   // operand is H with sign -1.  Otherwise they are assembled per entry (sign +1).
@@ -895,6 +943,10 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
     // - A_{c,c-1} x_{c-1} A_{c-1,c} and + A_{c,c-1} xl_{c-1} A_{c,c-1}^H (physical
     // couplings of block c - 1; x, xl of the top half), so that its x_c is G_cc and its
     // xl_c is G<_cc.  Greater: the top term goes to Tm[5] and is added to its Q below.
+    // With a BT right-hand side the top half's term also has the cross terms -V + V^H,
+    // V = A_{c,c-1} x_{c-1} Sigma^<_{c-1,c}.  Temporaries of the merge range: Tm[1], Tm[2]
+    // (assembled couplings), Tm[4], Tm[5] (Tm[0] keeps the bottom half's own T' for the
+    // cross terms of its later right-hand sides, Tm[3] holds its first Q).
     if (Zm > 0) {
       Mat Um, Lm;
       double sUm = -1.0, sLm = -1.0;
@@ -904,7 +956,7 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
       } else {
         const Mat SUm = k.s_id ? Mat{} : R.get(A_SU, 3, i, 0);
         const Mat SLm = k.s_id ? Mat{} : R.get(A_SL, 3, i, 0);
-        Um = ws_at(W.Tm[0], mlo);
+        Um = ws_at(W.Tm[2], mlo);
         Lm = ws_at(W.Tm[1], mlo);
         QTX_TRY(gm.go(Zm, OP_N, Mat{}, OP_N, Mat{}, Um, zero,
                       {addend_of(SUm, one, OP_N, 1), addend_of(R.get(A_HU, 3, i, 0), mone),
@@ -914,13 +966,34 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
                        addend_of(R.get(A_SRL, 3, i, 0), mone)}, zero, 0));
         sUm = sLm = 1.0;
       }
-      const Mat Xm = ws_at(W.X, mlo), T4 = ws_at(W.Tm[4], mlo), T5 = ws_at(W.Tm[5], mlo);
-      QTX_TRY(gm.go(Zm, OP_N, Lm, OP_N, R.get(A_GRD, 3, i, 0), T5, one, {}));
-      QTX_TRY(gm.go(Zm, OP_N, T5, OP_N, Um, Xm, cmk(-sLm * sUm, 0), {addend_of(Xm, one)}));
+      const Mat Xm = ws_at(W.X, mlo), T2 = ws_at(W.Tm[2], mlo), T4 = ws_at(W.Tm[4], mlo),
+                T5 = ws_at(W.Tm[5], mlo);
+      QTX_TRY(gm.go(Zm, OP_N, Lm, OP_N, R.get(A_GRD, 3, i, 0), T4, one, {}));              // T' = Lm' x_{c-1}
+      QTX_TRY(gm.go(Zm, OP_N, T4, OP_N, Um, Xm, cmk(-sLm * sUm, 0), {addend_of(Xm, one)}));
+      // V_q = T' Sigma_q,{c-1,c}: V_0 in Tm[2] (Um is dead), V_1 in Tm[5]
+      Mat Vq[2];
       for (size_t q = 0; q < rhs.size(); ++q) {
-        QTX_TRY(glm.go(Zm, OP_N, Lm, OP_N, R.get(rhs[q].Gd, 3, i, 0), T4, one, {}));
-        const Mat Qm = q == 0 ? ws_at(W.Tm[3], mlo) : T5;
-        QTX_TRY(glm.go(Zm, OP_N, T4, OP_C, Lm, Qm, one, {addend_of(q == 0 ? Qm : Mat{}, one)}, zero, -1, true));
+        if (rhs[q].SU < 0) continue;
+        Vq[q] = q == 0 ? T2 : T5;
+        QTX_TRY(glm.go(Zm, OP_N, T4, OP_N, R.get(rhs[q].SU, 3, i, 0), Vq[q], one, {}));
+      }
+      const double2 msl = cmk(-sLm, 0), psl = cmk(sLm, 0);
+      for (size_t q = 0; q < rhs.size(); ++q) {
+        QTX_TRY(glm.go(Zm, OP_N, Lm, OP_N, R.get(rhs[q].Gd, 3, i, 0), T4, one, {}));       // Lm' xl_{c-1}
+        const bool bt = rhs[q].SU >= 0;
+        if (q == 0) {
+          const Mat Qm = ws_at(W.Tm[3], mlo);
+          QTX_TRY(glm.go(Zm, OP_N, T4, OP_C, Lm, Qm, one,
+                         {addend_of(Qm, one), addend_of(bt ? Vq[0] : Mat{}, msl), addend_of(bt ? Vq[0] : Mat{}, psl, OP_C)},
+                         zero, -1, true));
+        } else if (!bt) {
+          QTX_TRY(glm.go(Zm, OP_N, T4, OP_C, Lm, T5, one, {}, zero, -1, true));
+        } else {
+          // out of place (V_1 is read transposed), then kept in Tm[5] past the inversion
+          QTX_TRY(glm.go(Zm, OP_N, T4, OP_C, Lm, T2, one, {addend_of(T5, msl), addend_of(T5, psl, OP_C)}, zero, -1,
+                         true));
+          QTX_TRY(glm.go(Zm, OP_N, Mat{}, OP_N, Mat{}, T5, zero, {addend_of(T2, one)}, zero, 0));
+        }
       }
     }
     if (!dry && Z > 0) {
@@ -1115,6 +1188,7 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
   size_t total_need = 0;
   for (size_t g = 0; g < keys.size(); ++g)
     for (const Unit& u : groups[g]) total_need += per_entry_bytes(keys[g]) * u.size();
+  int64_t rbt_elems = 0;
   const size_t budget = ws_budget(ctx);
   std::vector<Batch> batches;
   std::vector<size_t> lane_bytes;
@@ -1153,10 +1227,20 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
       B.lane = (int)g;
       lane_need = std::max(lane_need, batch_ws_bytes(B.key, (int)B.ent.size()));
       batches.push_back(std::move(B));
+      // bottom halves with a BT right-hand side: room for their reversed upper blocks
+      Batch& nb = batches.back();
+      const int64_t bbk = (int64_t)nb.key.b * nb.key.b;
+      for (Entry& en : nb.ent) {
+        if (!en.rev) continue;
+        const int64_t blocks = (int64_t)(en.p->n_b - 1 - en.c) * bbk;
+        if (nb.key.l_bt) { en.rbt_l = rbt_elems; rbt_elems += blocks; }
+        if (nb.key.g_bt) { en.rbt_g = rbt_elems; rbt_elems += blocks; }
+      }
     }
     lane_bytes.push_back(align_up(lane_need));
   }
   const int n_lanes = (int)keys.size();
+  if (rbt_elems > 0) QTX_TRYS(ensure_rbt(ctx, (size_t)rbt_elems * sizeof(double2)));
   // 2. dry pass: tables and per-entry data of every batch
   std::vector<Run> runs(batches.size());
   size_t tab_total = 0;
@@ -1488,6 +1572,7 @@ qtx_status qtx_rgf_destroy(qtx_rgf_ctx ctx) {
     (void)hipDeviceSynchronize();
     drop_graphs(ctx);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->rbt) (void)hipFree(ctx->rbt);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->upload_done) (void)hipEventDestroy(ctx->upload_done);
     for (auto& f : ctx->prof)

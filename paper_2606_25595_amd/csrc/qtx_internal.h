@@ -173,6 +173,8 @@ hipError_t launch_nan_fill_entries(double2* const* t, const int64_t* counts, int
 hipError_t launch_status_merge(int32_t* st, const int32_t* part, int batch, hipStream_t s);
 // X <- -X^H in place for `count` b x b blocks t[0 .. count-1].
 hipError_t launch_neg_ctrans_entries(double2* const* t, int b, int count, hipStream_t s);
+// dst[m] = -src[m]^H for `count` b x b blocks (distinct buffers).
+hipError_t launch_neg_ctrans_copy(const double2* const* src, double2* const* dst, int b, int count, hipStream_t s);
 hipError_t launch_scatter_status(const int32_t* st, int32_t* const* dst, int batch, hipStream_t s);
 hipError_t launch_observables(int b, int n_e, const double2* G, const double2* GL, int64_t sG,
                               const double2* M1, const double2* M2, const double2* gam,

@@ -179,12 +179,8 @@ def test_split_status_singular_and_nonfinite(ctx):
     check({k: v[:1] for k, v in out.items() if k != "status"}, oracle.rgf_selected(p.subset([0])))
 
 
-def test_split_rejects_bt_sigma_lesser_and_doubles_footprint(ctx):
+def test_split_doubles_footprint(ctx):
     from paper_2606_25595_amd import qtx
-    p = inputs.random_bt_problem(4, 16, np.array([0.3]), seed=78, bt_sigma=0.3)
-    dp = qtx.to_device(p)
-    dp.split = True
-    assert ctx.solve(dp, check=False) == qtx.QTX_ERR_UNSUPPORTED
     q = inputs.random_bt_problem(4, 16, np.array([0.3]), seed=78)
     dq = qtx.to_device(q)
     f1 = ctx.footprint(dq)
@@ -192,14 +188,66 @@ def test_split_rejects_bt_sigma_lesser_and_doubles_footprint(ctx):
     assert ctx.footprint(dq) == 2 * f1 > 0
 
 
+# BT Sigma^< / Sigma^>: the bottom half reads copies -(SL_u)^H of the physical upper
+# blocks, and the separator step adds the top half's cross terms.
+@pytest.mark.parametrize("n_b,b,n_e", [(3, 16, 2), (4, 33, 3), (5, 40, 2), (8, 64, 2)])
+def test_split_bt_sigma_matches_oracle(ctx, n_b, b, n_e):
+    p = inputs.random_bt_problem(n_b, b, np.linspace(-1.7, 1.5, n_e), seed=800 + n_b * b, with_greater=True,
+                                 bt_sigma=0.05)
+    keys = KEYS + ("GG_d", "GG_u")
+    _, out = solve(ctx, p)
+    assert np.all(out["status"] == 0)
+    check(out, oracle.rgf_selected(p), keys=keys)
+    _, one = solve(ctx, p, split=False)
+    for k in keys:
+        assert oracle.rel_fro_err(out[k], one[k]).max() <= 1e-11, k
+
+
+def test_split_bt_sigma_general_overlap(ctx):
+    """S != I, BT Sigma^R and BT Sigma^< together (couplings assembled per energy)."""
+    rng = np.random.default_rng(81)
+    n_b, b = 7, 24
+    p = inputs.random_bt_problem(n_b, b, np.array([-0.6, 0.4]), seed=82, with_greater=True, bt_sigma=0.05)
+    p.S_d = np.stack([np.eye(b) + 0.05 * (lambda X: X + X.conj().T)(crand(rng, b, b)) for _ in range(n_b)])
+    p.S_u = 0.05 * crand(rng, n_b - 1, b, b)
+    p.S_l = np.ascontiguousarray(np.conj(np.transpose(p.S_u, (0, 2, 1))))
+    _, out = solve(ctx, p)
+    assert np.all(out["status"] == 0)
+    check(out, oracle.rgf_selected(p), keys=KEYS + ("GG_d", "GG_u"))
+
+
+def test_split_bt_sigma_int8(ctx):
+    p = inputs.random_bt_problem(6, 96, np.linspace(-1.9, 1.9, 4), seed=83, bt_sigma=0.05)
+    _, out = solve(ctx, p, prec="int8", n_slices=11)
+    assert np.all(out["status"] == 0)
+    ref = oracle.rgf_selected(p)
+    for k in KEYS:
+        assert oracle.rel_fro_err(out[k], ref[k]).max() <= 1e-7, k
+
+
+def test_split_w_system(ctx):
+    """The screened Coulomb system (its right-hand side V P^< V^H is BT) solved split."""
+    import torch
+    from paper_2606_25595_amd import qtx
+    w = inputs.random_w_problem(7, 40, np.linspace(-1.5, 1.4, 3), seed=84, with_greater=True)
+    dw = qtx.w_to_device(w)
+    dp = ctx.w_problem(dw, ctx.w_assemble(dw))
+    dp.split = True
+    ctx.solve(dp)
+    torch.cuda.synchronize()
+    out = dp.outputs()
+    assert np.all(out["status"] == 0)
+    check(out, oracle.w_selected(w, "rgf"), keys=KEYS + ("GG_d", "GG_u"))
+
+
 @pytest.mark.parametrize("prec,ns", [("fp64", 0), ("int8", 10)])
 def test_split_with_lanes_and_overlap_bitwise(ctx, prec, ns):
     """Stream lanes (energies dealt to parallel streams, halves of one energy kept
     together) and the side-stream overlap of the first lesser products (off at a
-    separator step) leave the split solve's results unchanged, bit for bit."""
+    separator step) leave the split solve's results unchanged, bit for bit (BT Sigma^<)."""
     import torch
     from paper_2606_25595_amd import qtx
-    p = inputs.random_bt_problem(9, 48, np.linspace(-1.6, 1.4, 5), seed=79, with_greater=True)
+    p = inputs.random_bt_problem(9, 48, np.linspace(-1.6, 1.4, 5), seed=79, with_greater=True, bt_sigma=0.05)
     keys = KEYS + ("GG_d", "GG_u")
 
     def run():
