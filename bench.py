@@ -126,6 +126,8 @@ def main():
                          "b=256, 128 energies) | fpx (FPX storage codec GB/s on G^R blocks) | batch (512 uneven "
                          "problems, one graph launch) | "
                          "serve (Poisson arrivals, continuous batching, p50/p99)")
+    ap.add_argument("--workspace-gb", type=float, default=0.0,
+                    help="realistic/hard: library workspace cap in GiB (0 = a quarter of free HBM)")
     ap.add_argument("--split", action="store_true",
                     help="realistic/hard/serve: two half-chains per energy (QTX_SPLIT_CHAIN)")
     ap.add_argument("--eta", type=float, default=None, help="realistic/hard: broadening (default 1e-3 / 1e-6)")
@@ -173,7 +175,7 @@ def main():
                            GR_u=torch.empty((n_e, n_b - 1, b, b), **kw), GR_l=torch.empty((n_e, n_b - 1, b, b), **kw),
                            GL_d=torch.empty((n_e, n_b, b, b), **kw), GL_u=torch.empty((n_e, n_b - 1, b, b), **kw),
                            status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"), split=args.split)
-    ctx = qtx.Context(0)
+    ctx = qtx.Context(0, workspace_bytes=int(args.workspace_gb * (1 << 30)))
     sample = list(range(0, n_e, max(1, n_e // args.cpu_energies)))[: args.cpu_energies]
     gamma_L = 2.0 * gamma * np.eye(b, dtype=np.complex128)
     f_L = inputs.fermi(grid, mu_L, kT)
@@ -315,7 +317,8 @@ def main():
         "config": {"workload": "%sselected RGF solve: n_b=32 blocks, b=416, N_E=256 energies in [-2,2], "
                                "complex128, S=I, random Hermitian H (seed 0), eta=%g, gamma=0.5"
                                % ("realistic " if args.workload == "realistic" else "hard (ill-conditioned) ", eta),
-                   "precision": best, "energies_per_step": n_e, "split_chain": bool(args.split)},
+                   "precision": best, "energies_per_step": n_e, "split_chain": bool(args.split),
+                   "workspace_gb": args.workspace_gb or None},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": (achieved / peak) if achieved else None, "traffic": traffic,
                      "kernel": "%s: matrix-core kernel of the complex b x b x b block products (%s scheme); "
