@@ -185,19 +185,24 @@ __global__ __launch_bounds__(PT) void gje_panel_kernel(int n, int k0, double2* X
 
 // ---- 32-column panel (n <= 512) --------------------------------------------
 // Same elimination as gje_panel_kernel, organised for a short pivot step:
-//  * the column loop is 8 rolled groups of 4 unrolled columns, so the current
-//    column is picked with an 8-way select and only 8 columns need the
-//    "is this the pivot column" select;
+//  * 512 threads; the half h = tid / 256 holds columns 16h .. 16h+15 of rows l and
+//    l + 256 (l = tid % 256): 32 complex values per thread stay in VGPRs with two
+//    waves per SIMD (two rows of all 32 columns per thread would not fit the 256
+//    VGPRs and move through AGPRs at every step);
+//  * the column loop is 2 rolled halves of 16 unrolled columns, so the current column
+//    and the pivot-column test are compile-time, and only the half that holds the
+//    column (wave-uniform) searches it;
 //  * every row is updated with one formula, v <- s v - m pr, where s = 0 and
 //    m = -1/pivot for the pivot row (which turns into pr / pivot) and s = 1,
 //    m = v_k / pivot for the others; the pivot column then takes the transform
 //    entry (1/pivot, resp. -v_k / pivot);
-//  * 256 threads hold two rows each (one wave per SIMD, so the panel and the
-//    update's temporaries fit the register file);
-//  * the pivot search reduces (|re| + |im|, row) over each thread's rows, then
-//    within 16-lane groups with DPP moves; each group's winner puts its whole row
-//    in LDS next to its candidate, so after a single barrier every thread picks
-//    the best of the 16 candidates and reads the pivot row directly.
+//  * the searching half reduces (|re| + |im|, row) over each thread's rows, then
+//    within 16-lane groups with DPP moves; each group's winner puts its half of the
+//    row in LDS next to its candidate, and every thread of that half posts its
+//    column-k values (the other half's multipliers); after a barrier every thread
+//    picks the best of the 16 candidates, the thread of the other half that holds
+//    the pivot row posts its half of it, and after a second barrier every thread
+//    updates its 16 columns.
 template <int CTRL>
 __device__ inline void argmax_dpp(double& m, int& i) {
   const int2 mb = __builtin_bit_cast(int2, m);
@@ -215,92 +220,108 @@ __device__ inline void argmax_row16(double& m, int& i) {
   argmax_dpp<0x140>(m, i);   // row_mirror
 }
 
-constexpr int PT32 = 256;   // threads of the 32-column panel kernel (one wave per SIMD)
+constexpr int PT32 = 512;   // threads of the 32-column panel kernel
 
 __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double2* X, int64_t sX, GjeWork w,
                                                            int32_t* status) {
-  constexpr int NB = 32, RPT = 2, NG = PT32 / 16, GW = 4;   // GW: unrolled columns per group
+  constexpr int NB = 32, HB = 16, RPT = 2, NG = 16;
   const int z = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63;
+  const int h = tid >> 8, l = tid & 255;
   const int nbw = min(NB, n - k0);
   double2* __restrict__ Xz = X + (int64_t)z * sX;
   int32_t* __restrict__ prow = w.prow + (int64_t)z * n;
   int32_t* __restrict__ used = w.used + (int64_t)z * n;
 
-  __shared__ double2 cand_row[2][NG][NB];
+  __shared__ double2 cand_row[2][NG][HB];   // the searching half's columns of each group's candidate row
   __shared__ double cand_mag[2][NG];
   __shared__ int cand_idx[2][NG];
+  __shared__ double2 other_row[2][HB];      // the other half's columns of the pivot row
+  __shared__ double2 colk[2][RPT * 256];    // column k of every row
   __shared__ int piv_of[NB];
 
   bool u[RPT];
   int pivcol[RPT];
-  double2 v[RPT][NB];
+  double2 v[RPT][HB];
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    const int r = tid + PT32 * j;
+    const int r = l + 256 * j;
     u[j] = (r >= n) || (used[r] != 0);
     pivcol[j] = -1;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) v[j][c] = (r < n && c < nbw) ? Xz[(int64_t)r * n + k0 + c] : cmk(0.0, 0.0);
+    for (int c = 0; c < HB; ++c) {
+      const int gc = HB * h + c;
+      v[j][c] = (r < n && gc < nbw) ? Xz[(int64_t)r * n + k0 + gc] : cmk(0.0, 0.0);
+    }
   }
   bool singular = false;
 
-  for (int kg = 0; kg < NB / GW; ++kg) {
+  for (int hk = 0; hk < 2; ++hk) {
+    const bool srch = (h == hk);   // wave-uniform: this half holds the current column
 #pragma unroll
-    for (int kk = 0; kk < GW; ++kk) {
-      const int k = GW * kg + kk;
+    for (int kc = 0; kc < HB; ++kc) {
+      const int k = HB * hk + kc;
       if (k < nbw) {   // uniform
         const int buf = k & 1;
-        double2 ck[RPT];
-        double mag = -1.0;
-        int idx = 0x7fffffff;
+        if (srch) {
+          double mag = -1.0;
+          int idx = 0x7fffffff;
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-          ck[j] = v[j][kk];
-#pragma unroll
-          for (int g = 1; g < NB / GW; ++g)
-            if (g == kg) ck[j] = v[j][GW * g + kk];
-          if (!u[j]) {   // rows increase with j: strict > keeps the lower row on ties
-            double mg = fabs(ck[j].x) + fabs(ck[j].y);
-            if (mg != mg) mg = __builtin_huge_val();   // a NaN row is taken (its NaN propagates)
-            if (mg > mag) { mag = mg; idx = tid + PT32 * j; }
+          for (int j = 0; j < RPT; ++j) {
+            const double2 ck = v[j][kc];
+            colk[buf][l + 256 * j] = ck;
+            double mg = fabs(ck.x) + fabs(ck.y);
+            mg = (mg != mg) ? __builtin_huge_val() : mg;   // a NaN row is taken (its NaN propagates)
+            const bool take = !u[j] && mg > mag;           // rows increase with j: strict > keeps the lower
+            mag = take ? mg : mag;
+            idx = take ? l + 256 * j : idx;
           }
+          argmax_row16(mag, idx);
+          const int grp = l >> 4;
+          if ((lane & 15) == 0) { cand_mag[buf][grp] = mag; cand_idx[buf][grp] = idx; }
+#pragma unroll
+          for (int j = 0; j < RPT; ++j)
+            if (idx == l + 256 * j) {
+#pragma unroll
+              for (int c = 0; c < HB; ++c) cand_row[buf][grp][c] = v[j][c];
+            }
         }
-        argmax_row16(mag, idx);
-        const int grp = tid >> 4;
-        if ((lane & 15) == 0) { cand_mag[buf][grp] = mag; cand_idx[buf][grp] = idx; }
-#pragma unroll
-        for (int j = 0; j < RPT; ++j)
-          if (idx == tid + PT32 * j) {
-#pragma unroll
-            for (int c = 0; c < NB; ++c) cand_row[buf][grp][c] = v[j][c];
-          }
         __syncthreads();
-        // best of the NG candidates: lane l looks at candidate l % NG
-        double pm = cand_mag[buf][lane % NG];
-        int p = cand_idx[buf][lane % NG];
+        double pm = cand_mag[buf][lane & (NG - 1)];
+        int p = cand_idx[buf][lane & (NG - 1)];
         argmax_row16(pm, p);
         // p is an unused row while k0 + k < n; pm == 0 means singular.  Defensive clamp only.
         if ((unsigned)p >= (unsigned)n) p = 0;
-        const int pg = (p % PT32) >> 4;
-        const double2 pv = cand_row[buf][pg][k];
+        const int pl = p & 255, pj = p >> 8, pg = pl >> 4;
+        if (!srch && l == pl) {
+#pragma unroll
+          for (int j = 0; j < RPT; ++j)
+            if (j == pj) {
+#pragma unroll
+              for (int c = 0; c < HB; ++c) other_row[buf][c] = v[j][c];
+            }
+        }
+        __syncthreads();
+        const double2 pv = cand_row[buf][pg][kc];
         const double2 dinv = (pv.x == 0.0 && pv.y == 0.0) ? cmk(1.0, 0.0) : cinv(pv);
+        const double2* __restrict__ prs = srch ? &cand_row[buf][pg][0] : &other_row[buf][0];
         double s[RPT];
         double2 m[RPT], newk[RPT];
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-          const bool isp = (tid + PT32 * j == p);
-          const double2 fd = cmul(ck[j], dinv);
+          const bool isp = (l + 256 * j == p);
+          const double2 fd = cmul(colk[buf][l + 256 * j], dinv);
           s[j] = isp ? 0.0 : 1.0;
           m[j] = isp ? cmk(-dinv.x, -dinv.y) : fd;
           newk[j] = isp ? dinv : cmk(-fd.x, -fd.y);
-          if (isp) { u[j] = true; pivcol[j] = k; }
+          u[j] = u[j] || isp;
+          pivcol[j] = isp ? k : pivcol[j];
         }
 #pragma unroll
-        for (int c8 = 0; c8 < NB; c8 += 8) {
-          double2 pr[8];   // 8 pivot-row entries at a time
+        for (int c8 = 0; c8 < HB; c8 += 8) {
+          double2 pr[8];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) pr[q] = cand_row[buf][pg][c8 + q];
+          for (int q = 0; q < 8; ++q) pr[q] = prs[c8 + q];
 #pragma unroll
           for (int j = 0; j < RPT; ++j)
 #pragma unroll
@@ -309,10 +330,9 @@ __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double
               double2 nv;
               nv.x = fma(s[j], v[j][c].x, -fma(m[j].x, pr[q].x, -m[j].y * pr[q].y));
               nv.y = fma(s[j], v[j][c].y, -fma(m[j].x, pr[q].y, m[j].y * pr[q].x));
-              if (c % GW == kk && c / GW == kg) nv = newk[j];
+              if (c == kc && srch) nv = newk[j];
               v[j][c] = nv;
             }
-          asm volatile("" ::: "memory");
         }
         if (tid == 0) {
           piv_of[k] = p;
@@ -320,29 +340,28 @@ __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double
         }
         singular = singular || !(pm > 0.0);
       }
-      asm volatile("" ::: "memory");   // one step's temporaries die here
     }
   }
   __syncthreads();
 
-  // write back the panel, the shifted transform Wp and the usage flags
+  // write back this half's panel columns, its columns of the shifted transform Wp, the usage flags
   double2* __restrict__ Wp = w.Wp + (int64_t)z * n * NB;
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    const int r = tid + PT32 * j;
+    const int r = l + 256 * j;
     if (r < n) {
 #pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        if (c < nbw) Xz[(int64_t)r * n + k0 + c] = v[j][c];
-        double2 wv = (c < nbw) ? v[j][c] : cmk(0.0, 0.0);
-        if (c == pivcol[j]) wv.x -= 1.0;
-        Wp[(int64_t)r * NB + c] = wv;
+      for (int c = 0; c < HB; ++c) {
+        const int gc = HB * h + c;
+        if (gc < nbw) Xz[(int64_t)r * n + k0 + gc] = v[j][c];
+        double2 wv = (gc < nbw) ? v[j][c] : cmk(0.0, 0.0);
+        if (gc == pivcol[j]) wv.x -= 1.0;
+        Wp[(int64_t)r * NB + gc] = wv;
       }
-      if (pivcol[j] >= 0) used[r] = 1;
+      if (h == 0 && pivcol[j] >= 0) used[r] = 1;
     }
   }
-  // pivot rows of this panel (pre-update values outside the panel), panel columns
-  // zeroed; 8 loads in flight per thread before their stores
+  // pivot rows of this panel (pre-update values outside the panel), panel columns zeroed
   double2* __restrict__ Tp = w.Tp + (int64_t)z * NB * n;
   for (int base = 0; base < NB * n; base += PT32 * 8) {
     double2 val[8];
