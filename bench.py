@@ -791,7 +791,15 @@ def bench_serve(args):
     log("bench serve: %d requests over %.1f s at %.1f/s, budget %.1f GB" % (len(reqs), args.duration, args.rate,
                                                                            budget / 1e9))
     ex = GpuExecutor(n_slots=3, workspace_per_slot=int(free * 0.08), split=args.split)
-    srv = Server(ex, hbm_budget=budget, chunk_energies=16, max_pending=512)
+    n_done = [0]
+
+    def done(r):
+        n_done[0] += 1
+        if n_done[0] % 20 == 0:
+            log("bench serve: %d requests completed (latest: id %d, %d energies, %.2f s)"
+                % (n_done[0], r.rid, r.n_e, r.latency))
+
+    srv = Server(ex, hbm_budget=budget, chunk_energies=16, max_pending=512, on_done=done)
     rep = srv.run(reqs, time_limit=args.time_limit)
     ex.close()
     line = {"metric": "served RGF energy points/sec with p50/p99 request latency",

@@ -119,8 +119,10 @@ class Server:
     """
 
     def __init__(self, executor, hbm_budget: int, chunk_energies: int = 8, max_pending: int = 1 << 30,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter,
+                 on_done: Optional[Callable[[Request], None]] = None):
         self.ex = executor
+        self.on_done = on_done   # called with each request as it completes
         self.budget = int(hbm_budget)
         self.chunk_energies = int(chunk_energies)
         self.max_pending = int(max_pending)
@@ -169,6 +171,8 @@ class Server:
                         self.ex.finish_request(r)
                         self.active_requests.pop(r.rid, None)
                         self.used -= self.ex.request_bytes(r)
+                        if self.on_done is not None:
+                            self.on_done(r)
                 progress = True
         # admit in arrival order while memory allows (head-of-line: no overtaking,
         # so every request eventually runs)
