@@ -136,8 +136,8 @@ def main():
     ap.add_argument("--latency-split", default="0,1", help="latency workload: 0 = one chain, 1 = split")
     ap.add_argument("--problems", type=int, default=512, help="batch workload: number of problems")
     ap.add_argument("--rate", type=float, default=200.0, help="serve workload: arrivals per second")
-    ap.add_argument("--duration", type=float, default=10.0, help="serve workload: arrival window (s)")
-    ap.add_argument("--time-limit", type=float, default=60.0, help="serve workload: wall-clock cap (s)")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve workload: arrival window (s)")
+    ap.add_argument("--time-limit", type=float, default=150.0, help="serve workload: wall-clock cap (s)")
     ap.add_argument("--prec", default="fp64", help="batch workload scheme (fp64 | int8:11 | int8:10/int8:11 | ...)")
     args = ap.parse_args()
     if args.gpus != 1:
