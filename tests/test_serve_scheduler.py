@@ -104,3 +104,23 @@ def test_poisson_stream_is_reproducible():
     assert 150 < len(a) < 250
     assert all(128 <= r.b <= 512 and 8 <= r.n_b <= 48 and 16 <= r.n_e <= 128 for r in a)
     assert np.all(np.diff([r.t_arrive for r in a]) > 0)
+
+
+def test_on_done_called_once_per_completed_request_in_completion_order():
+    clock = VirtualClock()
+    ex = FakeExecutor(clock, n_slots=2, cost=0.02)
+    arrivals = [Request(rid=i, b=8, n_b=2, n_e=4 + 3 * i, seed=i, t_arrive=0.01 * i) for i in range(5)]
+    seen = []
+
+    def on_done(r):
+        assert r.t_done is not None and r.chunks_left == 0
+        seen.append((r.rid, r.t_done))
+
+    srv = Server(ex, hbm_budget=10 ** 6, chunk_energies=4, clock=clock, on_done=on_done)
+    drive(srv, clock, arrivals)
+    assert sorted(rid for rid, _ in seen) == list(range(5))
+    assert [t for _, t in seen] == sorted(t for _, t in seen)
+    rejected = Request(rid=9, b=64, n_b=8, n_e=4, seed=9)
+    small = Server(FakeExecutor(clock), hbm_budget=100, chunk_energies=4, clock=clock, on_done=on_done)
+    assert not small.submit(rejected)
+    assert len(seen) == 5   # a rejected request never completes
