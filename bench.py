@@ -20,6 +20,9 @@ Also reported:
                HIP events recorded by the library on the launch stream
   cpu_baseline the FP64 oracle (numpy/LAPACK) on the host cores, on a bounded
                sample of the same workload's energies, in energy points per second
+  p50/p99_latency_ms  per-solve latency of the K back-to-back timed solves (HIP
+               events on the solve's stream); request latency under load is the
+               serve workload's, one-energy latency the latency workload's
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precs fp64,...]
 """
@@ -235,13 +238,19 @@ def main():
         for fam in (qtx.QTX_KERNEL_GEMM, qtx.QTX_KERNEL_INV, qtx.QTX_KERNEL_CONVERT):
             ctx.profile_read(fam)
         log("bench: %s timed x%d" % (prec, args.steps))
+        # one event after each solve on the solve's stream: per-solve latency of back-to-back
+        # solves (recording events does not synchronise the host)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        evs[0].record()
         for k in range(args.steps):
             ctx.solve(dp, **skw)
+            evs[k + 1].record()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         ctx.profile(False)
+        lat_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
         g_ms, g_n, g_fl = ctx.profile_read(qtx.QTX_KERNEL_GEMM)
         i_ms, i_n, i_fl = ctx.profile_read(qtx.QTX_KERNEL_INV)
         c_ms, c_n, c_by = ctx.profile_read(qtx.QTX_KERNEL_CONVERT)
@@ -270,7 +279,9 @@ def main():
             errs_full = full_errors(*ctx.observables(dp, gamma_L, f_L))
         results[prec] = dict(ms_per_step=ms_step, value=n_e / (ms_step / 1e3), status_ok=bool(np.all(st == 0)),
                              gemm=(g_ms, g_n, g_fl), inv=(i_ms, i_n, i_fl), conv=(c_ms, c_n, c_by), errs=errs,
-                             errs_full=errs_full)
+                             errs_full=errs_full,
+                             latency_ms={"p50": float(np.percentile(lat_ms, 50)),
+                                         "p99": float(np.percentile(lat_ms, 99)), "solves": len(lat_ms)})
         log("bench: %s %.1f ms/step, %.1f energies/s, product kernel avg %.3f ms x%d, conversion %.1f ms/step, "
             "inv avg %.3f ms x%d, err %s, all-energy err vs fp64 %s" % (
                 prec, ms_step, n_e / (ms_step / 1e3), g_ms / max(g_n, 1), g_n, c_ms / args.steps,
@@ -326,9 +337,11 @@ def main():
                      "flops_per_launch": g_fl / max(g_n, 1), "avg_launch_ms": g_ms / max(g_n, 1),
                      "launches": g_n},
         "cpu_baseline": cpu,
+        "p50_latency_ms": r["latency_ms"]["p50"], "p99_latency_ms": r["latency_ms"]["p99"],
+        "latency": "one solve of all energies of the step, back to back (HIP events on the solve's stream)",
         "schemes": {p: {"energies_per_s": v["value"], "ms_per_step": v["ms_per_step"], "max_rel_err": v["errs"],
                         "max_rel_err_all_energies_vs_fp64": v["errs_full"],
-                        "status_ok": v["status_ok"],
+                        "status_ok": v["status_ok"], "solve_latency_ms": v["latency_ms"],
                         "products_tflops_fp64eq": gemm_fp64eq * args.steps / ((v["gemm"][0] + v["conv"][0]) / 1e3)
                         / 1e12 if v["gemm"][1] else None,
                         "product_kernel_ms_per_step": v["gemm"][0] / args.steps,
