@@ -9,10 +9,11 @@ G^< with every block inversion, inputs resident in HBM.  The metric is energy
 points per second.  Precision schemes: fp64 (reference) and the mixed schemes
 of the complex block products; `value` is the fastest scheme whose per-block
 error against the FP64 oracle on sampled energies is <= 1e-6 and whose error
-against the FP64 GPU run over all energies (diagonal G^R and G^< blocks, T_L,
-j_L) is <= 1e-6 as well (the FP64 path always qualifies; it is itself checked
-against the oracle on the sample), and every scheme's rate and error is reported
-beside it.
+against FP64 solves of all energies (every output block type, T_L, j_L; the
+FP64 solves run again in chunks after the timed region) is <= 1e-6 as well (the
+FP64 path always qualifies; it is itself checked against the oracle on the
+sample), and every scheme's rate and error is reported beside it.  If no scheme
+qualifies, the line carries "meets_tolerance": false.
 
 Also reported:
   roofline     the dominant kernel (the b x b x b complex block products),
@@ -122,6 +123,8 @@ def main():
                          "<retarded>/<lesser>")
     ap.add_argument("--cpu-energies", type=int, default=16, help="energies in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-full-check", action="store_true",
+                    help="skip the all-energy error check of the mixed schemes (then none qualifies)")
     ap.add_argument("--workload", default="realistic", choices=["realistic", "hard", "kappa", "w", "fpx", "batch", "serve", "latency"],
                     help="realistic (default, the headline line) | hard (the realistic shapes at eta = 1e-6, "
                          "condition numbers up to ~5e6) | kappa (error against the exact condition number, "
@@ -208,25 +211,44 @@ def main():
 
     results = {}
     tuned = {}
-    full_ref = None   # the FP64 run's G^R_ii, G^<_ii, T_L, j_L for every energy (device copies)
+    KEYS = ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")
+    chunk_e = 32
 
-    def full_errors(T, j):
-        """Max relative Frobenius error per (energy, diagonal block) of G^R and G^< over
-        all energies, against the FP64 GPU run, and T_L / j_L relative to their largest
-        magnitude; chunked over energies on the device."""
-        out = {}
-        for key in ("GR_d", "GL_d"):
-            X, R = getattr(dp, key), full_ref[key]
-            worst = 0.0
-            for e0 in range(0, n_e, 16):
-                d = (X[e0:e0 + 16] - R[e0:e0 + 16]).abs().pow(2).sum((-1, -2)).sqrt()
-                nr = R[e0:e0 + 16].abs().pow(2).sum((-1, -2)).sqrt()
-                worst = max(worst, float((d / nr.clamp_min(1e-300)).max().item()))
-            out[key] = worst
-        for key, got in (("T_L", T), ("j_L", j)):
-            ref_t = full_ref[key]
-            out[key] = float(((got - ref_t).abs().max() / ref_t.abs().max().clamp_min(1e-300)).item())
-        return out
+    def full_errors():
+        """Error of the current outputs over ALL energies against FP64 solves of the same
+        energies, run again here in chunks of 32 energies (every output block type:
+        max relative Frobenius error per (energy, block); T_L and j_L relative to their
+        largest magnitude over all energies).  Outside the timed region."""
+        worst = {k: 0.0 for k in KEYS}
+        dT = dj = mT = mj = 0.0
+        sub = None
+        for e0 in range(0, n_e, chunk_e):
+            e1 = min(n_e, e0 + chunk_e)
+            c = e1 - e0
+            if sub is None or sub.n_e != c:
+                sub = qtx.DeviceProblem(
+                    energies=grid[e0:e1], H_d=dp.H_d, H_u=dp.H_u, H_l=dp.H_l, SR_d=dp.SR_d[e0:e1],
+                    SL_d=dp.SL_d[e0:e1], GR_d=torch.empty((c, n_b, b, b), **kw),
+                    GR_u=torch.empty((c, n_b - 1, b, b), **kw), GR_l=torch.empty((c, n_b - 1, b, b), **kw),
+                    GL_d=torch.empty((c, n_b, b, b), **kw), GL_u=torch.empty((c, n_b - 1, b, b), **kw),
+                    status=torch.full((c,), -1, dtype=torch.int32, device="cuda"))
+            sub.energies = grid[e0:e1]
+            sub.SR_d, sub.SL_d = dp.SR_d[e0:e1], dp.SL_d[e0:e1]
+            ctx.solve(sub, prec="fp64")
+            for key in KEYS:
+                X, R = getattr(dp, key)[e0:e1], getattr(sub, key)
+                d = (X - R).abs().pow(2).sum((-1, -2)).sqrt()
+                nr = R.abs().pow(2).sum((-1, -2)).sqrt()
+                worst[key] = max(worst[key], float((d / nr.clamp_min(1e-300)).max().item()))
+            Tr, jr = ctx.observables(sub, gamma_L, f_L[e0:e1])
+            Tg, jg = ctx.observables_blocks(dp.GR_d[e0:e1], dp.GL_d[e0:e1], gamma_L, f_L[e0:e1])
+            dT = max(dT, float((Tg - Tr).abs().max().item()))
+            dj = max(dj, float((jg - jr).abs().max().item()))
+            mT = max(mT, float(Tr.abs().max().item()))
+            mj = max(mj, float(jr.abs().max().item()))
+        worst["T_L"] = dT / max(mT, 1e-300)
+        worst["j_L"] = dj / max(mj, 1e-300)
+        return worst
     for prec in args.precs.split(","):
         skw = parse_scheme(prec)
         tuned.update(autotune(ctx, skw, [(b, n_e)]))
@@ -270,13 +292,9 @@ def main():
                 g = got.cpu().numpy()[sample]
                 errs[key] = float(np.abs(g - ref[key]).max() / max(np.abs(ref[key]).max(), 1e-300))
         errs_full = None
-        if prec == "fp64" and full_ref is None:
-            need = 2 * dp.GR_d.numel() * 16
-            if torch.cuda.mem_get_info()[0] > need + (16 << 30):
-                T, j = ctx.observables(dp, gamma_L, f_L)
-                full_ref = {"GR_d": dp.GR_d.clone(), "GL_d": dp.GL_d.clone(), "T_L": T.clone(), "j_L": j.clone()}
-        elif full_ref is not None:
-            errs_full = full_errors(*ctx.observables(dp, gamma_L, f_L))
+        if prec != "fp64" and not args.no_full_check:
+            log("bench: %s all-energy check against chunked FP64 solves" % prec)
+            errs_full = full_errors()
         results[prec] = dict(ms_per_step=ms_step, value=n_e / (ms_step / 1e3), status_ok=bool(np.all(st == 0)),
                              gemm=(g_ms, g_n, g_fl), inv=(i_ms, i_n, i_fl), conv=(c_ms, c_n, c_by), errs=errs,
                              errs_full=errs_full,
@@ -286,7 +304,6 @@ def main():
             "inv avg %.3f ms x%d, err %s, all-energy err vs fp64 %s" % (
                 prec, ms_step, n_e / (ms_step / 1e3), g_ms / max(g_n, 1), g_n, c_ms / args.steps,
                 i_ms / max(i_n, 1), i_n, errs, errs_full))
-    full_ref = None
 
     # headline: fastest scheme meeting the error bar (FP64 always qualifies)
     def qualifies(p):
@@ -297,10 +314,12 @@ def main():
             return True
         if r["errs"] is None or max(r["errs"].values()) > TOL_MIXED:
             return False
-        # where the FP64 run's outputs could be kept, every energy's diagonal blocks too
-        return r["errs_full"] is None or max(r["errs_full"].values()) <= TOL_MIXED
-    # without the oracle (--no-cpu) no mixed scheme qualifies: report the fastest one that ran
-    cands = [p for p in results if qualifies(p)] or [p for p in results if results[p]["status_ok"]] or list(results)
+        # every output block type and the observables over all energies, too
+        return r["errs_full"] is not None and max(r["errs_full"].values()) <= TOL_MIXED
+    # without the oracle (--no-cpu) or the all-energy check no mixed scheme qualifies:
+    # the line then reports the fastest scheme that ran, flagged meets_tolerance = false
+    qual = [p for p in results if qualifies(p)]
+    cands = qual or [p for p in results if results[p]["status_ok"]] or list(results)
     best = max(cands, key=lambda p: results[p]["value"])
     r = results[best]
     g_ms, g_n, g_fl = r["gemm"]
@@ -337,6 +356,7 @@ def main():
                      "flops_per_launch": g_fl / max(g_n, 1), "avg_launch_ms": g_ms / max(g_n, 1),
                      "launches": g_n},
         "cpu_baseline": cpu,
+        "meets_tolerance": best in qual,
         "p50_latency_ms": r["latency_ms"]["p50"], "p99_latency_ms": r["latency_ms"]["p99"],
         "latency": "one solve of all energies of the step, back to back (HIP events on the solve's stream)",
         "schemes": {p: {"energies_per_s": v["value"], "ms_per_step": v["ms_per_step"], "max_rel_err": v["errs"],

@@ -31,6 +31,13 @@
  *    must not be read until the stream has passed the enqueued work.
  *  - No exception crosses the ABI.  A context is not thread-safe: use one
  *    host thread per context (several contexts may coexist).
+ *  - Calls on one context share its device workspace.  A call on a different
+ *    stream than the context's previous call makes its stream wait (on the
+ *    device, without blocking the host) for the previous call's work, so calls
+ *    on several streams run one after another.  This ordering does not cover
+ *    calls made while the caller captures the stream into a graph of its own:
+ *    the caller must not let such a graph's launches overlap other calls on
+ *    the same context.
  *  - Outputs must not alias inputs.
  */
 #ifndef QTX_RGF_H
@@ -76,6 +83,10 @@ typedef enum {
  *   is clipped so that kbits <= 47 (qtx_ozaki2_bits); the error of a product is about
  *   K 2^-kbits max|row of A| max|column of B|.  Complex products use four real
  *   products (4M).  K <= 65536.
+ * Non-finite operands: in the split and INT8 schemes a row of op(A) (a column of
+ *   op(B)) that holds a NaN or an Inf makes that whole row (column) of the product
+ *   NaN, the outputs it would spoil in FP64 arithmetic, so the solver's per-energy
+ *   QTX_ERR_NONFINITE status is the same in every scheme.
  * Inversions and the G^< / G^> epilogue sums are FP64 in every mode. */
 typedef enum {
   QTX_FP64 = 0,
@@ -204,9 +215,10 @@ qtx_status qtx_rgf_solve(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int32_t 
  *                  on an internal side stream (one per block-size lane, default
  *                  priority) that forks from and joins back into the solve's
  *                  stream; value = 0 (default): everything runs on the solve's
- *                  stream.  The results are bitwise the same either way.  Solves
- *                  captured into a hipGraph (QTX_OPT_GRAPH) never use the side
- *                  stream.  Off by default: at 256 energies of b = 416 the
+ *                  stream.  The results are bitwise the same either way.  Not
+ *                  available together with QTX_OPT_GRAPH: turning either option on
+ *                  while the other is on returns QTX_ERR_UNSUPPORTED (the side
+ *                  stream is never captured).  Off by default: at 256 energies of b = 416 the
  *                  persistent product kernels occupy every CU, so the overlap only
  *                  adds contention (measured 2% slower).
  *   QTX_OPT_LANE_SPLIT  value = k in 1..8 (default 1): the energies of each group of

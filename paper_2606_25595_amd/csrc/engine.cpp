@@ -96,6 +96,9 @@ struct qtx_rgf_ctx_s {
   // split solves with a BT Sigma^< / Sigma^>: the bottom halves' upper blocks -(SL_u)^H
   void* rbt = nullptr;
   size_t rbt_size = 0;
+  // the stream of the last call that enqueued work, and the event recorded at its end
+  hipStream_t last_s = nullptr;
+  hipEvent_t last_done = nullptr;
 };
 
 namespace {
@@ -262,6 +265,60 @@ struct ProfScope {
     ctx->prof[fam].pending.push_back({a, b, flops});
   }
 };
+
+// Every call on a context uses the context's one workspace (temporaries, converted
+// operands, pointer tables).  A call on a different stream than the previous call
+// first makes its stream wait for the event recorded at the end of that call, so
+// that two calls never use the workspace at the same time.  Calls on a stream that
+// is being captured into a caller's graph are not ordered this way (the header says
+// so): the graph's launches are the caller's to order.
+struct StreamOrder {
+  qtx_rgf_ctx ctx;
+  hipStream_t s;
+  bool track = false;
+  StreamOrder(qtx_rgf_ctx c, hipStream_t st) : ctx(c), s(st) {}
+  qtx_status enter() {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s != nullptr) QTX_TRY(hipStreamIsCapturing(s, &cs));
+    track = cs == hipStreamCaptureStatusNone;
+    if (track && ctx->last_done && ctx->last_s != s) QTX_TRY(hipStreamWaitEvent(s, ctx->last_done, 0));
+    return QTX_OK;
+  }
+  // After the call's work is enqueued (also after a failed call: the event then marks
+  // whatever was enqueued).
+  qtx_status leave() {
+    if (!track) return QTX_OK;
+    if (!ctx->last_done) QTX_TRY(hipEventCreateWithFlags(&ctx->last_done, hipEventDisableTiming));
+    QTX_TRY(hipEventRecord(ctx->last_done, s));
+    ctx->last_s = s;
+    return QTX_OK;
+  }
+};
+
+// The same as a scope: leave() runs when the call returns (its status is dropped).
+struct OrderScope {
+  StreamOrder o;
+  bool entered = false;
+  OrderScope(qtx_rgf_ctx c, hipStream_t st) : o(c, st) {}
+  qtx_status enter() {
+    const qtx_status st = o.enter();
+    entered = st == QTX_OK;
+    return st;
+  }
+  ~OrderScope() {
+    if (entered) (void)o.leave();
+  }
+};
+
+// Run f() between enter() and leave() of the stream order of ctx on stream s.
+template <class F>
+qtx_status ordered(qtx_rgf_ctx ctx, hipStream_t s, F&& f) {
+  StreamOrder o(ctx, s);
+  QTX_TRYS(o.enter());
+  const qtx_status st = f();
+  const qtx_status sl = o.leave();
+  return st != QTX_OK ? st : sl;
+}
 
 // ---------------------------------------------------------------- precision schemes
 
@@ -1311,9 +1368,9 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
   }
   if (replay) return QTX_OK;
   if (n_lanes > 1) QTX_TRYS(ensure_aux(ctx, n_lanes));
-  // The side stream is used in eager solves only: a captured solve runs every
-  // product on its lane's stream (a capture that forked the side stream from a lane
-  // stream at every forward step ended in a segmentation fault inside the runtime).
+  // The side stream is used in eager solves only (QTX_OPT_OVERLAP and QTX_OPT_GRAPH
+  // exclude each other): a capture that forked the side stream from a lane stream at
+  // every forward step ended in a segmentation fault inside the runtime.
   const bool use_side = ctx->overlap && !capture;
   if (use_side) QTX_TRYS(ensure_side(ctx, n_lanes));
   if (capture) {
@@ -1487,6 +1544,9 @@ qtx_status qtx_rgf_set_option(qtx_rgf_ctx ctx, int option, int64_t value) {
   if (!ctx) return QTX_ERR_ARG;
   switch (option) {
     case QTX_OPT_GRAPH:
+      // the side-stream overlap is not captured (one capture that forked it at every
+      // forward step ended in a host fault inside the runtime): the two are exclusive
+      if (value != 0 && ctx->overlap) return QTX_ERR_UNSUPPORTED;
       ctx->use_graph = value != 0;
       return QTX_OK;
     case QTX_OPT_RESERVE_WORKSPACE: {
@@ -1495,6 +1555,7 @@ qtx_status qtx_rgf_set_option(qtx_rgf_ctx ctx, int option, int64_t value) {
       return ensure_ws(ctx, (size_t)value);
     }
     case QTX_OPT_OVERLAP:
+      if (value != 0 && ctx->use_graph) return QTX_ERR_UNSUPPORTED;
       if (ctx->overlap != (value != 0)) {
         DeviceGuard guard(ctx->device);
         (void)hipDeviceSynchronize();
@@ -1575,6 +1636,7 @@ qtx_status qtx_rgf_destroy(qtx_rgf_ctx ctx) {
     if (ctx->rbt) (void)hipFree(ctx->rbt);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->upload_done) (void)hipEventDestroy(ctx->upload_done);
+    if (ctx->last_done) (void)hipEventDestroy(ctx->last_done);
     for (auto& f : ctx->prof)
       for (auto& r : f.pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
@@ -1608,7 +1670,7 @@ qtx_status qtx_rgf_solve(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int32_t 
     if (st != QTX_OK) return st;
   }
   DeviceGuard guard(ctx->device);
-  return solve_all(ctx, probs, n_probs, (hipStream_t)hip_stream);
+  return ordered(ctx, (hipStream_t)hip_stream, [&]() { return solve_all(ctx, probs, n_probs, (hipStream_t)hip_stream); });
 }
 
 qtx_status qtx_zgemm(qtx_rgf_ctx ctx, char opA, char opB, int32_t M, int32_t N, int32_t K, double alpha_re,
@@ -1651,8 +1713,10 @@ qtx_status qtx_zgemm(qtx_rgf_ctx ctx, char opA, char opB, int32_t M, int32_t N, 
     sb.S[1] = w; w += align_up(operand_digit_bytes(N, K, sc) * batch);
     sb.E[1] = (int32_t*)w;
   }
-  QTX_TRY(run_product(ctx, d, sc, sb, (hipStream_t)hip_stream));
-  return QTX_OK;
+  return ordered(ctx, (hipStream_t)hip_stream, [&]() -> qtx_status {
+    QTX_TRY(run_product(ctx, d, sc, sb, (hipStream_t)hip_stream));
+    return QTX_OK;
+  });
 }
 
 qtx_status qtx_rgf_tune(qtx_rgf_ctx ctx, int32_t b, int32_t prec, int32_t n_slices, int32_t batch,
@@ -1756,6 +1820,8 @@ qtx_status qtx_w_assemble(qtx_rgf_ctx ctx, int32_t n_b, int32_t b, int32_t n_e, 
   if (!make_scheme(prec, n_slices, &sc)) return QTX_ERR_UNSUPPORTED;
   DeviceGuard guard(ctx->device);
   hipStream_t s = (hipStream_t)hip_stream;
+  OrderScope order(ctx, s);
+  QTX_TRYS(order.enter());
   const int64_t bb = (int64_t)b * b;
   const int64_t sd = (int64_t)n_b * bb, su = (int64_t)(n_b - 1) * bb;   // per-energy strides
   // workspace: four Y blocks per energy and the converted operands of one product
@@ -1877,6 +1943,8 @@ qtx_status qtx_zinv(qtx_rgf_ctx ctx, int32_t n, const void* A, int64_t sA, void*
   if (sA < (int64_t)n * n || sAinv < (int64_t)n * n) return QTX_ERR_ARG;
   DeviceGuard guard(ctx->device);
   hipStream_t s = (hipStream_t)hip_stream;
+  OrderScope order(ctx, s);
+  QTX_TRYS(order.enter());
   const int64_t nn = (int64_t)n * n;
   const size_t need = align_up((size_t)batch * nn * sizeof(double2)) + align_up(gje_work_bytes(n, batch)) +
                       align_up((size_t)batch * sizeof(int32_t));
@@ -1909,6 +1977,8 @@ qtx_status qtx_rgf_observables(qtx_rgf_ctx ctx, int32_t b, int32_t n_e, const vo
     return QTX_ERR_ARG;
   DeviceGuard guard(ctx->device);
   hipStream_t s = (hipStream_t)hip_stream;
+  OrderScope order(ctx, s);
+  QTX_TRYS(order.enter());
   const int64_t bb = (int64_t)b * b;
   qtx_status st = ensure_ws(ctx, 2 * align_up((size_t)n_e * bb * sizeof(double2)));
   if (st != QTX_OK) return st;

@@ -108,8 +108,14 @@ int64_t split_digit_stride(int rows, int cols, int ns);
 int64_t split_exp_stride(int rows, int cols);
 hipError_t launch_split(const SplitDesc& sd, int fmt, int ns, hipStream_t s);
 hipError_t launch_zgemm_split(const SplitGemmDesc& g, int fmt, int ns, hipStream_t s);
-// Row exponents only: E[r] with max_k |S[r][k]| 2^-E[r] in [1/4, 1/2) (0 for a zero row).
+// Row exponents only: E[r] with max_k |S[r][k]| 2^-E[r] in [1/4, 1/2) (0 for a zero row,
+// kExpNonFinite for a row holding NaN or Inf).
 hipError_t launch_split_exp(const SplitDesc& sd, hipStream_t s);
+// Exponent of an operand row (column of op(B)) that holds a NaN or an Inf.  Its digits
+// or residues are written as zeros and every product output in that row (column) is
+// NaN, so a non-finite operand element spoils the same outputs it would in FP64
+// arithmetic and the solver's finiteness check sees it.
+constexpr int kExpNonFinite = 0x40000000;
 
 // Modular (Ozaki II) INT8 products.  Moduli m_0 > m_1 > ... are odd and pairwise
 // coprime (kO2Moduli); an operand row r becomes the integer vector

@@ -75,7 +75,9 @@ __global__ __launch_bounds__(NT) void o2_residue_kernel(SplitDesc sd, O2Params P
   const int r = tid >> 2, kq = (tid & 3) * 8;
   const bool live = r0 + r < sd.rows;
   const int KT = (sd.cols + KS - 1) / KS;
-  const double sc = live ? pow2(P.kbits + 1 - sd.E[(int64_t)z * sd.e_stride + r0 + r]) : 0.0;
+  const int er = live ? sd.E[(int64_t)z * sd.e_stride + r0 + r] : 0;
+  const bool fin = er != kExpNonFinite;   // a non-finite row gets zero residues
+  const double sc = (live && fin) ? pow2(P.kbits + 1 - er) : 0.0;
   int8_t* out = (int8_t*)sd.S + (int64_t)z * sd.s_stride;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -87,8 +89,8 @@ __global__ __launch_bounds__(NT) void o2_residue_kernel(SplitDesc sd, O2Params P
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const double2 v = tile[r][kq + j];
-      a[0][j] = rint(v.x * sc);   // exact scaling, then the one rounding of the scheme
-      a[1][j] = rint(v.y * sc);
+      a[0][j] = fin ? rint(v.x * sc) : 0.0;   // exact scaling, then the one rounding of the scheme
+      a[1][j] = fin ? rint(v.y * sc) : 0.0;
     }
     for (int i = 0; i < P.p; ++i) {
       const double m = P.m[i], im = P.inv_m[i];
@@ -167,20 +169,26 @@ __global__ __launch_bounds__(64 * RB) void o2_convert_kernel(SplitDesc sd, O2Par
   {
     const int r = wave;
     double mx = 0.0;
+    bool bad = false;   // NaN or Inf in the row (fmax alone would skip a NaN)
     for (int k = lane; k < KP; k += 64) {
       const double2 v = rows_lds[r * pitch + k];   // any order: all k of the row
+      bad |= !(isfinite(v.x) && isfinite(v.y));
       mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    bad = __any(bad);
     int e = 0;
-    if (mx > 0.0 && mx <= 1.7e308) e = ilogb(mx) + 2;   // max * 2^-e in [1/4, 1/2)
+    if (bad) e = kExpNonFinite;
+    else if (mx > 0.0 && mx <= 1.7e308) e = ilogb(mx) + 2;   // max * 2^-e in [1/4, 1/2)
     if (lane == 0 && r0 + r < sd.rows) sd.E[(int64_t)z * sd.e_stride + r0 + r] = e;
   }
   __syncthreads();   // the exponents are read back below (same workgroup)
   const int r = lane / LPR, c = (lane / (LPR / 2)) & 1, ks = lane % (LPR / 2);
   const bool live = r0 + r < sd.rows;
-  const double sc = live ? pow2(P.kbits + 1 - sd.E[(int64_t)z * sd.e_stride + r0 + r]) : 0.0;
+  const int er = live ? sd.E[(int64_t)z * sd.e_stride + r0 + r] : 0;
+  const bool fin = er != kExpNonFinite;   // a non-finite row gets zero residues
+  const double sc = (live && fin) ? pow2(P.kbits + 1 - er) : 0.0;
   int8_t* out = (int8_t*)sd.S + (int64_t)z * sd.s_stride;
   for (int kt = wave; kt < KT; kt += RB) {
     double a[VPL];
@@ -189,7 +197,7 @@ __global__ __launch_bounds__(64 * RB) void o2_convert_kernel(SplitDesc sd, O2Par
 #pragma unroll
     for (int j = 0; j < VPL; ++j) {
       const double2 v = src[(k0 + j) ^ r];
-      a[j] = rint((c ? v.y : v.x) * sc);
+      a[j] = fin ? rint((c ? v.y : v.x) * sc) : 0.0;
     }
     for (int i = 0; i < P.p; ++i) {
       const double m = P.m[i], im = P.inv_m[i];
@@ -563,7 +571,9 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
     const int rl = 32 * wm + 8 * (v >> 2) + 4 * lk + (v & 3);
     const int r = m0 + rl;
     if (wlive && r < M && col < N && !(skew && r > col)) {
-      const double sc = pow2(Ea[rl] + eb - 2 * P.kbits - 2) * P.M;
+      // a row of op(A) or column of op(B) with NaN / Inf gives NaN, as in FP64
+      const bool nf = Ea[rl] == kExpNonFinite || eb == kExpNonFinite;
+      const double sc = nf ? __builtin_nan("") : pow2(Ea[rl] + eb - 2 * P.kbits - 2) * P.M;
       const double cr = (acc.sre[v] - rint(acc.sre[v])) * sc;
       const double ci = (acc.sim[v] - rint(acc.sim[v])) * sc;
       double2 out = cmul(d.alpha, cmk(cr, ci));

@@ -109,6 +109,7 @@ __global__ __launch_bounds__(NT) void split_exp_kernel(SplitDesc sd) {
   const double2* X = sd.tX ? sd.tX[z] : sd.X + (int64_t)z * sd.stride;
   const int r = tid >> 2, kq = (tid & 3) * 8;
   double mx = 0.0;
+  int bad = 0;   // NaN or Inf in the row (fmax alone would skip a NaN)
   for (int k0 = 0; k0 < sd.cols; k0 += KS) {
     __syncthreads();
     load_strip(sd, X, r0, k0, tid, tile);
@@ -116,13 +117,17 @@ __global__ __launch_bounds__(NT) void split_exp_kernel(SplitDesc sd) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const double2 v = tile[r][kq + j];
+      bad |= !(isfinite(v.x) && isfinite(v.y));
       mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
     }
   }
   mx = fmax(mx, __shfl_xor(mx, 1));
   mx = fmax(mx, __shfl_xor(mx, 2));
+  bad |= __shfl_xor(bad, 1);
+  bad |= __shfl_xor(bad, 2);
   int e = 0;
-  if (mx > 0.0 && mx <= 1.7e308) e = ilogb(mx) + 2;   // max * 2^-e in [1/4, 1/2)
+  if (bad) e = kExpNonFinite;
+  else if (mx > 0.0 && mx <= 1.7e308) e = ilogb(mx) + 2;   // max * 2^-e in [1/4, 1/2)
   if ((tid & 3) == 0 && r0 + r < sd.rows) sd.E[(int64_t)z * sd.e_stride + r0 + r] = e;
 }
 
@@ -141,12 +146,14 @@ __global__ __launch_bounds__(NT) void split_kernel(SplitDesc sd) {
   // thread -> row tid/4, k = 8 (tid%4) .. +7
   const int r = tid >> 2, kq = (tid & 3) * 8;
   if (r0 + r >= sd.rows) return;
-  const double sc = pow2(-sd.E[(int64_t)z * sd.e_stride + r0 + r]);
+  const int er = sd.E[(int64_t)z * sd.e_stride + r0 + r];
+  const bool fin = er != kExpNonFinite;   // a non-finite row gets zero digits
+  const double sc = fin ? pow2(-er) : 0.0;
   uint16_t dig[NQ][8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const double2 v = tile[r][kq + j];
-    double part[2] = {v.x * sc, v.y * sc};
+    double part[2] = {fin ? v.x * sc : 0.0, fin ? v.y * sc : 0.0};
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       double rem = part[c];
@@ -250,7 +257,9 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(SplitGemmDesc g) {
         const int eb = Eb[16 * (wn + 2 * j) + li];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const double sc = pow2(Ea[16 * (wm + 2 * i) + 4 * lk + v] + eb - 2 * W);
+          const int ea = Ea[16 * (wm + 2 * i) + 4 * lk + v];
+          // non-finite rows / columns have zero digits; their outputs are set to NaN below
+          const double sc = (ea == kExpNonFinite || eb == kExpNonFinite) ? 0.0 : pow2(ea + eb - 2 * W);
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
             const double part = ((double)acc[i][j][c][0][v] + (double)acc[i][j][c][1][v]) + (double)acc[i][j][c][2][v];
@@ -366,7 +375,9 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(SplitGemmDesc g) {
         const int r = m0 + 16 * (wm + 2 * i) + 4 * lk + v;
         const int c = n0 + 16 * (wn + 2 * j) + li;
         if (r < M && c < N) {
-          double2 out = cmul(d.alpha, cmk(sum[i][j][0][v], sum[i][j][1][v]));
+          const bool nf = Ea[16 * (wm + 2 * i) + 4 * lk + v] == kExpNonFinite || Eb[16 * (wn + 2 * j) + li] == kExpNonFinite;
+          const double nan = __builtin_nan("");
+          double2 out = nf ? cmk(nan, nan) : cmul(d.alpha, cmk(sum[i][j][0][v], sum[i][j][1][v]));
 #pragma unroll
           for (int q = 0; q < kMaxAddends; ++q) {
             if (X[q]) {

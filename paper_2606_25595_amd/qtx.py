@@ -532,14 +532,21 @@ class Context:
     # -- qtx_rgf_observables
     def observables(self, dp: DeviceProblem, gamma_L, f_L, stream=None):
         """(T_L, j_L) per energy as device float64 tensors."""
+        return self.observables_blocks(dp.GR_d, dp.GL_d, gamma_L, f_L, stream=stream)
+
+    def observables_blocks(self, GR_d, GL_d, gamma_L, f_L, stream=None):
+        """(T_L, j_L) per energy from [n_e][n_b][b][b] G^R / G^< diagonal-block tensors
+        (contiguous; only block 0 of each energy is read)."""
         import torch
-        T = torch.empty(dp.n_e, dtype=torch.float64, device=dp.GR_d.device)
+        if not (GR_d.is_contiguous() and GL_d.is_contiguous()) or GR_d.shape != GL_d.shape or GR_d.dim() != 4:
+            raise ValueError("GR_d / GL_d: contiguous [n_e][n_b][b][b] tensors of one shape")
+        n_e, n_b, b = int(GR_d.shape[0]), int(GR_d.shape[1]), int(GR_d.shape[2])
+        T = torch.empty(n_e, dtype=torch.float64, device=GR_d.device)
         j = torch.empty_like(T)
-        fL = torch.as_tensor(np.ascontiguousarray(f_L, dtype=np.float64)).to(dp.GR_d.device)
-        g = torch.as_tensor(np.ascontiguousarray(gamma_L, dtype=np.complex128)).to(dp.GR_d.device)
-        rc = self.lib.qtx_rgf_observables(self.handle, dp.b, dp.n_e, _ptr(dp.GR_d), _ptr(dp.GL_d),
-                                          dp.n_b * dp.b * dp.b, _ptr(g), _ptr(fL), _ptr(T), _ptr(j),
-                                          _stream_ptr(stream))
+        fL = torch.as_tensor(np.ascontiguousarray(f_L, dtype=np.float64)).to(GR_d.device)
+        g = torch.as_tensor(np.ascontiguousarray(gamma_L, dtype=np.complex128)).to(GR_d.device)
+        rc = self.lib.qtx_rgf_observables(self.handle, b, n_e, _ptr(GR_d), _ptr(GL_d), n_b * b * b, _ptr(g),
+                                          _ptr(fL), _ptr(T), _ptr(j), _stream_ptr(stream))
         if rc != QTX_OK:
             raise QtxError(rc, "qtx_rgf_observables")
         return T, j

@@ -157,3 +157,51 @@ def test_lane_split_bitwise_equal(ctx, prec, ns):
     finally:
         ctx.set_lane_split(1)
         ctx.set_graph(False)
+
+
+@pytest.mark.parametrize("prec,ns,tol", [("fp64", 0, 1e-10), ("int8", 10, 1e-6)])
+def test_batch_c3_block_sizes_graph(ctx, prec, ns, tol):
+    """Problems at the batching workload's block sizes (b in {128, 256, 384, 512},
+    n_b = 16, one energy each) in one call: the 64 x 64 FP64 tiles and the persistent
+    INT8 tile variants these sizes select run here.  A captured graph replays to the
+    eager bits; a problem alone equals it in the mix; two problems (the smallest and
+    the largest block) against the oracle."""
+    import torch
+    from paper_2606_25595_amd import qtx
+    rng = np.random.default_rng(77)
+    bs = [128, 256, 384, 512, 256, 128]
+    probs = [inputs.random_bt_problem(16, b, rng.uniform(-2.0, 2.0, 1), seed=2000 + q) for q, b in enumerate(bs)]
+    dps = [qtx.to_device(p) for p in probs]
+    ctx.solve(dps, prec=prec, n_slices=ns)
+    torch.cuda.synchronize()
+    eager = [dp.outputs() for dp in dps]
+    for o in eager:
+        assert np.all(o["status"] == 0)
+    for q in (0, 3):
+        ref = oracle.rgf_selected(probs[q])
+        for k in KEYS:
+            err = oracle.rel_fro_err(eager[q][k], ref[k]).max()
+            assert err <= tol, (q, k, float(err))
+    alone = qtx.to_device(probs[1])
+    ctx.solve(alone, prec=prec, n_slices=ns)
+    torch.cuda.synchronize()
+    ao = alone.outputs()
+    for k in KEYS:
+        assert np.array_equal(ao[k], eager[1][k]), k
+    stream = torch.cuda.Stream()
+    ctx.set_graph(True)
+    try:
+        for rep in range(2):
+            for dp in dps:
+                for k in KEYS:
+                    getattr(dp, k).fill_(float("nan"))
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                ctx.solve(dps, prec=prec, n_slices=ns, stream=stream)
+            stream.synchronize()
+            for dp, ref in zip(dps, eager):
+                out = dp.outputs()
+                for k in KEYS:
+                    assert np.array_equal(out[k], ref[k]), (rep, k)
+    finally:
+        ctx.set_graph(False)

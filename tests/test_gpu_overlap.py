@@ -1,7 +1,7 @@
 """Products overlapped with the forward inversions on a side stream: the outputs
 are bitwise those of the single-stream order, for several block-size lanes,
-per-chain schemes and the greater recurrence; a captured solve (which runs on the
-lane streams only) replays to the same bits."""
+per-chain schemes and the greater recurrence.  The overlap is never captured into
+a graph: the two options exclude each other."""
 import numpy as np
 import pytest
 
@@ -78,30 +78,26 @@ def test_overlap_with_greater(ctx):
             assert np.array_equal(a[k], r[k]), k
 
 
-def test_overlap_graph_replays(ctx):
-    import torch
+def test_overlap_and_graph_are_exclusive(ctx):
+    """QTX_OPT_OVERLAP and QTX_OPT_GRAPH cannot both be on (the side stream is never
+    captured): turning either on while the other is on is QTX_ERR_UNSUPPORTED and
+    leaves the options as they were."""
     from paper_2606_25595_amd import qtx
-    probs = problems(3, 6)
-    ctx.set_overlap(False)
-    _, ref = run(ctx, probs, prec="int8", n_slices=11)
     ctx.set_overlap(True)
-    stream = torch.cuda.Stream()
-    dps = [qtx.to_device(p) for p in probs]
+    try:
+        with pytest.raises(qtx.QtxError) as ei:
+            ctx.set_graph(True)
+        assert ei.value.code == qtx.QTX_ERR_UNSUPPORTED
+    finally:
+        ctx.set_overlap(False)
     ctx.set_graph(True)
     try:
-        cap0 = ctx.stat(qtx.QTX_STAT_GRAPH_CAPTURES)
-        for rep in range(3):
-            for dp in dps:
-                for k in KEYS:
-                    getattr(dp, k).fill_(float("nan"))
-            torch.cuda.synchronize()
-            with torch.cuda.stream(stream):
-                ctx.solve(dps, prec="int8", n_slices=11, stream=stream)
-            stream.synchronize()
-            for dp, r in zip(dps, ref):
-                out = dp.outputs()
-                for k in KEYS:
-                    assert np.array_equal(out[k], r[k]), (rep, k)
-        assert ctx.stat(qtx.QTX_STAT_GRAPH_CAPTURES) == cap0 + 1
+        with pytest.raises(qtx.QtxError) as ei:
+            ctx.set_overlap(True)
+        assert ei.value.code == qtx.QTX_ERR_UNSUPPORTED
+        # the graph path still solves (no side stream involved)
+        probs = problems(2, 6)
+        _, ref = run(ctx, probs, prec="int8", n_slices=11)
+        assert all(np.all(r["status"] == 0) for r in ref)
     finally:
         ctx.set_graph(False)

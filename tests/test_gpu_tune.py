@@ -149,3 +149,38 @@ def test_solve_unchanged_by_tuning():
             assert oracle.rel_fro_err(before[k], ref[k]).max() <= 1e-6
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("M,N,K,batch,ops", [(416, 416, 416, 32, "NN"), (416, 416, 416, 32, "NC"),
+                                             (128, 128, 128, 256, "NN"), (128, 128, 128, 256, "CC")])
+def test_variants_bitwise_equal_persistent_rounds(ctx, M, N, K, batch, ops):
+    """Launches with more tiles than the persistent grid holds (416^3 x 32: 1568 64 x 64
+    tiles against 768 workgroups of variant 4; 128^3 x 256: 1024), so every persistent
+    variant runs several rounds per workgroup and reuses its LDS ring, exponents and
+    accumulators between tiles.  All variants give the same bits, within the bound."""
+    import torch
+    from paper_2606_25595_amd import qtx
+    p = 10
+    rng = np.random.default_rng(M + batch + (1 if ops == "NC" else 0))
+    A = rand_c(rng, batch, *((M, K) if ops[0] == "N" else (K, M)))
+    B = rand_c(rng, batch, *((K, N) if ops[1] == "N" else (N, K)))
+    At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    outs = []
+    try:
+        for v in range(N_VARIANTS):
+            ctx.set_int8_tile_variant(v)
+            C = torch.full((batch, M, N), float("nan"), dtype=torch.complex128, device="cuda")
+            ctx.zgemm(At, Bt, C, opA=ops[0], opB=ops[1], prec="int8", n_slices=p)
+            torch.cuda.synchronize()
+            outs.append(C.cpu().numpy())
+    finally:
+        ctx.set_int8_tile_variant(-1)
+    for v in range(1, N_VARIANTS):
+        assert np.array_equal(outs[v].view(np.float64), outs[0].view(np.float64)), v
+    opa = A if ops[0] == "N" else np.conj(np.swapaxes(A, 1, 2))
+    opb = B if ops[1] == "N" else np.conj(np.swapaxes(B, 1, 2))
+    ref = opa @ opb
+    kbits = qtx.ozaki2_bits(p, K)[1]
+    bound = 8 * 2.0 ** -kbits * K * np.abs(opa).max() * np.abs(opb).max()
+    assert np.all(np.isfinite(outs[0]))
+    assert np.abs(outs[0] - ref).max() <= bound
