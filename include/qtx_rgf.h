@@ -344,6 +344,29 @@ qtx_status qtx_zgemm(qtx_rgf_ctx ctx, char opA, char opB, int32_t M, int32_t N, 
                      void* C, int64_t ldc, int64_t sC,
                      int32_t batch, int32_t prec, int32_t n_slices, void* hip_stream);
 
+/* qtx_zgemm for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same product,
+ * arguments, kernels and results as qtx_zgemm (bitwise), but the split and INT8 schemes
+ * convert their operands into a fixed device buffer of QTX_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) per GPU instead of the context's workspace.  That buffer exists once per GPU
+ * from the library's load until the process ends; the call itself allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine, no timer events).  Limit: the
+ * converted operands must fit, about batch * 2 p (M + N) K bytes for p INT8 moduli and
+ * batch * 4 n_slices (M + N) K for the split schemes (an operand with batch stride 0
+ * counts once); larger calls return QTX_ERR_ARG with nothing enqueued.  FP64 / FP32
+ * products use no scratch.  Every call on one GPU uses the same buffer: two calls whose
+ * work overlaps on the device (different streams, or different contexts on that GPU)
+ * race and give wrong results; calls on one stream are ordered.  Not ordered against
+ * the context's other calls (it does not use the context's workspace). */
+#define QTX_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+qtx_status qtx_zgemm_noalloc(qtx_rgf_ctx ctx, char opA, char opB, int32_t M, int32_t N, int32_t K,
+                             double alpha_re, double alpha_im,
+                             const void* A, int64_t lda, int64_t sA,
+                             const void* B, int64_t ldb, int64_t sB,
+                             double beta_re, double beta_im,
+                             void* C, int64_t ldc, int64_t sC,
+                             int32_t batch, int32_t prec, int32_t n_slices, void* hip_stream);
+
 /* Batched inverse of n x n complex matrices by Gauss-Jordan elimination with
  * partial pivoting (pivot = largest |re|+|im| among the rows not yet used,
  * lowest row on ties), FP64 throughout.  A: [batch] matrices with stride sA

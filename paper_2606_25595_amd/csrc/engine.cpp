@@ -35,6 +35,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -134,6 +135,44 @@ struct DeviceGuard {
     if (prev >= 0) (void)hipSetDevice(prev);
   }
 };
+
+}  // namespace
+
+// ---------------------------------------------------------------- fixed scratch of qtx_zgemm_noalloc
+// The converted operands (digits or residues, and exponents) of qtx_zgemm_noalloc live in
+// this fixed device array instead of the context's workspace: one copy per GPU, created by
+// the runtime when the library's code object is loaded on that GPU and held until the
+// process ends.  On the host the name is only a stand-in, never a device address: the
+// address of each GPU's copy is looked up once per device (noalloc_scratch, first from
+// qtx_rgf_create) and that address is what the kernels receive.  Nothing in it needs to
+// start at zero: a conversion writes every byte the product kernel then reads.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, looked up with that device current on the first
+// call for the device and kept.
+qtx_status noalloc_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return QTX_ERR_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    DeviceGuard guard(device);
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return QTX_ERR_HIP;
+    }
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return QTX_OK;
+}
 
 void drop_graphs(qtx_rgf_ctx ctx) {
   for (auto& g : ctx->graphs)
@@ -1536,6 +1575,8 @@ qtx_status qtx_rgf_create(qtx_rgf_ctx* out, int device, size_t workspace_bytes, 
   ctx->ws_cap = workspace_bytes;
   if (tune_cache_path) ctx->tune_path = tune_cache_path;
   tune_load(ctx);
+  void* scr = nullptr;
+  (void)noalloc_scratch(device, &scr);   // set-up of qtx_zgemm_noalloc (it retries and reports a failure)
   *out = ctx;
   return QTX_OK;
 }
@@ -1717,6 +1758,59 @@ qtx_status qtx_zgemm(qtx_rgf_ctx ctx, char opA, char opB, int32_t M, int32_t N, 
     QTX_TRY(run_product(ctx, d, sc, sb, (hipStream_t)hip_stream));
     return QTX_OK;
   });
+}
+
+qtx_status qtx_zgemm_noalloc(qtx_rgf_ctx ctx, char opA, char opB, int32_t M, int32_t N, int32_t K,
+                             double alpha_re, double alpha_im, const void* A, int64_t lda, int64_t sA, const void* B,
+                             int64_t ldb, int64_t sB, double beta_re, double beta_im, void* C, int64_t ldc, int64_t sC,
+                             int32_t batch, int32_t prec, int32_t n_slices, void* hip_stream) {
+  if (!ctx) return QTX_ERR_ARG;
+  if (ctx->sticky != QTX_OK) return ctx->sticky;
+  if ((opA != 'N' && opA != 'C') || (opB != 'N' && opB != 'C')) return QTX_ERR_ARG;
+  if (M < 0 || N < 0 || K < 0 || batch < 1 || !C || ldc < N) return QTX_ERR_ARG;
+  if (K > 0 && (!A || !B)) return QTX_ERR_ARG;
+  if (K > 0 && (lda < (opA == 'N' ? K : M) || ldb < (opB == 'N' ? N : K))) return QTX_ERR_ARG;
+  Scheme sc;
+  if (!make_scheme(prec, n_slices, &sc)) return QTX_ERR_UNSUPPORTED;
+  if (sc.o2() && K > 0) {
+    O2Params P;
+    if (!o2_params(sc.ns, K, &P)) return QTX_ERR_UNSUPPORTED;
+  }
+  DeviceGuard guard(ctx->device);
+  GemmDesc d;
+  d.M = M; d.N = N; d.K = K;
+  d.opA = opA == 'N' ? OP_N : OP_C;
+  d.opB = opB == 'N' ? OP_N : OP_C;
+  d.A = (const double2*)A; d.lda = lda; d.sA = sA;
+  d.B = (const double2*)B; d.ldb = ldb; d.sB = sB;
+  d.C = (double2*)C; d.ldc = ldc; d.sC = sC;
+  d.alpha = cmk(alpha_re, alpha_im);
+  if (beta_re != 0.0 || beta_im != 0.0) {
+    d.add[0].X = (const double2*)C; d.add[0].ld = ldc; d.add[0].stride = sC; d.add[0].coef = cmk(beta_re, beta_im);
+  }
+  d.batch = batch;
+  SplitBufs sb;
+  if (sc.sliced() && K > 0) {
+    // converted operands in the fixed scratch: an operand shared by the batch (stride 0)
+    // is converted once, as in qtx_zgemm
+    const int ba = sA == 0 ? 1 : batch, bbn = sB == 0 ? 1 : batch;
+    const size_t need = operand_bytes(M, K, sc, ba) + operand_bytes(N, K, sc, bbn);
+    if (need > kNoAllocScratchBytes) return QTX_ERR_ARG;
+    void* base = nullptr;
+    QTX_TRYS(noalloc_scratch(ctx->device, &base));
+    char* w = (char*)base;
+    sb.S[0] = w; w += align_up(operand_digit_bytes(M, K, sc) * ba);
+    sb.E[0] = (int32_t*)w; w += align_up((size_t)split_exp_stride(M, K) * 4 * ba);
+    sb.S[1] = w; w += align_up(operand_digit_bytes(N, K, sc) * bbn);
+    sb.E[1] = (int32_t*)w;
+  }
+  // no per-launch timer events here (creating one could allocate)
+  const bool prof = ctx->profiling;
+  ctx->profiling = false;
+  const hipError_t e = run_product(ctx, d, sc, sb, (hipStream_t)hip_stream);
+  ctx->profiling = prof;
+  QTX_TRY(e);
+  return QTX_OK;
 }
 
 qtx_status qtx_rgf_tune(qtx_rgf_ctx ctx, int32_t b, int32_t prec, int32_t n_slices, int32_t batch,

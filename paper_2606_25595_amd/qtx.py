@@ -7,7 +7,7 @@ mirror the C ABI in include/qtx_rgf.h:
   Context                  qtx_rgf_create / qtx_rgf_destroy
   Context.solve            qtx_rgf_solve
   Context.footprint        qtx_rgf_footprint
-  Context.zgemm            qtx_zgemm
+  Context.zgemm            qtx_zgemm (noalloc=True: qtx_zgemm_noalloc)
   Context.zinv             qtx_zinv
   Context.observables      qtx_rgf_observables
 
@@ -36,7 +36,7 @@ PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16"
 EXPORTED = ("qtx_rgf_create", "qtx_rgf_solve", "qtx_rgf_destroy", "qtx_rgf_footprint", "qtx_status_str",
             "qtx_zgemm", "qtx_zinv", "qtx_rgf_observables", "qtx_rgf_profile", "qtx_rgf_profile_read",
             "qtx_rgf_set_option", "qtx_rgf_get_stat", "qtx_ozaki2_bits", "qtx_rgf_tune", "qtx_w_assemble",
-            "qtx_fpx_encode", "qtx_fpx_decode")
+            "qtx_fpx_encode", "qtx_fpx_decode", "qtx_zgemm_noalloc")
 QTX_OPT_GRAPH, QTX_OPT_RESERVE_WORKSPACE, QTX_OPT_INT8_TILE_VARIANT, QTX_OPT_OVERLAP, QTX_OPT_LANE_SPLIT = 1, 2, 3, 4, 5
 QTX_STAT_GRAPH_LAUNCHES, QTX_STAT_GRAPH_CAPTURES, QTX_STAT_WORKSPACE_BYTES, QTX_STAT_TUNE_RECORDS = 1, 2, 3, 4
 QTX_KERNEL_GEMM, QTX_KERNEL_INV, QTX_KERNEL_CONVERT = 0, 1, 2
@@ -92,6 +92,8 @@ def load_library(path: str = LIB_PATH):
     lib.qtx_zgemm.argtypes = [vp, ctypes.c_char, ctypes.c_char, i32, i32, i32, dbl, dbl, vp, i64, i64, vp, i64, i64,
                               dbl, dbl, vp, i64, i64, i32, i32, i32, vp]
     lib.qtx_zgemm.restype = ctypes.c_int
+    lib.qtx_zgemm_noalloc.argtypes = lib.qtx_zgemm.argtypes
+    lib.qtx_zgemm_noalloc.restype = ctypes.c_int
     lib.qtx_zinv.argtypes = [vp, i32, vp, i64, vp, i64, i32, vp, vp]
     lib.qtx_zinv.restype = ctypes.c_int
     lib.qtx_rgf_observables.argtypes = [vp, i32, i32, vp, vp, i64, vp, vp, vp, vp, vp]
@@ -435,8 +437,9 @@ class Context:
 
     # -- qtx_zgemm:  C = alpha op(A) op(B) + beta C  over a batch
     def zgemm(self, A, B, C, opA="N", opB="N", alpha=1.0, beta=0.0, prec="fp64", n_slices=0, stream=None,
-              check=True):
-        """A, B, C: complex128 tensors [batch][rows][cols] (or 2-D, batch 1)."""
+              check=True, noalloc=False):
+        """A, B, C: complex128 tensors [batch][rows][cols] (or 2-D, batch 1).
+        noalloc: call qtx_zgemm_noalloc (fixed per-GPU scratch, no allocation)."""
         def as3(t):
             return t if t.dim() == 3 else t.unsqueeze(0)
         A3, B3, C3 = as3(A), as3(B), as3(C)
@@ -446,12 +449,13 @@ class Context:
         sA = A3.shape[1] * A3.shape[2] if A3.shape[0] > 1 else 0
         sB = B3.shape[1] * B3.shape[2] if B3.shape[0] > 1 else 0
         alpha, beta = complex(alpha), complex(beta)
-        rc = self.lib.qtx_zgemm(self.handle, opA.encode(), opB.encode(), M, N, K, alpha.real, alpha.imag,
-                                _ptr(A3), A3.shape[2], sA, _ptr(B3), B3.shape[2], sB, beta.real, beta.imag,
-                                _ptr(C3), C3.shape[2], M * N, batch, PREC_NAMES.get(prec, prec), n_slices,
-                                _stream_ptr(stream))
+        fn = self.lib.qtx_zgemm_noalloc if noalloc else self.lib.qtx_zgemm
+        rc = fn(self.handle, opA.encode(), opB.encode(), M, N, K, alpha.real, alpha.imag,
+                _ptr(A3), A3.shape[2], sA, _ptr(B3), B3.shape[2], sB, beta.real, beta.imag,
+                _ptr(C3), C3.shape[2], M * N, batch, PREC_NAMES.get(prec, prec), n_slices,
+                _stream_ptr(stream))
         if check and rc != QTX_OK:
-            raise QtxError(rc, "qtx_zgemm")
+            raise QtxError(rc, "qtx_zgemm_noalloc" if noalloc else "qtx_zgemm")
         return rc
 
     # -- qtx_zinv
