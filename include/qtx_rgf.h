@@ -244,10 +244,10 @@ qtx_status qtx_rgf_get_stat(qtx_rgf_ctx ctx, int stat, int64_t* value);
  * take the recorded variant, from the record of the nearest batch class; cached
  * hipGraphs are dropped.  The table is written to
  * the context's tune_cache_path when one was given (QTX_ERR_ARG if that write
- * fails; the record is kept).  Only the INT8 scheme has variants (8: a 128 x 64
- * tile with one workgroup per CU, 64 x 64 tiles with two or three per CU, each
- * either in persistent workgroups or one tile per workgroup, and 32 x 64 tiles
- * with six per CU); for
+ * fails; the record is kept).  Only the INT8 scheme has variants (14: tiles of
+ * 32 x 64 to 128 x 128 with one or two 32 x 32 blocks per wave, one to six
+ * workgroups per CU, LDS rings of two to four stages, each either in persistent
+ * workgroups or one tile per workgroup); for
  * the other schemes nothing is timed, *out_count = 1 and *out_variant = 0.
  *   out_variant  chosen variant (nullable)
  *   out_ms       ms per product (operand conversion included) of each variant,

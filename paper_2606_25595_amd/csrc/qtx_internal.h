@@ -139,7 +139,7 @@ int64_t o2_res_stride(int rows, int cols, int p);           // bytes of residues
 hipError_t launch_o2_convert(const SplitDesc& sd, const O2Params& P, hipStream_t s);
 // Tile variants of the INT8 product kernel (bitwise the same results; they differ
 // in tile height, threads, LDS ring shape and workgroups per CU).
-constexpr int kO2Variants = 8;
+constexpr int kO2Variants = 14;
 int o2_variant_count();
 hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_t s, int variant);
 

@@ -254,71 +254,88 @@ __device__ inline void crt_fold(int c, double m, double im, double u, double& S)
   S = fma(r, im, S);
 }
 
-// BM x 64 complex output tile per workgroup of NT = 4 BM threads; wave w owns the
-// 32 x 32 block (w % (BM / 32), w / (BM / 32)).  MFMA 32x32x32 i8 layouts: operand lane l
-// holds row (column) l % 32 and k = 16 (l / 32) .. +15 of a 32-k step; result
-// lane l, element v -> row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
+// BM x BN complex output tile per workgroup; each wave owns WM x WN blocks of 32 x 32
+// (rows 32 (WM wm + i), columns 32 (WN wn + j) of the tile, wave w = wm + WAVES_M wn), so
+// one A fragment feeds WN products and one B fragment WM.  MFMA 32x32x32 i8 layouts:
+// operand lane l holds row (column) l % 32 and k = 16 (l / 32) .. +15 of a 32-k step;
+// result lane l, element v -> row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
 //
 // The (modulus, strip) tiles, modulus-major, stream through an NSTAGE-deep LDS
 // ring filled by direct global->LDS loads (no registers held for them), so
 // NSTAGE - 1 steps of SPI strips are in flight while one feeds the matrix
-// cores.  A stage holds SPI strips, each the BM A rows then the 64 B rows, 128 bytes each (two
-// planes x 64 k); the 16-byte slot s of row r sits at slot s ^ (r % 8), which keeps
-// the fragment reads (32 rows, one slot) free of bank conflicts.  Each thread
+// cores.  A stage holds SPI strips, each the BM A rows then the BN B rows, 128 bytes each
+// (two planes x 64 k); the 16-byte slot s of row r sits at slot s ^ ((r / 2) % 8).  The
+// LDS of gfx950 has 64 banks and serves a 16-byte-per-lane read 16 lanes per cycle; row r
+// covers banks 32 (r % 2) .. +31, so the 16 consecutive rows one cycle of a fragment read
+// touches (one slot each) fall into 16 distinct groups of four banks.  Each thread
 // issues exactly LPT loads per strip, so "strip j has landed" is a fixed count
 // of outstanding vector-memory operations.  Rows beyond M (N) load row M - 1
 // (N - 1): they only feed outputs that are never stored.
 //
 // Tile variants (the launch takes one by index; all give bitwise the same result,
 // since every output's INT32 sums and CRT fold run in the same order):
-//   0: BM = 128, 512 threads, 2 strips per step, 3 stages (144 KB of LDS, one
-//      workgroup per CU)
-//   1: BM = 64, 256 threads, 2 strips per step, 2 stages (64 KB, two per CU)
-//   2: BM = 64, 256 threads, 1 strip per step, 3 stages (48 KB, two per CU)
+//   0: 128 x 64, one block per wave, 512 threads, 2 strips per step, 3 stages
+//      (144 KB of LDS, one workgroup per CU)
+//   1: 64 x 64, one block per wave, 256 threads, 2 strips per step, 2 stages (64 KB,
+//      two per CU)
+//   2: 64 x 64, 256 threads, 1 strip per step, 3 stages (48 KB, two per CU)
 //   3: as 2, three per CU (registers capped at 168 per lane; some spill)
-//   4: BM = 64, 256 threads, 1 strip per step, 2 stages (32 KB, three per CU)
+//   4: 64 x 64, 256 threads, 1 strip per step, 2 stages (32 KB, three per CU)
 //   5, 6: variants 4 and 1 with one tile per workgroup instead of persistent
 //      workgroups (the hardware then keeps a window of consecutive tiles -- the
 //      same energies on one XCD -- in flight, in place of rounds that drift apart)
-//   7: BM = 32, 128 threads (two waves), 1 strip per step, 2 stages (24 KB, six per
-//      CU): 32 x 64 tiles, which cover b = 416 (13 x 32) without padding rows and
-//      give twice the workgroups of a 64 x 64 tiling, for about 1.4x the operand
-//      strips per output
-constexpr int O2_BN = 64;
+//   7: 32 x 64, 128 threads (two waves), 1 strip per step, 2 stages (24 KB, six per
+//      CU): covers b = 416 (13 x 32) without padding rows and gives twice the
+//      workgroups of a 64 x 64 tiling, for about 1.4x the operand strips per output
+//   8: 64 x 64, two blocks (64 x 32) per wave, 128 threads, 2 stages (32 KB, four per
+//      CU): a quarter fewer fragment reads per product than one block per wave
+//   9: 64 x 128, two blocks (32 x 64) per wave, 256 threads, 3 stages (72 KB, two per CU):
+//      a quarter fewer operand bytes per product than 64 x 64
+//  10: 128 x 128, two blocks (64 x 32) per wave, 512 threads, 2 stages (64 KB, one per
+//      CU, two waves per SIMD): half the operand bytes per product of 64 x 64
+//  11: variant 8 with one tile per workgroup
+//  12: 64 x 64, one block per wave, 256 threads, 4 stages (64 KB, two per CU); 13: the
+//      same, one tile per workgroup
 constexpr int kBufWord3 = 0x00020000;           // buffer descriptor word 3: raw 32-bit data, no swizzle
 
-template <int BM_, int NT_, int SPI_, int NSTAGE_, int WPC_>
+template <int BM_, int BN_, int WM_, int WN_, int SPI_, int NSTAGE_, int WPC_>
 struct O2Cfg {
-  static constexpr int BM = BM_, NT = NT_, SPI = SPI_, NSTAGE = NSTAGE_;
-  static constexpr int STRIP_U4 = (BM + O2_BN) * 8;   // 16-byte slots per strip
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, SPI = SPI_, NSTAGE = NSTAGE_;
+  static constexpr int WAVES_M = BM / (32 * WM), WAVES_N = BN / (32 * WN);
+  static constexpr int NT = 64 * WAVES_M * WAVES_N;
+  static constexpr int STRIP_U4 = (BM + BN) * 8;      // 16-byte slots per strip
   static constexpr int STAGE_U4 = SPI * STRIP_U4;     // per stage
   static constexpr int LPS = STRIP_U4 / NT;           // copies per thread per strip
   static constexpr int LPS_A = BM * 8 / NT;           // of which the first LPS_A copy A rows
   static constexpr int LPT = SPI * LPS;               // copies per thread per step
   static constexpr int WPC = WPC_;                    // workgroups per CU (LDS / registers)
-  static constexpr int WAVES_PER_SIMD = WPC * NT / 256;
-  static constexpr bool TWO_ACC = WPC >= 3;            // O2Acc layout
-  static_assert(NT == 4 * BM && (BM == 32 || BM == 64 || BM == 128), "tile shape");   // one wave per 32 x 32 block
+  static constexpr int WAVES_PER_SIMD = (WPC * NT / 256) > 0 ? WPC * NT / 256 : 1;
+  static constexpr bool TWO_ACC = WPC * NT >= 768 || WM * WN > 1;   // O2Acc layout
+  static_assert(BM % (32 * WM) == 0 && BN % (32 * WN) == 0, "wave blocks");
   static_assert(STRIP_U4 % NT == 0 && (BM * 8) % NT == 0, "copy split");
-  static_assert(NSTAGE == 2 || NSTAGE == 3, "ring depth");
+  static_assert(NSTAGE >= 2 && NSTAGE <= 4, "ring depth");
   static_assert(LPT < 64, "vmcnt range");
-  static_assert(NT >= BM + O2_BN && NT >= 16, "exponent and constant fills");
+  static_assert(NT >= BM + BN && NT >= 16, "exponent and constant fills");
 };
-typedef O2Cfg<128, 512, 2, 3, 1> O2V0;
-typedef O2Cfg<64, 256, 2, 2, 2> O2V1;
-typedef O2Cfg<64, 256, 1, 3, 2> O2V2;
-typedef O2Cfg<64, 256, 1, 3, 3> O2V3;
-typedef O2Cfg<64, 256, 1, 2, 3> O2V4;
-typedef O2Cfg<32, 128, 1, 2, 6> O2V7;
+typedef O2Cfg<128, 64, 1, 1, 2, 3, 1> O2V0;
+typedef O2Cfg<64, 64, 1, 1, 2, 2, 2> O2V1;
+typedef O2Cfg<64, 64, 1, 1, 1, 3, 2> O2V2;
+typedef O2Cfg<64, 64, 1, 1, 1, 3, 3> O2V3;
+typedef O2Cfg<64, 64, 1, 1, 1, 2, 3> O2V4;
+typedef O2Cfg<32, 64, 1, 1, 1, 2, 6> O2V7;
+typedef O2Cfg<64, 64, 2, 1, 1, 2, 4> O2V8;
+typedef O2Cfg<64, 128, 1, 2, 1, 3, 2> O2V9;
+typedef O2Cfg<128, 128, 2, 1, 1, 2, 1> O2V10;
+typedef O2Cfg<64, 64, 1, 1, 1, 4, 2> O2V12;
 
 typedef __attribute__((address_space(3))) u4 lds_u4;
 typedef __attribute__((address_space(3))) double lds_f64;
 
-// Accumulators of one wave's 32 x 32 output block.  INT32 sums of the current modulus:
+// Accumulators of one 32 x 32 output block.  INT32 sums of the current modulus:
 // with TWO, re = rr - ii in one accumulator (the imaginary B fragment negated in
-// registers, 16 fewer VGPRs: the variants with three workgroups per CU, whose registers
-// are capped, then spill less) and im = ri + ir; else rr, ii and ri + ir apart (no
-// negation work).  The INT32 sums, and so the results, are the same either way.
+// registers: 16 fewer VGPRs per block, which the register-capped variants need) and
+// im = ri + ir; else rr, ii and ri + ir apart (no negation work).  The INT32 sums, and
+// so the results, are the same either way.
 template <bool TWO>
 struct O2Acc;
 template <>
@@ -328,16 +345,17 @@ struct O2Acc<true> {
   __device__ inline void clear(int v) { are[v] = 0; aim[v] = 0; }
   __device__ inline int re(int v) const { return are[v]; }
   __device__ inline int im(int v) const { return aim[v]; }
-  __device__ inline void step(i4 ar, i4 ai, i4 br, i4 bi) {
+  // bn = the imaginary B fragment negated
+  __device__ inline void step(i4 ar, i4 ai, i4 br, i4 bi, i4 bn) {
     are = mfma_i8(ar, br, are);
     aim = mfma_i8(ar, bi, aim);
-    are = mfma_i8(ai, neg_i8x16(bi), are);
+    are = mfma_i8(ai, bn, are);
     aim = mfma_i8(ai, br, aim);
   }
   // the same with B conjugated (bi -> -bi): the negation moves to the other product
-  __device__ inline void step_conj(i4 ar, i4 ai, i4 br, i4 bi) {
+  __device__ inline void step_conj(i4 ar, i4 ai, i4 br, i4 bi, i4 bn) {
     are = mfma_i8(ar, br, are);
-    aim = mfma_i8(ar, neg_i8x16(bi), aim);
+    aim = mfma_i8(ar, bn, aim);
     are = mfma_i8(ai, bi, are);
     aim = mfma_i8(ai, br, aim);
   }
@@ -349,23 +367,24 @@ struct O2Acc<false> {
   __device__ inline void clear(int v) { arr[v] = 0; aii[v] = 0; ari[v] = 0; }
   __device__ inline int re(int v) const { return arr[v] - aii[v]; }
   __device__ inline int im(int v) const { return ari[v]; }
-  __device__ inline void step(i4 ar, i4 ai, i4 br, i4 bi) {
+  __device__ inline void step(i4 ar, i4 ai, i4 br, i4 bi, i4) {
     arr = mfma_i8(ar, br, arr);
     aii = mfma_i8(ai, bi, aii);
     ari = mfma_i8(ar, bi, ari);
     ari = mfma_i8(ai, br, ari);
   }
-  __device__ inline void step_conj(i4 ar, i4 ai, i4 br, i4 bi) { step(ar, ai, br, neg_i8x16(bi)); }
+  __device__ inline void step_conj(i4 ar, i4 ai, i4 br, i4 bi, i4 bn) { step(ar, ai, br, bn, bi); }
 };
 
 // Per-thread constants of the strip loop.
-template <int LPS>
+template <int LPS, int WM, int WN>
 struct O2Ctx {
   int off[LPS];              // byte offset (in A's or B's residues) of each of the thread's slots of a strip
   int sstride_a, sstride_b;  // bytes from one strip to the next (residue offsets are < 2^31)
   const lds_f64* cst;        // moduli, their reciprocals, the CRT factors u (LDS)
-  int tid, la, lb, lk, KT, K, NSTRIP;
-  bool wlive;
+  int tid, la[WM], lb[WN], lk, KT, K, NSTRIP;
+  bool live[WM][WN];         // the wave's 32 x 32 blocks that hold outputs (wave-uniform)
+  bool wlive;                // any of them
 };
 
 __device__ inline void lds_barrier() {
@@ -392,22 +411,31 @@ __device__ inline void wait_vm() {
 // later steps in flight during the reads; their completion is awaited
 // explicitly.  Every thread issues exactly LPT copies per step (a step past the
 // last strip re-copies that strip into its unused part), so "step s landed" is a
-// fixed count of outstanding vector-memory operations: with 3 stages step s + 1
-// may still be in flight, with 2 nothing else is.
+// fixed count of outstanding vector-memory operations: with NSTAGE stages steps
+// s + 1 .. s + NSTAGE - 2 may still be in flight.
+// (fi, fkt): modulus and strip of the next strip this step consumes (advanced here).
 template <class CF, bool CONJB>
 __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u4* __restrict__ rd,
                                                             lds_u4* __restrict__ dma, const int8_t* __restrict__ gA,
                                                             const int8_t* __restrict__ gB,
-                                                            const O2Ctx<CF::LPS>& c, O2Acc<CF::TWO_ACC>& a) {
-  constexpr int SPI = CF::SPI, NSTAGE = CF::NSTAGE, LPS = CF::LPS, LPT = CF::LPT;
+                                                            const O2Ctx<CF::LPS, CF::WM, CF::WN>& c,
+                                                            O2Acc<CF::TWO_ACC> (&a)[CF::WM][CF::WN], int& fi,
+                                                            int& fkt) {
+  constexpr int SPI = CF::SPI, NSTAGE = CF::NSTAGE, LPS = CF::LPS, LPT = CF::LPT, WM = CF::WM, WN = CF::WN;
   const int nstep = (c.NSTRIP + SPI - 1) / SPI;
   if (s >= 0) {
-    if (NSTAGE == 3 && s + 1 < nstep) wait_vm<LPT>();   // step s + 1 may still be pending
+    // steps s + 1 .. s + NSTAGE - 2 (those that exist) may still be pending
+    const int pend = min(NSTAGE - 2, nstep - 1 - s);
+    if (NSTAGE >= 4 && pend >= 2) wait_vm<(NSTAGE >= 4 ? 2 : 0) * LPT>();
+    else if (NSTAGE >= 3 && pend >= 1) wait_vm<LPT>();
     else wait_vm<0>();
   }
   lds_barrier();
   const int sd = s + NSTAGE - 1;   // >= 0
   if (sd < nstep) {
+    // (the resources are made here from the restrict pointers: built once per tile
+    // instead, the copies lose their alias scope and the compiler drains them before
+    // every fragment read)
     const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void*)gA, 0, 0x7fffffff, kBufWord3);
     const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc((void*)gB, 0, 0x7fffffff, kBufWord3);
 #pragma unroll
@@ -424,37 +452,68 @@ __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u
   for (int h = 0; h < SPI; ++h) {
     const int f = SPI * s + h;
     if (f >= c.NSTRIP) break;
-    const int i = f / c.KT;
-    const int kt = f - i * c.KT;
-    if (c.wlive) {
-      const lds_u4* st = rd + h * CF::STRIP_U4;
-      const int sa = c.la & 7, sb = c.lb & 7;
-      i4 fr[8];
+    const int i = fi;
+    const int kt = fkt;
+    if (++fkt == c.KT) { fkt = 0; ++fi; }
+    const lds_u4* st = rd + h * CF::STRIP_U4;
+    const bool two = !(kt == c.KT - 1 && c.K - kt * KS <= 32);   // a half strip at the end has one step
+    // A wave with no output in the tile skips the strip.  The blocks of a wave with
+    // several run unconditionally (a block past the matrix edge computes on the
+    // clamped rows and is never stored): branches per block cost more registers than
+    // the idle products at the edges.
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int w = 2 * t + c.lk;
-        fr[4 * t + 0] = __builtin_bit_cast(i4, st[c.la * 8 + (w ^ sa)]);
-        fr[4 * t + 1] = __builtin_bit_cast(i4, st[c.la * 8 + ((4 + w) ^ sa)]);
-        fr[4 * t + 2] = __builtin_bit_cast(i4, st[c.lb * 8 + (w ^ sb)]);
-        fr[4 * t + 3] = __builtin_bit_cast(i4, st[c.lb * 8 + ((4 + w) ^ sb)]);
+    for (int t = 0; t < 2; ++t) {
+      if (t == 1 && !two) break;
+      if (!c.wlive) break;
+      const int w = 2 * t + c.lk;
+      i4 far_[WM], fai[WM], fbr[WN], fbi[WN], fbn[WN];
+#pragma unroll
+      for (int x = 0; x < WM; ++x) {
+        const int sa = (c.la[x] >> 1) & 7;
+        far_[x] = __builtin_bit_cast(i4, st[c.la[x] * 8 + (w ^ sa)]);
+        fai[x] = __builtin_bit_cast(i4, st[c.la[x] * 8 + ((4 + w) ^ sa)]);
       }
-      if (CONJB) a.step_conj(fr[0], fr[1], fr[2], fr[3]);
-      else a.step(fr[0], fr[1], fr[2], fr[3]);
-      if (!(kt == c.KT - 1 && c.K - kt * KS <= 32)) {   // a half strip at the end has one step
-        if (CONJB) a.step_conj(fr[4], fr[5], fr[6], fr[7]);
-        else a.step(fr[4], fr[5], fr[6], fr[7]);
+#pragma unroll
+      for (int y = 0; y < WN; ++y) {
+        const int sb = (c.lb[y] >> 1) & 7;
+        fbr[y] = __builtin_bit_cast(i4, st[c.lb[y] * 8 + (w ^ sb)]);
+        fbi[y] = __builtin_bit_cast(i4, st[c.lb[y] * 8 + ((4 + w) ^ sb)]);
+        fbn[y] = (CF::TWO_ACC || CONJB) ? neg_i8x16(fbi[y]) : fbi[y];
       }
+#pragma unroll
+      for (int x = 0; x < WM; ++x)
+#pragma unroll
+        for (int y = 0; y < WN; ++y) {
+          if (CONJB) a[x][y].step_conj(far_[x], fai[x], fbr[y], fbi[y], fbn[y]);
+          else a[x][y].step(far_[x], fai[x], fbr[y], fbi[y], fbn[y]);
+        }
     }
     if (kt == c.KT - 1) {
       const double m = c.cst[i], im = c.cst[kO2MaxModuli + i], u = c.cst[2 * kO2MaxModuli + i];
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        crt_fold(a.re(v), m, im, u, a.sre[v]);
-        crt_fold(a.im(v), m, im, u, a.sim[v]);
-        a.clear(v);
-      }
+      for (int x = 0; x < WM; ++x)
+#pragma unroll
+        for (int y = 0; y < WN; ++y)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            crt_fold(a[x][y].re(v), m, im, u, a[x][y].sre[v]);
+            crt_fold(a[x][y].im(v), m, im, u, a[x][y].sim[v]);
+            a[x][y].clear(v);
+          }
     }
   }
+}
+
+// The product descriptor as the kernel's first argument in the kernel-argument segment,
+// through a pointer laundered by an empty asm: loads through it cannot be hoisted above
+// the call site (the strip loop's barriers order it), so the epilogue's parameters are
+// read where they are used.
+typedef const __attribute__((address_space(4))) SplitGemmDesc KSplitGemmDesc;
+typedef const __attribute__((address_space(4))) GemmDesc KGemmDesc;
+__device__ inline KGemmDesc& kernarg_desc() {
+  uint64_t v = (uint64_t)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(v));
+  return ((KSplitGemmDesc*)v)->d;
 }
 
 // Persistent grid (persist = 1): WPC workgroups per CU; workgroup w runs on XCD
@@ -464,11 +523,11 @@ __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u
 // Otherwise one tile per workgroup.
 template <class CF, bool CONJB>
 __global__ __launch_bounds__(CF::NT) __attribute__((amdgpu_waves_per_eu(CF::WAVES_PER_SIMD)))
-void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
-                                                          int persist) {
-  constexpr int O2_BM = CF::BM, O2_NT = CF::NT, NSTAGE = CF::NSTAGE, SPI = CF::SPI, LPS = CF::LPS;
+void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles, int persist) {
+  constexpr int BM = CF::BM, BN = CF::BN, NT = CF::NT, NSTAGE = CF::NSTAGE, SPI = CF::SPI, LPS = CF::LPS;
+  constexpr int WM = CF::WM, WN = CF::WN;
   __shared__ u4 ring[NSTAGE][CF::STAGE_U4];
-  __shared__ int Ea[O2_BM], Eb[O2_BN];
+  __shared__ int Ea[BM], Eb[BN];
   __shared__ double cst[3 * kO2MaxModuli];
 
   if (threadIdx.x < kO2MaxModuli) {
@@ -476,9 +535,8 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
     cst[kO2MaxModuli + threadIdx.x] = P.inv_m[threadIdx.x];
     cst[2 * kO2MaxModuli + threadIdx.x] = P.u[threadIdx.x];
   }
-  const GemmDesc& d = g.d;
-  const int tiles_m = (d.M + O2_BM - 1) / O2_BM;
-  const int tiles_n = (d.N + O2_BN - 1) / O2_BN;
+  const int tiles_m = (g.d.M + BM - 1) / BM;
+  const int tiles_n = (g.d.N + BN - 1) / BN;
   const int per = tiles_m * tiles_n;
   int first, last, step;
   if (persist) {
@@ -495,11 +553,11 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
   for (int tile = first; tile < last; tile += step) {
   const int z = tile / per;
   const int t = tile - z * per;
-  const int m0 = (t % tiles_m) * O2_BM;
-  const int n0 = (t / tiles_m) * O2_BN;
-  const bool skew = d.skew != 0;
-  if (skew && m0 >= n0 + O2_BN) continue;   // strictly below the diagonal (workgroup-uniform)
-  const int M = d.M, N = d.N, K = d.K;
+  const int m0 = (t % tiles_m) * BM;
+  const int n0 = (t / tiles_m) * BN;
+  const bool skew = g.d.skew != 0;
+  if (skew && m0 >= n0 + BN) continue;   // strictly below the diagonal (workgroup-uniform)
+  const int M = g.d.M, N = g.d.N, K = g.d.K;
   const int KT = (K + KS - 1) / KS;
   const int NSTRIP = P.p * KT;                  // (modulus, strip) pairs, modulus-major
 
@@ -509,88 +567,117 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles,
   const int32_t* EB = g.EB + (int64_t)z * g.eb_stride;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave % (O2_BM / 32), wn = wave / (O2_BM / 32);
-  const bool wlive = (m0 + 32 * wm < M) && (n0 + 32 * wn < N) &&
-                     !(skew && m0 + 32 * wm >= n0 + 32 * wn + 32);   // wave-uniform
+  const int wm = wave % CF::WAVES_M, wn = wave / CF::WAVES_M;
 
-  if (tid < O2_BM) Ea[tid] = (m0 + tid < M) ? EA[m0 + tid] : 0;
-  else if (tid < O2_BM + O2_BN) Eb[tid - O2_BM] = (n0 + tid - O2_BM < N) ? EB[n0 + tid - O2_BM] : 0;
+  if (tid < BM) Ea[tid] = (m0 + tid < M) ? EA[m0 + tid] : 0;
+  else if (tid < BM + BN) Eb[tid - BM] = (n0 + tid - BM < N) ? EB[n0 + tid - BM] : 0;
   __syncthreads();   // also drains these loads before the counted ring loads start
 
   // Per-thread source of each of its LPS slots of a strip (the strip offset added
   // per strip): slot cs = q * NT + tid; A rows first, then B rows.
-  O2Ctx<LPS> c;
+  O2Ctx<LPS, WM, WN> c;
 #pragma unroll
   for (int q = 0; q < LPS; ++q) {
-    const int cs = q * O2_NT + tid;
+    const int cs = q * NT + tid;
     const int row = cs >> 3, slot = cs & 7;
-    const int word = slot ^ (row & 7);
-    const int rg = row < O2_BM ? min(m0 + row, M - 1) : min(n0 + row - O2_BM, N - 1);   // q < LPS_A: A rows
+    const int word = slot ^ ((row >> 1) & 7);
+    const int rg = row < BM ? min(m0 + row, M - 1) : min(n0 + row - BM, N - 1);   // q < LPS_A: A rows
     c.off[q] = rg * 128 + 16 * word;
   }
   c.sstride_a = M * 128;
   c.sstride_b = N * 128;
   c.cst = (const lds_f64*)&cst[0];
   c.tid = tid;
-  c.la = 32 * wm + (lane & 31);
-  c.lb = O2_BM + 32 * wn + (lane & 31);
+#pragma unroll
+  for (int x = 0; x < WM; ++x) c.la[x] = 32 * (WM * wm + x) + (lane & 31);
+#pragma unroll
+  for (int y = 0; y < WN; ++y) c.lb[y] = BM + 32 * (WN * wn + y) + (lane & 31);
   c.lk = lane >> 5;
   c.KT = KT;
   c.K = K;
   c.NSTRIP = NSTRIP;
-  c.wlive = wlive;
-
-  O2Acc<CF::TWO_ACC> acc;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    acc.clear(v);
-    acc.sre[v] = 0.0; acc.sim[v] = 0.0;
-  }
+  for (int x = 0; x < WM; ++x)
+#pragma unroll
+    for (int y = 0; y < WN; ++y) {
+      const int rb = m0 + 32 * (WM * wm + x), cb = n0 + 32 * (WN * wn + y);
+      c.live[x][y] = rb < M && cb < N && !(skew && rb >= cb + 32);   // wave-uniform
+    }
+  c.wlive = false;
+#pragma unroll
+  for (int x = 0; x < WM; ++x)
+#pragma unroll
+    for (int y = 0; y < WN; ++y) c.wlive |= c.live[x][y];
+
+  O2Acc<CF::TWO_ACC> acc[WM][WN];
+#pragma unroll
+  for (int x = 0; x < WM; ++x)
+#pragma unroll
+    for (int y = 0; y < WN; ++y)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc[x][y].clear(v);
+        acc[x][y].sre[v] = 0.0; acc[x][y].sim[v] = 0.0;
+      }
   auto stage = [&](int f) { return (lds_u4*)&ring[(f + NSTAGE) % NSTAGE][0]; };   // f >= -NSTAGE
   const int nstep = (NSTRIP + SPI - 1) / SPI;
+  int fi = 0, fkt = 0;
   for (int st = -(NSTAGE - 1); st < nstep; ++st)
-    o2_step<CF, CONJB>(st, stage(st), stage(st + NSTAGE - 1), SA, SB, c, acc);
+    o2_step<CF, CONJB>(st, stage(st), stage(st + NSTAGE - 1), SA, SB, c, acc, fi, fkt);
 
-  // epilogue in FP64 (same addend semantics as the FP64 kernels)
+  // epilogue in FP64 (same addend semantics as the FP64 kernels).  Its parameters are
+  // read here from the kernel-argument segment through a pointer the compiler cannot
+  // see through, so that they are loaded after the strip loop instead of being held in
+  // scalar registers across it (about 40 of them: they used to spill, and the spill
+  // slots cost vector registers the strip loop needs).
+  KGemmDesc& d = kernarg_desc();
   double2* __restrict__ C = d.tC ? d.tC[z] : d.C + (int64_t)z * d.sC;
   const double bs = d.bscal ? d.bscal[z] : 1.0;
+  const double2 alpha = cmk(d.alpha.x, d.alpha.y);
   double2 coef[kMaxAddends];
   const double2* X[kMaxAddends];
 #pragma unroll
   for (int q = 0; q < kMaxAddends; ++q) {
-    coef[q] = d.add[q].coef;
+    coef[q] = cmk(d.add[q].coef.x, d.add[q].coef.y);
     if (d.add[q].scale_by_batch) coef[q] = cmk(coef[q].x * bs, coef[q].y * bs);
     X[q] = d.add[q].tX ? d.add[q].tX[z] : (d.add[q].X ? d.add[q].X + (int64_t)z * d.add[q].stride : nullptr);
   }
-  const double2 dg = d.diag_by_batch ? cmk(d.diag.x * bs, d.diag.y * bs) : d.diag;
-  const int lb = c.lb, lk = c.lk;
-  const int col = n0 + lb - O2_BM;
-  const int eb = Eb[lb - O2_BM];
+  const double2 dg = d.diag_by_batch ? cmk(d.diag.x * bs, d.diag.y * bs) : cmk(d.diag.x, d.diag.y);
+  const int lk = c.lk;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int rl = 32 * wm + 8 * (v >> 2) + 4 * lk + (v & 3);
-    const int r = m0 + rl;
-    if (wlive && r < M && col < N && !(skew && r > col)) {
-      // a row of op(A) or column of op(B) with NaN / Inf gives NaN, as in FP64
-      const bool nf = Ea[rl] == kExpNonFinite || eb == kExpNonFinite;
-      const double sc = nf ? __builtin_nan("") : pow2(Ea[rl] + eb - 2 * P.kbits - 2) * P.M;
-      const double cr = (acc.sre[v] - rint(acc.sre[v])) * sc;
-      const double ci = (acc.sim[v] - rint(acc.sim[v])) * sc;
-      double2 out = cmul(d.alpha, cmk(cr, ci));
+  for (int x = 0; x < WM; ++x)
 #pragma unroll
-      for (int q = 0; q < kMaxAddends; ++q) {
-        if (X[q]) {
-          const double2 x = (d.add[q].op == OP_N) ? X[q][(int64_t)r * d.add[q].ld + col]
-                                                   : cconj(X[q][(int64_t)col * d.add[q].ld + r]);
-          out = cadd(out, cmul(coef[q], x));
+    for (int y = 0; y < WN; ++y) {
+      if (!c.live[x][y]) continue;
+      const int colt = c.lb[y] - BM;
+      const int col = n0 + colt;
+      const int eb = Eb[colt];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int rl = 32 * (WM * wm + x) + 8 * (v >> 2) + 4 * lk + (v & 3);
+        const int r = m0 + rl;
+        if (r < M && col < N && !(skew && r > col)) {
+          // a row of op(A) or column of op(B) with NaN / Inf gives NaN, as in FP64
+          const bool nf = Ea[rl] == kExpNonFinite || eb == kExpNonFinite;
+          const double sc = nf ? __builtin_nan("") : pow2(Ea[rl] + eb - 2 * P.kbits - 2) * P.M;
+          const double cr = (acc[x][y].sre[v] - rint(acc[x][y].sre[v])) * sc;
+          const double ci = (acc[x][y].sim[v] - rint(acc[x][y].sim[v])) * sc;
+          double2 out = cmul(alpha, cmk(cr, ci));
+#pragma unroll
+          for (int q = 0; q < kMaxAddends; ++q) {
+            if (X[q]) {
+              const double2 xv = (d.add[q].op == OP_N) ? X[q][(int64_t)r * d.add[q].ld + col]
+                                                        : cconj(X[q][(int64_t)col * d.add[q].ld + r]);
+              out = cadd(out, cmul(coef[q], xv));
+            }
+          }
+          if (r == col) out = cadd(out, dg);
+          if (skew && r == col) out.x = 0.0;   // a skew-Hermitian diagonal is imaginary
+          C[(int64_t)r * d.ldc + col] = out;
+          if (skew && r < col) C[(int64_t)col * d.ldc + r] = cmk(-out.x, out.y);
         }
       }
-      if (r == col) out = cadd(out, dg);
-      if (skew && r == col) out.x = 0.0;   // a skew-Hermitian diagonal is imaginary
-      C[(int64_t)r * d.ldc + col] = out;
-      if (skew && r < col) C[(int64_t)col * d.ldc + r] = cmk(-out.x, out.y);
     }
-  }
   __syncthreads();   // Ea / Eb and the ring are reused by the next tile
   }
 }
@@ -678,7 +765,7 @@ namespace {
 template <class CF>
 hipError_t launch_o2_variant(const SplitGemmDesc& g, const O2Params& P, hipStream_t s, bool allow_persist) {
   const GemmDesc& d = g.d;
-  const int64_t total = (int64_t)((d.M + CF::BM - 1) / CF::BM) * ((d.N + O2_BN - 1) / O2_BN) * d.batch;
+  const int64_t total = (int64_t)((d.M + CF::BM - 1) / CF::BM) * ((d.N + CF::BN - 1) / CF::BN) * d.batch;
   if (total > 0x7fffffff) return hipErrorInvalidValue;
   // WPC workgroups per CU (what the kernel's LDS and registers admit) when there are more tiles
   static int cus[64] = {0};
@@ -720,6 +807,12 @@ hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_
     case 5: return launch_o2_variant<O2V4>(g, P, s, false);
     case 6: return launch_o2_variant<O2V1>(g, P, s, false);
     case 7: return launch_o2_variant<O2V7>(g, P, s, persist);
+    case 8: return launch_o2_variant<O2V8>(g, P, s, persist);
+    case 9: return launch_o2_variant<O2V9>(g, P, s, persist);
+    case 10: return launch_o2_variant<O2V10>(g, P, s, persist);
+    case 11: return launch_o2_variant<O2V8>(g, P, s, false);
+    case 12: return launch_o2_variant<O2V12>(g, P, s, persist);
+    case 13: return launch_o2_variant<O2V12>(g, P, s, false);
     default: return hipErrorInvalidValue;
   }
 }

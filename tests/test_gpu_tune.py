@@ -9,7 +9,7 @@ import oracle
 from paper_2606_25595_amd import inputs
 
 pytestmark = pytest.mark.gpu
-N_VARIANTS = 8      # tile variants of the INT8 product kernel
+N_VARIANTS = 14     # tile variants of the INT8 product kernel
 
 
 @pytest.fixture(scope="module")
