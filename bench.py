@@ -63,16 +63,15 @@ def parse_scheme(spec):
 
 
 def autotune(ctx, skw, shapes):
-    """Autotuner pass (outside any timed region): for each INT8 scheme of `skw`
-    (retarded and lesser chain) and each (b, batch) in `shapes`, time the product
-    kernel's tile variants and keep the fastest in the context."""
+    """Autotuner pass (outside any timed region): for each scheme of `skw` (retarded
+    and lesser chain) and each (b, batch) in `shapes`, time the product kernel's tile
+    variants (INT8: 14 tile shapes; FP64, FP32, split: 32 x 32 or 64 x 64 tiles) and
+    keep the fastest in the context."""
     out = {}
     chains = [(skw["prec"], skw.get("n_slices", 0))]
     if skw.get("prec_lesser"):
         chains.append((skw["prec_lesser"], skw.get("n_slices_lesser", 0)))
     for prec, ns in sorted(set(chains)):
-        if prec != "int8":
-            continue
         for b, batch in shapes:
             v, ms = ctx.tune(b, prec, ns, batch=batch)
             out["%s:%d b=%d batch=%d" % (prec, ns, b, batch)] = {"variant": v, "ms_per_product": [round(t, 4) for t in ms]}
@@ -113,6 +112,43 @@ def traffic_from_profile(scheme):
         return None
 
 
+def _oracle_one_energy(args):
+    """Process-pool worker of the CPU baseline: the FP64 oracle on one energy of a named
+    workload with one BLAS thread; returns (start, end) wall-clock times of the oracle
+    call (the problem is built before the clock starts)."""
+    name, e, eta = args
+    from threadpoolctl import threadpool_limits
+    import oracle
+    from paper_2606_25595_amd import inputs
+    p = inputs.config_problem(name, energy_index=[e], eta=eta)
+    with threadpool_limits(1):
+        t0 = time.time()
+        oracle.rgf_selected(p)
+        t1 = time.time()
+    return t0, t1
+
+
+def host_cores():
+    """CPU cores this process may use (its affinity mask), at most 16 (one GPU's share
+    of the machine's host cores)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def oracle_pool_rate(name, energies, eta, workers):
+    """Energy points/s of the oracle run as a process pool over the energies, one BLAS
+    thread per process (wall time from the first oracle start to the last end)."""
+    import multiprocessing as mp
+    ctxp = mp.get_context("spawn")
+    with ctxp.Pool(workers) as pool:
+        spans = pool.map(_oracle_one_energy, [(name, e, eta) for e in energies], chunksize=1)
+    wall = max(t1 for _, t1 in spans) - min(t0 for t0, _ in spans)
+    return len(energies) / wall, wall
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,7 +161,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-full-check", action="store_true",
                     help="skip the all-energy error check of the mixed schemes (then none qualifies)")
-    ap.add_argument("--workload", default="realistic", choices=["realistic", "hard", "kappa", "w", "fpx", "batch", "serve", "latency"],
+    ap.add_argument("--workload", default="realistic",
+                    choices=["realistic", "hard", "kappa", "w", "fpx", "batch", "serve", "latency", "tiny"],
                     help="realistic (default, the headline line) | hard (the realistic shapes at eta = 1e-6, "
                          "condition numbers up to ~5e6) | kappa (error against the exact condition number, "
                          "n_b=8, b=128, eta 1e-3..1e-6) | w (screened Coulomb system: assembly + solve, n_b=16, "
@@ -167,10 +204,21 @@ def main():
         return bench_fpx(args)
     if args.workload == "latency":
         return bench_latency(args)
+    if args.workload == "tiny":
+        return bench_tiny(args)
 
     cfg = inputs.CONFIGS["realistic"]
     n_b, b, n_e = cfg["n_b"], cfg["b"], cfg["n_e"]
     eta = args.eta if args.eta is not None else (1e-6 if args.workload == "hard" else 1e-3)
+    sample = list(range(0, n_e, max(1, n_e // args.cpu_energies)))[: args.cpu_energies]
+    pool = None
+    if not args.no_cpu:
+        # the oracle as a process pool (one BLAS thread per process), started before this
+        # process touches the GPU
+        workers = host_cores()
+        log("bench: oracle process pool, %d workers, %d energies" % (workers, len(sample)))
+        rate, wall = oracle_pool_rate("realistic", sample, eta, workers)
+        pool = {"value": rate, "cores": workers, "wall_s": wall}
     gamma, mu_L, kT = 0.5, 0.1, 0.025
     grid = np.linspace(-2.0, 2.0, n_e)
     log("bench: building realistic workload n_b=%d b=%d n_e=%d eta=%g on the device" % (n_b, b, n_e, eta))
@@ -182,7 +230,6 @@ def main():
                            GL_d=torch.empty((n_e, n_b, b, b), **kw), GL_u=torch.empty((n_e, n_b - 1, b, b), **kw),
                            status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"), split=args.split)
     ctx = qtx.Context(0, workspace_bytes=int(args.workspace_gb * (1 << 30)))
-    sample = list(range(0, n_e, max(1, n_e // args.cpu_energies)))[: args.cpu_energies]
     gamma_L = 2.0 * gamma * np.eye(b, dtype=np.complex128)
     f_L = inputs.fermi(grid, mu_L, kT)
     kappa = None
@@ -205,9 +252,17 @@ def main():
         ref["T_L"] = oracle.transmission_left(ref["GR_d"][:, 0], p_s.gamma_L)
         ref["j_L"] = oracle.contact_current_left(ref["GR_d"][:, 0], ref["GL_d"][:, 0], p_s.gamma_L, p_s.f_L)
         kappa = kappa_bounds(p_s, ref, eta) if args.workload == "hard" else None
-        cpu = {"value": len(sample) / t_cpu, "unit": "energy points/s", "cores": int(threads), "kind": "oracle",
+        seq = {"value": len(sample) / t_cpu, "cores": int(threads), "wall_s": t_cpu}
+        best = "pool" if pool and pool["value"] > seq["value"] else "threads"
+        top = pool if best == "pool" else seq
+        cpu = {"value": top["value"], "unit": "energy points/s", "cores": int(top["cores"]), "kind": "oracle",
                "sample": "%d of the 256 energies (every %dth) of the realistic workload, block recurrences in "
-                         "numpy/LAPACK FP64, %.1f s" % (len(sample), n_e // len(sample), t_cpu)}
+                         "numpy/LAPACK FP64; faster of: one energy at a time on %d BLAS threads (%.1f s), a pool of "
+                         "%d processes with one BLAS thread each (%s)"
+                         % (len(sample), n_e // len(sample), seq["cores"], seq["wall_s"],
+                            pool["cores"] if pool else 0, ("%.1f s" % pool["wall_s"]) if pool else "not run"),
+               "mode": best, "modes": {"threads": seq, "pool": pool},
+               "host_cpus": os.cpu_count(), "host_cpus_usable": host_cores()}
 
     results = {}
     tuned = {}
@@ -786,7 +841,7 @@ def bench_batch(args):
         stream.synchronize()
         t = (time.perf_counter() - t0) / args.steps
     ok = all(int(dp.status.item()) == 0 for dp in dps)
-    sample = list(range(0, n, max(1, n // 8)))[:8]
+    sample = list(range(0, n, max(1, n // 16)))[:16]
     errs = {k: 0.0 for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")}
     for q in sample:
         dp = dps[q]
@@ -808,6 +863,66 @@ def bench_batch(args):
             "graph_captures": ctx.stat(qtx.QTX_STAT_GRAPH_CAPTURES),
             "graph_launches": ctx.stat(qtx.QTX_STAT_GRAPH_LAUNCHES),
             "sampled_max_rel_err": errs, "sampled_problems": len(sample), "autotune": tuned}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def bench_tiny(args):
+    """The tiny workload (n_b = 8, b = 16, all 32 energies of [-2, 2]): GPU solve latency
+    of all 32 energies (eager and replayed as a hipGraph; the launch-bound case), the
+    error of every output block against the dense FP64 oracle, and both CPU oracles
+    (dense inverse and block recurrences) timed on all 32 energies."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2606_25595_amd import inputs, qtx
+    p = inputs.config_problem("tiny")
+    t0 = time.perf_counter()
+    dense = oracle.dense_selected(p)
+    t_dense = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rgf = oracle.rgf_selected(p)
+    t_rgf = time.perf_counter() - t0
+    ctx = qtx.Context(0)
+    dp = qtx.to_device(p)
+    stream = torch.cuda.Stream()
+    res = {}
+    for graph in (False, True):
+        ctx.set_graph(graph)
+        with torch.cuda.stream(stream):
+            for _ in range(max(1, args.warmup)):
+                ctx.solve(dp, stream=stream)
+            stream.synchronize()
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+            evs[0].record(stream)
+            for k in range(args.steps):
+                ctx.solve(dp, stream=stream)
+                evs[k + 1].record(stream)
+            stream.synchronize()
+        lat = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+        res["graph" if graph else "eager"] = {"p50_ms": float(np.percentile(lat, 50)),
+                                              "p99_ms": float(np.percentile(lat, 99)),
+                                              "energies_per_s": p.n_e / (float(np.median(lat)) / 1e3)}
+    ctx.set_graph(False)
+    out = dp.outputs()
+    errs = {k: float(oracle.rel_fro_err(out[k], dense[k]).max()) for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")}
+    errs_rgf = {k: float(oracle.rel_fro_err(rgf[k], dense[k]).max()) for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")}
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info() if t.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    best = res["graph"] if res["graph"]["p50_ms"] < res["eager"]["p50_ms"] else res["eager"]
+    line = {"metric": "RGF energy points/sec, tiny workload (launch-bound)", "value": best["energies_per_s"],
+            "unit": "energy points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": best["p50_ms"], "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "tiny: n_b=8 blocks, b=16, N_E=32 energies in [-2,2], complex128, S=I, seed 0"},
+            "gpu": res, "max_rel_err_vs_dense_oracle": errs, "status_ok": bool(np.all(out["status"] == 0)),
+            "cpu_oracles": {"dense_s": t_dense, "rgf_s": t_rgf, "dense_energies_per_s": p.n_e / t_dense,
+                            "rgf_energies_per_s": p.n_e / t_rgf, "blas_threads": int(threads),
+                            "rgf_vs_dense_max_rel_err": errs_rgf,
+                            "note": "all 32 energies, one at a time, numpy/LAPACK FP64"},
+            "flops_per_energy": (144 * (p.n_b - 1) + 24) * p.b ** 3}
     print(json.dumps(line), flush=True)
     ctx.close()
 

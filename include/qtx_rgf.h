@@ -239,16 +239,17 @@ qtx_status qtx_rgf_get_stat(qtx_rgf_ctx ctx, int stat, int64_t* value);
  * (prec, n_slices) uses on synthetic complex b x b x b products over `batch`
  * entries (deterministic pseudo-random operands in [-1, 1)), 1 warm-up and 3 timed
  * products each on hip_stream, and records the fastest for the shape (b, b, b),
- * the batch class ceil(log2(batch)) (classes 0..9) and the modulus count used.
- * Later products of that shape and modulus count (in qtx_rgf_solve and qtx_zgemm)
- * take the recorded variant, from the record of the nearest batch class; cached
- * hipGraphs are dropped.  The table is written to
- * the context's tune_cache_path when one was given (QTX_ERR_ARG if that write
- * fails; the record is kept).  Only the INT8 scheme has variants (14: tiles of
- * 32 x 64 to 128 x 128 with one or two 32 x 32 blocks per wave, one to six
- * workgroups per CU, LDS rings of two to four stages, each either in persistent
- * workgroups or one tile per workgroup); for
- * the other schemes nothing is timed, *out_count = 1 and *out_variant = 0.
+ * the batch class ceil(log2(batch)) (classes 0..9) and the scheme (modulus count or
+ * slice count).  Later products of that shape and scheme (in qtx_rgf_solve and
+ * qtx_zgemm) take the recorded variant, from the record of the nearest batch class;
+ * cached hipGraphs are dropped.  The table is written to the context's
+ * tune_cache_path when one was given (QTX_ERR_ARG if that write fails; the record is
+ * kept).  Variants: the INT8 scheme has 14 (tiles of 32 x 64 to 128 x 128 with one or
+ * two 32 x 32 blocks per wave, one to six workgroups per CU, LDS rings of two to four
+ * stages, each either in persistent workgroups or one tile per workgroup); FP64, FP32
+ * and the split schemes have 2 (0: 32 x 32 output tiles, 1: 64 x 64; without a record
+ * they take 32 x 32 where a 64 x 64 tiling pads C by more than 8% or gives fewer than
+ * 4096 tiles).  All variants of a scheme give bitwise the same products.
  *   out_variant  chosen variant (nullable)
  *   out_ms       ms per product (operand conversion included) of each variant,
  *                up to max_variants entries (nullable when max_variants = 0)
@@ -389,6 +390,22 @@ qtx_status qtx_rgf_observables(qtx_rgf_ctx ctx, int32_t b, int32_t n_e,
                                const void* GR_11, const void* GL_11, int64_t sG,
                                const void* gamma_L, const double* f_L,
                                double* T_L, double* j_L, void* hip_stream);
+
+/* Bond currents from solver outputs (Section II-B: the current, and its conservation
+ * along the device, is the accuracy criterion).  For energy e and bond i (blocks i and
+ * i + 1, i < n_b - 1):
+ *   J[e][i] = 2 Re Tr[(H_{i,i+1} - E_e S_{i,i+1}) G^<_{i+1,i}],  G^<_{i+1,i} = -(G^<_{i,i+1})^H,
+ * the particle current from block i to block i + 1 (in units where the contact current
+ * j_L of qtx_rgf_observables is the same quantity at the left contact: with no
+ * broadening inside the device, J[e][i] = j_L[e] = -j_R[e] for every bond).
+ * H_u: [n_b-1][b][b] device couplings H_{i,i+1}; S_u: the same for S, or NULL (S = I,
+ * whose off-diagonal blocks are zero).  energies: device [n_e] doubles.  GL_u: the
+ * solver's G^<_{i,i+1} blocks, energy e at GL_u + e * sGu (complex elements;
+ * sGu >= (n_b-1) b^2).  J: device [n_e][n_b-1] double output.  Limits: b >= 1,
+ * n_b >= 2, n_e >= 1.  Uses no workspace. */
+qtx_status qtx_rgf_bond_currents(qtx_rgf_ctx ctx, int32_t b, int32_t n_b, int32_t n_e, const void* H_u,
+                                 const void* S_u, const double* energies, const void* GL_u, int64_t sGu, double* J,
+                                 void* hip_stream);
 
 /* ---------------------------------------------------------------------------
  * Per-launch timing of the library's own kernels (roofline measurement).

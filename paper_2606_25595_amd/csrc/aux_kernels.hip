@@ -173,7 +173,45 @@ __global__ __launch_bounds__(256) void observables_kernel(int b, const double2* 
   }
 }
 
+// Bond current of energy e = blockIdx.y across bond i = blockIdx.x (Section II-B uses the
+// current and its conservation as the accuracy criterion):
+//   J = 2 Re Tr[(H_{i,i+1} - E S_{i,i+1}) G^<_{i+1,i}],   G^<_{i+1,i} = -(G^<_{i,i+1})^H,
+// so J = -2 sum_jk Re(c_jk conj(g_jk)) with c the coupling and g = G^<_{i,i+1}.
+// Fixed-order FP64 reduction (deterministic).
+__global__ __launch_bounds__(256) void bond_current_kernel(int b, int nbond, const double2* Hu, const double2* Su,
+                                                           const double* E, const double2* GLu, int64_t sGu,
+                                                           double* J) {
+  const int i = blockIdx.x, e = blockIdx.y;
+  const int64_t bb = (int64_t)b * b;
+  const double2* h = Hu + (int64_t)i * bb;
+  const double2* sm = Su ? Su + (int64_t)i * bb : nullptr;
+  const double2* g = GLu + (int64_t)e * sGu + (int64_t)i * bb;
+  const double en = E[e];
+  double acc = 0.0;
+  for (int64_t idx = threadIdx.x; idx < bb; idx += blockDim.x) {
+    double2 c = h[idx];
+    if (sm) { c.x = fma(-en, sm[idx].x, c.x); c.y = fma(-en, sm[idx].y, c.y); }
+    const double2 v = g[idx];
+    acc = fma(c.x, v.x, fma(c.y, v.y, acc));
+  }
+  __shared__ double sh[256];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) J[(int64_t)e * nbond + i] = -2.0 * sh[0];
+}
+
 }  // namespace
+
+hipError_t launch_bond_currents(int b, int n_b, int n_e, const double2* Hu, const double2* Su, const double* E,
+                                const double2* GLu, int64_t sGu, double* J, hipStream_t s) {
+  if (n_b < 2 || n_e <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bond_current_kernel, dim3(n_b - 1, n_e), dim3(256), 0, s, b, n_b - 1, Hu, Su, E, GLu, sGu, J);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_hash(double2* p, int64_t n, uint32_t seed, hipStream_t s) {
   if (n <= 0) return hipSuccess;

@@ -57,14 +57,16 @@ struct GraphCacheEntry {
   hipGraphExec_t exec = nullptr;
 };
 
-// Autotuner record: the tile variant of the INT8 product kernel chosen for one
-// product shape (M, N, K), batch class and modulus count, with the measured ms
-// per variant.
+// Autotuner record: the tile variant of a product kernel chosen for one product shape
+// (M, N, K), batch class and scheme code (the modulus count of the INT8 scheme, else
+// kTileCodeBase + 10 prec + slices, whose variants are 0 = 32 x 32 and 1 = 64 x 64
+// tiles), with the measured ms per variant.
 struct TuneRec {
   int variant = 0;
   std::vector<double> ms;
 };
-typedef std::tuple<int, int, int, int, int> TuneKey;   // M, N, K, batch class, moduli
+typedef std::tuple<int, int, int, int, int> TuneKey;   // M, N, K, batch class, scheme code
+constexpr int kTileCodeBase = 100;
 
 struct qtx_rgf_ctx_s {
   int device = 0;
@@ -75,6 +77,7 @@ struct qtx_rgf_ctx_s {
   std::string tune_path;
   std::map<TuneKey, TuneRec> tune;
   int o2_force = -1;       // >= 0: every INT8 product uses this tile variant
+  int tile_force = 0;      // 32 / 64: every FP64 / FP32 / split product uses this tile (the tuner's timing runs)
   bool overlap = false;    // run independent products on a side stream during inversions
   int lane_split = 1;      // stream lanes each batch group is split over
   bool profiling = false;
@@ -473,10 +476,29 @@ int o2_variant_for(qtx_rgf_ctx ctx, const GemmDesc& d, int p) {
   return (d.K >= 256 && tiles >= 512) ? 4 : 1;
 }
 
+// Scheme code of the tile records of the FP64 / FP32 / split products.
+int tile_code(const Scheme& sc) { return kTileCodeBase + 10 * sc.prec + sc.ns; }
+
+// Output tile of an FP64 / FP32 / split product: the forced one, else the tuned record
+// of the shape and scheme at the nearest batch class, else 0 (the kernels' rule from
+// the shape).
+int tile_for(qtx_rgf_ctx ctx, const GemmDesc& d, const Scheme& sc) {
+  if (ctx->tile_force) return ctx->tile_force;
+  const int bc = batch_class(d.batch), code = tile_code(sc);
+  int best = -1, dist = 1 << 30;
+  for (int c = 0; c <= 9; ++c) {
+    auto it = ctx->tune.find(TuneKey(d.M, d.N, d.K, c, code));
+    if (it != ctx->tune.end() && std::abs(c - bc) < dist) { dist = std::abs(c - bc); best = it->second.variant; }
+  }
+  return best < 0 ? 0 : (best ? 64 : 32);
+}
+
 // One batched complex block product with a precision scheme.  Elementwise (K = 0)
 // launches stay FP64.
-hipError_t run_product(qtx_rgf_ctx ctx, const GemmDesc& d, const Scheme& sc, const SplitBufs& sb, hipStream_t s,
+hipError_t run_product(qtx_rgf_ctx ctx, const GemmDesc& d0, const Scheme& sc, const SplitBufs& sb, hipStream_t s,
                        ConvUse use = ConvUse()) {
+  GemmDesc d = d0;
+  if (d.K > 0 && !sc.o2() && d.tile == 0) d.tile = tile_for(ctx, d, sc);
   // per-launch timers: the matrix-core kernel (its own operations) and the operand
   // conversion passes (their algorithmic bytes) separately
   // a skew-Hermitian result needs only its elements r <= c (the split scheme
@@ -1477,9 +1499,10 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
   return result;
 }
 
-// Tuning cache file: a text file, first line "qtx-tune 2 <arch> <CUs>", then one
-// line per record "o2 M N K class p variant ms_0 .. ms_{n-1}".  A file written on a
-// different device kind, or lines that do not parse, are ignored.
+// Tuning cache file: a text file, first line "qtx-tune 3 <arch> <CUs>", then one
+// line per record "o2 M N K class p variant ms_0 .. ms_{n-1}" (INT8 tile variants) or
+// "tm M N K class code variant ms_32 ms_64" (tile edge of the other schemes).  A file
+// written on a different device kind or format, or lines that do not parse, are ignored.
 std::string device_tag(int device) {
   hipDeviceProp_t pr;
   if (hipGetDeviceProperties(&pr, device) != hipSuccess) return "unknown 0";
@@ -1498,7 +1521,7 @@ void tune_load(qtx_rgf_ctx ctx) {
   if (!f) return;
   char line[1024];
   bool ok = false;
-  const std::string tag = "qtx-tune 2 " + device_tag(ctx->device);
+  const std::string tag = "qtx-tune 3 " + device_tag(ctx->device);
   if (std::fgets(line, sizeof line, f)) {
     std::string h(line);
     while (!h.empty() && (h.back() == '\n' || h.back() == '\r' || h.back() == ' ')) h.pop_back();
@@ -1506,10 +1529,14 @@ void tune_load(qtx_rgf_ctx ctx) {
   }
   while (ok && std::fgets(line, sizeof line, f)) {
     int M, N, K, c, p, v, used = 0;
-    if (std::sscanf(line, "o2 %d %d %d %d %d %d%n", &M, &N, &K, &c, &p, &v, &used) != 6) continue;
-    if (M < 1 || N < 1 || K < 1 || c < 0 || c > 9 || p < 1 || p > kO2MaxModuli || v < 0 ||
-        v >= o2_variant_count())
-      continue;
+    bool tile = false;
+    if (std::sscanf(line, "o2 %d %d %d %d %d %d%n", &M, &N, &K, &c, &p, &v, &used) != 6) {
+      if (std::sscanf(line, "tm %d %d %d %d %d %d%n", &M, &N, &K, &c, &p, &v, &used) != 6) continue;
+      tile = true;
+    }
+    if (M < 1 || N < 1 || K < 1 || c < 0 || c > 9) continue;
+    if (!tile && (p < 1 || p > kO2MaxModuli || v < 0 || v >= o2_variant_count())) continue;
+    if (tile && (p < kTileCodeBase || v < 0 || v > 1)) continue;
     TuneRec r;
     r.variant = v;
     const char* q = line + used;
@@ -1526,10 +1553,11 @@ bool tune_save(qtx_rgf_ctx ctx) {
   const std::string tmp = ctx->tune_path + ".tmp";
   FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) return false;
-  std::fprintf(f, "qtx-tune 2 %s\n", device_tag(ctx->device).c_str());
+  std::fprintf(f, "qtx-tune 3 %s\n", device_tag(ctx->device).c_str());
   for (const auto& kv : ctx->tune) {
-    std::fprintf(f, "o2 %d %d %d %d %d %d", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                 std::get<3>(kv.first), std::get<4>(kv.first), kv.second.variant);
+    std::fprintf(f, "%s %d %d %d %d %d %d", std::get<4>(kv.first) >= kTileCodeBase ? "tm" : "o2",
+                 std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
+                 std::get<4>(kv.first), kv.second.variant);
     for (double ms : kv.second.ms) std::fprintf(f, " %.4f", ms);
     std::fprintf(f, "\n");
   }
@@ -1821,14 +1849,8 @@ qtx_status qtx_rgf_tune(qtx_rgf_ctx ctx, int32_t b, int32_t prec, int32_t n_slic
   if (b < 1 || b > 1024 || batch < 1 || max_variants < 0 || (max_variants > 0 && !out_ms)) return QTX_ERR_ARG;
   Scheme sc;
   if (!make_scheme(prec, n_slices, &sc)) return QTX_ERR_UNSUPPORTED;
-  if (!sc.o2()) {   // one kernel configuration: nothing to choose
-    if (out_variant) *out_variant = 0;
-    if (out_count) *out_count = 1;
-    if (max_variants > 0) out_ms[0] = 0.0;
-    return QTX_OK;
-  }
   O2Params P;
-  if (!o2_params(sc.ns, b, &P)) return QTX_ERR_UNSUPPORTED;
+  if (sc.o2() && !o2_params(sc.ns, b, &P)) return QTX_ERR_UNSUPPORTED;
   DeviceGuard guard(ctx->device);
   hipStream_t s = (hipStream_t)hip_stream;
   const int64_t bb = (int64_t)b * b;
@@ -1847,14 +1869,16 @@ qtx_status qtx_rgf_tune(qtx_rgf_ctx ctx, int32_t b, int32_t prec, int32_t n_slic
       launch_fill_hash(buf[0], bb * batch, 1u, s) != hipSuccess ||
       launch_fill_hash(buf[1], bb * batch, 2u, s) != hipSuccess)
     st = hip_fail(ctx, hipErrorUnknown);
-  const int nv = o2_variant_count();
+  // INT8: the tile variants; the other schemes: 32 x 32 (variant 0) or 64 x 64 tiles
+  const int nv = sc.o2() ? o2_variant_count() : 2;
   std::vector<double> ms(nv, 0.0);
-  const int saved_force = ctx->o2_force;
+  const int saved_force = ctx->o2_force, saved_tile = ctx->tile_force;
   const bool saved_prof = ctx->profiling;
   ctx->profiling = false;
   const int reps = 3;
   for (int v = 0; v < nv && st == QTX_OK; ++v) {
-    ctx->o2_force = v;
+    if (sc.o2()) ctx->o2_force = v;
+    else ctx->tile_force = v ? 64 : 32;
     auto one = [&]() {
       return qtx_zgemm(ctx, 'N', 'N', b, b, b, 1.0, 0.0, buf[0], b, bb, buf[1], b, bb, 0.0, 0.0, buf[2], b, bb,
                        batch, prec, n_slices, hip_stream);
@@ -1872,6 +1896,7 @@ qtx_status qtx_rgf_tune(qtx_rgf_ctx ctx, int32_t b, int32_t prec, int32_t n_slic
     ms[v] = t / reps;
   }
   ctx->o2_force = saved_force;
+  ctx->tile_force = saved_tile;
   ctx->profiling = saved_prof;
   (void)hipStreamSynchronize(s);
   for (auto& p : buf) (void)hipFree(p);
@@ -1884,7 +1909,7 @@ qtx_status qtx_rgf_tune(qtx_rgf_ctx ctx, int32_t b, int32_t prec, int32_t n_slic
   TuneRec rec;
   rec.variant = best;
   rec.ms = ms;
-  ctx->tune[TuneKey(b, b, b, batch_class(batch), P.p)] = rec;
+  ctx->tune[TuneKey(b, b, b, batch_class(batch), sc.o2() ? P.p : tile_code(sc))] = rec;
   drop_graphs(ctx);   // captured launches carry the old choice
   if (out_variant) *out_variant = best;
   if (out_count) *out_count = nv;
@@ -2090,6 +2115,19 @@ qtx_status qtx_rgf_observables(qtx_rgf_ctx ctx, int32_t b, int32_t n_e, const vo
   QTX_TRY(launch_zgemm_f64(d, s));
   QTX_TRY(launch_observables(b, n_e, (const double2*)GR_11, (const double2*)GL_11, sG, M1, M2,
                              (const double2*)gamma_L, f_L, T_L, j_L, s));
+  return QTX_OK;
+}
+
+qtx_status qtx_rgf_bond_currents(qtx_rgf_ctx ctx, int32_t b, int32_t n_b, int32_t n_e, const void* H_u,
+                                 const void* S_u, const double* energies, const void* GL_u, int64_t sGu, double* J,
+                                 void* hip_stream) {
+  if (!ctx) return QTX_ERR_ARG;
+  if (ctx->sticky != QTX_OK) return ctx->sticky;
+  if (b < 1 || n_b < 2 || n_e < 1 || !H_u || !energies || !GL_u || !J || sGu < (int64_t)(n_b - 1) * b * b)
+    return QTX_ERR_ARG;
+  DeviceGuard guard(ctx->device);
+  QTX_TRY(launch_bond_currents(b, n_b, n_e, (const double2*)H_u, (const double2*)S_u, energies,
+                               (const double2*)GL_u, sGu, J, (hipStream_t)hip_stream));
   return QTX_OK;
 }
 

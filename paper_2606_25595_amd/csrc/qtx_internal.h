@@ -68,6 +68,10 @@ struct GemmDesc {
   // -conj, and store the diagonal with its real part set to zero; the other schemes
   // compute every element.
   int skew = 0;
+  // Output tile edge of the FP64 / FP32 and split-digit products: 32 or 64, or 0 for the
+  // rule from the shape (the autotuner's choice when it has one).  Results do not depend
+  // on it.
+  int tile = 0;
 };
 
 // Precision schemes of the complex block products.
@@ -182,6 +186,10 @@ hipError_t launch_neg_ctrans_entries(double2* const* t, int b, int count, hipStr
 // dst[m] = -src[m]^H for `count` b x b blocks (distinct buffers).
 hipError_t launch_neg_ctrans_copy(const double2* const* src, double2* const* dst, int b, int count, hipStream_t s);
 hipError_t launch_scatter_status(const int32_t* st, int32_t* const* dst, int batch, hipStream_t s);
+// J[e][i] = 2 Re Tr[(Hu_i - E_e Su_i) G^<_{i+1,i}] for the n_b - 1 bonds of n_e energies
+// (G^<_{i+1,i} = -(GLu_i)^H; Su may be null for S = I; GLu of energy e at e * sGu).
+hipError_t launch_bond_currents(int b, int n_b, int n_e, const double2* Hu, const double2* Su, const double* E,
+                                const double2* GLu, int64_t sGu, double* J, hipStream_t s);
 hipError_t launch_observables(int b, int n_e, const double2* G, const double2* GL, int64_t sG,
                               const double2* M1, const double2* M2, const double2* gam,
                               const double* fL, double* T, double* j, hipStream_t s);

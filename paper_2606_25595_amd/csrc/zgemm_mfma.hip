@@ -367,13 +367,16 @@ static void launch_kind_tm(const GemmDesc& d, hipStream_t s) {
   else hipLaunchKernelGGL((zgemm_mfma_kernel<OP_C, OP_C, KIND, MATH, TM>), grid, block, 0, s, d);
 }
 
-// 64 x 64 tiles, or 32 x 32 when the 64 x 64 tiling pads C by more than 8% (its edge
+// 64 x 64 tiles, or 32 x 32 (the descriptor's tile when it names one, else the rule:
+// 32 x 32 when the 64 x 64 tiling pads C by more than 8% (its edge
 // tiles leave matrix cores idle: b = 416 is 6.5 tiles of 64 but 13 of 32; measured at
 // 256 products of 416^3, 2.385 ms with 32 x 32 tiles against 2.621 ms) or when the
 // launch has fewer than 4096 of them (16 per CU of the MI355X: at 8 to 64 energies of
-// b = 416 the smaller tiles were 10% faster, at one energy 25%).
+// b = 416 the smaller tiles were 10% faster, at one energy 25%)).
 constexpr int64_t kSmallTileBelow = 4096;
 static bool small_tiles(const GemmDesc& d) {
+  if (d.tile == 32) return true;
+  if (d.tile == 64) return false;
   const int64_t tm64 = (d.M + 63) / 64, tn64 = (d.N + 63) / 64, tm32 = (d.M + 31) / 32, tn32 = (d.N + 31) / 32;
   const int64_t area64 = tm64 * tn64 * 4096, area32 = tm32 * tn32 * 1024;
   return tm64 * tn64 * d.batch < kSmallTileBelow || 100 * area64 > 108 * area32;

@@ -39,7 +39,7 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));   // 16 bytes: 8 di
 namespace {
 
 constexpr int KS = 32;     // K strip = MFMA K of the 16-bit instructions
-constexpr int BM = 64, BN = 64, NT = 256;
+constexpr int NT = 256;
 
 __device__ inline int xcd_remap(int pid, int total) {
   const int nx = 8;
@@ -192,17 +192,22 @@ __device__ inline f4 mfma16(u4 a, u4 b, f4 c) {
 template <int FMT>
 constexpr int flush_strips() { return FMT == 1 ? 16 : 1; }
 
-template <int FMT, int NS, bool ONEFLUSH>
+// TM x TM output tile (TM = 64: each wave owns 2 x 2 blocks of 16 x 16; TM = 32: one
+// block per wave); both tilings sum every element in the same order, so they give the
+// same bits.
+template <int FMT, int NS, bool ONEFLUSH, int TM>
 __global__ __launch_bounds__(NT) void zgemm_split_kernel(SplitGemmDesc g) {
   constexpr int W = DigitFmt<FMT>::W;
   constexpr int FLUSH = flush_strips<FMT>();
   constexpr int NQ = 2 * NS;
+  constexpr int BM = TM, BN = TM, NW = TM / 32;
   constexpr int ROW_U4 = NQ * KS / 8 + 1;         // u4 per LDS row (+1 pad: conflict-free reads)
-  constexpr int TILE_U4 = 64 * NQ * KS / 8;       // u4 per operand tile in global memory
+  constexpr int TILE_U4 = TM * NQ * KS / 8;       // u4 per operand tile in global memory
   constexpr int PER_T = TILE_U4 / NT;             // u4 per thread
-  __shared__ u4 As[64 * ROW_U4];
-  __shared__ u4 Bs[64 * ROW_U4];
-  __shared__ int Ea[64], Eb[64];
+  static_assert(TILE_U4 % NT == 0, "tile copy split");
+  __shared__ u4 As[TM * ROW_U4];
+  __shared__ u4 Bs[TM * ROW_U4];
+  __shared__ int Ea[TM], Eb[TM];
 
   const GemmDesc& d = g.d;
   const int tiles_m = (d.M + BM - 1) / BM;
@@ -224,19 +229,19 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(SplitGemmDesc g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int li = lane & 15, lk = lane >> 4;
-  bool rv[2], cv[2];
+  bool rv[NW], cv[NW];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < NW; ++i) {
     rv[i] = m0 + 16 * (wm + 2 * i) < M;
     cv[i] = n0 + 16 * (wn + 2 * i) < N;
   }
 
-  f4 acc[2][2][2][3];   // [i][j][re/im][group]
-  double sum[2][2][2][4];
+  f4 acc[NW][NW][2][3];   // [i][j][re/im][group]
+  double sum[NW][NW][2][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NW; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NW; ++j)
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
 #pragma unroll
@@ -245,15 +250,15 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(SplitGemmDesc g) {
         for (int v = 0; v < 4; ++v) sum[i][j][c][v] = 0.0;
       }
   // row / column exponents of this tile (one per row of op(A), column of op(B))
-  if (tid < 64) Ea[tid] = (m0 + tid < M) ? EA[m0 + tid] : 0;
-  else if (tid < 128) Eb[tid - 64] = (n0 + tid - 64 < N) ? EB[n0 + tid - 64] : 0;
+  if (tid < TM) Ea[tid] = (m0 + tid < M) ? EA[m0 + tid] : 0;
+  else if (tid < 2 * TM) Eb[tid - TM] = (n0 + tid - TM < N) ? EB[n0 + tid - TM] : 0;
   // FP64 sums += 2^{eA + eB - 2W} (g2 + g3 + g4), then the groups restart.  16-bit
   // MFMA result layout: lane l, element v -> row 4(l/16) + v, column l%16.
   auto flush = [&]() {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NW; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NW; ++j) {
         const int eb = Eb[16 * (wn + 2 * j) + li];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -306,11 +311,11 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(SplitGemmDesc g) {
     // compile-time).  Every A digit fragment is read from LDS once per strip and
     // every B digit fragment once per strip; blocks outside C run on the zero
     // padding, so the MFMA stream has no branches.
-    u4 a[NS][2][2], an[NS][2];
+    u4 a[NS][NW][2], an[NS][NW];
     static_for<0, NS>([&](auto sc) {
       constexpr int s = decltype(sc)::value;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < NW; ++i) {
         const int row = 16 * (wm + 2 * i) + li;
         a[s][i][0] = As[row * ROW_U4 + (2 * s + 0) * (KS / 8) + lk];
         a[s][i][1] = As[row * ROW_U4 + (2 * s + 1) * (KS / 8) + lk];
@@ -319,9 +324,9 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(SplitGemmDesc g) {
     });
     static_for<0, NS>([&](auto tc) {
       constexpr int tt = decltype(tc)::value;
-      u4 b[2][2];
+      u4 b[NW][2];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NW; ++j) {
         const int col = 16 * (wn + 2 * j) + li;
         b[j][0] = Bs[col * ROW_U4 + (2 * tt + 0) * (KS / 8) + lk];
         b[j][1] = Bs[col * ROW_U4 + (2 * tt + 1) * (KS / 8) + lk];
@@ -331,21 +336,21 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(SplitGemmDesc g) {
         if constexpr (s + tt + 2 <= NS + 1) {
           constexpr int grp = (s + tt == 0) ? 0 : (s + tt == 1 ? 1 : 2);
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < NW; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j][0][grp] = mfma16<FMT>(a[s][i][0], b[j][0], acc[i][j][0][grp]);
+            for (int j = 0; j < NW; ++j) acc[i][j][0][grp] = mfma16<FMT>(a[s][i][0], b[j][0], acc[i][j][0][grp]);
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < NW; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j][1][grp] = mfma16<FMT>(a[s][i][0], b[j][1], acc[i][j][1][grp]);
+            for (int j = 0; j < NW; ++j) acc[i][j][1][grp] = mfma16<FMT>(a[s][i][0], b[j][1], acc[i][j][1][grp]);
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < NW; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j][0][grp] = mfma16<FMT>(an[s][i], b[j][1], acc[i][j][0][grp]);
+            for (int j = 0; j < NW; ++j) acc[i][j][0][grp] = mfma16<FMT>(an[s][i], b[j][1], acc[i][j][0][grp]);
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < NW; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j][1][grp] = mfma16<FMT>(a[s][i][1], b[j][0], acc[i][j][1][grp]);
+            for (int j = 0; j < NW; ++j) acc[i][j][1][grp] = mfma16<FMT>(a[s][i][1], b[j][0], acc[i][j][1][grp]);
         }
       });
     });
@@ -366,9 +371,9 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(SplitGemmDesc g) {
   }
   const double2 dg = d.diag_by_batch ? cmk(d.diag.x * bs, d.diag.y * bs) : d.diag;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NW; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NW; ++j) {
       if (!(rv[i] && cv[j])) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -401,18 +406,24 @@ hipError_t launch_split_t(const SplitDesc& sd, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int FMT, int NS>
-hipError_t launch_gemm_t(const SplitGemmDesc& g, hipStream_t s) {
+template <int FMT, int NS, int TM>
+hipError_t launch_gemm_tm(const SplitGemmDesc& g, hipStream_t s) {
   const GemmDesc& d = g.d;
-  const int tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
-  const int64_t total = (int64_t)tiles * d.batch;
+  const int64_t total = (int64_t)((d.M + TM - 1) / TM) * ((d.N + TM - 1) / TM) * d.batch;
   if (total > 0x7fffffff) return hipErrorInvalidValue;
   const int KT = (d.K + KS - 1) / KS;
   if (KT <= flush_strips<FMT>())
-    hipLaunchKernelGGL((zgemm_split_kernel<FMT, NS, true>), dim3((unsigned)total), dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((zgemm_split_kernel<FMT, NS, true, TM>), dim3((unsigned)total), dim3(NT), 0, s, g);
   else
-    hipLaunchKernelGGL((zgemm_split_kernel<FMT, NS, false>), dim3((unsigned)total), dim3(NT), 0, s, g);
+    hipLaunchKernelGGL((zgemm_split_kernel<FMT, NS, false, TM>), dim3((unsigned)total), dim3(NT), 0, s, g);
   return hipGetLastError();
+}
+
+// 64 x 64 tiles unless the descriptor asks for 32 x 32 (the autotuner's choice).
+template <int FMT, int NS>
+hipError_t launch_gemm_t(const SplitGemmDesc& g, hipStream_t s) {
+  if (g.d.tile == 32) return launch_gemm_tm<FMT, NS, 32>(g, s);
+  return launch_gemm_tm<FMT, NS, 64>(g, s);
 }
 
 }  // namespace

@@ -36,7 +36,7 @@ PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16"
 EXPORTED = ("qtx_rgf_create", "qtx_rgf_solve", "qtx_rgf_destroy", "qtx_rgf_footprint", "qtx_status_str",
             "qtx_zgemm", "qtx_zinv", "qtx_rgf_observables", "qtx_rgf_profile", "qtx_rgf_profile_read",
             "qtx_rgf_set_option", "qtx_rgf_get_stat", "qtx_ozaki2_bits", "qtx_rgf_tune", "qtx_w_assemble",
-            "qtx_fpx_encode", "qtx_fpx_decode", "qtx_zgemm_noalloc")
+            "qtx_fpx_encode", "qtx_fpx_decode", "qtx_zgemm_noalloc", "qtx_rgf_bond_currents")
 QTX_OPT_GRAPH, QTX_OPT_RESERVE_WORKSPACE, QTX_OPT_INT8_TILE_VARIANT, QTX_OPT_OVERLAP, QTX_OPT_LANE_SPLIT = 1, 2, 3, 4, 5
 QTX_STAT_GRAPH_LAUNCHES, QTX_STAT_GRAPH_CAPTURES, QTX_STAT_WORKSPACE_BYTES, QTX_STAT_TUNE_RECORDS = 1, 2, 3, 4
 QTX_KERNEL_GEMM, QTX_KERNEL_INV, QTX_KERNEL_CONVERT = 0, 1, 2
@@ -98,6 +98,8 @@ def load_library(path: str = LIB_PATH):
     lib.qtx_zinv.restype = ctypes.c_int
     lib.qtx_rgf_observables.argtypes = [vp, i32, i32, vp, vp, i64, vp, vp, vp, vp, vp]
     lib.qtx_rgf_observables.restype = ctypes.c_int
+    lib.qtx_rgf_bond_currents.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, i64, vp, vp]
+    lib.qtx_rgf_bond_currents.restype = ctypes.c_int
     lib.qtx_rgf_profile.argtypes = [vp, ctypes.c_int]
     lib.qtx_rgf_profile.restype = ctypes.c_int
     lib.qtx_rgf_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(i64),
@@ -537,6 +539,41 @@ class Context:
     def observables(self, dp: DeviceProblem, gamma_L, f_L, stream=None):
         """(T_L, j_L) per energy as device float64 tensors."""
         return self.observables_blocks(dp.GR_d, dp.GL_d, gamma_L, f_L, stream=stream)
+
+    def observables_right(self, dp: DeviceProblem, gamma_R, f_R, stream=None):
+        """(T_R, j_R) per energy: the observables of the last block (the right contact,
+        broadening gamma_R, occupation f_R), from the same kernel as the left ones."""
+        import torch
+        n_e, n_b, b = dp.n_e, dp.n_b, dp.b
+        T = torch.empty(n_e, dtype=torch.float64, device=dp.GR_d.device)
+        j = torch.empty_like(T)
+        fR = torch.as_tensor(np.ascontiguousarray(f_R, dtype=np.float64)).to(dp.GR_d.device)
+        g = torch.as_tensor(np.ascontiguousarray(gamma_R, dtype=np.complex128)).to(dp.GR_d.device)
+        if not (dp.GR_d.is_contiguous() and dp.GL_d.is_contiguous()):
+            raise ValueError("GR_d / GL_d must be contiguous")
+        off = (n_b - 1) * b * b * 16                      # bytes to block n_b - 1 of energy 0
+        gr = ctypes.c_void_p(dp.GR_d.data_ptr() + off)
+        gl = ctypes.c_void_p(dp.GL_d.data_ptr() + off)
+        rc = self.lib.qtx_rgf_observables(self.handle, b, n_e, gr, gl, n_b * b * b, _ptr(g), _ptr(fR), _ptr(T),
+                                          _ptr(j), _stream_ptr(stream))
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_rgf_observables")
+        return T, j
+
+    def bond_currents(self, dp: DeviceProblem, stream=None):
+        """J[e][i] = 2 Re Tr[(H_{i,i+1} - E S_{i,i+1}) G^<_{i+1,i}] per energy and bond,
+        a device float64 tensor [n_e][n_b - 1] (qtx_rgf_bond_currents)."""
+        import torch
+        n_e, n_b, b = dp.n_e, dp.n_b, dp.b
+        J = torch.empty((n_e, max(n_b - 1, 0)), dtype=torch.float64, device=dp.GR_d.device)
+        if n_b < 2:
+            return J
+        E = torch.as_tensor(np.ascontiguousarray(dp.energies, dtype=np.float64)).to(dp.GR_d.device)
+        rc = self.lib.qtx_rgf_bond_currents(self.handle, b, n_b, n_e, _ptr(dp.H_u), _ptr(dp.S_u), _ptr(E),
+                                            _ptr(dp.GL_u), (n_b - 1) * b * b, _ptr(J), _stream_ptr(stream))
+        if rc != QTX_OK:
+            raise QtxError(rc, "qtx_rgf_bond_currents")
+        return J
 
     def observables_blocks(self, GR_d, GL_d, gamma_L, f_L, stream=None):
         """(T_L, j_L) per energy from [n_e][n_b][b][b] G^R / G^< diagonal-block tensors

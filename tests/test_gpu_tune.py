@@ -76,18 +76,23 @@ def test_tune_records_and_cache(tmp_path):
         assert c.stat(qtx.QTX_STAT_TUNE_RECORDS) == 2
         v3, _ = c.tune(96, "int8", 9, batch=16)            # another modulus count: a third record
         assert c.stat(qtx.QTX_STAT_TUNE_RECORDS) == 3
-        assert c.tune(96, "fp64") == (0, [0.0])           # one configuration: nothing recorded
-        assert c.stat(qtx.QTX_STAT_TUNE_RECORDS) == 3
+        # FP64 / FP32 / split: two tilings (32 x 32, 64 x 64), one record per scheme
+        v4, ms4 = c.tune(96, "fp64", batch=16)
+        assert v4 in (0, 1) and len(ms4) == 2 and all(t > 0 for t in ms4) and ms4[v4] == min(ms4)
+        v5, _ = c.tune(96, "bf16", 3, batch=16)
+        v6, _ = c.tune(96, "fp32", batch=16)
+        assert c.stat(qtx.QTX_STAT_TUNE_RECORDS) == 6
     finally:
         c.close()
     lines = open(path).read().splitlines()
-    assert lines[0].startswith("qtx-tune 2 ")
+    assert lines[0].startswith("qtx-tune 3 ")
     recs = sorted(l.split()[:7] for l in lines[1:])
     assert recs == sorted([["o2", "96", "96", "96", "4", "8", str(v)], ["o2", "96", "96", "96", "8", "8", str(v2)],
-                           ["o2", "96", "96", "96", "4", "9", str(v3)]])
+                           ["o2", "96", "96", "96", "4", "9", str(v3)], ["tm", "96", "96", "96", "4", "100", str(v4)],
+                           ["tm", "96", "96", "96", "4", "123", str(v5)], ["tm", "96", "96", "96", "4", "110", str(v6)]])
     c2 = qtx.Context(0, tune_cache=path)
     try:
-        assert c2.stat(qtx.QTX_STAT_TUNE_RECORDS) == 3
+        assert c2.stat(qtx.QTX_STAT_TUNE_RECORDS) == 6
     finally:
         c2.close()
 
@@ -95,7 +100,7 @@ def test_tune_records_and_cache(tmp_path):
 def test_bad_cache_file_is_ignored(tmp_path):
     from paper_2606_25595_amd import qtx
     path = tmp_path / "bad.txt"
-    path.write_text("qtx-tune 2 some-other-device 7\no2 96 96 96 4 8 1 1.0 2.0 3.0\n")
+    path.write_text("qtx-tune 3 some-other-device 7\no2 96 96 96 4 8 1 1.0 2.0 3.0\n")
     c = qtx.Context(0, tune_cache=str(path))
     try:
         assert c.stat(qtx.QTX_STAT_TUNE_RECORDS) == 0
@@ -184,3 +189,56 @@ def test_variants_bitwise_equal_persistent_rounds(ctx, M, N, K, batch, ops):
     bound = 8 * 2.0 ** -kbits * K * np.abs(opa).max() * np.abs(opb).max()
     assert np.all(np.isfinite(outs[0]))
     assert np.abs(outs[0] - ref).max() <= bound
+
+
+@pytest.mark.parametrize("prec,ns", [("fp64", 0), ("fp32", 0), ("bf16", 4), ("fp16", 3)])
+def test_tile_tuning_bitwise_and_solve_unchanged(prec, ns):
+    """FP64, FP32 and split products with 32 x 32 or 64 x 64 tiles (forced through the
+    tuner's records) give the same bits; a solve before and after tuning is unchanged."""
+    import torch
+    from paper_2606_25595_amd import qtx
+    p = inputs.random_bt_problem(4, 100, np.array([-0.7, 0.4]), seed=23)
+    c = qtx.Context(0)
+    try:
+        dp = qtx.to_device(p)
+        c.solve(dp, prec=prec, n_slices=ns)
+        torch.cuda.synchronize()
+        before = dp.outputs()
+        rng = np.random.default_rng(5)
+        A = torch.from_numpy(rand_c(rng, 6, 100, 100)).cuda()
+        B = torch.from_numpy(rand_c(rng, 6, 100, 100)).cuda()
+        C1 = torch.empty_like(A)
+        C2 = torch.empty_like(A)
+        v, ms = c.tune(100, prec, ns, batch=6)      # records one tiling for this shape
+        c.zgemm(A, B, C1, opB="C", prec=prec, n_slices=ns)
+        # the other tiling: a record with the other variant, through a cache file round trip
+        import os, tempfile
+        fd, path = tempfile.mkstemp()
+        os.close(fd)
+        try:
+            code = {"fp64": 100, "fp32": 110, "bf16": 120 + ns, "fp16": 130 + ns}[prec]
+            from paper_2606_25595_amd import qtx as q
+            tag = open(path, "w")
+            tag.close()
+            c2 = q.Context(0, tune_cache=path)
+            c2.tune(100, prec, ns, batch=6)
+            c2.close()
+            lines = open(path).read().splitlines()
+            with open(path, "w") as fh:
+                fh.write(lines[0] + "\n")
+                fh.write("tm 100 100 100 3 %d %d 1.0 1.0\n" % (code, 1 - v))
+            c3 = q.Context(0, tune_cache=path)
+            c3.zgemm(A, B, C2, opB="C", prec=prec, n_slices=ns)
+            torch.cuda.synchronize()
+            c3.close()
+        finally:
+            os.unlink(path)
+        assert torch.equal(torch.view_as_real(C1), torch.view_as_real(C2))
+        dp2 = qtx.to_device(p)
+        c.solve(dp2, prec=prec, n_slices=ns)
+        torch.cuda.synchronize()
+        after = dp2.outputs()
+        for k in before:
+            assert np.array_equal(before[k], after[k]), k
+    finally:
+        c.close()
