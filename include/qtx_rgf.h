@@ -98,6 +98,7 @@ typedef enum {
 
 enum {
   QTX_S_IDENTITY = 1u,      /* S = I: S_d/S_u/S_l are ignored                        */
+  QTX_SIGMA_DIAG = 2u,      /* SR_d / SL_d / SG_d hold diagonals [n_e][n_b][b]        */
   QTX_WANT_GREATER = 8u,    /* also compute G^> from Sigma^> (SG_*)                   */
   QTX_SPLIT_CHAIN = 16u     /* solve each energy as two half-chains (see below)        */
 };
@@ -120,6 +121,11 @@ enum {
  *   are): the recurrences use that symmetry to evaluate a term and its
  *   conjugate transpose with one product (the cross terms of a BT Sigma^<
  *   cost one more product per forward step and two per backward step).
+ *   QTX_SIGMA_DIAG: the diagonal blocks of the self-energies are diagonal matrices
+ *   (as the contact and broadening terms of the paper's synthetic devices are): SR_d,
+ *   SL_d and SG_d are then [n_e][n_b][b] complex vectors, block i of energy e at
+ *   (e n_b + i) b, instead of b x b blocks (b times less HBM).  SR_u / SR_l / SL_u /
+ *   SG_u keep their dense layout.  Results equal those of the dense blocks.
  * Outputs (device, caller-allocated, written entirely):
  *   GR_d [n_e][n_b][b][b], GR_u [n_e][n_b-1][b][b] = G^R_{i,i+1},
  *   GR_l [n_e][n_b-1][b][b] = G^R_{i+1,i},
@@ -128,6 +134,16 @@ enum {
  *   status  [n_e] int32 per-energy qtx_status (QTX_OK, QTX_ERR_SINGULAR or
  *           QTX_ERR_NONFINITE), or NULL.  An energy that fails has every
  *           output block filled with NaN; other energies are unaffected.
+ *   out_bits  64 (or 0): every output is complex128.  16, 24, .., 56: the
+ *           off-diagonal outputs GR_u, GR_l, GL_u (and GG_u) are stored in the FPX
+ *           format of that width (Section V-A; see qtx_fpx_encode) -- each complex
+ *           element as two FPX codes (re, im), block i of energy e at byte
+ *           (e (n_b - 1) + i) b^2 out_bits / 4 -- encoded on the GPU from the FP64
+ *           result of each backward step (the recurrences themselves stay FP64; the
+ *           diagonal outputs GR_d, GL_d, GG_d hold recurrence state and stay
+ *           complex128).  A failed energy's FPX blocks hold the FPX NaN code.  With
+ *           out_bits = 32 the off-diagonal outputs take half the HBM.  Not available
+ *           with QTX_SPLIT_CHAIN (QTX_ERR_UNSUPPORTED).
  * Precision per chain: the products that build x_i and G^R (forward Schur
  * complements, backward G^R blocks) use (prec, n_slices); the products of the
  * lesser/greater recurrences use (prec_lesser, n_slices_lesser).  The lesser
@@ -166,6 +182,7 @@ typedef struct {
   void *GL_d, *GL_u;
   void *GG_d, *GG_u;
   int32_t* status;
+  int32_t out_bits;        /* 64 / 0: complex128 outputs; 16..56: FPX off-diagonal outputs */
 } qtx_rgf_problem;
 
 /* Create a context on HIP device `device`.  workspace_bytes caps the device

@@ -246,6 +246,7 @@ hipError_t launch_check_finite(const double2* X, int64_t per_batch, int64_t stri
 hipError_t launch_check_finite_entries(const double2* const* t, int64_t count, int batch, int32_t* status,
                                        hipStream_t s) {
   if (count <= 0 || batch <= 0) return hipSuccess;
+  if (!t) return hipErrorInvalidValue;
   int64_t g = (count + 1023) / 1024;
   if (g > 1024) g = 1024;
   hipLaunchKernelGGL(check_finite_entries_kernel, dim3((unsigned)g, batch), dim3(256), 0, s, t, count, status);
@@ -255,6 +256,7 @@ hipError_t launch_check_finite_entries(const double2* const* t, int64_t count, i
 hipError_t launch_nan_fill_entries(double2* const* t, const int64_t* counts, int batch, const int32_t* status,
                                    hipStream_t s) {
   if (batch <= 0) return hipSuccess;
+  if (!t) return hipErrorInvalidValue;
   hipLaunchKernelGGL(nan_fill_entries_kernel, dim3(256, batch), dim3(256), 0, s, t, counts, status);
   return hipGetLastError();
 }
@@ -267,6 +269,7 @@ hipError_t launch_status_merge(int32_t* st, const int32_t* part, int batch, hipS
 
 hipError_t launch_neg_ctrans_entries(double2* const* t, int b, int count, hipStream_t s) {
   if (count <= 0 || b <= 0) return hipSuccess;
+  if (!t) return hipErrorInvalidValue;
   const int nt = (b + 31) / 32;
   const int gy = count < 65535 ? count : 65535;
   hipLaunchKernelGGL(neg_ctrans_kernel, dim3((unsigned)(nt * (nt + 1) / 2), gy), dim3(256), 0, s, t, b, count);
@@ -275,6 +278,7 @@ hipError_t launch_neg_ctrans_entries(double2* const* t, int b, int count, hipStr
 
 hipError_t launch_neg_ctrans_copy(const double2* const* src, double2* const* dst, int b, int count, hipStream_t s) {
   if (count <= 0 || b <= 0) return hipSuccess;
+  if (!src || !dst) return hipErrorInvalidValue;
   const int nt = (b + 31) / 32;
   const int gy = count < 65535 ? count : 65535;
   hipLaunchKernelGGL(neg_ctrans_copy_kernel, dim3((unsigned)(nt * nt), gy), dim3(256), 0, s, src, dst, b, count);

@@ -570,6 +570,9 @@ hipError_t run_product(qtx_rgf_ctx ctx, const GemmDesc& d0, const Scheme& sc, co
 
 // ---------------------------------------------------------------- problem validation
 
+// Width of the off-diagonal outputs: 64 (complex128) or an FPX width.
+int out_fpx_bits(const qtx_rgf_problem& p) { return (p.out_bits == 0 || p.out_bits == 64) ? 64 : p.out_bits; }
+
 bool valid_problem(const qtx_rgf_problem* p) {
   if (!p) return false;
   if (p->n_b < 1 || p->b < 1 || p->n_e < 1 || p->b > 1024) return false;
@@ -598,7 +601,11 @@ qtx_status check_supported(const qtx_rgf_problem* p) {
   Scheme sc;
   if (!make_scheme(p->prec, p->n_slices, &sc)) return QTX_ERR_UNSUPPORTED;
   if (p->prec_lesser >= 0 && !make_scheme(p->prec_lesser, p->n_slices_lesser, &sc)) return QTX_ERR_UNSUPPORTED;
-  if (p->flags & ~(uint32_t)(QTX_S_IDENTITY | QTX_WANT_GREATER | QTX_SPLIT_CHAIN)) return QTX_ERR_ARG;
+  if (p->flags & ~(uint32_t)(QTX_S_IDENTITY | QTX_SIGMA_DIAG | QTX_WANT_GREATER | QTX_SPLIT_CHAIN)) return QTX_ERR_ARG;
+  if (p->out_bits != 0 && p->out_bits != 64 && !fpx_supported(p->out_bits)) return QTX_ERR_ARG;
+  // FPX off-diagonal outputs are encoded per backward step; the bottom halves of split
+  // energies fix up their lower blocks after the whole solve, so the two do not combine
+  if (out_fpx_bits(*p) < 64 && (p->flags & QTX_SPLIT_CHAIN) && p->n_b >= 3) return QTX_ERR_UNSUPPORTED;
   return QTX_OK;
 }
 
@@ -638,9 +645,11 @@ struct BatchKey {
   Scheme r, l;
   bool s_id = true, greater = false, coupled = false;
   bool l_bt = false, g_bt = false;   // Sigma^< / Sigma^> with off-diagonal blocks
+  bool sdiag = false;                // the diagonal self-energy blocks come as vectors
+  int obits = 64;                    // width of the off-diagonal outputs (64 or FPX)
   bool operator==(const BatchKey& o) const {
     return b == o.b && r == o.r && l == o.l && s_id == o.s_id && greater == o.greater && coupled == o.coupled &&
-           l_bt == o.l_bt && g_bt == o.g_bt;
+           l_bt == o.l_bt && g_bt == o.g_bt && sdiag == o.sdiag && obits == o.obits;
   }
 };
 
@@ -653,13 +662,20 @@ BatchKey key_of(const qtx_rgf_problem& p) {
   k.coupled = !k.s_id || p.SR_u || p.SR_l;
   k.l_bt = p.n_b > 1 && p.SL_u != nullptr;
   k.g_bt = k.greater && p.n_b > 1 && p.SG_u != nullptr;
+  k.sdiag = (p.flags & QTX_SIGMA_DIAG) != 0;
+  k.obits = out_fpx_bits(p);
   return k;
 }
+
+// Off-diagonal output blocks staged in FP64 before their FPX encoding: G^R_{i,i+1},
+// G^R_{i+1,i}, G^<_{i,i+1}, G^>_{i,i+1}.
+constexpr int kOutTemps = 4;
 
 // Workspace of a batch of Z entries (excluding its pointer tables).
 size_t batch_ws_bytes(const BatchKey& k, int Z) {
   const size_t blk = align_up((size_t)Z * k.b * k.b * sizeof(double2));
-  return blk * (1 + kTemps + 2) + align_up(gje_work_bytes(k.b, Z)) + align_up((size_t)Z * sizeof(int32_t)) +
+  return blk * (1 + kTemps + 2 + (k.obits < 64 ? kOutTemps : 0)) + align_up(gje_work_bytes(k.b, Z)) +
+         align_up((size_t)Z * sizeof(int32_t)) +
          split_pair_bytes(k.b, larger_split(k.r, k.l), Z, 2 + kKeepSlots) + split_pair_bytes(k.b, k.l, Z) + 1024;
 }
 
@@ -725,6 +741,7 @@ struct Run {
   hipEvent_t side_fork = nullptr, side_join = nullptr;
   Batch* B = nullptr;
   bool dry = true;
+  bool late = false;   // a pointer table was first requested after the dry pass (an internal error)
   std::map<TabKey, TabVal> tabs;
   std::vector<char> host;          // this batch's table area (per-entry data + tables)
   char* dev = nullptr;             // its device copy (launch pass)
@@ -806,7 +823,16 @@ struct Run {
       }
     }
     if (!base) return nullptr;
+    // diagonal self-energy blocks given as vectors: b elements per block
+    if (B->key.sdiag && (a == A_SRD || a == A_SLD || a == A_SGD)) return (const double2*)base + idx * B->key.b;
+    // FPX off-diagonal outputs: bb * obits / 4 bytes per block (a byte address)
+    if (is_fpx(a)) return (const double2*)((const char*)base + idx * bb * (B->key.obits / 4));
     return (const double2*)base + idx * bb;
+  }
+
+  // Arrays of this batch stored as FPX bytes (always addressed through tables).
+  bool is_fpx(int a) const {
+    return B->key.obits < 64 && (a == A_GRU || a == A_GRL || a == A_GLU || a == A_GGU);
   }
 
   Mat get(int a, int mode, int step, int delta) {
@@ -833,7 +859,7 @@ struct Run {
       bool any_null = false;
       for (int z = 0; z < Z; ++z) any_null |= (v[z] == nullptr);
       TabVal tv;
-      bool affine = mode != 2 && mode != 4 && Z > 0 && !any_null;
+      bool affine = mode != 2 && mode != 4 && Z > 0 && !any_null && !is_fpx(a);
       int64_t stride = 0;
       if (affine && Z > 1) {
         stride = v[1] - v[0];
@@ -844,6 +870,13 @@ struct Run {
       } else if (affine) {
         tv.base = v[0];
         tv.stride = stride;
+      } else if (!dry) {
+        // A pointer table first asked for after the dry pass has no uploaded copy: the
+        // launch pass must request exactly the tables of the dry pass.  Refuse (null
+        // operand; products and the entry launchers return an error) rather than
+        // hand a kernel an address past the uploaded tables.
+        late = true;
+        return Mat{};
       } else {
         const size_t off = align_up(host.size());
         host.resize(off + (size_t)Z * sizeof(void*));
@@ -865,9 +898,10 @@ struct Run {
   }
 };
 
-inline Addend addend_of(const Mat& m, double2 coef, int op = OP_N, int by_batch = 0) {
+inline Addend addend_of(const Mat& m, double2 coef, int op = OP_N, int by_batch = 0, int diag = 0) {
   Addend a;
   a.X = m.p; a.stride = m.stride; a.tX = m.tab; a.coef = coef; a.op = op; a.scale_by_batch = by_batch;
+  a.diag = diag;
   return a;
 }
 
@@ -884,6 +918,7 @@ struct Gemm {
   hipError_t go(int Z, int opA, Mat A, int opB, Mat B, Mat C, double2 alpha, std::initializer_list<Addend> adds,
                 double2 diag = cmk(0, 0), int K = -1, bool skew = false, ConvUse use = ConvUse()) const {
     if (run->dry || Z <= 0) return hipSuccess;
+    if (run->late) return hipErrorInvalidValue;
     GemmDesc d;
     d.M = b; d.N = b; d.K = (K < 0) ? b : K;
     d.opA = opA; d.opB = opB;
@@ -914,6 +949,7 @@ struct BatchWs {
   double2* Tm[kTemps] = {};
   double2* Uw = nullptr;
   double2* Lw = nullptr;
+  double2* Ot[kOutTemps] = {};   // FPX outputs: the FP64 off-diagonal blocks of a backward step
   GjeWork gw;
   int32_t* st = nullptr;
   SplitBufs sb;
@@ -933,6 +969,8 @@ BatchWs carve_batch(char* w, const BatchKey& k, int Z) {
   for (int t = 0; t < kTemps; ++t) { L.Tm[t] = (double2*)w; w += blk; }
   L.Uw = (double2*)w; w += blk;
   L.Lw = (double2*)w; w += blk;
+  if (k.obits < 64)
+    for (int t = 0; t < kOutTemps; ++t) { L.Ot[t] = (double2*)w; w += blk; }
   L.gw = gje_carve(w, k.b, Z); w += align_up(gje_work_bytes(k.b, Z));
   L.st = (int32_t*)w; w += align_up((size_t)Z * sizeof(int32_t));
   L.sb = carve_split(w, k.b, larger_split(k.r, k.l), Z, 2 + kKeepSlots);
@@ -1016,7 +1054,8 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
     if (W.en) { gm.energies = W.en + mlo; glm.energies = W.en + mlo; }
     // A_i = E S_ii - H_ii - Sigma^R_ii(E) as epilogue addends
     const Addend aH = addend_of(R.get(A_HD, 0, i, 0), mone);
-    const Addend aS = addend_of(R.get(A_SRD, 0, i, 0), mone);
+    const int sd = k.sdiag ? 1 : 0;   // diagonal self-energy blocks come as vectors
+    const Addend aS = addend_of(R.get(A_SRD, 0, i, 0), mone, OP_N, 0, sd);
     const Addend aO = k.s_id ? Addend{} : addend_of(R.get(A_SD, 0, i, 0), one, OP_N, 1);
     const double2 dg = k.s_id ? one : zero;
     if (i == 0) {
@@ -1041,11 +1080,13 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
       const Mat Bi = R.get(r.S, 0, i, 0);
       hipError_t e = G.go(Z, OP_N, L, OP_N, R.get(r.Gd, 0, i, -1), ws(W.Tm[1]), one, {});
       if (e != hipSuccess) return e;
-      if (r.SU < 0) return G.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one, {addend_of(Bi, one)}, zero, -1, true);
+      if (r.SU < 0)
+        return G.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one, {addend_of(Bi, one, OP_N, 0, sd)}, zero, -1, true);
       e = G.go(Z, OP_N, ws(W.Tm[0]), OP_N, R.get(r.SU, 0, i, -1), ws(W.Tm[4]), one, {});
       if (e != hipSuccess) return e;
       return G.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, ws(W.Tm[3]), one,
-                  {addend_of(Bi, one), addend_of(ws(W.Tm[4]), cmk(-sL, 0)), addend_of(ws(W.Tm[4]), cmk(sL, 0), OP_C)},
+                  {addend_of(Bi, one, OP_N, 0, sd), addend_of(ws(W.Tm[4]), cmk(-sL, 0)),
+                   addend_of(ws(W.Tm[4]), cmk(sL, 0), OP_C)},
                   zero, -1, true);
     };
     if (i > 0) {
@@ -1129,7 +1170,13 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
       const Rhs& r = rhs[q];
       const Mat Bi = R.get(r.S, 0, i, 0);
       if (i == 0) {
-        QTX_TRY(gl.go(Z, OP_N, xi, OP_N, Bi, ws(W.Tm[2]), one, {}, zero, -1, false, xA));
+        if (sd) {
+          // a diagonal B_0 is expanded into a dense block first (Tm[3] is free at i = 0)
+          QTX_TRY(gl.go(Z, OP_N, Mat{}, OP_N, Mat{}, ws(W.Tm[3]), zero, {addend_of(Bi, one, OP_N, 0, 1)}, zero, 0));
+          QTX_TRY(gl.go(Z, OP_N, xi, OP_N, ws(W.Tm[3]), ws(W.Tm[2]), one, {}, zero, -1, false, xA));
+        } else {
+          QTX_TRY(gl.go(Z, OP_N, xi, OP_N, Bi, ws(W.Tm[2]), one, {}, zero, -1, false, xA));
+        }
       } else {
         // Q_i (done above for the first recurrence);  Z = x_i Q
         if (q > 0) {
@@ -1156,8 +1203,11 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
     QTX_TRY(coupling(Z, 1, kk, 0));
     const Mat xi = R.get(A_GRD, 1, kk, 0);
     const Mat Gn = R.get(A_GRD, 1, kk, 1);
-    const Mat GRu = R.get(A_GRU, 1, kk, 0);
-    const Mat GRl = R.get(A_GRL, 1, kk, 0);
+    // With FPX off-diagonal outputs the step's blocks are formed in FP64 temporaries
+    // (Ot[0..3]), used from there as operands, and encoded at the end of the step.
+    const bool fpx = k.obits < 64;
+    const Mat GRu = fpx ? ws(W.Ot[0]) : R.get(A_GRU, 1, kk, 0);
+    const Mat GRl = fpx ? ws(W.Ot[1]) : R.get(A_GRL, 1, kk, 0);
     // Converted operands kept for a second use (slots 2..5): P' as A of G_{i,i+1} and V',
     // R' as B of G_{i+1,i} and G_ii, G_{i,i+1} as A of W' and G_ii; across the two chains
     // only when they use the same scheme.  With the INT8 scheme the left-operand residues
@@ -1185,7 +1235,9 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
     // With P = sU P', W = sL W', L = sL L' and the skew-Hermitian xl and BL = -BU^H:
     //   Y = -sL W' xl + x BU G_{i,i+1}^H,  Z = -sL xl L'^H + x BU,
     //   G<_{i,i+1} = Z G_{i+1}^H - sU V',  G<_ii = xl + V' P'^H + Y - Y^H,  V' = P' G<_{i+1}.
-    for (const Rhs& r : rhs) {
+    for (size_t q = 0; q < rhs.size(); ++q) {
+      const Rhs& r = rhs[q];
+      const Mat Gu = fpx ? ws(W.Ot[2 + q]) : R.get(r.Gu, 1, kk, 0);
       const Mat xl = R.get(r.Gd, 1, kk, 0);
       const Mat Gln = R.get(r.Gd, 1, kk, 1);
       const double2 msl = cmk(-sL, 0);
@@ -1199,12 +1251,22 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
         QTX_TRY(gl.go(Z, OP_N, xl, OP_C, L, Zp, msl, {}));                        // Z = -sL xl_i L'^H
       }
       QTX_TRY(gl.go(Z, OP_N, Pp, OP_N, Gln, Vp, one, {}, zero, -1, false, useP));   // V' = P' G<_{i+1}
-      QTX_TRY(gl.go(Z, OP_N, Zp, OP_C, Gn, R.get(r.Gu, 1, kk, 0), one, {addend_of(Vp, cmk(-sU, 0))}, zero, -1, false,
-                    gnH));
+      QTX_TRY(gl.go(Z, OP_N, Zp, OP_C, Gn, Gu, one, {addend_of(Vp, cmk(-sU, 0))}, zero, -1, false, gnH));
       QTX_TRY(gl.go(Z, OP_N, Vp, OP_C, Pp, xl, one,                               // G<_ii (in place)
                     {addend_of(xl, one), addend_of(Yp, one), addend_of(Yp, cmk(-1, 0), OP_C)}, zero, -1, true, pH));
     }
     QTX_TRY(g.go(Z, OP_N, GRu, OP_N, Rp, xi, cmk(-sL, 0), {addend_of(xi, one)}, zero, -1, false, useRG));   // G_ii
+    if (fpx) {
+      std::vector<std::pair<int, double2*>> enc{{A_GRU, W.Ot[0]}, {A_GRL, W.Ot[1]}};
+      for (size_t q = 0; q < rhs.size(); ++q) enc.push_back({rhs[q].Gu, W.Ot[2 + q]});
+      for (auto& e : enc) {
+        // the table is requested in the dry pass too: tables are laid out and uploaded there
+        const Mat dst = R.get(e.first, 1, kk, 0);
+        if (!dry)
+          QTX_TRY(launch_fpx_encode_entries(k.obits, 2 * bb, (const double*)e.second, 2 * bb, (uint8_t* const*)dst.tab,
+                                            Z, s));
+      }
+    }
   }
   // The bottom halves wrote their logical G^<_{i,i+1} (physical G^<_{j+1,j}) into the
   // physical upper slot j: the upper block is its negated conjugate transpose
@@ -1236,10 +1298,14 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
   for (const Rhs& r : rhs) { outs.push_back({r.Gd, true}); outs.push_back({r.Gu, false}); }
   for (auto& o : outs) {
     const Mat m = R.get(o.first, 2, 0, 0);
-    if (!dry) QTX_TRY(launch_nan_fill_entries((double2* const*)m.tab, o.second ? W.cnt_d : W.cnt_u, Zall, W.st, s));
+    if (dry) continue;
+    if (R.is_fpx(o.first))
+      QTX_TRY(launch_fpx_nan_fill_entries(k.obits, W.cnt_u, (uint8_t* const*)m.tab, Zall, W.st, s));
+    else
+      QTX_TRY(launch_nan_fill_entries((double2* const*)m.tab, o.second ? W.cnt_d : W.cnt_u, Zall, W.st, s));
   }
   if (!dry) QTX_TRY(launch_scatter_status(W.st, W.ust, Zall, s));
-  return QTX_OK;
+  return R.late ? QTX_ERR_HIP : QTX_OK;
 }
 
 // FNV-1a over bytes.

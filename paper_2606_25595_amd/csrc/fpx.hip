@@ -73,14 +73,16 @@ __device__ inline double fpx_value(uint64_t c) {
 // FP64 values in a rotated order to spread the LDS banks.
 constexpr int kTile = 2048;
 
+// Tile `tile` of the encode of n values x -> out (the body of the encode kernels).
 template <int X>
-__global__ __launch_bounds__(256) void fpx_encode_kernel(int64_t n, const double* __restrict__ x,
-                                                          uint8_t* __restrict__ out) {
+__device__ inline void fpx_encode_tile(int64_t n, const double* __restrict__ x, uint8_t* __restrict__ out,
+                                       int64_t tile) {
   constexpr int W = X / 8;   // 64-bit words per group of 8 values
   __shared__ __align__(16) double vin[kTile];
   __shared__ uint64_t wout[256 * W];
   const int t = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
+  const int64_t base = tile * kTile;
+  if (base >= n) return;
   const int cnt = (n - base >= kTile) ? kTile : (int)(n - base);   // values in this tile
   if (cnt == kTile && ((uintptr_t)x & 15) == 0) {   // 16-byte loads need 16-byte alignment
     const double2* src = (const double2*)(x + base);
@@ -111,11 +113,39 @@ __global__ __launch_bounds__(256) void fpx_encode_kernel(int64_t n, const double
   const int64_t obase = base / 8 * X;                   // byte offset of the tile's codes
   const int nbytes = cnt * (X / 8);
   uint8_t* dst = out + obase;
-  if (nbytes % 8 == 0) {
+  if (nbytes % 8 == 0 && ((uintptr_t)dst & 7) == 0) {
     for (int q = t; q < nbytes / 8; q += 256) ((uint64_t*)dst)[q] = wout[q];
   } else {
     for (int q = t; q < nbytes; q += 256) dst[q] = (uint8_t)(wout[q / 8] >> (8 * (q % 8)));
   }
+}
+
+template <int X>
+__global__ __launch_bounds__(256) void fpx_encode_kernel(int64_t n, const double* __restrict__ x,
+                                                          uint8_t* __restrict__ out) {
+  fpx_encode_tile<X>(n, x, out, blockIdx.x);
+}
+
+// Batch entry z = blockIdx.y: n values at x + z * sx into the byte buffer dst[z].
+template <int X>
+__global__ __launch_bounds__(256) void fpx_encode_entries_kernel(int64_t n, const double* __restrict__ x, int64_t sx,
+                                                                  uint8_t* const* __restrict__ dst) {
+  fpx_encode_tile<X>(n, x + (int64_t)blockIdx.y * sx, dst[blockIdx.y], blockIdx.x);
+}
+
+// The quiet-NaN code of every one of n values of the byte buffers dst[z] of failed
+// entries (status[z] != 0).
+template <int X>
+__global__ __launch_bounds__(256) void fpx_nan_fill_entries_kernel(const int64_t* __restrict__ counts,
+                                                                    uint8_t* const* __restrict__ dst,
+                                                                    const int32_t* __restrict__ status) {
+  const int z = blockIdx.y;
+  if (status[z] == 0) return;
+  const uint64_t code = fpx_code<X>(__builtin_nan(""));
+  uint8_t* out = dst[z];
+  const int64_t nbytes = 2 * counts[z] * (X / 8);   // counts: complex elements
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nbytes; q += (int64_t)gridDim.x * blockDim.x)
+    out[q] = (uint8_t)(code >> (8 * (q % (X / 8))));
 }
 
 template <int X>
@@ -171,7 +201,45 @@ hipError_t launch_x(bool enc, int64_t n, const void* a, void* b, hipStream_t s) 
   return hipGetLastError();
 }
 
+template <int X>
+hipError_t launch_entries_x(int64_t n, const double* x, int64_t sx, uint8_t* const* dst, int count,
+                            const int64_t* counts, const int32_t* status, hipStream_t s) {
+  if (status) {
+    hipLaunchKernelGGL(fpx_nan_fill_entries_kernel<X>, dim3(256, count), dim3(256), 0, s, counts, dst, status);
+  } else {
+    const int64_t blocks = (n + kTile - 1) / kTile;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fpx_encode_entries_kernel<X>, dim3((unsigned)blocks, count), dim3(256), 0, s, n, x, sx, dst);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_entries(int bits, int64_t n, const double* x, int64_t sx, uint8_t* const* dst, int count,
+                          const int64_t* counts, const int32_t* status, hipStream_t s) {
+  if ((!status && n <= 0) || count <= 0) return hipSuccess;
+  if (!dst || (!status && !x)) return hipErrorInvalidValue;
+  switch (bits) {
+    case 16: return launch_entries_x<16>(n, x, sx, dst, count, counts, status, s);
+    case 24: return launch_entries_x<24>(n, x, sx, dst, count, counts, status, s);
+    case 32: return launch_entries_x<32>(n, x, sx, dst, count, counts, status, s);
+    case 40: return launch_entries_x<40>(n, x, sx, dst, count, counts, status, s);
+    case 48: return launch_entries_x<48>(n, x, sx, dst, count, counts, status, s);
+    case 56: return launch_entries_x<56>(n, x, sx, dst, count, counts, status, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_fpx_encode_entries(int bits, int64_t n, const double* x, int64_t sx, uint8_t* const* dst, int count,
+                                     hipStream_t s) {
+  return launch_entries(bits, n, x, sx, dst, count, nullptr, nullptr, s);
+}
+
+hipError_t launch_fpx_nan_fill_entries(int bits, const int64_t* counts, uint8_t* const* dst, int count,
+                                       const int32_t* status, hipStream_t s) {
+  return launch_entries(bits, 0, nullptr, 0, dst, count, counts, status, s);
+}
 
 bool fpx_supported(int bits) {
   return bits == 16 || bits == 24 || bits == 32 || bits == 40 || bits == 48 || bits == 56;

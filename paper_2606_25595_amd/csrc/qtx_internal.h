@@ -30,7 +30,8 @@ __host__ __device__ inline double2 cinv(double2 a) {
 
 enum Op { OP_N = 0, OP_C = 1 };
 
-// An epilogue addend: out += coef * (scale_by_batch ? bscal[z] : 1) * op(X_z)
+// An epilogue addend: out += coef * (scale_by_batch ? bscal[z] : 1) * op(X_z), or with
+// diag = 1 the diagonal matrix of the vector X_z (element r at X_z[r], added where r == c).
 struct Addend {
   const double2* const* tX = nullptr;   // per-batch-entry pointers (overrides X + z*stride)
   const double2* X = nullptr;
@@ -38,7 +39,14 @@ struct Addend {
   double2 coef = {0.0, 0.0};
   int op = OP_N;
   int scale_by_batch = 0;
+  int diag = 0;
 };
+
+// op(X)[r][c] of an addend (the caller checks diag addends for r == c).
+__device__ inline double2 addend_value(const double2* X, int diag, int op, int64_t ld, int r, int c) {
+  if (diag) return op == OP_N ? X[r] : cconj(X[r]);
+  return op == OP_N ? X[(int64_t)r * ld + c] : cconj(X[(int64_t)c * ld + r]);
+}
 
 constexpr int kMaxAddends = 3;
 
@@ -166,6 +174,13 @@ hipError_t launch_gje_invert(int n, double2* X, int64_t sX, double2* Out, int64_
 // reads n doubles and writes n X / 8 bytes, decode the reverse.
 bool fpx_supported(int bits);
 hipError_t launch_fpx(bool encode, int bits, int64_t n, const void* src, void* dst, hipStream_t s);
+// Batched: entry z encodes n doubles at x + z * sx into the byte buffer dst[z] (a device
+// table of count pointers); the NaN fill writes the NaN code over the 2 counts[z] values
+// (counts in complex elements) of dst[z] of every entry with status[z] != 0.
+hipError_t launch_fpx_encode_entries(int bits, int64_t n, const double* x, int64_t sx, uint8_t* const* dst, int count,
+                                     hipStream_t s);
+hipError_t launch_fpx_nan_fill_entries(int bits, const int64_t* counts, uint8_t* const* dst, int count,
+                                       const int32_t* status, hipStream_t s);
 
 // Status / NaN fill / observables helpers.
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

@@ -240,9 +240,8 @@ __global__ __launch_bounds__(NT) void zgemm_mfma_kernel(GemmDesc d) {
           double2 out = cmul(d.alpha, cmk((double)acc_re[i][j][v], (double)acc_im[i][j][v]));
 #pragma unroll
           for (int q = 0; q < kMaxAddends; ++q) {
-            if (X[q]) {
-              double2 x = (d.add[q].op == OP_N) ? X[q][(int64_t)r * d.add[q].ld + c]
-                                                 : cconj(X[q][(int64_t)c * d.add[q].ld + r]);
+            if (X[q] && (!d.add[q].diag || r == c)) {
+              const double2 x = addend_value(X[q], d.add[q].diag, d.add[q].op, d.add[q].ld, r, c);
               out = cadd(out, cmul(coef[q], x));
             }
           }
@@ -404,7 +403,7 @@ static hipError_t launch_zgemm_mfma(const GemmDesc& d, hipStream_t s, int kind, 
     // contract of the update form: C = X + A B, op N, K <= BK, X the only addend (op N)
     if (d.K > BK || d.opA != OP_N || d.opB != OP_N || d.alpha.x != 1.0 || d.alpha.y != 0.0 ||
         (!d.add[0].X && !d.add[0].tX) || d.add[0].op != OP_N || d.add[0].coef.x != 1.0 || d.add[0].coef.y != 0.0 ||
-        d.add[0].scale_by_batch || d.add[1].X || d.add[1].tX || d.add[2].X || d.add[2].tX || d.diag.x != 0.0 ||
+        d.add[0].scale_by_batch || d.add[0].diag || d.add[1].X || d.add[1].tX || d.add[2].X || d.add[2].tX || d.diag.x != 0.0 ||
         d.diag.y != 0.0)
       return hipErrorInvalidValue;
     if (small_tiles(d)) {

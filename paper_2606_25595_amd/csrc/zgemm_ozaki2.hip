@@ -665,9 +665,8 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles, int persist) 
           double2 out = cmul(alpha, cmk(cr, ci));
 #pragma unroll
           for (int q = 0; q < kMaxAddends; ++q) {
-            if (X[q]) {
-              const double2 xv = (d.add[q].op == OP_N) ? X[q][(int64_t)r * d.add[q].ld + col]
-                                                        : cconj(X[q][(int64_t)col * d.add[q].ld + r]);
+            if (X[q] && (!d.add[q].diag || r == col)) {
+              const double2 xv = addend_value(X[q], d.add[q].diag, d.add[q].op, d.add[q].ld, r, col);
               out = cadd(out, cmul(coef[q], xv));
             }
           }

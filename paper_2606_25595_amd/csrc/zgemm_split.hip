@@ -385,9 +385,8 @@ __global__ __launch_bounds__(NT) void zgemm_split_kernel(SplitGemmDesc g) {
           double2 out = nf ? cmk(nan, nan) : cmul(d.alpha, cmk(sum[i][j][0][v], sum[i][j][1][v]));
 #pragma unroll
           for (int q = 0; q < kMaxAddends; ++q) {
-            if (X[q]) {
-              double2 x = (d.add[q].op == OP_N) ? X[q][(int64_t)r * d.add[q].ld + c]
-                                                 : cconj(X[q][(int64_t)c * d.add[q].ld + r]);
+            if (X[q] && (!d.add[q].diag || r == c)) {
+              const double2 x = addend_value(X[q], d.add[q].diag, d.add[q].op, d.add[q].ld, r, c);
               out = cadd(out, cmul(coef[q], x));
             }
           }

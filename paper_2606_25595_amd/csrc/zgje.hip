@@ -446,7 +446,7 @@ GjeWork gje_carve(void* base, int n, int batch) {
 hipError_t launch_gje_invert(int n, double2* X, int64_t sX, double2* Out, int64_t sOut, int batch,
                              const GjeWork& w, int32_t* status, hipStream_t s, double2* const* tOut) {
   if (n <= 0 || batch <= 0) return hipSuccess;
-  if (n > 1024) return hipErrorInvalidValue;
+  if (n > 1024 || !X || (!Out && !tOut)) return hipErrorInvalidValue;
   const int nb = gje_panel_width(n);
   {
     const int64_t tot = (int64_t)n * batch;

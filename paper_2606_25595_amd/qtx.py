@@ -28,6 +28,7 @@ LIB_PATH = os.path.join(HERE, "libqtx_rgf.so")
 QTX_OK, QTX_ERR_ARG, QTX_ERR_NOMEM, QTX_ERR_HIP, QTX_ERR_UNSUPPORTED, QTX_ERR_SINGULAR, QTX_ERR_NONFINITE = range(7)
 QTX_FP64, QTX_FP32, QTX_BF16_SPLIT, QTX_FP16_SPLIT, QTX_INT8_OZAKI2 = range(5)
 QTX_S_IDENTITY = 1
+QTX_SIGMA_DIAG = 2
 QTX_WANT_GREATER = 8
 QTX_SPLIT_CHAIN = 16
 PREC_NAMES = {"fp64": QTX_FP64, "fp32": QTX_FP32, "bf16": QTX_BF16_SPLIT, "fp16": QTX_FP16_SPLIT,
@@ -63,6 +64,7 @@ class _Problem(ctypes.Structure):
         ("GL_d", ctypes.c_void_p), ("GL_u", ctypes.c_void_p),
         ("GG_d", ctypes.c_void_p), ("GG_u", ctypes.c_void_p),
         ("status", ctypes.c_void_p),
+        ("out_bits", ctypes.c_int32),
     ]
 
 
@@ -180,6 +182,8 @@ class DeviceProblem:
     GG_d: object = None
     GG_u: object = None
     split: bool = False     # QTX_SPLIT_CHAIN: two half-chains per energy
+    sigma_diag: bool = False   # QTX_SIGMA_DIAG: SR_d / SL_d / SG_d are [n_e, n_b, b] diagonals
+    out_bits: int = 64      # 64: complex128 outputs; 16..56: GR_u/GR_l/GL_u/GG_u as FPX bytes
 
     @property
     def n_b(self):
@@ -194,7 +198,8 @@ class DeviceProblem:
         return int(self.energies.shape[0])
 
     def outputs(self):
-        """Host copies of the outputs, keyed like the oracle's results."""
+        """Host copies of the outputs, keyed like the oracle's results (FPX outputs as
+        their bytes, [n_e, n_b - 1, b * b * out_bits / 4] uint8)."""
         out = {k: getattr(self, k).cpu().numpy() for k in ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")}
         if self.GG_d is not None:
             out["GG_d"] = self.GG_d.cpu().numpy()
@@ -203,11 +208,14 @@ class DeviceProblem:
         return out
 
 
-def to_device(p, device="cuda", greater: Optional[bool] = None) -> DeviceProblem:
+def to_device(p, device="cuda", greater: Optional[bool] = None, sigma_diag: bool = False,
+              out_bits: int = 64) -> DeviceProblem:
     """Copy a host problem (paper_2606_25595_amd.inputs.BTProblem) to the device
     and allocate its outputs (uninitialised).  A BT Sigma^< / Sigma^> travels as its
     upper blocks only (SL_u / SG_u): the library takes the lower blocks as
-    -(upper)^H, so SL_l / SG_l are not copied."""
+    -(upper)^H, so SL_l / SG_l are not copied.  sigma_diag: the diagonal self-energy
+    blocks travel as their diagonals (they must be diagonal matrices).  out_bits < 64:
+    the off-diagonal outputs are FPX byte buffers of that width."""
     import torch
 
     def dev(a):
@@ -215,24 +223,38 @@ def to_device(p, device="cuda", greater: Optional[bool] = None) -> DeviceProblem
             return None
         return torch.from_numpy(np.require(a, dtype=np.complex128, requirements=["C", "W"])).to(device)
 
+    def sdiag(a):
+        if a is None or not sigma_diag:
+            return dev(a)
+        d = np.diagonal(a, axis1=-2, axis2=-1)
+        off = ~np.eye(a.shape[-1], dtype=bool)
+        if np.any(a[..., off] != 0):
+            raise ValueError("sigma_diag: a diagonal self-energy block has off-diagonal entries")
+        return dev(d)
+
     n_e, n_b, b = p.n_e, p.n_b, p.b
     if greater is None:
         greater = p.SG_d is not None
+    out_bits = 64 if out_bits in (0, 64) else int(out_bits)
     kw = dict(dtype=torch.complex128, device=device)
+
+    def offdiag():
+        if out_bits == 64:
+            return torch.empty((n_e, max(n_b - 1, 0), b, b), **kw)
+        return torch.empty((n_e, max(n_b - 1, 0), b * b * out_bits // 4), dtype=torch.uint8, device=device)
     dp = DeviceProblem(
         energies=np.ascontiguousarray(p.energies, dtype=np.float64),
-        H_d=dev(p.H_d), H_u=dev(p.H_u), H_l=dev(p.H_l), SR_d=dev(p.SR_d), SL_d=dev(p.SL_d),
-        GR_d=torch.empty((n_e, n_b, b, b), **kw), GR_u=torch.empty((n_e, max(n_b - 1, 0), b, b), **kw),
-        GR_l=torch.empty((n_e, max(n_b - 1, 0), b, b), **kw), GL_d=torch.empty((n_e, n_b, b, b), **kw),
-        GL_u=torch.empty((n_e, max(n_b - 1, 0), b, b), **kw),
+        H_d=dev(p.H_d), H_u=dev(p.H_u), H_l=dev(p.H_l), SR_d=sdiag(p.SR_d), SL_d=sdiag(p.SL_d),
+        GR_d=torch.empty((n_e, n_b, b, b), **kw), GR_u=offdiag(), GR_l=offdiag(),
+        GL_d=torch.empty((n_e, n_b, b, b), **kw), GL_u=offdiag(),
         status=torch.full((n_e,), -1, dtype=torch.int32, device=device),
         S_d=dev(p.S_d), S_u=dev(p.S_u), S_l=dev(p.S_l), SR_u=dev(p.SR_u), SR_l=dev(p.SR_l),
-        SL_u=dev(p.SL_u))
+        SL_u=dev(p.SL_u), sigma_diag=bool(sigma_diag), out_bits=out_bits)
     if greater:
-        dp.SG_d = dev(p.SG_d)
+        dp.SG_d = sdiag(p.SG_d)
         dp.SG_u = dev(p.SG_u)
         dp.GG_d = torch.empty((n_e, n_b, b, b), **kw)
-        dp.GG_u = torch.empty((n_e, max(n_b - 1, 0), b, b), **kw)
+        dp.GG_u = offdiag()
     return dp
 
 
@@ -287,7 +309,10 @@ def _problem_struct(dp: DeviceProblem, prec: int, n_slices: int, prec_lesser: in
         flags |= QTX_WANT_GREATER
     if dp.split:
         flags |= QTX_SPLIT_CHAIN
+    if dp.sigma_diag:
+        flags |= QTX_SIGMA_DIAG
     st.flags = flags
+    st.out_bits = int(dp.out_bits)
     en = np.ascontiguousarray(dp.energies, dtype=np.float64)
     st.energies = en.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     for name in ("H_d", "H_u", "H_l", "S_d", "S_u", "S_l", "SR_d", "SR_u", "SR_l", "SL_d", "SL_u", "SG_d", "SG_u",
