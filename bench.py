@@ -162,13 +162,15 @@ def main():
     ap.add_argument("--no-full-check", action="store_true",
                     help="skip the all-energy error check of the mixed schemes (then none qualifies)")
     ap.add_argument("--workload", default="realistic",
-                    choices=["realistic", "hard", "kappa", "w", "fpx", "batch", "serve", "latency", "tiny"],
+                    choices=["realistic", "hard", "kappa", "w", "fpx", "batch", "serve", "latency", "tiny", "memory"],
                     help="realistic (default, the headline line) | hard (the realistic shapes at eta = 1e-6, "
                          "condition numbers up to ~5e6) | kappa (error against the exact condition number, "
                          "n_b=8, b=128, eta 1e-3..1e-6) | w (screened Coulomb system: assembly + solve, n_b=16, "
                          "b=256, 128 energies) | fpx (FPX storage codec GB/s on G^R blocks) | batch (512 uneven "
                          "problems, one graph launch) | "
-                         "serve (Poisson arrivals, continuous batching, p50/p99)")
+                         "serve (Poisson arrivals, continuous batching, p50/p99) | latency (few energies) | "
+                         "tiny (n_b=8, b=16, 32 energies; both CPU oracles) | memory (energies resident per GPU "
+                         "under dense / diagonal Sigma and complex128 / FPX32 outputs)")
     ap.add_argument("--workspace-gb", type=float, default=0.0,
                     help="realistic/hard: library workspace cap in GiB (0 = a quarter of free HBM)")
     ap.add_argument("--split", action="store_true",
@@ -182,6 +184,7 @@ def main():
     ap.add_argument("--duration", type=float, default=60.0, help="serve workload: arrival window (s)")
     ap.add_argument("--time-limit", type=float, default=150.0, help="serve workload: wall-clock cap (s)")
     ap.add_argument("--prec", default="fp64", help="batch workload scheme (fp64 | int8:11 | int8:10/int8:11 | ...)")
+    ap.add_argument("--mem-prec", default="int8:10/int8:10", help="memory workload scheme")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: energies shard across GPUs with no exchange inside a solve, "
@@ -206,6 +209,8 @@ def main():
         return bench_latency(args)
     if args.workload == "tiny":
         return bench_tiny(args)
+    if args.workload == "memory":
+        return bench_memory(args)
 
     cfg = inputs.CONFIGS["realistic"]
     n_b, b, n_e = cfg["n_b"], cfg["b"], cfg["n_e"]
@@ -691,6 +696,123 @@ def bench_fpx(args):
                          "achieved": rows[best]["encode_GBps"], "frac": rows[best]["encode_GBps"] / 8000.0,
                          "kernel": "fpx_encode_kernel<%d>" % best},
             "formats": rows}
+    print(json.dumps(line), flush=True)
+
+
+def bench_memory(args):
+    """Energies a GPU keeps resident under each HBM storage form of the realistic device
+    (n_b = 32, b = 416, eta = 1e-3, the grid linspace(-2, 2, n_e)), the memory lever of
+    Section V-A (Table IV):
+      dense_sigma_c128   Sigma^R_ii, Sigma^<_ii as b x b blocks, every output complex128;
+      diag_sigma_c128    the diagonal self-energy blocks as b-vectors (QTX_SIGMA_DIAG);
+      diag_sigma_fpx32   and the off-diagonal outputs G^R_{i,i+1}, G^R_{i+1,i}, G^<_{i,i+1}
+                         as FPX32 (out_bits = 32; the diagonal outputs carry recurrence
+                         state and stay complex128).
+    With the library workspace fixed (--workspace-gb, default 24 GiB, reserved first), each
+    form gets the largest energy count whose inputs and outputs fit the free HBM (less
+    2 GiB); that many energies are then allocated, built on the device and solved (one
+    warm-up solve, one timed), which shows that they fit.  The FPX error: the decoded
+    off-diagonal blocks of 32 energies against the complex128 outputs of the same scheme,
+    for X = 32, 40, 48, next to the scheme's own error against FP64 solves."""
+    import numpy as np
+    import torch
+    from paper_2606_25595_amd import inputs, qtx
+    cfg = inputs.CONFIGS["realistic"]
+    n_b, b = cfg["n_b"], cfg["b"]
+    skw = parse_scheme(args.mem_prec)
+    ws = int((args.workspace_gb or 24.0) * (1 << 30))
+    ctx = qtx.Context(0, workspace_bytes=ws)
+    ctx.reserve_workspace(ws)
+    tuned = autotune(ctx, skw, [(b, 256)])
+    blk = b * b * 16
+    forms = {"dense_sigma_c128": dict(sigma_diag=False, out_bits=64),
+             "diag_sigma_c128": dict(sigma_diag=True, out_bits=64),
+             "diag_sigma_fpx32": dict(sigma_diag=True, out_bits=32)}
+
+    def per_energy(f):
+        s_in = 2 * n_b * (b * 16 if f["sigma_diag"] else blk)
+        off = 3 * (n_b - 1) * (blk if f["out_bits"] == 64 else b * b * f["out_bits"] // 4)
+        return s_in + 2 * n_b * blk + off + 4
+
+    H_d, H_u, H_l = (torch.from_numpy(np.ascontiguousarray(a)).to("cuda") for a in inputs.random_hamiltonian(n_b, b, 0))
+
+    def build(n_e, f, grid=None):
+        grid = np.linspace(-2.0, 2.0, n_e) if grid is None else grid
+        sr, sl = inputs.random_bt_scalars(n_b, grid, eta=1e-3)
+        if f["sigma_diag"]:
+            def vec(x):
+                return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")[:, :, None].expand(n_e, n_b, b).contiguous()
+            SR, SL = vec(sr), vec(sl)
+        else:
+            SR, SL = inputs.diag_blocks_device(sr, b), inputs.diag_blocks_device(sl, b)
+        kw = dict(dtype=torch.complex128, device="cuda")
+
+        def offd():
+            if f["out_bits"] == 64:
+                return torch.empty((n_e, n_b - 1, b, b), **kw)
+            return torch.empty((n_e, n_b - 1, b * b * f["out_bits"] // 4), dtype=torch.uint8, device="cuda")
+        return qtx.DeviceProblem(energies=grid, H_d=H_d, H_u=H_u, H_l=H_l, SR_d=SR, SL_d=SL,
+                                 GR_d=torch.empty((n_e, n_b, b, b), **kw), GR_u=offd(), GR_l=offd(),
+                                 GL_d=torch.empty((n_e, n_b, b, b), **kw), GL_u=offd(),
+                                 status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"),
+                                 sigma_diag=f["sigma_diag"], out_bits=f["out_bits"])
+
+    rows = {}
+    for name, f in forms.items():
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        free, total = torch.cuda.mem_get_info()
+        n_e = int((free - (2 << 30)) // per_energy(f))
+        log("bench memory: %s: %.1f MB per energy, %.1f GiB free -> %d energies"
+            % (name, per_energy(f) / 1e6, free / 2 ** 30, n_e))
+        dp = build(n_e, f)
+        ctx.solve(dp, **skw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.solve(dp, **skw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = bool((dp.status == 0).all().item())
+        rows[name] = {"bytes_per_energy": per_energy(f), "energies_resident": n_e, "solve_s": dt,
+                      "energies_per_s": n_e / dt, "status_ok": ok, "hbm_free_gib": free / 2 ** 30}
+        log("bench memory: %s: %d energies solved in %.2f s (%.1f energies/s), status ok %s"
+            % (name, n_e, dt, n_e / dt, ok))
+        del dp
+    # FPX error on 32 energies: decoded blocks against the complex128 outputs of the same
+    # scheme, and that scheme against FP64
+    grid = np.linspace(-2.0, 2.0, 256)[::8]
+    ref64 = build(32, forms["diag_sigma_c128"], grid)
+    ctx.solve(ref64, prec="fp64")
+    mixed = build(32, forms["diag_sigma_c128"], grid)
+    ctx.solve(mixed, **skw)
+
+    def rel(X, R):
+        d = (X - R).abs().pow(2).sum((-1, -2)).sqrt()
+        return float((d / R.abs().pow(2).sum((-1, -2)).sqrt().clamp_min(1e-300)).max().item())
+    err = {"scheme_vs_fp64": {k: rel(getattr(mixed, k), getattr(ref64, k)) for k in ("GR_u", "GR_l", "GL_u")}}
+    for bits in (32, 40, 48):
+        fx = build(32, dict(sigma_diag=True, out_bits=bits), grid)
+        ctx.solve(fx, **skw)
+        e_fmt, e_tot = {}, {}
+        for k in ("GR_u", "GR_l", "GL_u"):
+            raw = getattr(fx, k)
+            dec = ctx.fpx_decode(raw.reshape(-1), bits, raw.numel() * 8 // bits)
+            dec = torch.view_as_complex(dec.view(-1, 2)).view(32, n_b - 1, b, b)
+            e_fmt[k] = rel(dec, getattr(mixed, k))
+            e_tot[k] = rel(dec, getattr(ref64, k))
+        err["fpx%d" % bits] = {"decoded_vs_scheme_c128": e_fmt, "decoded_vs_fp64": e_tot}
+        log("bench memory: FPX%d decoded vs %s complex128 %s, vs fp64 %s" % (bits, args.mem_prec, e_fmt, e_tot))
+        del fx
+    ctx.close()
+    base = rows["dense_sigma_c128"]["energies_resident"]
+    best = rows["diag_sigma_fpx32"]
+    line = {"metric": "energies resident per GPU (inputs + selected outputs in HBM), realistic device",
+            "value": best["energies_resident"], "unit": "energies", "n_gpus": 1, "higher_is_better": True,
+            "data": "synthetic", "dtype": "f64+" + args.mem_prec.replace(":", "x"),
+            "config": {"workload": "memory: realistic device n_b=32, b=416, eta=1e-3, library workspace %.0f GiB"
+                                   % (ws / 2 ** 30), "precision": args.mem_prec},
+            "gain_vs_dense_c128": best["energies_resident"] / base,
+            "forms": rows, "fpx_error": err, "autotune": tuned}
     print(json.dumps(line), flush=True)
 
 
