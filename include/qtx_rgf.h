@@ -144,6 +144,25 @@ enum {
  *           complex128).  A failed energy's FPX blocks hold the FPX NaN code.  With
  *           out_bits = 32 the off-diagonal outputs take half the HBM.  Not available
  *           with QTX_SPLIT_CHAIN (QTX_ERR_UNSUPPORTED).
+ *   partitions  P >= 2: the spatially parallel selected solve of each energy (the
+ *           partitioned selected inversion the paper cites for long devices).  The
+ *           chain is cut by P - 1 separator blocks into P partitions with interiors of
+ *           equal length (to within one block).  Every partition eliminates its
+ *           interior top-down at the same time (the forward recurrence, plus the fill-in
+ *           blocks that couple the interior to the partition's upper separator, for M
+ *           and for the right-hand sides), which leaves a block tridiagonal system over
+ *           the separators (reduced blocks, couplings and right-hand sides); its selected
+ *           solve gives G^R, G^<, G^> at the separators; then every partition runs its
+ *           backward recurrence at once, with the upper separator as a second
+ *           neighbour of each interior block.  The sequential step count per energy is
+ *           about 2 n_b / P + 2 P instead of 2 n_b - 1, with P times the independent
+ *           products per step: it lowers the latency of solves with few energies and
+ *           long chains.  Results agree with the one-chain solve to rounding (the fill-in
+ *           chains cost some digits on G^< blocks much smaller than the energy's largest:
+ *           see the tests).  Requires n_b >= 2 P - 1 (every interior at least one
+ *           block) and P <= 64; not with QTX_SPLIT_CHAIN (QTX_ERR_ARG) or FPX outputs
+ *           (QTX_ERR_UNSUPPORTED).  Energies of problems with equal (n_b, b, P) and
+ *           schemes share launches.
  * Precision per chain: the products that build x_i and G^R (forward Schur
  * complements, backward G^R blocks) use (prec, n_slices); the products of the
  * lesser/greater recurrences use (prec_lesser, n_slices_lesser).  The lesser
@@ -183,6 +202,7 @@ typedef struct {
   void *GG_d, *GG_u;
   int32_t* status;
   int32_t out_bits;        /* 64 / 0: complex128 outputs; 16..56: FPX off-diagonal outputs */
+  int32_t partitions;      /* 0 / 1: one chain per energy; P >= 2: P-way partitioned solve */
 } qtx_rgf_problem;
 
 /* Create a context on HIP device `device`.  workspace_bytes caps the device

@@ -606,6 +606,11 @@ qtx_status check_supported(const qtx_rgf_problem* p) {
   // FPX off-diagonal outputs are encoded per backward step; the bottom halves of split
   // energies fix up their lower blocks after the whole solve, so the two do not combine
   if (out_fpx_bits(*p) < 64 && (p->flags & QTX_SPLIT_CHAIN) && p->n_b >= 3) return QTX_ERR_UNSUPPORTED;
+  if (p->partitions < 0 || p->partitions > 64) return QTX_ERR_ARG;
+  if (p->partitions > 1) {
+    if ((p->flags & QTX_SPLIT_CHAIN) || p->n_b < 2 * p->partitions - 1) return QTX_ERR_ARG;
+    if (out_fpx_bits(*p) < 64) return QTX_ERR_UNSUPPORTED;
+  }
   return QTX_OK;
 }
 
@@ -637,6 +642,8 @@ struct Entry {
   int part = -1;      // top half: index of its bottom half in the batch
   int64_t rbt_l = -1, rbt_g = -1;   // bottom half with a BT Sigma^< / Sigma^>: element offsets
                                     // of its -(SL_u)^H / -(SG_u)^H copies (blocks c .. n_b - 2)
+  int q = -1;         // partitioned solve: partition index (logical block j = physical off + j;
+  int off = 0;        // nf interior blocks; upper separator off - 1, lower separator off + nf)
 };
 
 // The common properties of a batch's entries.
@@ -647,9 +654,11 @@ struct BatchKey {
   bool l_bt = false, g_bt = false;   // Sigma^< / Sigma^> with off-diagonal blocks
   bool sdiag = false;                // the diagonal self-energy blocks come as vectors
   int obits = 64;                    // width of the off-diagonal outputs (64 or FPX)
+  int parts = 1;                     // partitioned solve: partitions per energy
+  int nb = 0;                        // and the chain length (one partition layout per batch)
   bool operator==(const BatchKey& o) const {
     return b == o.b && r == o.r && l == o.l && s_id == o.s_id && greater == o.greater && coupled == o.coupled &&
-           l_bt == o.l_bt && g_bt == o.g_bt && sdiag == o.sdiag && obits == o.obits;
+           l_bt == o.l_bt && g_bt == o.g_bt && sdiag == o.sdiag && obits == o.obits && parts == o.parts && nb == o.nb;
   }
 };
 
@@ -664,6 +673,7 @@ BatchKey key_of(const qtx_rgf_problem& p) {
   k.g_bt = k.greater && p.n_b > 1 && p.SG_u != nullptr;
   k.sdiag = (p.flags & QTX_SIGMA_DIAG) != 0;
   k.obits = out_fpx_bits(p);
+  if (p.partitions > 1) { k.parts = p.partitions; k.nb = p.n_b; }
   return k;
 }
 
@@ -671,10 +681,18 @@ BatchKey key_of(const qtx_rgf_problem& p) {
 // G^R_{i+1,i}, G^<_{i,i+1}, G^>_{i,i+1}.
 constexpr int kOutTemps = 4;
 
+// Per-entry blocks of a partitioned batch (see PartWs).
+constexpr int kPartTemps = 8;
+int part_blocks(const BatchKey& k) {
+  if (k.parts <= 1) return 0;
+  const int nr = k.greater ? 2 : 1;
+  return 3 + 2 * nr + 2 + nr + 4 + 2 * nr + kPartTemps;
+}
+
 // Workspace of a batch of Z entries (excluding its pointer tables).
 size_t batch_ws_bytes(const BatchKey& k, int Z) {
   const size_t blk = align_up((size_t)Z * k.b * k.b * sizeof(double2));
-  return blk * (1 + kTemps + 2 + (k.obits < 64 ? kOutTemps : 0)) + align_up(gje_work_bytes(k.b, Z)) +
+  return blk * (1 + kTemps + 2 + (k.obits < 64 ? kOutTemps : 0) + part_blocks(k)) + align_up(gje_work_bytes(k.b, Z)) +
          align_up((size_t)Z * sizeof(int32_t)) +
          split_pair_bytes(k.b, larger_split(k.r, k.l), Z, 2 + kKeepSlots) + split_pair_bytes(k.b, k.l, Z) + 1024;
 }
@@ -698,6 +716,8 @@ struct Batch {
 // mode 3: bottom halves that reach their separator c at forward step `step` ->
 //         physical block c - 1 + delta (the top half's last forward block)
 // mode 4: every physical upper block c .. n_b - 2 of every bottom half
+// mode 8: partitioned solve, logical block nf + delta of every entry (the lower separator)
+// mode 9: partitioned solve, logical block -1 + delta of every entry (the upper separator)
 struct TabKey {
   int arr, mode, step, delta;
   bool operator<(const TabKey& o) const {
@@ -792,6 +812,14 @@ struct Run {
       j = diag ? p.n_b - 1 - j : p.n_b - 2 - j;
     }
     const int64_t nd = p.n_b, nu = (int64_t)p.n_b - 1;
+    if (B->ent[z].q >= 0) {
+      // partitioned solve: logical block j of the entry is physical off + j; blocks past
+      // either end of the chain do not exist
+      j += B->ent[z].off;
+      const bool upper = a == A_HU || a == A_HL || a == A_SU || a == A_SL || a == A_SRU || a == A_SRL ||
+                         a == A_GRU || a == A_GRL || a == A_GLU || a == A_GGU || a == A_SLU || a == A_SGU;
+      if (j < 0 || j >= (upper ? nu : nd)) return nullptr;
+    }
     const void* base = nullptr;
     int64_t idx = 0;
     switch (a) {
@@ -848,6 +876,9 @@ struct Run {
         for (int z = 0; z < (int)B->ent.size(); ++z)
           if (B->ent[z].rev)
             for (int j = B->ent[z].c; j <= B->ent[z].p->n_b - 2; ++j) v.push_back(ptr(a, z, j, true));
+      } else if (mode == 8 || mode == 9) {
+        for (int z = 0; z < (int)B->ent.size(); ++z)
+          v.push_back(ptr(a, z, (mode == 8 ? B->ent[z].nf : -1) + delta));
       } else {
         const int Z = mode == 0 ? active_fwd(step) : (mode == 1 ? active_bwd(step) : (int)B->ent.size());
         for (int z = 0; z < Z; ++z) {
@@ -865,7 +896,12 @@ struct Run {
         stride = v[1] - v[0];
         for (int z = 2; z < Z && affine; ++z) affine = (v[z] - v[z - 1] == stride);
       }
-      if (Z == 0 || (mode != 2 && v[0] == nullptr)) {
+      // an absent array: no pointer (a partitioned batch has entries without some blocks,
+      // and its products run over entry ranges)
+      bool all_null = true;
+      for (int z = 0; z < Z; ++z) all_null &= (v[z] == nullptr);
+      const bool absent = B->key.parts > 1 ? all_null : (mode != 2 && v[0] == nullptr);
+      if (Z == 0 || absent) {
         tv.base = nullptr;
       } else if (affine) {
         tv.base = v[0];
@@ -950,6 +986,21 @@ struct BatchWs {
   double2* Uw = nullptr;
   double2* Lw = nullptr;
   double2* Ot[kOutTemps] = {};   // FPX outputs: the FP64 off-diagonal blocks of a backward step
+  // Partitioned solve, per entry z (partition q of energy e, z = q n_e + e): the reduced
+  // system's blocks that partition q produces -- Ahd: M-hat of its lower separator e_q;
+  // Ahu / Ahl: the couplings M-hat_{e_(q-1), e_q} / M-hat_{e_q, e_(q-1)}; Bhd / Bhu the same
+  // for each right-hand side; Ghu / Ghl / GLhu: the reduced solve's G^R_{e_(q-1), e_q},
+  // G^R_{e_q, e_(q-1)}, G^<_{e_(q-1), e_q}; Gnu / Gun / GLnu: the backward recurrence's
+  // G_{j,u}, G_{u,j}, G^<_{j,u} (u the upper separator; two slots, alternating steps);
+  // Pt: temporaries.
+  double2 *Ahd = nullptr, *Ahu = nullptr, *Ahl = nullptr, *Ghu = nullptr, *Ghl = nullptr;
+  double2* Bhd[2] = {};
+  double2* Bhu[2] = {};
+  double2* GLhu[2] = {};
+  double2* Gnu[2] = {};
+  double2* Gun[2] = {};
+  double2* GLnu[2][2] = {};
+  double2* Pt[kPartTemps] = {};
   GjeWork gw;
   int32_t* st = nullptr;
   SplitBufs sb;
@@ -971,6 +1022,18 @@ BatchWs carve_batch(char* w, const BatchKey& k, int Z) {
   L.Lw = (double2*)w; w += blk;
   if (k.obits < 64)
     for (int t = 0; t < kOutTemps; ++t) { L.Ot[t] = (double2*)w; w += blk; }
+  if (k.parts > 1) {
+    const int nr = k.greater ? 2 : 1;
+    auto take = [&]() { double2* p = (double2*)w; w += blk; return p; };
+    L.Ahd = take(); L.Ahu = take(); L.Ahl = take();
+    for (int r = 0; r < nr; ++r) { L.Bhd[r] = take(); L.Bhu[r] = take(); }
+    L.Ghu = take(); L.Ghl = take();
+    for (int r = 0; r < nr; ++r) L.GLhu[r] = take();
+    for (int t = 0; t < 2; ++t) { L.Gnu[t] = take(); L.Gun[t] = take(); }
+    for (int r = 0; r < nr; ++r)
+      for (int t = 0; t < 2; ++t) L.GLnu[r][t] = take();
+    for (int t = 0; t < kPartTemps; ++t) L.Pt[t] = take();
+  }
   L.gw = gje_carve(w, k.b, Z); w += align_up(gje_work_bytes(k.b, Z));
   L.st = (int32_t*)w; w += align_up((size_t)Z * sizeof(int32_t));
   L.sb = carve_split(w, k.b, larger_split(k.r, k.l), Z, 2 + kKeepSlots);
@@ -1308,6 +1371,480 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
   return R.late ? QTX_ERR_HIP : QTX_OK;
 }
 
+// ------------------------------------------------------------------ partitioned solve
+// P-way partitioned selected solve of every energy (the spatially parallel selected
+// inversion the paper cites, in its one-sided form): the separators e_0 < .. < e_{P-2}
+// cut the chain into P partitions; entry z = q n_e + e is partition q of energy e, with
+// interior blocks off .. off + nf - 1 (logical 0 .. nf - 1), upper separator u = off - 1
+// (q > 0) and lower separator d = off + nf (q < P - 1).  Notation: M_jj, U_j = M_{j,j+1}
+// = sU U', L_j = M_{j+1,j} = sL L', B the right-hand side (Sigma^<, Sigma^>), BU_j its
+// upper block, BL_j = -BU_j^H.
+//
+// 1. Elimination of every interior, top-down: x_j = (M_jj - L_{j-1} x_{j-1} U_{j-1})^-1
+//    (no term for the first interior block) and xl_j = x_j Q_j x_j^H as in the one-chain
+//    recurrence; and the fill-ins that couple block j to u, Fr_j = M~_{j,u},
+//    Fc_j = M~_{u,j}, Br_j = B~_{j,u}:
+//      Fr_lo = L_u, Fc_lo = U_u, Br_lo = BL_u;
+//      Fr_j = -L_{j-1} x_{j-1} Fr_{j-1},  Fc_j = -Fc_{j-1} x_{j-1} U_{j-1},
+//      Br_j = -L_{j-1} x_{j-1} Br_{j-1} + L_{j-1} xl_{j-1} Fc_{j-1}^H + (Fc_{j-1} x_{j-1} BU_{j-1})^H.
+//    Each eliminated block updates the separators: M^_uu -= Fc_j x_j Fr_j,
+//    B^_uu += -V + V^H + Fc_j xl_j Fc_j^H (V = Fc_j x_j Br_j); the last one (t) also
+//    M^_dd -= L_t x_t U_t, B^_dd += L_t xl_t L_t^H - W + W^H (W = L_t x_t BU_t), and the
+//    reduced couplings M^_{d,u} = -L_t x_t Fr_t, M^_{u,d} = -Fc_t x_t U_t,
+//    B^_{u,d} = -(B^_{d,u})^H with B^_{d,u} = -L_t x_t Br_t + L_t xl_t Fc_t^H + (Fc_t x_t BU_t)^H.
+//    Fr_j, Fc_j, Br_j are kept in the output slots GR_l, GR_u, GL_u (GG_u) of block j - 1,
+//    which the backward recurrence writes only after reading them.
+// 2. The block tridiagonal system (M^, B^) over the separators, by the one-chain
+//    recurrences: G^R, G^<, G^> of the separator blocks (into the outputs) and of their
+//    couplings (Ghu, Ghl, GLhu).
+// 3. Backward recurrence of every partition, j = last .. first interior block, over the
+//    neighbours N = {j + 1, u} of block j at its elimination:
+//      G_{j,j+1} = -x_j (U_j G_{j+1,j+1} + Fr_j G_{u,j+1}),   G_{j+1,j} = -(G_{j+1,j+1} L_j + G_{j+1,u} Fc_j) x_j,
+//      G_{j,u} = -x_j (U_j G_{j+1,u} + Fr_j G_uu),           G_{u,j} = -(G_{u,j+1} L_j + G_uu Fc_j) x_j,
+//      G_jj = x_j - (G_{j,j+1} L_j + G_{j,u} Fc_j) x_j;
+//    with K1 = x_j BU_j - xl_j L_j^H, K2 = x_j Br_j - xl_j Fc_j^H (x_j times the
+//    transformed right-hand side's row) and X_n = x_j U_j, X_u = x_j Fr_j:
+//      G^<_{j,j+1} = K1 G_{j+1,j+1}^H + K2 G_{j+1,u}^H - X_n G^<_{j+1,j+1} + X_u G^<_{j+1,u}^H,
+//      G^<_{j,u}   = K1 G_{u,j+1}^H + K2 G_uu^H - X_n G^<_{j+1,u} - X_u G^<_uu,
+//      G^<_jj = xl_j + M1 - M1^H + M2 - M2^H + X_n G^<_{j+1,j+1} X_n^H + X_u G^<_uu X_u^H + V4 - V4^H,
+//      M1 = K1 G_{j,j+1}^H, M2 = K2 G_{j,u}^H, V4 = X_n G^<_{j+1,u} X_u^H
+//    (terms of a neighbour the partition lacks are absent).
+// Partition 0 has no u, the last partition no d (its last block starts the backward
+// recurrence without a j + 1 neighbour).  Products run over entry ranges: the
+// interiors shrink with q, so the active entries of a step are a prefix, those with u
+// the entries from n_e on, those with d the entries before (P - 1) n_e.
+qtx_status run_partition(Run& R, const BatchWs& W) {
+  qtx_rgf_ctx ctx = R.ctx;
+  const Batch& B = *R.B;
+  const BatchKey& k = B.key;
+  const int b = k.b;
+  const int64_t bb = R.bb;
+  const int Zall = (int)B.ent.size();
+  const int P = k.parts;
+  const int ne = Zall / P;
+  const int U0 = ne;               // entries with an upper separator: [ne, Zall)
+  const int Zd = Zall - ne;        // entries with a lower separator: [0, Zd)
+  hipStream_t s = R.s;
+  const bool dry = R.dry;
+  Gemm g{&R, b, W.en, k.r, W.sb};
+  Gemm gl{&R, b, W.en, k.l, W.sb};
+  const double2 one = cmk(1, 0), mone = cmk(-1, 0), zero = cmk(0, 0);
+  auto ws_at = [&](double2* p, int z0) { Mat m; m.p = p ? p + (int64_t)z0 * bb : nullptr; m.stride = bb; return m; };
+  auto ws = [&](double2* p) { return ws_at(p, 0); };
+  auto at = [](Mat m, int z0) {
+    if (m.tab) m.tab += z0;
+    else if (m.p) m.p += (int64_t)z0 * m.stride;
+    return m;
+  };
+  auto on = [&](const Gemm& G0, int z0) { Gemm G1 = G0; if (W.en) G1.energies = W.en + z0; return G1; };
+  const int sd = k.sdiag ? 1 : 0;
+
+  if (!dry) QTX_TRY(launch_fill_i32(W.st, 0, Zall, s));
+  struct Rhs { int S, SU, Gd, Gu; };
+  std::vector<Rhs> rhs{{A_SLD, k.l_bt ? A_SLU : -1, A_GLD, A_GLU}};
+  if (k.greater) rhs.push_back({A_SGD, k.g_bt ? A_SGU : -1, A_GGD, A_GGU});
+  const int nr = (int)rhs.size();
+
+  // Couplings of entries [z0, z0 + Z) at (mode, step, delta), as Mats of that range.
+  auto coupling = [&](int z0, int Z, int mode, int step, int delta, Mat* U, Mat* L, double* sU,
+                      double* sL) -> hipError_t {
+    if (!k.coupled) {
+      *U = at(R.get(A_HU, mode, step, delta), z0); *sU = -1.0;
+      *L = at(R.get(A_HL, mode, step, delta), z0); *sL = -1.0;
+      return hipSuccess;
+    }
+    const Mat SU = k.s_id ? Mat{} : at(R.get(A_SU, mode, step, delta), z0);
+    const Mat SL = k.s_id ? Mat{} : at(R.get(A_SL, mode, step, delta), z0);
+    const Gemm gz = on(g, z0);
+    hipError_t e = gz.go(Z, OP_N, Mat{}, OP_N, Mat{}, ws_at(W.Uw, z0), zero,
+                         {addend_of(SU, one, OP_N, 1), addend_of(at(R.get(A_HU, mode, step, delta), z0), mone),
+                          addend_of(at(R.get(A_SRU, mode, step, delta), z0), mone)}, zero, 0);
+    if (e != hipSuccess) return e;
+    e = gz.go(Z, OP_N, Mat{}, OP_N, Mat{}, ws_at(W.Lw, z0), zero,
+              {addend_of(SL, one, OP_N, 1), addend_of(at(R.get(A_HL, mode, step, delta), z0), mone),
+               addend_of(at(R.get(A_SRL, mode, step, delta), z0), mone)}, zero, 0);
+    *U = ws_at(W.Uw, z0); *sU = 1.0;
+    *L = ws_at(W.Lw, z0); *sL = 1.0;
+    return e;
+  };
+  // M_jj of the entries' blocks at (mode, step, delta) as epilogue addends (+ E on the diagonal)
+  auto diag_terms = [&](int mode, int step, int delta, Addend* aH, Addend* aS, Addend* aO) {
+    *aH = addend_of(R.get(A_HD, mode, step, delta), mone);
+    *aS = addend_of(R.get(A_SRD, mode, step, delta), mone, OP_N, 0, sd);
+    *aO = k.s_id ? Addend{} : addend_of(R.get(A_SD, mode, step, delta), one, OP_N, 1);
+  };
+  const double2 dg = k.s_id ? one : zero;
+  // Entries [*f0, *f1) whose last interior block is logical i.
+  auto finishing = [&](int i, int* f0, int* f1) {
+    int z = 0;
+    while (z < Zall && B.ent[z].nf > i + 1) ++z;
+    *f0 = z;
+    while (z < Zall && B.ent[z].nf == i + 1) ++z;
+    *f1 = z;
+  };
+
+  // ---------------------------------------------------------- 1. interiors
+  // reduced diagonal blocks start as M_dd, B_dd of every lower separator
+  {
+    Addend aH, aS, aO;
+    diag_terms(8, 0, 0, &aH, &aS, &aO);
+    QTX_TRY(g.go(Zd, OP_N, Mat{}, OP_N, Mat{}, ws(W.Ahd), zero, {aH, aS, aO}, dg, 0));
+    for (int r = 0; r < nr; ++r)
+      QTX_TRY(gl.go(Zd, OP_N, Mat{}, OP_N, Mat{}, ws(W.Bhd[r]), zero,
+                    {addend_of(R.get(rhs[r].S, 8, 0, 0), one, OP_N, 0, sd)}, zero, 0));
+  }
+  // Separator-u terms of the entries [z0, z0 + Z) (all with u) for their block at
+  // logical i, whose x, xl, Fr, Fc, Br are known:  M^_uu -= C1 Fr,
+  // B^_uu += -V + V^H + Fc xl Fc^H  (C1 = Fc x, V = C1 Br).  C1 stays in Pt[0].
+  auto sep_u_terms = [&](int z0, int Z, int i) -> hipError_t {
+    if (Z <= 0) return hipSuccess;
+    const Gemm gu = on(g, z0), glu = on(gl, z0);
+    const Mat x = at(R.get(A_GRD, 0, i, 0), z0);
+    const Mat Fr = at(R.get(A_GRL, 0, i, -1), z0), Fc = at(R.get(A_GRU, 0, i, -1), z0);
+    const Mat C1 = ws_at(W.Pt[0], z0), Ahd_u = ws_at(W.Ahd, z0 - ne);
+    hipError_t e = gu.go(Z, OP_N, Fc, OP_N, x, C1, one, {});
+    if (e == hipSuccess) e = gu.go(Z, OP_N, C1, OP_N, Fr, Ahd_u, mone, {addend_of(Ahd_u, one)});
+    for (int r = 0; r < nr && e == hipSuccess; ++r) {
+      const Mat Br = at(R.get(rhs[r].Gu, 0, i, -1), z0), xl = at(R.get(rhs[r].Gd, 0, i, 0), z0);
+      const Mat V = ws_at(W.Pt[1], z0), C2 = ws_at(W.Pt[2], z0), Bhd_u = ws_at(W.Bhd[r], z0 - ne);
+      e = glu.go(Z, OP_N, C1, OP_N, Br, V, one, {});
+      if (e == hipSuccess) e = glu.go(Z, OP_N, Fc, OP_N, xl, C2, one, {});
+      if (e == hipSuccess)
+        e = glu.go(Z, OP_N, C2, OP_C, Fc, Bhd_u, one,
+                   {addend_of(Bhd_u, one), addend_of(V, mone), addend_of(V, one, OP_C)});
+    }
+    return e;
+  };
+
+  for (int i = 0; i < B.max_nf; ++i) {
+    const int Z = R.active_fwd(i);
+    const int Zu = std::max(0, Z - U0);
+    Addend aH, aS, aO;
+    diag_terms(0, i, 0, &aH, &aS, &aO);
+    const Mat xi = R.get(A_GRD, 0, i, 0);
+    Mat U, L;
+    double sU = -1.0, sL = -1.0;
+    if (i == 0) {
+      QTX_TRY(g.go(Z, OP_N, Mat{}, OP_N, Mat{}, ws(W.X), zero, {aH, aS, aO}, dg, 0));
+      // fill-in seeds of the entries with u: Fr = L_u, Fc = U_u, Br = BL_u = -(BU_u)^H
+      if (Zu > 0) {
+        Mat Us, Ls;
+        double sUs, sLs;
+        QTX_TRY(coupling(U0, Zu, 0, 0, -1, &Us, &Ls, &sUs, &sLs));
+        const Gemm gu = on(g, U0), glu = on(gl, U0);
+        QTX_TRY(gu.go(Zu, OP_N, Mat{}, OP_N, Mat{}, at(R.get(A_GRL, 0, 0, -1), U0), zero, {addend_of(Ls, cmk(sLs, 0))},
+                      zero, 0));
+        QTX_TRY(gu.go(Zu, OP_N, Mat{}, OP_N, Mat{}, at(R.get(A_GRU, 0, 0, -1), U0), zero, {addend_of(Us, cmk(sUs, 0))},
+                      zero, 0));
+        for (int r = 0; r < nr; ++r) {
+          const Mat BU = rhs[r].SU >= 0 ? at(R.get(rhs[r].SU, 0, 0, -1), U0) : Mat{};
+          QTX_TRY(glu.go(Zu, OP_N, Mat{}, OP_N, Mat{}, at(R.get(rhs[r].Gu, 0, 0, -1), U0), zero,
+                         {addend_of(BU, mone, OP_C)}, zero, 0));
+        }
+      }
+    } else {
+      QTX_TRY(coupling(0, Z, 0, i, -1, &U, &L, &sU, &sL));
+      QTX_TRY(g.go(Z, OP_N, L, OP_N, R.get(A_GRD, 0, i, -1), ws(W.Tm[0]), one, {}));            // T' = L' x_{j-1}
+      QTX_TRY(g.go(Z, OP_N, ws(W.Tm[0]), OP_N, U, ws(W.X), cmk(-sL * sU, 0), {aH, aS, aO}, dg));
+      if (Zu > 0) {
+        // block j - 1's separator terms, then the fill-ins of block j
+        QTX_TRY(sep_u_terms(U0, Zu, i - 1));
+        const Gemm gu = on(g, U0), glu = on(gl, U0);
+        const Mat Tp = ws_at(W.Tm[0], U0), C1 = ws_at(W.Pt[0], U0);   // C1 = Fc_{j-1} x_{j-1}
+        QTX_TRY(gu.go(Zu, OP_N, Tp, OP_N, at(R.get(A_GRL, 0, i, -2), U0), at(R.get(A_GRL, 0, i, -1), U0),
+                      cmk(-sL, 0), {}));                                                          // Fr_j
+        QTX_TRY(gu.go(Zu, OP_N, C1, OP_N, at(U, U0), at(R.get(A_GRU, 0, i, -1), U0), cmk(-sU, 0), {}));   // Fc_j
+        for (int r = 0; r < nr; ++r) {
+          const Mat Yq = ws_at(W.Pt[1], U0), CB = ws_at(W.Pt[2], U0);
+          const Mat Brp = at(R.get(rhs[r].Gu, 0, i, -2), U0), Brj = at(R.get(rhs[r].Gu, 0, i, -1), U0);
+          const Mat Fcp = at(R.get(A_GRU, 0, i, -2), U0);
+          QTX_TRY(glu.go(Zu, OP_N, at(L, U0), OP_N, at(R.get(rhs[r].Gd, 0, i, -1), U0), Yq, one, {}));   // L' xl_{j-1}
+          const bool bt = rhs[r].SU >= 0;
+          if (bt) QTX_TRY(glu.go(Zu, OP_N, C1, OP_N, at(R.get(rhs[r].SU, 0, i, -1), U0), CB, one, {}));   // C1 BU_{j-1}
+          QTX_TRY(glu.go(Zu, OP_N, Tp, OP_N, Brp, Brj, cmk(-sL, 0), {}));
+          QTX_TRY(glu.go(Zu, OP_N, Yq, OP_C, Fcp, Brj, cmk(sL, 0),
+                         {addend_of(Brj, one), addend_of(bt ? CB : Mat{}, one, OP_C)}));
+        }
+      }
+    }
+    if (!dry && Z > 0) {
+      ProfScope ps(ctx, QTX_KERNEL_INV, s, 8.0 * (double)b * b * b * Z, true);
+      QTX_TRY(launch_gje_invert(b, W.X, bb, (double2*)xi.p, xi.stride, Z, W.gw, W.st, s, (double2* const*)xi.tab));
+    }
+    // lesser recurrence: Q = B_j (+ L xl L^H - L x BU - BL x^H L^H), xl_j = x_j Q x_j^H
+    for (int r = 0; r < nr; ++r) {
+      const Mat Bj = R.get(rhs[r].S, 0, i, 0);
+      const Mat Q = ws(W.Tm[3]);
+      if (i == 0) {
+        QTX_TRY(gl.go(Z, OP_N, Mat{}, OP_N, Mat{}, Q, zero, {addend_of(Bj, one, OP_N, 0, sd)}, zero, 0));
+      } else {
+        QTX_TRY(gl.go(Z, OP_N, L, OP_N, R.get(rhs[r].Gd, 0, i, -1), ws(W.Tm[1]), one, {}));
+        if (rhs[r].SU < 0) {
+          QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, Q, one, {addend_of(Bj, one, OP_N, 0, sd)}));
+        } else {
+          QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[0]), OP_N, R.get(rhs[r].SU, 0, i, -1), ws(W.Tm[4]), one, {}));
+          QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, Q, one,
+                        {addend_of(Bj, one, OP_N, 0, sd), addend_of(ws(W.Tm[4]), cmk(-sL, 0)),
+                         addend_of(ws(W.Tm[4]), cmk(sL, 0), OP_C)}));
+        }
+      }
+      QTX_TRY(gl.go(Z, OP_N, xi, OP_N, Q, ws(W.Tm[2]), one, {}));
+      QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[2]), OP_C, xi, R.get(rhs[r].Gd, 0, i, 0), one, {}));
+    }
+    // entries whose last interior block is i: their separator terms
+    int f0, f1;
+    finishing(i, &f0, &f1);
+    if (f1 > f0) {
+      const int u0 = std::max(f0, U0);
+      QTX_TRY(sep_u_terms(u0, f1 - u0, i));   // leaves C1 = Fc_t x_t in Pt[0]
+      const int d1 = std::min(f1, Zd);
+      if (d1 > f0) {
+        const int Zf = d1 - f0;
+        Mat Ut, Lt;
+        double sUt, sLt;
+        QTX_TRY(coupling(f0, Zf, 0, i, 0, &Ut, &Lt, &sUt, &sLt));
+        const Gemm gf = on(g, f0), glf = on(gl, f0);
+        const Mat x = at(xi, f0), T2 = ws_at(W.Pt[3], f0), Ahd_d = ws_at(W.Ahd, f0);
+        QTX_TRY(gf.go(Zf, OP_N, Lt, OP_N, x, T2, one, {}));                                        // T'' = L'_t x_t
+        QTX_TRY(gf.go(Zf, OP_N, T2, OP_N, Ut, Ahd_d, cmk(-sLt * sUt, 0), {addend_of(Ahd_d, one)}));
+        const int b0 = std::max(f0, U0), Zb = d1 - b0;   // entries with both separators
+        if (Zb > 0) {
+          const Gemm gb = on(g, b0);
+          QTX_TRY(gb.go(Zb, OP_N, ws_at(W.Pt[3], b0), OP_N, at(R.get(A_GRL, 0, i, -1), b0), ws_at(W.Ahl, b0),
+                        cmk(-sLt, 0), {}));                                                          // M^_{d,u}
+          QTX_TRY(gb.go(Zb, OP_N, ws_at(W.Pt[0], b0), OP_N, at(Ut, b0 - f0), ws_at(W.Ahu, b0), cmk(-sUt, 0), {}));
+        }
+        for (int r = 0; r < nr; ++r) {
+          const Mat Yt = ws_at(W.Pt[4], f0), V3 = ws_at(W.Pt[5], f0), Bhd_d = ws_at(W.Bhd[r], f0);
+          const bool bt = rhs[r].SU >= 0;
+          QTX_TRY(glf.go(Zf, OP_N, Lt, OP_N, at(R.get(rhs[r].Gd, 0, i, 0), f0), Yt, one, {}));        // L'_t xl_t
+          if (bt) QTX_TRY(glf.go(Zf, OP_N, T2, OP_N, at(R.get(rhs[r].SU, 0, i, 0), f0), V3, one, {}));  // T'' BU_t
+          QTX_TRY(glf.go(Zf, OP_N, Yt, OP_C, Lt, Bhd_d, one,
+                         {addend_of(Bhd_d, one), addend_of(bt ? V3 : Mat{}, cmk(-sLt, 0)),
+                          addend_of(bt ? V3 : Mat{}, cmk(sLt, 0), OP_C)}));
+          if (Zb > 0) {
+            // B^_{d,u} = -sL T'' Br_t + sL Y'' Fc_t^H + (C1 BU_t)^H  (in Pt[6]), B^_{u,d} = -(B^_{d,u})^H
+            const Gemm glb = on(gl, b0);
+            const Mat Bdu = ws_at(W.Pt[6], b0), CB = ws_at(W.Pt[7], b0);
+            if (bt) QTX_TRY(glb.go(Zb, OP_N, ws_at(W.Pt[0], b0), OP_N, at(R.get(rhs[r].SU, 0, i, 0), b0), CB, one, {}));
+            QTX_TRY(glb.go(Zb, OP_N, ws_at(W.Pt[3], b0), OP_N, at(R.get(rhs[r].Gu, 0, i, -1), b0), Bdu,
+                           cmk(-sLt, 0), {}));
+            QTX_TRY(glb.go(Zb, OP_N, ws_at(W.Pt[4], b0), OP_C, at(R.get(A_GRU, 0, i, -1), b0), Bdu, cmk(sLt, 0),
+                           {addend_of(Bdu, one), addend_of(bt ? CB : Mat{}, one, OP_C)}));
+            QTX_TRY(glb.go(Zb, OP_N, Mat{}, OP_N, Mat{}, ws_at(W.Bhu[r], b0), zero, {addend_of(Bdu, mone, OP_C)}, zero,
+                           0));
+          }
+        }
+      }
+    }
+  }
+
+  // ---------------------------------------------------------- 2. separator system
+  // separator c of energy e lives with entry c n_e + e (partition c, its lower separator);
+  // the coupling (c - 1, c) with entry c n_e + e (partition c).  Energies: entries 0 .. n_e - 1.
+  const int nsep = P - 1;
+  auto sep_x = [&](int a, int c) { return at(R.get(a, 8, 0, 0), c * ne); };
+  for (int c = 0; c < nsep; ++c) {
+    const Mat x = sep_x(A_GRD, c);
+    if (c == 0) {
+      QTX_TRY(g.go(ne, OP_N, Mat{}, OP_N, Mat{}, ws(W.X), zero, {addend_of(ws_at(W.Ahd, 0), one)}, zero, 0));
+    } else {
+      QTX_TRY(g.go(ne, OP_N, ws_at(W.Ahl, c * ne), OP_N, sep_x(A_GRD, c - 1), ws(W.Tm[0]), one, {}));
+      QTX_TRY(g.go(ne, OP_N, ws(W.Tm[0]), OP_N, ws_at(W.Ahu, c * ne), ws(W.X), mone,
+                   {addend_of(ws_at(W.Ahd, c * ne), one)}));
+    }
+    if (!dry) {
+      ProfScope ps(ctx, QTX_KERNEL_INV, s, 8.0 * (double)b * b * b * ne, true);
+      QTX_TRY(launch_gje_invert(b, W.X, bb, (double2*)x.p, x.stride, ne, W.gw, W.st, s, (double2* const*)x.tab));
+    }
+    for (int r = 0; r < nr; ++r) {
+      const Mat Q = ws(W.Tm[3]);
+      if (c == 0) {
+        QTX_TRY(gl.go(ne, OP_N, Mat{}, OP_N, Mat{}, Q, zero, {addend_of(ws_at(W.Bhd[r], 0), one)}, zero, 0));
+      } else {
+        // Q = B^_cc + A^_{c,c-1} xl A^_{c,c-1}^H - V + V^H,  V = T B^_{c-1,c},  T = A^_{c,c-1} x_{c-1}
+        QTX_TRY(gl.go(ne, OP_N, ws_at(W.Ahl, c * ne), OP_N, sep_x(rhs[r].Gd, c - 1), ws(W.Tm[1]), one, {}));
+        QTX_TRY(gl.go(ne, OP_N, ws(W.Tm[0]), OP_N, ws_at(W.Bhu[r], c * ne), ws(W.Tm[4]), one, {}));
+        QTX_TRY(gl.go(ne, OP_N, ws(W.Tm[1]), OP_C, ws_at(W.Ahl, c * ne), Q, one,
+                      {addend_of(ws_at(W.Bhd[r], c * ne), one), addend_of(ws(W.Tm[4]), mone),
+                       addend_of(ws(W.Tm[4]), one, OP_C)}));
+      }
+      QTX_TRY(gl.go(ne, OP_N, x, OP_N, Q, ws(W.Tm[2]), one, {}));
+      QTX_TRY(gl.go(ne, OP_N, ws(W.Tm[2]), OP_C, x, sep_x(rhs[r].Gd, c), one, {}));
+    }
+  }
+  for (int c = nsep - 2; c >= 0; --c) {
+    const Mat x = sep_x(A_GRD, c), Gn = sep_x(A_GRD, c + 1);
+    const Mat Au = ws_at(W.Ahu, (c + 1) * ne), Al = ws_at(W.Ahl, (c + 1) * ne);
+    const Mat Pp = ws(W.Tm[0]), Rp = ws(W.Tm[1]);
+    const Mat Gu = ws_at(W.Ghu, (c + 1) * ne), Gl = ws_at(W.Ghl, (c + 1) * ne);
+    QTX_TRY(g.go(ne, OP_N, x, OP_N, Au, Pp, one, {}));                     // x_c A^_{c,c+1}
+    QTX_TRY(g.go(ne, OP_N, Al, OP_N, x, Rp, one, {}));                     // A^_{c+1,c} x_c
+    QTX_TRY(g.go(ne, OP_N, Pp, OP_N, Gn, Gu, mone, {}));                   // G_{c,c+1}
+    QTX_TRY(g.go(ne, OP_N, Gn, OP_N, Rp, Gl, mone, {}));                   // G_{c+1,c}
+    for (int r = 0; r < nr; ++r) {
+      const Mat xl = sep_x(rhs[r].Gd, c), Gln = sep_x(rhs[r].Gd, c + 1);
+      const Mat K1 = ws(W.Tm[2]), Vp = ws(W.Tm[3]), M1 = ws(W.Tm[4]);
+      QTX_TRY(gl.go(ne, OP_N, x, OP_N, ws_at(W.Bhu[r], (c + 1) * ne), K1, one, {}));
+      QTX_TRY(gl.go(ne, OP_N, xl, OP_C, Al, K1, mone, {addend_of(K1, one)}));      // K1 = x B^u - xl A^l^H
+      QTX_TRY(gl.go(ne, OP_N, Pp, OP_N, Gln, Vp, one, {}));
+      QTX_TRY(gl.go(ne, OP_N, K1, OP_C, Gn, ws_at(W.GLhu[r], (c + 1) * ne), one, {addend_of(Vp, mone)}));
+      QTX_TRY(gl.go(ne, OP_N, K1, OP_C, Gu, M1, one, {}));
+      QTX_TRY(gl.go(ne, OP_N, Vp, OP_C, Pp, xl, one, {addend_of(xl, one), addend_of(M1, one), addend_of(M1, mone, OP_C)}));
+    }
+    QTX_TRY(g.go(ne, OP_N, Gu, OP_N, Rp, x, mone, {addend_of(x, one)}));   // G_cc = x - G_{c,c+1} A^l x
+  }
+
+  // ---------------------------------------------------------- 3. interiors, backward
+  // the first step's G_{j+1,u} = G_{d,u}, G_{u,j+1} = G_{u,d}, G^<_{d,u} = -(G^<_{u,d})^H
+  if (Zd > U0) {
+    const int Zb = Zd - U0;
+    const Gemm gb = on(g, U0), glb = on(gl, U0);
+    QTX_TRY(gb.go(Zb, OP_N, Mat{}, OP_N, Mat{}, ws_at(W.Gnu[0], U0), zero, {addend_of(ws_at(W.Ghl, U0), one)}, zero, 0));
+    QTX_TRY(gb.go(Zb, OP_N, Mat{}, OP_N, Mat{}, ws_at(W.Gun[0], U0), zero, {addend_of(ws_at(W.Ghu, U0), one)}, zero, 0));
+    for (int r = 0; r < nr; ++r)
+      QTX_TRY(glb.go(Zb, OP_N, Mat{}, OP_N, Mat{}, ws_at(W.GLnu[r][0], U0), zero,
+                     {addend_of(ws_at(W.GLhu[r], U0), mone, OP_C)}, zero, 0));
+  }
+  for (int kk = 0;; ++kk) {
+    const int Z = R.active_bwd(kk);
+    if (Z == 0) break;
+    const int cur = kk & 1, nxt = cur ^ 1;
+    const int Zn = kk == 0 ? std::min(Z, Zd) : Z;     // entries with a j + 1 neighbour
+    const int Zu = std::max(0, Z - U0);               // entries with u
+    const int Znu = std::max(0, Zn - U0);             // entries with both
+    const Mat xi = R.get(A_GRD, 1, kk, 0), Gn = R.get(A_GRD, 1, kk, 1);
+    const Mat GRu = R.get(A_GRU, 1, kk, 0), GRl = R.get(A_GRL, 1, kk, 0);
+    const Mat Pp = ws(W.Tm[0]), Rp = ws(W.Tm[1]);
+    Mat U, L;
+    double sU = -1.0, sL = -1.0;
+    if (Zn > 0) {
+      QTX_TRY(coupling(0, Zn, 1, kk, 0, &U, &L, &sU, &sL));
+      QTX_TRY(g.go(Zn, OP_N, xi, OP_N, U, Pp, one, {}));                   // P' = x_j U'
+      QTX_TRY(g.go(Zn, OP_N, L, OP_N, xi, Rp, one, {}));                   // R' = L' x_j
+      QTX_TRY(g.go(Zn, OP_N, Pp, OP_N, Gn, GRu, cmk(-sU, 0), {}));         // G_{j,j+1} (n part)
+      QTX_TRY(g.go(Zn, OP_N, Gn, OP_N, Rp, GRl, cmk(-sL, 0), {}));         // G_{j+1,j} (n part)
+    }
+    // u side: XF = x Fr, CX = Fc x; G_{j,u}, G_{u,j} into the next slots
+    const Gemm gu = on(g, U0), glu = on(gl, U0);
+    const Mat XF = ws_at(W.Pt[0], U0), CX = ws_at(W.Pt[1], U0);
+    const Mat Guu = at(R.get(A_GRD, 9, 0, 0), U0);
+    const Mat Gnu_p = ws_at(W.Gnu[cur], U0), Gun_p = ws_at(W.Gun[cur], U0);
+    const Mat Gnu_n = ws_at(W.Gnu[nxt], U0), Gun_n = ws_at(W.Gun[nxt], U0);
+    if (Zu > 0) {
+      QTX_TRY(gu.go(Zu, OP_N, at(xi, U0), OP_N, at(R.get(A_GRL, 1, kk, -1), U0), XF, one, {}));
+      QTX_TRY(gu.go(Zu, OP_N, at(R.get(A_GRU, 1, kk, -1), U0), OP_N, at(xi, U0), CX, one, {}));
+      if (Znu > 0) {
+        QTX_TRY(gu.go(Znu, OP_N, XF, OP_N, Gun_p, at(GRu, U0), mone, {addend_of(at(GRu, U0), one)}));
+        QTX_TRY(gu.go(Znu, OP_N, Gnu_p, OP_N, CX, at(GRl, U0), mone, {addend_of(at(GRl, U0), one)}));
+      }
+      QTX_TRY(gu.go(Zu, OP_N, XF, OP_N, Guu, Gnu_n, mone, {}));
+      QTX_TRY(gu.go(Zu, OP_N, Guu, OP_N, CX, Gun_n, mone, {}));
+      if (Znu > 0) {
+        QTX_TRY(gu.go(Znu, OP_N, at(Pp, U0), OP_N, Gnu_p, Gnu_n, cmk(-sU, 0), {addend_of(Gnu_n, one)}));
+        QTX_TRY(gu.go(Znu, OP_N, Gun_p, OP_N, at(Rp, U0), Gun_n, cmk(-sL, 0), {addend_of(Gun_n, one)}));
+      }
+    }
+    // lesser blocks (x_j is unchanged until G_jj below)
+    for (int r = 0; r < nr; ++r) {
+      const Mat xl = R.get(rhs[r].Gd, 1, kk, 0), Gln = R.get(rhs[r].Gd, 1, kk, 1);
+      const Mat GLu = R.get(rhs[r].Gu, 1, kk, 0);
+      const Mat K1 = ws(W.Pt[2]), Vp = ws(W.Pt[3]), M1 = ws(W.Pt[4]);
+      const Mat K2 = ws_at(W.Pt[5], U0), xlu = at(xl, U0);
+      // K1 = x BU - xl L^H and K2 = x Br - xl Fc^H, both from xl_j before G^<_jj replaces it
+      if (Zn > 0) {
+        if (rhs[r].SU >= 0) {
+          QTX_TRY(gl.go(Zn, OP_N, xi, OP_N, R.get(rhs[r].SU, 1, kk, 0), K1, one, {}));
+          QTX_TRY(gl.go(Zn, OP_N, xl, OP_C, L, K1, cmk(-sL, 0), {addend_of(K1, one)}));
+        } else {
+          QTX_TRY(gl.go(Zn, OP_N, xl, OP_C, L, K1, cmk(-sL, 0), {}));
+        }
+      }
+      if (Zu > 0) {
+        QTX_TRY(glu.go(Zu, OP_N, at(xi, U0), OP_N, at(R.get(rhs[r].Gu, 1, kk, -1), U0), K2, one, {}));
+        QTX_TRY(glu.go(Zu, OP_N, xlu, OP_C, at(R.get(A_GRU, 1, kk, -1), U0), K2, mone, {addend_of(K2, one)}));
+      }
+      if (Zn > 0) {
+        QTX_TRY(gl.go(Zn, OP_N, Pp, OP_N, Gln, Vp, one, {}));                         // X_n G^<_{j+1,j+1} (/ sU)
+        QTX_TRY(gl.go(Zn, OP_N, K1, OP_C, Gn, GLu, one, {addend_of(Vp, cmk(-sU, 0))}));
+        QTX_TRY(gl.go(Zn, OP_N, K1, OP_C, GRu, M1, one, {}));
+        QTX_TRY(gl.go(Zn, OP_N, Vp, OP_C, Pp, xl, one, {addend_of(xl, one), addend_of(M1, one), addend_of(M1, mone, OP_C)}));
+      }
+      if (Zu > 0) {
+        const Mat GLuu = at(R.get(rhs[r].Gd, 9, 0, 0), U0);
+        const Mat GLnu_p = ws_at(W.GLnu[r][cur], U0), GLnu_n = ws_at(W.GLnu[r][nxt], U0);
+        const Mat M2 = ws_at(W.Pt[6], U0), T5 = ws_at(W.Pt[7], U0);
+        if (Znu > 0) {
+          const Mat GLuj = at(GLu, U0);
+          QTX_TRY(glu.go(Znu, OP_N, K2, OP_C, Gnu_p, GLuj, one, {addend_of(GLuj, one)}));
+          QTX_TRY(glu.go(Znu, OP_N, XF, OP_C, GLnu_p, GLuj, one, {addend_of(GLuj, one)}));
+        }
+        // G^<_{j,u} = K2 G_uu^H - X_u G^<_uu (+ K1 G_{u,j+1}^H - X_n G^<_{j+1,u})
+        QTX_TRY(glu.go(Zu, OP_N, K2, OP_C, Guu, GLnu_n, one, {}));
+        QTX_TRY(glu.go(Zu, OP_N, XF, OP_N, GLuu, GLnu_n, mone, {addend_of(GLnu_n, one)}));
+        if (Znu > 0) {
+          QTX_TRY(glu.go(Znu, OP_N, at(K1, U0), OP_C, Gun_p, GLnu_n, one, {addend_of(GLnu_n, one)}));
+          QTX_TRY(glu.go(Znu, OP_N, at(Pp, U0), OP_N, GLnu_p, GLnu_n, cmk(-sU, 0), {addend_of(GLnu_n, one)}));
+        }
+        // G^<_jj += M2 - M2^H + X_u G^<_uu X_u^H (+ V4 - V4^H),  M2 = K2 G_{j,u}^H
+        QTX_TRY(glu.go(Zu, OP_N, K2, OP_C, Gnu_n, M2, one, {}));
+        QTX_TRY(glu.go(Zu, OP_N, XF, OP_N, GLuu, T5, one, {}));
+        QTX_TRY(glu.go(Zu, OP_N, T5, OP_C, XF, xlu, one, {addend_of(xlu, one), addend_of(M2, one), addend_of(M2, mone, OP_C)}));
+        if (Znu > 0) {
+          // V4 = X_n G^<_{j+1,u} X_u^H = sU P' G^<_{j+1,u} XF^H
+          QTX_TRY(glu.go(Znu, OP_N, at(Pp, U0), OP_N, GLnu_p, T5, one, {}));
+          QTX_TRY(glu.go(Znu, OP_N, T5, OP_C, XF, M2, cmk(sU, 0), {}));
+          QTX_TRY(glu.go(Znu, OP_N, Mat{}, OP_N, Mat{}, xlu, zero,
+                         {addend_of(xlu, one), addend_of(M2, one), addend_of(M2, mone, OP_C)}, zero, 0));
+        }
+      }
+    }
+    // G_jj = x_j - sL G_{j,j+1} R' - G_{j,u} CX
+    if (Zn > 0) QTX_TRY(g.go(Zn, OP_N, GRu, OP_N, Rp, xi, cmk(-sL, 0), {addend_of(xi, one)}));
+    if (Zu > 0) QTX_TRY(gu.go(Zu, OP_N, Gnu_n, OP_N, CX, at(xi, U0), mone, {addend_of(at(xi, U0), one)}));
+    // entries whose first interior block is this step's: G_{u,lo}, G_{lo,u}, G^<_{u,lo}
+    int f0 = 0, f1 = 0;
+    {
+      int z = 0;
+      while (z < Zall && B.ent[z].nf - 1 > kk) ++z;
+      f0 = std::max(z, U0);
+      while (z < Zall && B.ent[z].nf - 1 == kk) ++z;
+      f1 = z;
+    }
+    if (f1 > f0) {
+      const int Zf = f1 - f0;
+      const Gemm gf = on(g, f0), glf = on(gl, f0);
+      QTX_TRY(gf.go(Zf, OP_N, Mat{}, OP_N, Mat{}, at(R.get(A_GRU, 1, kk, -1), f0), zero,
+                    {addend_of(ws_at(W.Gun[nxt], f0), one)}, zero, 0));
+      QTX_TRY(gf.go(Zf, OP_N, Mat{}, OP_N, Mat{}, at(R.get(A_GRL, 1, kk, -1), f0), zero,
+                    {addend_of(ws_at(W.Gnu[nxt], f0), one)}, zero, 0));
+      for (int r = 0; r < nr; ++r)
+        QTX_TRY(glf.go(Zf, OP_N, Mat{}, OP_N, Mat{}, at(R.get(rhs[r].Gu, 1, kk, -1), f0), zero,
+                       {addend_of(ws_at(W.GLnu[r][nxt], f0), mone, OP_C)}, zero, 0));
+    }
+  }
+
+  // ---------------------------------------------------------- status
+  // Non-finite values reach every partition's first interior block; a failure of any
+  // partition (or of the separator system, recorded on partition 0) is carried to
+  // partition 0 (P - 1 passes along the chain of partitions), which fills and reports.
+  std::vector<int> first{A_GRD};
+  for (const Rhs& r : rhs) first.push_back(r.Gd);
+  for (int a : first) {
+    const Mat m = R.get(a, 2, 0, 0);
+    if (!dry) QTX_TRY(launch_check_finite_entries(m.tab, bb, Zall, W.st, s));
+  }
+  for (int q = 1; q < P && !dry; ++q) QTX_TRY(launch_status_merge(W.st, W.part, Zall, s));
+  std::vector<std::pair<int, bool>> outs{{A_GRD, true}, {A_GRU, false}, {A_GRL, false}};
+  for (const Rhs& r : rhs) { outs.push_back({r.Gd, true}); outs.push_back({r.Gu, false}); }
+  for (auto& o : outs) {
+    const Mat m = R.get(o.first, 2, 0, 0);
+    if (!dry) QTX_TRY(launch_nan_fill_entries((double2* const*)m.tab, o.second ? W.cnt_d : W.cnt_u, Zall, W.st, s));
+  }
+  if (!dry) QTX_TRY(launch_scatter_status(W.st, W.ust, Zall, s));
+  return R.late ? QTX_ERR_HIP : QTX_OK;
+}
+
 // FNV-1a over bytes.
 struct Hasher {
   uint64_t h = 1469598103934665603ull;
@@ -1325,10 +1862,35 @@ struct Hasher {
 int split_point(int n_b) { return (n_b - 1) / 2; }
 
 // The entries of one energy: one chain, or the two halves of a split chain.
+// Interior lengths of the P partitions of a chain of n_b blocks: n_b - (P - 1) blocks
+// (the separators taken out), as equal as possible, longer ones first.
+std::vector<int> partition_lengths(int n_b, int P) {
+  const int m = n_b - (P - 1);
+  std::vector<int> len(P);
+  for (int q = 0; q < P; ++q) len[q] = m / P + (q < m % P ? 1 : 0);
+  return len;
+}
+
 std::vector<Entry> entries_of(const qtx_rgf_problem& p, int e) {
   Entry a;
   a.p = &p;
   a.e = e;
+  if (p.partitions > 1) {
+    // partition q: interior blocks off .. off + nf - 1, separators off - 1 (q > 0) and
+    // off + nf (q < P - 1); the backward recurrence starts at the last interior block
+    std::vector<Entry> out;
+    int off = 0;
+    for (const int len : partition_lengths(p.n_b, p.partitions)) {
+      Entry t = a;
+      t.q = (int)out.size();
+      t.off = off;
+      t.nf = len;
+      t.nbk = len + 1;
+      out.push_back(t);
+      off += len + 1;
+    }
+    return out;
+  }
   if (!(p.flags & QTX_SPLIT_CHAIN) || p.n_b < 3) {
     a.nf = a.nbk = p.n_b;
     return {a};
@@ -1396,10 +1958,20 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
       u0 = u1;
       // Sort by (nf, nbk, rev) descending: the entries active at a forward step and
       // at a backward step are prefixes (nbk is nf or nf + 1), and the bottom halves
-      // that reach their separator at one step are a contiguous run.
-      std::stable_sort(B.ent.begin(), B.ent.end(), [](const Entry& a, const Entry& b) {
-        return std::make_tuple(a.nf, a.nbk, a.rev) > std::make_tuple(b.nf, b.nbk, b.rev);
-      });
+      // that reach their separator at one step are a contiguous run.  A partitioned
+      // batch goes partition-major (entry q n_e + e; the interiors shrink with q, so
+      // the active entries are still prefixes).
+      if (B.key.parts > 1)
+        std::stable_sort(B.ent.begin(), B.ent.end(), [](const Entry& a, const Entry& b) { return a.q < b.q; });
+      else
+        std::stable_sort(B.ent.begin(), B.ent.end(), [](const Entry& a, const Entry& b) {
+          return std::make_tuple(a.nf, a.nbk, a.rev) > std::make_tuple(b.nf, b.nbk, b.rev);
+        });
+      if (B.key.parts > 1) {
+        // status chain: partition q takes the failure of partition q + 1 of its energy
+        const int ne = (int)B.ent.size() / B.key.parts;
+        for (size_t z = 0; z + ne < B.ent.size(); ++z) B.ent[z].part = (int)z + ne;
+      }
       for (size_t z = 0; z < B.ent.size(); ++z) {
         B.max_nf = std::max(B.max_nf, B.ent[z].nf);
         B.max_nbk = std::max(B.max_nbk, B.ent[z].nbk);
@@ -1441,8 +2013,10 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
       const Entry& en = R.B->ent[z];
       const double E = en.p->energies[en.e];
       // a bottom half neither reports nor fills: its top half does both for the energy
-      int32_t* us = en.p->status && !en.rev ? en.p->status + en.e : nullptr;
-      const int64_t cd = en.rev ? 0 : (int64_t)en.p->n_b * R.bb, cu = en.rev ? 0 : (int64_t)(en.p->n_b - 1) * R.bb;
+      // (likewise partitions q > 0: partition 0 reports and fills the whole chain)
+      const bool lead = !en.rev && en.q <= 0;
+      int32_t* us = en.p->status && lead ? en.p->status + en.e : nullptr;
+      const int64_t cd = lead ? (int64_t)en.p->n_b * R.bb : 0, cu = lead ? (int64_t)(en.p->n_b - 1) * R.bb : 0;
       const int32_t part = en.part;
       std::memcpy(R.host.data() + ed.en + z * sizeof(double), &E, sizeof(double));
       std::memcpy(R.host.data() + ed.ust + z * sizeof(void*), &us, sizeof(void*));
@@ -1451,7 +2025,7 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
       std::memcpy(R.host.data() + ed.part + z * sizeof(int32_t), &part, sizeof(int32_t));
     }
     BatchWs W;
-    qtx_status st = run_batch(R, W);
+    qtx_status st = R.B->key.parts > 1 ? run_partition(R, W) : run_batch(R, W);
     if (st != QTX_OK) return st;
     batches[bi].tab_off = tab_total;
     tab_total += align_up(R.host.size());
@@ -1533,7 +2107,7 @@ qtx_status solve_all(qtx_rgf_ctx ctx, const qtx_rgf_problem* probs, int n_probs,
       W.cnt_d = (const int64_t*)(R.dev + ed.cnt_d);
       W.cnt_u = (const int64_t*)(R.dev + ed.cnt_u);
       W.part = (const int32_t*)(R.dev + ed.part);
-      result = run_batch(R, W);
+      result = R.B->key.parts > 1 ? run_partition(R, W) : run_batch(R, W);
     }
     if (n_lanes > 1 && result == QTX_OK) {
       if (hipEventRecord(ctx->join_ev[l], ls) != hipSuccess || hipStreamWaitEvent(s, ctx->join_ev[l], 0) != hipSuccess)

@@ -65,6 +65,7 @@ class _Problem(ctypes.Structure):
         ("GG_d", ctypes.c_void_p), ("GG_u", ctypes.c_void_p),
         ("status", ctypes.c_void_p),
         ("out_bits", ctypes.c_int32),
+        ("partitions", ctypes.c_int32),
     ]
 
 
@@ -184,6 +185,7 @@ class DeviceProblem:
     split: bool = False     # QTX_SPLIT_CHAIN: two half-chains per energy
     sigma_diag: bool = False   # QTX_SIGMA_DIAG: SR_d / SL_d / SG_d are [n_e, n_b, b] diagonals
     out_bits: int = 64      # 64: complex128 outputs; 16..56: GR_u/GR_l/GL_u/GG_u as FPX bytes
+    partitions: int = 0     # P >= 2: P-way partitioned solve of every energy
 
     @property
     def n_b(self):
@@ -313,6 +315,7 @@ def _problem_struct(dp: DeviceProblem, prec: int, n_slices: int, prec_lesser: in
         flags |= QTX_SIGMA_DIAG
     st.flags = flags
     st.out_bits = int(dp.out_bits)
+    st.partitions = int(dp.partitions)
     en = np.ascontiguousarray(dp.energies, dtype=np.float64)
     st.energies = en.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     for name in ("H_d", "H_u", "H_l", "S_d", "S_u", "S_l", "SR_d", "SR_u", "SR_l", "SL_d", "SL_u", "SG_d", "SG_u",
