@@ -162,7 +162,8 @@ def main():
     ap.add_argument("--no-full-check", action="store_true",
                     help="skip the all-energy error check of the mixed schemes (then none qualifies)")
     ap.add_argument("--workload", default="realistic",
-                    choices=["realistic", "hard", "kappa", "w", "fpx", "batch", "serve", "latency", "tiny", "memory"],
+                    choices=["realistic", "hard", "kappa", "w", "fpx", "batch", "serve", "latency", "tiny", "memory",
+                             "longchain"],
                     help="realistic (default, the headline line) | hard (the realistic shapes at eta = 1e-6, "
                          "condition numbers up to ~5e6) | kappa (error against the exact condition number, "
                          "n_b=8, b=128, eta 1e-3..1e-6) | w (screened Coulomb system: assembly + solve, n_b=16, "
@@ -170,7 +171,8 @@ def main():
                          "problems, one graph launch) | "
                          "serve (Poisson arrivals, continuous batching, p50/p99) | latency (few energies) | "
                          "tiny (n_b=8, b=16, 32 energies; both CPU oracles) | memory (energies resident per GPU "
-                         "under dense / diagonal Sigma and complex128 / FPX32 outputs)")
+                         "under dense / diagonal Sigma and complex128 / FPX32 outputs) | longchain (latency of "
+                         "few energies on a long device: one chain, split, P-way partitions)")
     ap.add_argument("--workspace-gb", type=float, default=0.0,
                     help="realistic/hard: library workspace cap in GiB (0 = a quarter of free HBM)")
     ap.add_argument("--split", action="store_true",
@@ -185,6 +187,10 @@ def main():
     ap.add_argument("--time-limit", type=float, default=150.0, help="serve workload: wall-clock cap (s)")
     ap.add_argument("--prec", default="fp64", help="batch workload scheme (fp64 | int8:11 | int8:10/int8:11 | ...)")
     ap.add_argument("--mem-prec", default="int8:10/int8:10", help="memory workload scheme")
+    ap.add_argument("--long-nb", type=int, default=128, help="longchain workload: blocks of the device")
+    ap.add_argument("--long-ne", default="1,4", help="longchain workload: energy counts")
+    ap.add_argument("--long-modes", default="chain,split,p2,p4,p8,p16",
+                    help="longchain workload: chain | split | pP (P-way partitions)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: energies shard across GPUs with no exchange inside a solve, "
@@ -211,6 +217,8 @@ def main():
         return bench_tiny(args)
     if args.workload == "memory":
         return bench_memory(args)
+    if args.workload == "longchain":
+        return bench_longchain(args)
 
     cfg = inputs.CONFIGS["realistic"]
     n_b, b, n_e = cfg["n_b"], cfg["b"], cfg["n_e"]
@@ -904,6 +912,89 @@ def bench_latency(args):
                                    % args.latency_ne, "split_chain": head["split"]},
             "speedup_split": {"%d:%s" % (n, pr): best[(n, False, pr)]["p50_ms"] / best[(n, True, pr)]["p50_ms"]
                               for (n, sp, pr) in best if sp and (n, False, pr) in best},
+            "rows": rows}
+    print(json.dumps(line), flush=True)
+
+
+def bench_longchain(args):
+    """Latency of solves with few energies on a long device (random BT device of
+    --long-nb blocks, b = 416, eta = 1e-3, seed 0, energies spread over [-2, 2]): one
+    chain per energy, the two-sided split (QTX_SPLIT_CHAIN), and P-way partitions;
+    FP64 and INT8 10/10; each configuration captured once into a hipGraph and replayed
+    (2 warm-up, then `reps` timed one by one, host clock, synchronised): p50 and max.
+    Each mode's outputs against the one-chain solve of the same scheme: max relative
+    Frobenius difference per block of G^R_ii, and per block of G^<_ii over the energy's
+    largest G^<_ii block."""
+    import numpy as np
+    import torch
+    from paper_2606_25595_amd import inputs, qtx
+    n_b, b = args.long_nb, 416
+    grid = np.linspace(-2.0, 2.0, 256)
+    ctx = qtx.Context(0)
+    stream = torch.cuda.Stream()
+    modes = args.long_modes.split(",")
+    precs = args.latency_precs.split(",")
+    kw = dict(dtype=torch.complex128, device="cuda")
+    rows = []
+    for n_e in [int(x) for x in args.long_ne.split(",")]:
+        E = grid[np.linspace(0, 255, n_e + 2).astype(int)[1:-1]]
+        d = inputs.device_random_problem(n_b, b, E, seed=0, eta=1e-3)
+        dp = qtx.DeviceProblem(energies=d["energies"], H_d=d["H_d"], H_u=d["H_u"], H_l=d["H_l"],
+                               SR_d=d["SR_d"], SL_d=d["SL_d"], GR_d=torch.empty((n_e, n_b, b, b), **kw),
+                               GR_u=torch.empty((n_e, n_b - 1, b, b), **kw),
+                               GR_l=torch.empty((n_e, n_b - 1, b, b), **kw),
+                               GL_d=torch.empty((n_e, n_b, b, b), **kw),
+                               GL_u=torch.empty((n_e, n_b - 1, b, b), **kw),
+                               status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"))
+        for prec in precs:
+            skw = parse_scheme(prec)
+            ref = None
+            for mode in modes:
+                dp.split = mode == "split"
+                dp.partitions = int(mode[1:]) if mode.startswith("p") else 0
+                ctx.set_graph(True)
+                reps = 8
+                ts = []
+                with torch.cuda.stream(stream):
+                    for k in range(2 + reps):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        ctx.solve(dp, stream=stream, **skw)
+                        stream.synchronize()
+                        if k >= 2:
+                            ts.append(time.perf_counter() - t0)
+                ctx.set_graph(False)
+                ts = np.array(ts) * 1e3
+                ok = bool((dp.status == 0).all().item())
+                row = {"n_e": n_e, "mode": mode, "prec": prec, "p50_ms": float(np.median(ts)),
+                       "max_ms": float(ts.max()), "status_ok": ok}
+                if ref is None:
+                    ref = (dp.GR_d.clone(), dp.GL_d.clone())
+                else:
+                    dn = (dp.GR_d - ref[0]).abs().pow(2).sum((-1, -2)).sqrt()
+                    nr = ref[0].abs().pow(2).sum((-1, -2)).sqrt().clamp_min(1e-300)
+                    row["GR_d_vs_chain"] = float((dn / nr).max().item())
+                    dn = (dp.GL_d - ref[1]).abs().pow(2).sum((-1, -2)).sqrt()
+                    nr = ref[1].abs().pow(2).sum((-1, -2)).sqrt().amax(dim=1, keepdim=True).clamp_min(1e-300)
+                    row["GL_d_vs_chain"] = float((dn / nr).max().item())
+                rows.append(row)
+                log("bench longchain: n_b=%d n_e=%d %s %s p50 %.1f ms max %.1f ms%s%s"
+                    % (n_b, n_e, prec, mode, row["p50_ms"], row["max_ms"],
+                       (" vs chain G^R %.1e G^< %.1e" % (row["GR_d_vs_chain"], row["GL_d_vs_chain"]))
+                       if "GR_d_vs_chain" in row else "", "" if ok else " STATUS FAIL"))
+        del d, dp, ref
+        torch.cuda.empty_cache()
+    ctx.close()
+    n0 = min(r["n_e"] for r in rows)
+    chain = {(r["n_e"], r["prec"]): r["p50_ms"] for r in rows if r["mode"] == "chain"}
+    best = min((r for r in rows if r["n_e"] == n0 and r["prec"] == precs[0]), key=lambda r: r["p50_ms"])
+    line = {"metric": "selected-solve latency (p50) at %d energies on a %d-block device, %s" % (n0, n_b, precs[0]),
+            "value": best["p50_ms"], "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "longchain: random BT device n_b=%d, b=416, eta=1e-3, %s energies"
+                                   % (n_b, args.long_ne), "mode": best["mode"]},
+            "speedup_vs_chain": {"%d:%s:%s" % (r["n_e"], r["prec"], r["mode"]): chain[(r["n_e"], r["prec"])] / r["p50_ms"]
+                                 for r in rows if (r["n_e"], r["prec"]) in chain},
             "rows": rows}
     print(json.dumps(line), flush=True)
 

@@ -151,16 +151,20 @@ enum {
  *           interior top-down at the same time (the forward recurrence, plus the fill-in
  *           blocks that couple the interior to the partition's upper separator, for M
  *           and for the right-hand sides), which leaves a block tridiagonal system over
- *           the separators (reduced blocks, couplings and right-hand sides); its selected
- *           solve gives G^R, G^<, G^> at the separators; then every partition runs its
- *           backward recurrence at once, with the upper separator as a second
- *           neighbour of each interior block.  The sequential step count per energy is
- *           about 2 n_b / P + 2 P instead of 2 n_b - 1, with P times the independent
- *           products per step: it lowers the latency of solves with few energies and
- *           long chains.  Results agree with the one-chain solve to rounding (the fill-in
- *           chains cost some digits on G^< blocks much smaller than the energy's largest:
- *           see the tests).  Requires n_b >= 2 P - 1 (every interior at least one
- *           block) and P <= 64; not with QTX_SPLIT_CHAIN (QTX_ERR_ARG) or FPX outputs
+ *           the separators (reduced blocks, couplings and right-hand sides); its solve
+ *           gives G^R, G^<, G^> at the separators and each separator's left-connected
+ *           functions; then every partition runs the one-chain forward recurrence again
+ *           from those of its upper separator, and the backward recurrence from its
+ *           lower separator's G.  The sequential step count per energy is about
+ *           3 n_b / P + 2 P instead of 2 n_b - 1, with P times the independent products
+ *           per step: it lowers the latency of solves with few energies and long
+ *           chains.  The separator system comes from fill-in chains over interiors cut
+ *           off from the contacts (whose partial inverses reach 1 / broadening), so it
+ *           is always built and solved in FP64; the outputs come from the one-chain
+ *           recurrences with exact boundary functions (in the problem's schemes) and
+ *           keep the one-chain accuracy to within the separator system's rounding.
+ *           Requires n_b >= 2 P - 1 (every interior at least one block) and P <= 64;
+ *           not with QTX_SPLIT_CHAIN (QTX_ERR_ARG) or FPX outputs
  *           (QTX_ERR_UNSUPPORTED).  Energies of problems with equal (n_b, b, P) and
  *           schemes share launches.
  * Precision per chain: the products that build x_i and G^R (forward Schur

@@ -686,7 +686,7 @@ constexpr int kPartTemps = 8;
 int part_blocks(const BatchKey& k) {
   if (k.parts <= 1) return 0;
   const int nr = k.greater ? 2 : 1;
-  return 3 + 2 * nr + 2 + nr + 4 + 2 * nr + kPartTemps;
+  return 4 + 3 * nr + 1 + nr + kPartTemps;
 }
 
 // Workspace of a batch of Z entries (excluding its pointer tables).
@@ -986,20 +986,19 @@ struct BatchWs {
   double2* Uw = nullptr;
   double2* Lw = nullptr;
   double2* Ot[kOutTemps] = {};   // FPX outputs: the FP64 off-diagonal blocks of a backward step
-  // Partitioned solve, per entry z (partition q of energy e, z = q n_e + e): the reduced
-  // system's blocks that partition q produces -- Ahd: M-hat of its lower separator e_q;
-  // Ahu / Ahl: the couplings M-hat_{e_(q-1), e_q} / M-hat_{e_q, e_(q-1)}; Bhd / Bhu the same
-  // for each right-hand side; Ghu / Ghl / GLhu: the reduced solve's G^R_{e_(q-1), e_q},
-  // G^R_{e_q, e_(q-1)}, G^<_{e_(q-1), e_q}; Gnu / Gun / GLnu: the backward recurrence's
-  // G_{j,u}, G_{u,j}, G^<_{j,u} (u the upper separator; two slots, alternating steps);
-  // Pt: temporaries.
-  double2 *Ahd = nullptr, *Ahu = nullptr, *Ahl = nullptr, *Ghu = nullptr, *Ghl = nullptr;
+  // Partitioned solve, per entry z (partition q of energy e, z = q n_e + e): the separator
+  // system's blocks -- Ahd: M-hat of the lower separator e_q with the terms from above it
+  // (M_dd, the eliminated partition q), AhU: the terms of e_(q-1) from below it (the
+  // eliminated partition q); Ahu / Ahl: the couplings M-hat_{e_(q-1), e_q} /
+  // M-hat_{e_q, e_(q-1)}; Bhd, BhU, Bhu the same for each right-hand side; XL / XLl: the
+  // left-connected x, x^< of the upper separator e_(q-1) (everything above it
+  // eliminated), from which partition q's one-chain forward recurrence restarts; Pt:
+  // temporaries.
+  double2 *Ahd = nullptr, *AhU = nullptr, *Ahu = nullptr, *Ahl = nullptr, *XL = nullptr;
   double2* Bhd[2] = {};
+  double2* BhU[2] = {};
   double2* Bhu[2] = {};
-  double2* GLhu[2] = {};
-  double2* Gnu[2] = {};
-  double2* Gun[2] = {};
-  double2* GLnu[2][2] = {};
+  double2* XLl[2] = {};
   double2* Pt[kPartTemps] = {};
   GjeWork gw;
   int32_t* st = nullptr;
@@ -1025,13 +1024,8 @@ BatchWs carve_batch(char* w, const BatchKey& k, int Z) {
   if (k.parts > 1) {
     const int nr = k.greater ? 2 : 1;
     auto take = [&]() { double2* p = (double2*)w; w += blk; return p; };
-    L.Ahd = take(); L.Ahu = take(); L.Ahl = take();
-    for (int r = 0; r < nr; ++r) { L.Bhd[r] = take(); L.Bhu[r] = take(); }
-    L.Ghu = take(); L.Ghl = take();
-    for (int r = 0; r < nr; ++r) L.GLhu[r] = take();
-    for (int t = 0; t < 2; ++t) { L.Gnu[t] = take(); L.Gun[t] = take(); }
-    for (int r = 0; r < nr; ++r)
-      for (int t = 0; t < 2; ++t) L.GLnu[r][t] = take();
+    L.Ahd = take(); L.AhU = take(); L.Ahu = take(); L.Ahl = take(); L.XL = take();
+    for (int r = 0; r < nr; ++r) { L.Bhd[r] = take(); L.BhU[r] = take(); L.Bhu[r] = take(); L.XLl[r] = take(); }
     for (int t = 0; t < kPartTemps; ++t) L.Pt[t] = take();
   }
   L.gw = gje_carve(w, k.b, Z); w += align_up(gje_work_bytes(k.b, Z));
@@ -1373,46 +1367,40 @@ qtx_status run_batch(Run& R, const BatchWs& W) {
 
 // ------------------------------------------------------------------ partitioned solve
 // P-way partitioned selected solve of every energy (the spatially parallel selected
-// inversion the paper cites, in its one-sided form): the separators e_0 < .. < e_{P-2}
-// cut the chain into P partitions; entry z = q n_e + e is partition q of energy e, with
-// interior blocks off .. off + nf - 1 (logical 0 .. nf - 1), upper separator u = off - 1
-// (q > 0) and lower separator d = off + nf (q < P - 1).  Notation: M_jj, U_j = M_{j,j+1}
-// = sU U', L_j = M_{j+1,j} = sL L', B the right-hand side (Sigma^<, Sigma^>), BU_j its
-// upper block, BL_j = -BU_j^H.
+// inversion the paper cites): the separators e_0 < .. < e_{P-2} cut the chain into P
+// partitions; entry z = q n_e + e is partition q of energy e, with interior blocks
+// off .. off + nf - 1 (logical 0 .. nf - 1), upper separator u = off - 1 (q > 0) and
+// lower separator d = off + nf (q < P - 1).  Notation: M_jj, U_j = M_{j,j+1} = sU U',
+// L_j = M_{j+1,j} = sL L', B a right-hand side (Sigma^<, Sigma^>), BU_j its upper block,
+// BL_j = -BU_j^H.
 //
-// 1. Elimination of every interior, top-down: x_j = (M_jj - L_{j-1} x_{j-1} U_{j-1})^-1
-//    (no term for the first interior block) and xl_j = x_j Q_j x_j^H as in the one-chain
-//    recurrence; and the fill-ins that couple block j to u, Fr_j = M~_{j,u},
-//    Fc_j = M~_{u,j}, Br_j = B~_{j,u}:
+// 1. Separator system.  Every interior is eliminated top-down at once (the one-chain
+//    forward recurrence x_j, xl_j, started without a previous block), with the fill-ins
+//    that couple block j to u, Fr_j = M~_{j,u}, Fc_j = M~_{u,j}, Br_j = B~_{j,u}:
 //      Fr_lo = L_u, Fc_lo = U_u, Br_lo = BL_u;
 //      Fr_j = -L_{j-1} x_{j-1} Fr_{j-1},  Fc_j = -Fc_{j-1} x_{j-1} U_{j-1},
 //      Br_j = -L_{j-1} x_{j-1} Br_{j-1} + L_{j-1} xl_{j-1} Fc_{j-1}^H + (Fc_{j-1} x_{j-1} BU_{j-1})^H.
-//    Each eliminated block updates the separators: M^_uu -= Fc_j x_j Fr_j,
-//    B^_uu += -V + V^H + Fc_j xl_j Fc_j^H (V = Fc_j x_j Br_j); the last one (t) also
-//    M^_dd -= L_t x_t U_t, B^_dd += L_t xl_t L_t^H - W + W^H (W = L_t x_t BU_t), and the
-//    reduced couplings M^_{d,u} = -L_t x_t Fr_t, M^_{u,d} = -Fc_t x_t U_t,
-//    B^_{u,d} = -(B^_{d,u})^H with B^_{d,u} = -L_t x_t Br_t + L_t xl_t Fc_t^H + (Fc_t x_t BU_t)^H.
-//    Fr_j, Fc_j, Br_j are kept in the output slots GR_l, GR_u, GL_u (GG_u) of block j - 1,
-//    which the backward recurrence writes only after reading them.
-// 2. The block tridiagonal system (M^, B^) over the separators, by the one-chain
-//    recurrences: G^R, G^<, G^> of the separator blocks (into the outputs) and of their
-//    couplings (Ghu, Ghl, GLhu).
-// 3. Backward recurrence of every partition, j = last .. first interior block, over the
-//    neighbours N = {j + 1, u} of block j at its elimination:
-//      G_{j,j+1} = -x_j (U_j G_{j+1,j+1} + Fr_j G_{u,j+1}),   G_{j+1,j} = -(G_{j+1,j+1} L_j + G_{j+1,u} Fc_j) x_j,
-//      G_{j,u} = -x_j (U_j G_{j+1,u} + Fr_j G_uu),           G_{u,j} = -(G_{u,j+1} L_j + G_uu Fc_j) x_j,
-//      G_jj = x_j - (G_{j,j+1} L_j + G_{j,u} Fc_j) x_j;
-//    with K1 = x_j BU_j - xl_j L_j^H, K2 = x_j Br_j - xl_j Fc_j^H (x_j times the
-//    transformed right-hand side's row) and X_n = x_j U_j, X_u = x_j Fr_j:
-//      G^<_{j,j+1} = K1 G_{j+1,j+1}^H + K2 G_{j+1,u}^H - X_n G^<_{j+1,j+1} + X_u G^<_{j+1,u}^H,
-//      G^<_{j,u}   = K1 G_{u,j+1}^H + K2 G_uu^H - X_n G^<_{j+1,u} - X_u G^<_uu,
-//      G^<_jj = xl_j + M1 - M1^H + M2 - M2^H + X_n G^<_{j+1,j+1} X_n^H + X_u G^<_uu X_u^H + V4 - V4^H,
-//      M1 = K1 G_{j,j+1}^H, M2 = K2 G_{j,u}^H, V4 = X_n G^<_{j+1,u} X_u^H
-//    (terms of a neighbour the partition lacks are absent).
-// Partition 0 has no u, the last partition no d (its last block starts the backward
-// recurrence without a j + 1 neighbour).  Products run over entry ranges: the
-// interiors shrink with q, so the active entries of a step are a prefix, those with u
-// the entries from n_e on, those with d the entries before (P - 1) n_e.
+//    Each eliminated block contributes to its upper separator M^U_uu -= Fc_j x_j Fr_j,
+//    B^U_uu += -V + V^H + Fc_j xl_j Fc_j^H (V = Fc_j x_j Br_j); the last one (t) to the
+//    lower separator M^_dd = M_dd - L_t x_t U_t, B^_dd = B_dd + L_t xl_t L_t^H - W + W^H
+//    (W = L_t x_t BU_t), and to the couplings M^_{d,u} = -L_t x_t Fr_t,
+//    M^_{u,d} = -Fc_t x_t U_t, B^_{u,d} = -(B^_{d,u})^H with
+//    B^_{d,u} = -L_t x_t Br_t + L_t xl_t Fc_t^H + (Fc_t x_t BU_t)^H.
+// 2. The separator chain by the one-chain recurrences on (M^ + M^U, B^ + B^U): G^R,
+//    G^<, G^> of the separator blocks (into the outputs); and, per separator c, its
+//    left-connected x^L_c, xl^L_c (the same step without the partition below it,
+//    M^U and B^U): the functions of the chain's blocks 0 .. e_c alone.
+// 3. Every partition q >= 1 runs the one-chain forward recurrence again from x^L, xl^L
+//    of its upper separator (which replaces the fill-in chains: those are only used to
+//    build the separator system, and carry the cancellation of the isolated interior's
+//    1 / eta-sized partial inverses), then every partition runs the one-chain backward
+//    recurrence from its lower separator's G (the last partition from its last block);
+//    finally the couplings of each upper separator with the first interior block,
+//    G_{u,lo} = -x^L U_u G_lo, G_{lo,u} = -G_lo L_u x^L,
+//    G^<_{u,lo} = -x^L U_u G^<_lo - xl^L L_u^H G_lo^H + x^L BU_u G_lo^H.
+// Products run over entry ranges: the interiors shrink with q, so the active entries of
+// a step are a prefix, those with u the entries from n_e on, those with d the entries
+// before (P - 1) n_e.
 qtx_status run_partition(Run& R, const BatchWs& W) {
   qtx_rgf_ctx ctx = R.ctx;
   const Batch& B = *R.B;
@@ -1426,8 +1414,12 @@ qtx_status run_partition(Run& R, const BatchWs& W) {
   const int Zd = Zall - ne;        // entries with a lower separator: [0, Zd)
   hipStream_t s = R.s;
   const bool dry = R.dry;
-  Gemm g{&R, b, W.en, k.r, W.sb};
-  Gemm gl{&R, b, W.en, k.l, W.sb};
+  // The separator system (phases 1 and 2) is built and solved in FP64 whatever the
+  // schemes: its fill-in chains carry the 1 / eta-sized partial inverses of interiors cut
+  // off from the contacts, which would scale a sliced scheme's product errors up.  The
+  // interiors' one-chain recurrences (phase 3) use the problem's schemes.
+  const Gemm g_r{&R, b, W.en, k.r, W.sb}, g_l{&R, b, W.en, k.l, W.sb}, g_64{&R, b, W.en, Scheme{}, W.sb};
+  Gemm g = g_64, gl = g_64;
   const double2 one = cmk(1, 0), mone = cmk(-1, 0), zero = cmk(0, 0);
   auto ws_at = [&](double2* p, int z0) { Mat m; m.p = p ? p + (int64_t)z0 * bb : nullptr; m.stride = bb; return m; };
   auto ws = [&](double2* p) { return ws_at(p, 0); };
@@ -1438,6 +1430,7 @@ qtx_status run_partition(Run& R, const BatchWs& W) {
   };
   auto on = [&](const Gemm& G0, int z0) { Gemm G1 = G0; if (W.en) G1.energies = W.en + z0; return G1; };
   const int sd = k.sdiag ? 1 : 0;
+  const double2 dg = k.s_id ? one : zero;
 
   if (!dry) QTX_TRY(launch_fill_i32(W.st, 0, Zall, s));
   struct Rhs { int S, SU, Gd, Gu; };
@@ -1446,11 +1439,11 @@ qtx_status run_partition(Run& R, const BatchWs& W) {
   const int nr = (int)rhs.size();
 
   // Couplings of entries [z0, z0 + Z) at (mode, step, delta), as Mats of that range.
-  auto coupling = [&](int z0, int Z, int mode, int step, int delta, Mat* U, Mat* L, double* sU,
-                      double* sL) -> hipError_t {
+  struct Cpl { Mat U, L; double sU = -1.0, sL = -1.0; };
+  auto coupling = [&](int z0, int Z, int mode, int step, int delta, Cpl* c) -> hipError_t {
     if (!k.coupled) {
-      *U = at(R.get(A_HU, mode, step, delta), z0); *sU = -1.0;
-      *L = at(R.get(A_HL, mode, step, delta), z0); *sL = -1.0;
+      c->U = at(R.get(A_HU, mode, step, delta), z0); c->sU = -1.0;
+      c->L = at(R.get(A_HL, mode, step, delta), z0); c->sL = -1.0;
       return hipSuccess;
     }
     const Mat SU = k.s_id ? Mat{} : at(R.get(A_SU, mode, step, delta), z0);
@@ -1463,173 +1456,190 @@ qtx_status run_partition(Run& R, const BatchWs& W) {
     e = gz.go(Z, OP_N, Mat{}, OP_N, Mat{}, ws_at(W.Lw, z0), zero,
               {addend_of(SL, one, OP_N, 1), addend_of(at(R.get(A_HL, mode, step, delta), z0), mone),
                addend_of(at(R.get(A_SRL, mode, step, delta), z0), mone)}, zero, 0);
-    *U = ws_at(W.Uw, z0); *sU = 1.0;
-    *L = ws_at(W.Lw, z0); *sL = 1.0;
+    c->U = ws_at(W.Uw, z0); c->sU = 1.0;
+    c->L = ws_at(W.Lw, z0); c->sL = 1.0;
     return e;
   };
-  // M_jj of the entries' blocks at (mode, step, delta) as epilogue addends (+ E on the diagonal)
-  auto diag_terms = [&](int mode, int step, int delta, Addend* aH, Addend* aS, Addend* aO) {
-    *aH = addend_of(R.get(A_HD, mode, step, delta), mone);
-    *aS = addend_of(R.get(A_SRD, mode, step, delta), mone, OP_N, 0, sd);
-    *aO = k.s_id ? Addend{} : addend_of(R.get(A_SD, mode, step, delta), one, OP_N, 1);
-  };
-  const double2 dg = k.s_id ? one : zero;
-  // Entries [*f0, *f1) whose last interior block is logical i.
-  auto finishing = [&](int i, int* f0, int* f1) {
-    int z = 0;
-    while (z < Zall && B.ent[z].nf > i + 1) ++z;
-    *f0 = z;
-    while (z < Zall && B.ent[z].nf == i + 1) ++z;
-    *f1 = z;
+  // M_jj of the entries' blocks at (mode, step, delta), entries from z0, as epilogue
+  // addends (+ E on the diagonal)
+  auto diag_terms = [&](int z0, int mode, int step, int delta, Addend* aH, Addend* aS, Addend* aO) {
+    *aH = addend_of(at(R.get(A_HD, mode, step, delta), z0), mone);
+    *aS = addend_of(at(R.get(A_SRD, mode, step, delta), z0), mone, OP_N, 0, sd);
+    *aO = k.s_id ? Addend{} : addend_of(at(R.get(A_SD, mode, step, delta), z0), one, OP_N, 1);
   };
 
-  // ---------------------------------------------------------- 1. interiors
-  // reduced diagonal blocks start as M_dd, B_dd of every lower separator
+  // One-chain forward step at logical block i of the entries [z0, z0 + Z):
+  // X = M_jj - L_{j-1} xp U_{j-1}, x_j = X^-1, xl_j = x_j (B_j + L xlp L^H - V + V^H) x_j^H
+  // (V = L xp BU_{j-1}); xp, xlp: the previous block's x, x^<, or for i = 0 with `seed`
+  // the upper separator's left-connected ones (XL, XLl), else none.  fwd_x leaves X in
+  // W.X and T' = L' xp in Tm[0]; fwd_inv inverts and runs the lesser step.
+  struct Step { Cpl c; bool prev = false; };
+  auto fwd_x = [&](int z0, int Z, int i, bool seed, Step* st) -> hipError_t {
+    Addend aH, aS, aO;
+    diag_terms(z0, 0, i, 0, &aH, &aS, &aO);
+    const Gemm gz = on(g, z0);
+    st->prev = i > 0 || seed;
+    if (!st->prev) return gz.go(Z, OP_N, Mat{}, OP_N, Mat{}, ws_at(W.X, z0), zero, {aH, aS, aO}, dg, 0);
+    hipError_t e = coupling(z0, Z, 0, i, -1, &st->c);
+    if (e != hipSuccess) return e;
+    const Mat xp = i > 0 ? at(R.get(A_GRD, 0, i, -1), z0) : ws_at(W.XL, z0);
+    e = gz.go(Z, OP_N, st->c.L, OP_N, xp, ws_at(W.Tm[0], z0), one, {});
+    if (e != hipSuccess) return e;
+    return gz.go(Z, OP_N, ws_at(W.Tm[0], z0), OP_N, st->c.U, ws_at(W.X, z0), cmk(-st->c.sL * st->c.sU, 0),
+                 {aH, aS, aO}, dg);
+  };
+  auto fwd_inv = [&](int z0, int Z, int i, const Step& st) -> hipError_t {
+    const Mat xi = at(R.get(A_GRD, 0, i, 0), z0);
+    if (!dry && Z > 0) {
+      ProfScope ps(ctx, QTX_KERNEL_INV, s, 8.0 * (double)b * b * b * Z, true);
+      const hipError_t e = launch_gje_invert(b, W.X + (int64_t)z0 * bb, bb, (double2*)xi.p, xi.stride, Z, W.gw,
+                                             W.st + z0, s, (double2* const*)xi.tab);
+      if (e != hipSuccess) return e;
+    }
+    const Gemm glz = on(gl, z0);
+    const Mat Q = ws_at(W.Tm[3], z0), T1 = ws_at(W.Tm[1], z0), T4 = ws_at(W.Tm[4], z0), Zq = ws_at(W.Tm[2], z0);
+    for (int r = 0; r < nr; ++r) {
+      const Addend aB = addend_of(at(R.get(rhs[r].S, 0, i, 0), z0), one, OP_N, 0, sd);
+      hipError_t e;
+      if (!st.prev) {
+        e = glz.go(Z, OP_N, Mat{}, OP_N, Mat{}, Q, zero, {aB}, zero, 0);
+      } else {
+        const Mat xlp = i > 0 ? at(R.get(rhs[r].Gd, 0, i, -1), z0) : ws_at(W.XLl[r], z0);
+        e = glz.go(Z, OP_N, st.c.L, OP_N, xlp, T1, one, {});
+        if (e == hipSuccess && rhs[r].SU >= 0) {
+          e = glz.go(Z, OP_N, ws_at(W.Tm[0], z0), OP_N, at(R.get(rhs[r].SU, 0, i, -1), z0), T4, one, {});
+          if (e == hipSuccess)
+            e = glz.go(Z, OP_N, T1, OP_C, st.c.L, Q, one,
+                       {aB, addend_of(T4, cmk(-st.c.sL, 0)), addend_of(T4, cmk(st.c.sL, 0), OP_C)});
+        } else if (e == hipSuccess) {
+          e = glz.go(Z, OP_N, T1, OP_C, st.c.L, Q, one, {aB});
+        }
+      }
+      if (e == hipSuccess) e = glz.go(Z, OP_N, xi, OP_N, Q, Zq, one, {});
+      if (e == hipSuccess) e = glz.go(Z, OP_N, Zq, OP_C, xi, at(R.get(rhs[r].Gd, 0, i, 0), z0), one, {});
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+
+  // ---------------------------------------------------------- 1. separator system
+  // lower-separator blocks start as M_dd, B_dd; the upper-side sums at zero
   {
     Addend aH, aS, aO;
-    diag_terms(8, 0, 0, &aH, &aS, &aO);
+    diag_terms(0, 8, 0, 0, &aH, &aS, &aO);
     QTX_TRY(g.go(Zd, OP_N, Mat{}, OP_N, Mat{}, ws(W.Ahd), zero, {aH, aS, aO}, dg, 0));
-    for (int r = 0; r < nr; ++r)
+    QTX_TRY(g.go(Zd, OP_N, Mat{}, OP_N, Mat{}, ws(W.AhU), zero, {}, zero, 0));
+    for (int r = 0; r < nr; ++r) {
       QTX_TRY(gl.go(Zd, OP_N, Mat{}, OP_N, Mat{}, ws(W.Bhd[r]), zero,
                     {addend_of(R.get(rhs[r].S, 8, 0, 0), one, OP_N, 0, sd)}, zero, 0));
+      QTX_TRY(gl.go(Zd, OP_N, Mat{}, OP_N, Mat{}, ws(W.BhU[r]), zero, {}, zero, 0));
+    }
   }
-  // Separator-u terms of the entries [z0, z0 + Z) (all with u) for their block at
-  // logical i, whose x, xl, Fr, Fc, Br are known:  M^_uu -= C1 Fr,
-  // B^_uu += -V + V^H + Fc xl Fc^H  (C1 = Fc x, V = C1 Br).  C1 stays in Pt[0].
+  // Upper-separator terms of the entries [z0, z0 + Z) (all with u) for their block at
+  // logical i: M^U_uu -= C1 Fr, B^U_uu += -V + V^H + Fc xl Fc^H (C1 = Fc x, V = C1 Br).
+  // C1 stays in Pt[0].
   auto sep_u_terms = [&](int z0, int Z, int i) -> hipError_t {
     if (Z <= 0) return hipSuccess;
     const Gemm gu = on(g, z0), glu = on(gl, z0);
     const Mat x = at(R.get(A_GRD, 0, i, 0), z0);
     const Mat Fr = at(R.get(A_GRL, 0, i, -1), z0), Fc = at(R.get(A_GRU, 0, i, -1), z0);
-    const Mat C1 = ws_at(W.Pt[0], z0), Ahd_u = ws_at(W.Ahd, z0 - ne);
+    const Mat C1 = ws_at(W.Pt[0], z0), AU = ws_at(W.AhU, z0 - ne);
     hipError_t e = gu.go(Z, OP_N, Fc, OP_N, x, C1, one, {});
-    if (e == hipSuccess) e = gu.go(Z, OP_N, C1, OP_N, Fr, Ahd_u, mone, {addend_of(Ahd_u, one)});
+    if (e == hipSuccess) e = gu.go(Z, OP_N, C1, OP_N, Fr, AU, mone, {addend_of(AU, one)});
     for (int r = 0; r < nr && e == hipSuccess; ++r) {
       const Mat Br = at(R.get(rhs[r].Gu, 0, i, -1), z0), xl = at(R.get(rhs[r].Gd, 0, i, 0), z0);
-      const Mat V = ws_at(W.Pt[1], z0), C2 = ws_at(W.Pt[2], z0), Bhd_u = ws_at(W.Bhd[r], z0 - ne);
+      const Mat V = ws_at(W.Pt[1], z0), C2 = ws_at(W.Pt[2], z0), BU = ws_at(W.BhU[r], z0 - ne);
       e = glu.go(Z, OP_N, C1, OP_N, Br, V, one, {});
       if (e == hipSuccess) e = glu.go(Z, OP_N, Fc, OP_N, xl, C2, one, {});
       if (e == hipSuccess)
-        e = glu.go(Z, OP_N, C2, OP_C, Fc, Bhd_u, one,
-                   {addend_of(Bhd_u, one), addend_of(V, mone), addend_of(V, one, OP_C)});
+        e = glu.go(Z, OP_N, C2, OP_C, Fc, BU, one, {addend_of(BU, one), addend_of(V, mone), addend_of(V, one, OP_C)});
     }
     return e;
   };
-
   for (int i = 0; i < B.max_nf; ++i) {
     const int Z = R.active_fwd(i);
     const int Zu = std::max(0, Z - U0);
-    Addend aH, aS, aO;
-    diag_terms(0, i, 0, &aH, &aS, &aO);
-    const Mat xi = R.get(A_GRD, 0, i, 0);
-    Mat U, L;
-    double sU = -1.0, sL = -1.0;
-    if (i == 0) {
-      QTX_TRY(g.go(Z, OP_N, Mat{}, OP_N, Mat{}, ws(W.X), zero, {aH, aS, aO}, dg, 0));
+    Step st;
+    QTX_TRY(fwd_x(0, Z, i, false, &st));
+    if (Zu > 0 && i == 0) {
       // fill-in seeds of the entries with u: Fr = L_u, Fc = U_u, Br = BL_u = -(BU_u)^H
-      if (Zu > 0) {
-        Mat Us, Ls;
-        double sUs, sLs;
-        QTX_TRY(coupling(U0, Zu, 0, 0, -1, &Us, &Ls, &sUs, &sLs));
-        const Gemm gu = on(g, U0), glu = on(gl, U0);
-        QTX_TRY(gu.go(Zu, OP_N, Mat{}, OP_N, Mat{}, at(R.get(A_GRL, 0, 0, -1), U0), zero, {addend_of(Ls, cmk(sLs, 0))},
-                      zero, 0));
-        QTX_TRY(gu.go(Zu, OP_N, Mat{}, OP_N, Mat{}, at(R.get(A_GRU, 0, 0, -1), U0), zero, {addend_of(Us, cmk(sUs, 0))},
-                      zero, 0));
-        for (int r = 0; r < nr; ++r) {
-          const Mat BU = rhs[r].SU >= 0 ? at(R.get(rhs[r].SU, 0, 0, -1), U0) : Mat{};
-          QTX_TRY(glu.go(Zu, OP_N, Mat{}, OP_N, Mat{}, at(R.get(rhs[r].Gu, 0, 0, -1), U0), zero,
-                         {addend_of(BU, mone, OP_C)}, zero, 0));
-        }
+      Cpl cs;
+      QTX_TRY(coupling(U0, Zu, 0, 0, -1, &cs));
+      const Gemm gu = on(g, U0), glu = on(gl, U0);
+      QTX_TRY(gu.go(Zu, OP_N, Mat{}, OP_N, Mat{}, at(R.get(A_GRL, 0, 0, -1), U0), zero, {addend_of(cs.L, cmk(cs.sL, 0))},
+                    zero, 0));
+      QTX_TRY(gu.go(Zu, OP_N, Mat{}, OP_N, Mat{}, at(R.get(A_GRU, 0, 0, -1), U0), zero, {addend_of(cs.U, cmk(cs.sU, 0))},
+                    zero, 0));
+      for (int r = 0; r < nr; ++r) {
+        const Mat BU = rhs[r].SU >= 0 ? at(R.get(rhs[r].SU, 0, 0, -1), U0) : Mat{};
+        QTX_TRY(glu.go(Zu, OP_N, Mat{}, OP_N, Mat{}, at(R.get(rhs[r].Gu, 0, 0, -1), U0), zero,
+                       {addend_of(BU, mone, OP_C)}, zero, 0));
       }
-    } else {
-      QTX_TRY(coupling(0, Z, 0, i, -1, &U, &L, &sU, &sL));
-      QTX_TRY(g.go(Z, OP_N, L, OP_N, R.get(A_GRD, 0, i, -1), ws(W.Tm[0]), one, {}));            // T' = L' x_{j-1}
-      QTX_TRY(g.go(Z, OP_N, ws(W.Tm[0]), OP_N, U, ws(W.X), cmk(-sL * sU, 0), {aH, aS, aO}, dg));
-      if (Zu > 0) {
-        // block j - 1's separator terms, then the fill-ins of block j
-        QTX_TRY(sep_u_terms(U0, Zu, i - 1));
-        const Gemm gu = on(g, U0), glu = on(gl, U0);
-        const Mat Tp = ws_at(W.Tm[0], U0), C1 = ws_at(W.Pt[0], U0);   // C1 = Fc_{j-1} x_{j-1}
-        QTX_TRY(gu.go(Zu, OP_N, Tp, OP_N, at(R.get(A_GRL, 0, i, -2), U0), at(R.get(A_GRL, 0, i, -1), U0),
-                      cmk(-sL, 0), {}));                                                          // Fr_j
-        QTX_TRY(gu.go(Zu, OP_N, C1, OP_N, at(U, U0), at(R.get(A_GRU, 0, i, -1), U0), cmk(-sU, 0), {}));   // Fc_j
-        for (int r = 0; r < nr; ++r) {
-          const Mat Yq = ws_at(W.Pt[1], U0), CB = ws_at(W.Pt[2], U0);
-          const Mat Brp = at(R.get(rhs[r].Gu, 0, i, -2), U0), Brj = at(R.get(rhs[r].Gu, 0, i, -1), U0);
-          const Mat Fcp = at(R.get(A_GRU, 0, i, -2), U0);
-          QTX_TRY(glu.go(Zu, OP_N, at(L, U0), OP_N, at(R.get(rhs[r].Gd, 0, i, -1), U0), Yq, one, {}));   // L' xl_{j-1}
-          const bool bt = rhs[r].SU >= 0;
-          if (bt) QTX_TRY(glu.go(Zu, OP_N, C1, OP_N, at(R.get(rhs[r].SU, 0, i, -1), U0), CB, one, {}));   // C1 BU_{j-1}
-          QTX_TRY(glu.go(Zu, OP_N, Tp, OP_N, Brp, Brj, cmk(-sL, 0), {}));
-          QTX_TRY(glu.go(Zu, OP_N, Yq, OP_C, Fcp, Brj, cmk(sL, 0),
-                         {addend_of(Brj, one), addend_of(bt ? CB : Mat{}, one, OP_C)}));
-        }
+    } else if (Zu > 0) {
+      // block j - 1's upper-separator terms, then the fill-ins of block j
+      QTX_TRY(sep_u_terms(U0, Zu, i - 1));
+      const Gemm gu = on(g, U0), glu = on(gl, U0);
+      const Mat Tp = ws_at(W.Tm[0], U0), C1 = ws_at(W.Pt[0], U0);   // C1 = Fc_{j-1} x_{j-1}
+      QTX_TRY(gu.go(Zu, OP_N, Tp, OP_N, at(R.get(A_GRL, 0, i, -2), U0), at(R.get(A_GRL, 0, i, -1), U0),
+                    cmk(-st.c.sL, 0), {}));                                                        // Fr_j
+      QTX_TRY(gu.go(Zu, OP_N, C1, OP_N, at(st.c.U, U0), at(R.get(A_GRU, 0, i, -1), U0), cmk(-st.c.sU, 0), {}));   // Fc_j
+      for (int r = 0; r < nr; ++r) {
+        const Mat Yq = ws_at(W.Pt[1], U0), CB = ws_at(W.Pt[2], U0);
+        const Mat Brp = at(R.get(rhs[r].Gu, 0, i, -2), U0), Brj = at(R.get(rhs[r].Gu, 0, i, -1), U0);
+        const Mat Fcp = at(R.get(A_GRU, 0, i, -2), U0);
+        const bool bt = rhs[r].SU >= 0;
+        QTX_TRY(glu.go(Zu, OP_N, at(st.c.L, U0), OP_N, at(R.get(rhs[r].Gd, 0, i, -1), U0), Yq, one, {}));   // L' xl_{j-1}
+        if (bt) QTX_TRY(glu.go(Zu, OP_N, C1, OP_N, at(R.get(rhs[r].SU, 0, i, -1), U0), CB, one, {}));       // C1 BU_{j-1}
+        QTX_TRY(glu.go(Zu, OP_N, Tp, OP_N, Brp, Brj, cmk(-st.c.sL, 0), {}));
+        QTX_TRY(glu.go(Zu, OP_N, Yq, OP_C, Fcp, Brj, cmk(st.c.sL, 0),
+                       {addend_of(Brj, one), addend_of(bt ? CB : Mat{}, one, OP_C)}));
       }
     }
-    if (!dry && Z > 0) {
-      ProfScope ps(ctx, QTX_KERNEL_INV, s, 8.0 * (double)b * b * b * Z, true);
-      QTX_TRY(launch_gje_invert(b, W.X, bb, (double2*)xi.p, xi.stride, Z, W.gw, W.st, s, (double2* const*)xi.tab));
-    }
-    // lesser recurrence: Q = B_j (+ L xl L^H - L x BU - BL x^H L^H), xl_j = x_j Q x_j^H
-    for (int r = 0; r < nr; ++r) {
-      const Mat Bj = R.get(rhs[r].S, 0, i, 0);
-      const Mat Q = ws(W.Tm[3]);
-      if (i == 0) {
-        QTX_TRY(gl.go(Z, OP_N, Mat{}, OP_N, Mat{}, Q, zero, {addend_of(Bj, one, OP_N, 0, sd)}, zero, 0));
-      } else {
-        QTX_TRY(gl.go(Z, OP_N, L, OP_N, R.get(rhs[r].Gd, 0, i, -1), ws(W.Tm[1]), one, {}));
-        if (rhs[r].SU < 0) {
-          QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, Q, one, {addend_of(Bj, one, OP_N, 0, sd)}));
-        } else {
-          QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[0]), OP_N, R.get(rhs[r].SU, 0, i, -1), ws(W.Tm[4]), one, {}));
-          QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[1]), OP_C, L, Q, one,
-                        {addend_of(Bj, one, OP_N, 0, sd), addend_of(ws(W.Tm[4]), cmk(-sL, 0)),
-                         addend_of(ws(W.Tm[4]), cmk(sL, 0), OP_C)}));
-        }
-      }
-      QTX_TRY(gl.go(Z, OP_N, xi, OP_N, Q, ws(W.Tm[2]), one, {}));
-      QTX_TRY(gl.go(Z, OP_N, ws(W.Tm[2]), OP_C, xi, R.get(rhs[r].Gd, 0, i, 0), one, {}));
-    }
+    QTX_TRY(fwd_inv(0, Z, i, st));
     // entries whose last interior block is i: their separator terms
-    int f0, f1;
-    finishing(i, &f0, &f1);
+    int f0 = 0, f1 = 0;
+    {
+      int z = 0;
+      while (z < Zall && B.ent[z].nf > i + 1) ++z;
+      f0 = z;
+      while (z < Zall && B.ent[z].nf == i + 1) ++z;
+      f1 = z;
+    }
     if (f1 > f0) {
       const int u0 = std::max(f0, U0);
       QTX_TRY(sep_u_terms(u0, f1 - u0, i));   // leaves C1 = Fc_t x_t in Pt[0]
       const int d1 = std::min(f1, Zd);
       if (d1 > f0) {
         const int Zf = d1 - f0;
-        Mat Ut, Lt;
-        double sUt, sLt;
-        QTX_TRY(coupling(f0, Zf, 0, i, 0, &Ut, &Lt, &sUt, &sLt));
+        Cpl ct;
+        QTX_TRY(coupling(f0, Zf, 0, i, 0, &ct));
         const Gemm gf = on(g, f0), glf = on(gl, f0);
-        const Mat x = at(xi, f0), T2 = ws_at(W.Pt[3], f0), Ahd_d = ws_at(W.Ahd, f0);
-        QTX_TRY(gf.go(Zf, OP_N, Lt, OP_N, x, T2, one, {}));                                        // T'' = L'_t x_t
-        QTX_TRY(gf.go(Zf, OP_N, T2, OP_N, Ut, Ahd_d, cmk(-sLt * sUt, 0), {addend_of(Ahd_d, one)}));
+        const Mat x = at(R.get(A_GRD, 0, i, 0), f0), T2 = ws_at(W.Pt[3], f0), Ahd_d = ws_at(W.Ahd, f0);
+        QTX_TRY(gf.go(Zf, OP_N, ct.L, OP_N, x, T2, one, {}));                                         // T'' = L'_t x_t
+        QTX_TRY(gf.go(Zf, OP_N, T2, OP_N, ct.U, Ahd_d, cmk(-ct.sL * ct.sU, 0), {addend_of(Ahd_d, one)}));
         const int b0 = std::max(f0, U0), Zb = d1 - b0;   // entries with both separators
         if (Zb > 0) {
           const Gemm gb = on(g, b0);
           QTX_TRY(gb.go(Zb, OP_N, ws_at(W.Pt[3], b0), OP_N, at(R.get(A_GRL, 0, i, -1), b0), ws_at(W.Ahl, b0),
-                        cmk(-sLt, 0), {}));                                                          // M^_{d,u}
-          QTX_TRY(gb.go(Zb, OP_N, ws_at(W.Pt[0], b0), OP_N, at(Ut, b0 - f0), ws_at(W.Ahu, b0), cmk(-sUt, 0), {}));
+                        cmk(-ct.sL, 0), {}));                                                         // M^_{d,u}
+          QTX_TRY(gb.go(Zb, OP_N, ws_at(W.Pt[0], b0), OP_N, at(ct.U, b0 - f0), ws_at(W.Ahu, b0), cmk(-ct.sU, 0), {}));
         }
         for (int r = 0; r < nr; ++r) {
           const Mat Yt = ws_at(W.Pt[4], f0), V3 = ws_at(W.Pt[5], f0), Bhd_d = ws_at(W.Bhd[r], f0);
           const bool bt = rhs[r].SU >= 0;
-          QTX_TRY(glf.go(Zf, OP_N, Lt, OP_N, at(R.get(rhs[r].Gd, 0, i, 0), f0), Yt, one, {}));        // L'_t xl_t
+          QTX_TRY(glf.go(Zf, OP_N, ct.L, OP_N, at(R.get(rhs[r].Gd, 0, i, 0), f0), Yt, one, {}));        // L'_t xl_t
           if (bt) QTX_TRY(glf.go(Zf, OP_N, T2, OP_N, at(R.get(rhs[r].SU, 0, i, 0), f0), V3, one, {}));  // T'' BU_t
-          QTX_TRY(glf.go(Zf, OP_N, Yt, OP_C, Lt, Bhd_d, one,
-                         {addend_of(Bhd_d, one), addend_of(bt ? V3 : Mat{}, cmk(-sLt, 0)),
-                          addend_of(bt ? V3 : Mat{}, cmk(sLt, 0), OP_C)}));
+          QTX_TRY(glf.go(Zf, OP_N, Yt, OP_C, ct.L, Bhd_d, one,
+                         {addend_of(Bhd_d, one), addend_of(bt ? V3 : Mat{}, cmk(-ct.sL, 0)),
+                          addend_of(bt ? V3 : Mat{}, cmk(ct.sL, 0), OP_C)}));
           if (Zb > 0) {
-            // B^_{d,u} = -sL T'' Br_t + sL Y'' Fc_t^H + (C1 BU_t)^H  (in Pt[6]), B^_{u,d} = -(B^_{d,u})^H
+            // B^_{d,u} = -sL T'' Br_t + sL Y'' Fc_t^H + (C1 BU_t)^H (in Pt[6]);  B^_{u,d} = -(B^_{d,u})^H
             const Gemm glb = on(gl, b0);
             const Mat Bdu = ws_at(W.Pt[6], b0), CB = ws_at(W.Pt[7], b0);
             if (bt) QTX_TRY(glb.go(Zb, OP_N, ws_at(W.Pt[0], b0), OP_N, at(R.get(rhs[r].SU, 0, i, 0), b0), CB, one, {}));
             QTX_TRY(glb.go(Zb, OP_N, ws_at(W.Pt[3], b0), OP_N, at(R.get(rhs[r].Gu, 0, i, -1), b0), Bdu,
-                           cmk(-sLt, 0), {}));
-            QTX_TRY(glb.go(Zb, OP_N, ws_at(W.Pt[4], b0), OP_C, at(R.get(A_GRU, 0, i, -1), b0), Bdu, cmk(sLt, 0),
+                           cmk(-ct.sL, 0), {}));
+            QTX_TRY(glb.go(Zb, OP_N, ws_at(W.Pt[4], b0), OP_C, at(R.get(A_GRU, 0, i, -1), b0), Bdu, cmk(ct.sL, 0),
                            {addend_of(Bdu, one), addend_of(bt ? CB : Mat{}, one, OP_C)}));
             QTX_TRY(glb.go(Zb, OP_N, Mat{}, OP_N, Mat{}, ws_at(W.Bhu[r], b0), zero, {addend_of(Bdu, mone, OP_C)}, zero,
                            0));
@@ -1639,194 +1649,151 @@ qtx_status run_partition(Run& R, const BatchWs& W) {
     }
   }
 
-  // ---------------------------------------------------------- 2. separator system
+  // ---------------------------------------------------------- 2. separator chain
   // separator c of energy e lives with entry c n_e + e (partition c, its lower separator);
-  // the coupling (c - 1, c) with entry c n_e + e (partition c).  Energies: entries 0 .. n_e - 1.
+  // the coupling (c - 1, c) with entry c n_e + e (partition c); x^L_c, xl^L_c go to the
+  // slots of entry (c + 1) n_e + e (partition c + 1, whose upper separator c is).
+  // Energies: entries 0 .. n_e - 1.
   const int nsep = P - 1;
   auto sep_x = [&](int a, int c) { return at(R.get(a, 8, 0, 0), c * ne); };
+  auto invert = [&](const Mat& X, const Mat& out) -> hipError_t {
+    if (dry) return hipSuccess;
+    ProfScope ps(ctx, QTX_KERNEL_INV, s, 8.0 * (double)b * b * b * ne, true);
+    return launch_gje_invert(b, (double2*)X.p, bb, (double2*)out.p, out.stride, ne, W.gw, W.st, s,
+                             (double2* const*)out.tab);
+  };
   for (int c = 0; c < nsep; ++c) {
-    const Mat x = sep_x(A_GRD, c);
+    const Mat XLm = ws(W.Pt[0]), xh = sep_x(A_GRD, c), xL = ws_at(W.XL, (c + 1) * ne);
+    // M^L = M^_cc - A^_{c,c-1} xh_{c-1} A^_{c-1,c};  x^L = (M^L)^-1,  xh = (M^L + M^U_cc)^-1
     if (c == 0) {
-      QTX_TRY(g.go(ne, OP_N, Mat{}, OP_N, Mat{}, ws(W.X), zero, {addend_of(ws_at(W.Ahd, 0), one)}, zero, 0));
+      QTX_TRY(g.go(ne, OP_N, Mat{}, OP_N, Mat{}, XLm, zero, {addend_of(ws_at(W.Ahd, 0), one)}, zero, 0));
     } else {
       QTX_TRY(g.go(ne, OP_N, ws_at(W.Ahl, c * ne), OP_N, sep_x(A_GRD, c - 1), ws(W.Tm[0]), one, {}));
-      QTX_TRY(g.go(ne, OP_N, ws(W.Tm[0]), OP_N, ws_at(W.Ahu, c * ne), ws(W.X), mone,
-                   {addend_of(ws_at(W.Ahd, c * ne), one)}));
+      QTX_TRY(g.go(ne, OP_N, ws(W.Tm[0]), OP_N, ws_at(W.Ahu, c * ne), XLm, mone, {addend_of(ws_at(W.Ahd, c * ne), one)}));
     }
-    if (!dry) {
-      ProfScope ps(ctx, QTX_KERNEL_INV, s, 8.0 * (double)b * b * b * ne, true);
-      QTX_TRY(launch_gje_invert(b, W.X, bb, (double2*)x.p, x.stride, ne, W.gw, W.st, s, (double2* const*)x.tab));
-    }
+    QTX_TRY(g.go(ne, OP_N, Mat{}, OP_N, Mat{}, ws(W.X), zero, {addend_of(XLm, one)}, zero, 0));
+    QTX_TRY(invert(ws(W.X), xL));
+    QTX_TRY(g.go(ne, OP_N, Mat{}, OP_N, Mat{}, ws(W.X), zero, {addend_of(XLm, one), addend_of(ws_at(W.AhU, c * ne), one)},
+                 zero, 0));
+    QTX_TRY(invert(ws(W.X), xh));
     for (int r = 0; r < nr; ++r) {
-      const Mat Q = ws(W.Tm[3]);
+      // Q^L = B^_cc + A^_{c,c-1} xlh_{c-1} A^_{c,c-1}^H - V + V^H (V = T B^_{c-1,c}, T = A^_{c,c-1} xh_{c-1})
+      const Mat QL = ws(W.Pt[1]), Qh = ws(W.Tm[3]);
       if (c == 0) {
-        QTX_TRY(gl.go(ne, OP_N, Mat{}, OP_N, Mat{}, Q, zero, {addend_of(ws_at(W.Bhd[r], 0), one)}, zero, 0));
+        QTX_TRY(gl.go(ne, OP_N, Mat{}, OP_N, Mat{}, QL, zero, {addend_of(ws_at(W.Bhd[r], 0), one)}, zero, 0));
       } else {
-        // Q = B^_cc + A^_{c,c-1} xl A^_{c,c-1}^H - V + V^H,  V = T B^_{c-1,c},  T = A^_{c,c-1} x_{c-1}
         QTX_TRY(gl.go(ne, OP_N, ws_at(W.Ahl, c * ne), OP_N, sep_x(rhs[r].Gd, c - 1), ws(W.Tm[1]), one, {}));
         QTX_TRY(gl.go(ne, OP_N, ws(W.Tm[0]), OP_N, ws_at(W.Bhu[r], c * ne), ws(W.Tm[4]), one, {}));
-        QTX_TRY(gl.go(ne, OP_N, ws(W.Tm[1]), OP_C, ws_at(W.Ahl, c * ne), Q, one,
+        QTX_TRY(gl.go(ne, OP_N, ws(W.Tm[1]), OP_C, ws_at(W.Ahl, c * ne), QL, one,
                       {addend_of(ws_at(W.Bhd[r], c * ne), one), addend_of(ws(W.Tm[4]), mone),
                        addend_of(ws(W.Tm[4]), one, OP_C)}));
       }
-      QTX_TRY(gl.go(ne, OP_N, x, OP_N, Q, ws(W.Tm[2]), one, {}));
-      QTX_TRY(gl.go(ne, OP_N, ws(W.Tm[2]), OP_C, x, sep_x(rhs[r].Gd, c), one, {}));
+      QTX_TRY(gl.go(ne, OP_N, xL, OP_N, QL, ws(W.Tm[2]), one, {}));
+      QTX_TRY(gl.go(ne, OP_N, ws(W.Tm[2]), OP_C, xL, ws_at(W.XLl[r], (c + 1) * ne), one, {}));
+      QTX_TRY(gl.go(ne, OP_N, Mat{}, OP_N, Mat{}, Qh, zero, {addend_of(QL, one), addend_of(ws_at(W.BhU[r], c * ne), one)},
+                    zero, 0));
+      QTX_TRY(gl.go(ne, OP_N, xh, OP_N, Qh, ws(W.Tm[2]), one, {}));
+      QTX_TRY(gl.go(ne, OP_N, ws(W.Tm[2]), OP_C, xh, sep_x(rhs[r].Gd, c), one, {}));
     }
   }
   for (int c = nsep - 2; c >= 0; --c) {
     const Mat x = sep_x(A_GRD, c), Gn = sep_x(A_GRD, c + 1);
     const Mat Au = ws_at(W.Ahu, (c + 1) * ne), Al = ws_at(W.Ahl, (c + 1) * ne);
-    const Mat Pp = ws(W.Tm[0]), Rp = ws(W.Tm[1]);
-    const Mat Gu = ws_at(W.Ghu, (c + 1) * ne), Gl = ws_at(W.Ghl, (c + 1) * ne);
+    const Mat Pp = ws(W.Tm[0]), Rp = ws(W.Tm[1]), Gu = ws(W.Tm[5]);
     QTX_TRY(g.go(ne, OP_N, x, OP_N, Au, Pp, one, {}));                     // x_c A^_{c,c+1}
     QTX_TRY(g.go(ne, OP_N, Al, OP_N, x, Rp, one, {}));                     // A^_{c+1,c} x_c
     QTX_TRY(g.go(ne, OP_N, Pp, OP_N, Gn, Gu, mone, {}));                   // G_{c,c+1}
-    QTX_TRY(g.go(ne, OP_N, Gn, OP_N, Rp, Gl, mone, {}));                   // G_{c+1,c}
     for (int r = 0; r < nr; ++r) {
       const Mat xl = sep_x(rhs[r].Gd, c), Gln = sep_x(rhs[r].Gd, c + 1);
       const Mat K1 = ws(W.Tm[2]), Vp = ws(W.Tm[3]), M1 = ws(W.Tm[4]);
       QTX_TRY(gl.go(ne, OP_N, x, OP_N, ws_at(W.Bhu[r], (c + 1) * ne), K1, one, {}));
       QTX_TRY(gl.go(ne, OP_N, xl, OP_C, Al, K1, mone, {addend_of(K1, one)}));      // K1 = x B^u - xl A^l^H
       QTX_TRY(gl.go(ne, OP_N, Pp, OP_N, Gln, Vp, one, {}));
-      QTX_TRY(gl.go(ne, OP_N, K1, OP_C, Gn, ws_at(W.GLhu[r], (c + 1) * ne), one, {addend_of(Vp, mone)}));
       QTX_TRY(gl.go(ne, OP_N, K1, OP_C, Gu, M1, one, {}));
       QTX_TRY(gl.go(ne, OP_N, Vp, OP_C, Pp, xl, one, {addend_of(xl, one), addend_of(M1, one), addend_of(M1, mone, OP_C)}));
     }
     QTX_TRY(g.go(ne, OP_N, Gu, OP_N, Rp, x, mone, {addend_of(x, one)}));   // G_cc = x - G_{c,c+1} A^l x
   }
 
-  // ---------------------------------------------------------- 3. interiors, backward
-  // the first step's G_{j+1,u} = G_{d,u}, G_{u,j+1} = G_{u,d}, G^<_{d,u} = -(G^<_{u,d})^H
-  if (Zd > U0) {
-    const int Zb = Zd - U0;
-    const Gemm gb = on(g, U0), glb = on(gl, U0);
-    QTX_TRY(gb.go(Zb, OP_N, Mat{}, OP_N, Mat{}, ws_at(W.Gnu[0], U0), zero, {addend_of(ws_at(W.Ghl, U0), one)}, zero, 0));
-    QTX_TRY(gb.go(Zb, OP_N, Mat{}, OP_N, Mat{}, ws_at(W.Gun[0], U0), zero, {addend_of(ws_at(W.Ghu, U0), one)}, zero, 0));
-    for (int r = 0; r < nr; ++r)
-      QTX_TRY(glb.go(Zb, OP_N, Mat{}, OP_N, Mat{}, ws_at(W.GLnu[r][0], U0), zero,
-                     {addend_of(ws_at(W.GLhu[r], U0), mone, OP_C)}, zero, 0));
+  // ---------------------------------------------------------- 3. interiors
+  g = g_r;
+  gl = g_l;
+  // forward again for the partitions with an upper separator, from its x^L, xl^L
+  for (int i = 0; i < B.max_nf; ++i) {
+    const int Zu = R.active_fwd(i) - U0;
+    if (Zu <= 0) break;
+    Step st;
+    QTX_TRY(fwd_x(U0, Zu, i, i == 0, &st));
+    QTX_TRY(fwd_inv(U0, Zu, i, st));
   }
+  // one-chain backward recurrence of every partition (the last partition's last block
+  // keeps G = x, G^< = xl)
   for (int kk = 0;; ++kk) {
     const int Z = R.active_bwd(kk);
     if (Z == 0) break;
-    const int cur = kk & 1, nxt = cur ^ 1;
-    const int Zn = kk == 0 ? std::min(Z, Zd) : Z;     // entries with a j + 1 neighbour
-    const int Zu = std::max(0, Z - U0);               // entries with u
-    const int Znu = std::max(0, Zn - U0);             // entries with both
+    const int Zn = kk == 0 ? std::min(Z, Zd) : Z;
+    if (Zn <= 0) continue;
+    Cpl c;
+    QTX_TRY(coupling(0, Zn, 1, kk, 0, &c));
     const Mat xi = R.get(A_GRD, 1, kk, 0), Gn = R.get(A_GRD, 1, kk, 1);
     const Mat GRu = R.get(A_GRU, 1, kk, 0), GRl = R.get(A_GRL, 1, kk, 0);
-    const Mat Pp = ws(W.Tm[0]), Rp = ws(W.Tm[1]);
-    Mat U, L;
-    double sU = -1.0, sL = -1.0;
-    if (Zn > 0) {
-      QTX_TRY(coupling(0, Zn, 1, kk, 0, &U, &L, &sU, &sL));
-      QTX_TRY(g.go(Zn, OP_N, xi, OP_N, U, Pp, one, {}));                   // P' = x_j U'
-      QTX_TRY(g.go(Zn, OP_N, L, OP_N, xi, Rp, one, {}));                   // R' = L' x_j
-      QTX_TRY(g.go(Zn, OP_N, Pp, OP_N, Gn, GRu, cmk(-sU, 0), {}));         // G_{j,j+1} (n part)
-      QTX_TRY(g.go(Zn, OP_N, Gn, OP_N, Rp, GRl, cmk(-sL, 0), {}));         // G_{j+1,j} (n part)
+    const Mat Pp = ws(W.Tm[0]), Rp = ws(W.Tm[1]), Vp = ws(W.Tm[2]), Wp = ws(W.Tm[3]), Yp = ws(W.Tm[4]),
+              Zp = ws(W.Tm[5]);
+    QTX_TRY(g.go(Zn, OP_N, xi, OP_N, c.U, Pp, one, {}));                        // P' = x_j U'
+    QTX_TRY(g.go(Zn, OP_N, c.L, OP_N, xi, Rp, one, {}));                        // R' = L' x_j
+    QTX_TRY(g.go(Zn, OP_N, Pp, OP_N, Gn, GRu, cmk(-c.sU, 0), {}));              // G_{j,j+1}
+    QTX_TRY(g.go(Zn, OP_N, Gn, OP_N, Rp, GRl, cmk(-c.sL, 0), {}));              // G_{j+1,j}
+    QTX_TRY(gl.go(Zn, OP_N, GRu, OP_N, c.L, Wp, one, {}));                      // W' = G_{j,j+1} L'
+    // Y = -sL W' xl + x BU G_{j,j+1}^H,  Z = -sL xl L'^H + x BU,
+    // G^<_{j,j+1} = Z G_{j+1,j+1}^H - sU P' G^<_{j+1,j+1},  G^<_jj = xl + V' P'^H + Y - Y^H
+    for (const Rhs& r : rhs) {
+      const Mat xl = R.get(r.Gd, 1, kk, 0), Gln = R.get(r.Gd, 1, kk, 1);
+      const double2 msl = cmk(-c.sL, 0);
+      if (r.SU >= 0) {
+        QTX_TRY(gl.go(Zn, OP_N, xi, OP_N, R.get(r.SU, 1, kk, 0), Zp, one, {}));
+        QTX_TRY(gl.go(Zn, OP_N, Zp, OP_C, GRu, Yp, one, {}));
+        QTX_TRY(gl.go(Zn, OP_N, Wp, OP_N, xl, Yp, msl, {addend_of(Yp, one)}));
+        QTX_TRY(gl.go(Zn, OP_N, xl, OP_C, c.L, Zp, msl, {addend_of(Zp, one)}));
+      } else {
+        QTX_TRY(gl.go(Zn, OP_N, Wp, OP_N, xl, Yp, msl, {}));
+        QTX_TRY(gl.go(Zn, OP_N, xl, OP_C, c.L, Zp, msl, {}));
+      }
+      QTX_TRY(gl.go(Zn, OP_N, Pp, OP_N, Gln, Vp, one, {}));
+      QTX_TRY(gl.go(Zn, OP_N, Zp, OP_C, Gn, R.get(r.Gu, 1, kk, 0), one, {addend_of(Vp, cmk(-c.sU, 0))}));
+      QTX_TRY(gl.go(Zn, OP_N, Vp, OP_C, Pp, xl, one, {addend_of(xl, one), addend_of(Yp, one), addend_of(Yp, mone, OP_C)}));
     }
-    // u side: XF = x Fr, CX = Fc x; G_{j,u}, G_{u,j} into the next slots
+    QTX_TRY(g.go(Zn, OP_N, GRu, OP_N, Rp, xi, cmk(-c.sL, 0), {addend_of(xi, one)}));   // G_jj
+  }
+  // couplings of every upper separator with its partition's first block
+  if (Zall > U0) {
+    const int Zu = Zall - U0;
+    Cpl c;
+    QTX_TRY(coupling(U0, Zu, 9, 0, 0, &c));
     const Gemm gu = on(g, U0), glu = on(gl, U0);
-    const Mat XF = ws_at(W.Pt[0], U0), CX = ws_at(W.Pt[1], U0);
-    const Mat Guu = at(R.get(A_GRD, 9, 0, 0), U0);
-    const Mat Gnu_p = ws_at(W.Gnu[cur], U0), Gun_p = ws_at(W.Gun[cur], U0);
-    const Mat Gnu_n = ws_at(W.Gnu[nxt], U0), Gun_n = ws_at(W.Gun[nxt], U0);
-    if (Zu > 0) {
-      QTX_TRY(gu.go(Zu, OP_N, at(xi, U0), OP_N, at(R.get(A_GRL, 1, kk, -1), U0), XF, one, {}));
-      QTX_TRY(gu.go(Zu, OP_N, at(R.get(A_GRU, 1, kk, -1), U0), OP_N, at(xi, U0), CX, one, {}));
-      if (Znu > 0) {
-        QTX_TRY(gu.go(Znu, OP_N, XF, OP_N, Gun_p, at(GRu, U0), mone, {addend_of(at(GRu, U0), one)}));
-        QTX_TRY(gu.go(Znu, OP_N, Gnu_p, OP_N, CX, at(GRl, U0), mone, {addend_of(at(GRl, U0), one)}));
+    const Mat xL = ws_at(W.XL, U0), Glo = at(R.get(A_GRD, 2, 0, 0), U0);
+    const Mat Pp = ws_at(W.Pt[0], U0), Rp = ws_at(W.Pt[1], U0), T = ws_at(W.Pt[2], U0);
+    QTX_TRY(gu.go(Zu, OP_N, xL, OP_N, c.U, Pp, one, {}));                        // x^L U'_u
+    QTX_TRY(gu.go(Zu, OP_N, c.L, OP_N, xL, Rp, one, {}));                        // L'_u x^L
+    QTX_TRY(gu.go(Zu, OP_N, Pp, OP_N, Glo, at(R.get(A_GRU, 9, 0, 0), U0), cmk(-c.sU, 0), {}));
+    QTX_TRY(gu.go(Zu, OP_N, Glo, OP_N, Rp, at(R.get(A_GRL, 9, 0, 0), U0), cmk(-c.sL, 0), {}));
+    for (const Rhs& r : rhs) {
+      const Mat xlL = ws_at(W.XLl[&r - &rhs[0]], U0), Gllo = at(R.get(r.Gd, 2, 0, 0), U0);
+      // T = -sL xl^L L'^H (+ x^L BU_u);  G^<_{u,lo} = T G_lo^H - sU P' G^<_lo
+      if (r.SU >= 0) {
+        QTX_TRY(glu.go(Zu, OP_N, xL, OP_N, at(R.get(r.SU, 9, 0, 0), U0), T, one, {}));
+        QTX_TRY(glu.go(Zu, OP_N, xlL, OP_C, c.L, T, cmk(-c.sL, 0), {addend_of(T, one)}));
+      } else {
+        QTX_TRY(glu.go(Zu, OP_N, xlL, OP_C, c.L, T, cmk(-c.sL, 0), {}));
       }
-      QTX_TRY(gu.go(Zu, OP_N, XF, OP_N, Guu, Gnu_n, mone, {}));
-      QTX_TRY(gu.go(Zu, OP_N, Guu, OP_N, CX, Gun_n, mone, {}));
-      if (Znu > 0) {
-        QTX_TRY(gu.go(Znu, OP_N, at(Pp, U0), OP_N, Gnu_p, Gnu_n, cmk(-sU, 0), {addend_of(Gnu_n, one)}));
-        QTX_TRY(gu.go(Znu, OP_N, Gun_p, OP_N, at(Rp, U0), Gun_n, cmk(-sL, 0), {addend_of(Gun_n, one)}));
-      }
-    }
-    // lesser blocks (x_j is unchanged until G_jj below)
-    for (int r = 0; r < nr; ++r) {
-      const Mat xl = R.get(rhs[r].Gd, 1, kk, 0), Gln = R.get(rhs[r].Gd, 1, kk, 1);
-      const Mat GLu = R.get(rhs[r].Gu, 1, kk, 0);
-      const Mat K1 = ws(W.Pt[2]), Vp = ws(W.Pt[3]), M1 = ws(W.Pt[4]);
-      const Mat K2 = ws_at(W.Pt[5], U0), xlu = at(xl, U0);
-      // K1 = x BU - xl L^H and K2 = x Br - xl Fc^H, both from xl_j before G^<_jj replaces it
-      if (Zn > 0) {
-        if (rhs[r].SU >= 0) {
-          QTX_TRY(gl.go(Zn, OP_N, xi, OP_N, R.get(rhs[r].SU, 1, kk, 0), K1, one, {}));
-          QTX_TRY(gl.go(Zn, OP_N, xl, OP_C, L, K1, cmk(-sL, 0), {addend_of(K1, one)}));
-        } else {
-          QTX_TRY(gl.go(Zn, OP_N, xl, OP_C, L, K1, cmk(-sL, 0), {}));
-        }
-      }
-      if (Zu > 0) {
-        QTX_TRY(glu.go(Zu, OP_N, at(xi, U0), OP_N, at(R.get(rhs[r].Gu, 1, kk, -1), U0), K2, one, {}));
-        QTX_TRY(glu.go(Zu, OP_N, xlu, OP_C, at(R.get(A_GRU, 1, kk, -1), U0), K2, mone, {addend_of(K2, one)}));
-      }
-      if (Zn > 0) {
-        QTX_TRY(gl.go(Zn, OP_N, Pp, OP_N, Gln, Vp, one, {}));                         // X_n G^<_{j+1,j+1} (/ sU)
-        QTX_TRY(gl.go(Zn, OP_N, K1, OP_C, Gn, GLu, one, {addend_of(Vp, cmk(-sU, 0))}));
-        QTX_TRY(gl.go(Zn, OP_N, K1, OP_C, GRu, M1, one, {}));
-        QTX_TRY(gl.go(Zn, OP_N, Vp, OP_C, Pp, xl, one, {addend_of(xl, one), addend_of(M1, one), addend_of(M1, mone, OP_C)}));
-      }
-      if (Zu > 0) {
-        const Mat GLuu = at(R.get(rhs[r].Gd, 9, 0, 0), U0);
-        const Mat GLnu_p = ws_at(W.GLnu[r][cur], U0), GLnu_n = ws_at(W.GLnu[r][nxt], U0);
-        const Mat M2 = ws_at(W.Pt[6], U0), T5 = ws_at(W.Pt[7], U0);
-        if (Znu > 0) {
-          const Mat GLuj = at(GLu, U0);
-          QTX_TRY(glu.go(Znu, OP_N, K2, OP_C, Gnu_p, GLuj, one, {addend_of(GLuj, one)}));
-          QTX_TRY(glu.go(Znu, OP_N, XF, OP_C, GLnu_p, GLuj, one, {addend_of(GLuj, one)}));
-        }
-        // G^<_{j,u} = K2 G_uu^H - X_u G^<_uu (+ K1 G_{u,j+1}^H - X_n G^<_{j+1,u})
-        QTX_TRY(glu.go(Zu, OP_N, K2, OP_C, Guu, GLnu_n, one, {}));
-        QTX_TRY(glu.go(Zu, OP_N, XF, OP_N, GLuu, GLnu_n, mone, {addend_of(GLnu_n, one)}));
-        if (Znu > 0) {
-          QTX_TRY(glu.go(Znu, OP_N, at(K1, U0), OP_C, Gun_p, GLnu_n, one, {addend_of(GLnu_n, one)}));
-          QTX_TRY(glu.go(Znu, OP_N, at(Pp, U0), OP_N, GLnu_p, GLnu_n, cmk(-sU, 0), {addend_of(GLnu_n, one)}));
-        }
-        // G^<_jj += M2 - M2^H + X_u G^<_uu X_u^H (+ V4 - V4^H),  M2 = K2 G_{j,u}^H
-        QTX_TRY(glu.go(Zu, OP_N, K2, OP_C, Gnu_n, M2, one, {}));
-        QTX_TRY(glu.go(Zu, OP_N, XF, OP_N, GLuu, T5, one, {}));
-        QTX_TRY(glu.go(Zu, OP_N, T5, OP_C, XF, xlu, one, {addend_of(xlu, one), addend_of(M2, one), addend_of(M2, mone, OP_C)}));
-        if (Znu > 0) {
-          // V4 = X_n G^<_{j+1,u} X_u^H = sU P' G^<_{j+1,u} XF^H
-          QTX_TRY(glu.go(Znu, OP_N, at(Pp, U0), OP_N, GLnu_p, T5, one, {}));
-          QTX_TRY(glu.go(Znu, OP_N, T5, OP_C, XF, M2, cmk(sU, 0), {}));
-          QTX_TRY(glu.go(Znu, OP_N, Mat{}, OP_N, Mat{}, xlu, zero,
-                         {addend_of(xlu, one), addend_of(M2, one), addend_of(M2, mone, OP_C)}, zero, 0));
-        }
-      }
-    }
-    // G_jj = x_j - sL G_{j,j+1} R' - G_{j,u} CX
-    if (Zn > 0) QTX_TRY(g.go(Zn, OP_N, GRu, OP_N, Rp, xi, cmk(-sL, 0), {addend_of(xi, one)}));
-    if (Zu > 0) QTX_TRY(gu.go(Zu, OP_N, Gnu_n, OP_N, CX, at(xi, U0), mone, {addend_of(at(xi, U0), one)}));
-    // entries whose first interior block is this step's: G_{u,lo}, G_{lo,u}, G^<_{u,lo}
-    int f0 = 0, f1 = 0;
-    {
-      int z = 0;
-      while (z < Zall && B.ent[z].nf - 1 > kk) ++z;
-      f0 = std::max(z, U0);
-      while (z < Zall && B.ent[z].nf - 1 == kk) ++z;
-      f1 = z;
-    }
-    if (f1 > f0) {
-      const int Zf = f1 - f0;
-      const Gemm gf = on(g, f0), glf = on(gl, f0);
-      QTX_TRY(gf.go(Zf, OP_N, Mat{}, OP_N, Mat{}, at(R.get(A_GRU, 1, kk, -1), f0), zero,
-                    {addend_of(ws_at(W.Gun[nxt], f0), one)}, zero, 0));
-      QTX_TRY(gf.go(Zf, OP_N, Mat{}, OP_N, Mat{}, at(R.get(A_GRL, 1, kk, -1), f0), zero,
-                    {addend_of(ws_at(W.Gnu[nxt], f0), one)}, zero, 0));
-      for (int r = 0; r < nr; ++r)
-        QTX_TRY(glf.go(Zf, OP_N, Mat{}, OP_N, Mat{}, at(R.get(rhs[r].Gu, 1, kk, -1), f0), zero,
-                       {addend_of(ws_at(W.GLnu[r][nxt], f0), mone, OP_C)}, zero, 0));
+      QTX_TRY(glu.go(Zu, OP_N, Pp, OP_N, Gllo, ws_at(W.Pt[3], U0), one, {}));
+      QTX_TRY(glu.go(Zu, OP_N, T, OP_C, Glo, at(R.get(r.Gu, 9, 0, 0), U0), one,
+                     {addend_of(ws_at(W.Pt[3], U0), cmk(-c.sU, 0))}));
     }
   }
 
   // ---------------------------------------------------------- status
   // Non-finite values reach every partition's first interior block; a failure of any
-  // partition (or of the separator system, recorded on partition 0) is carried to
+  // partition (or of the separator chain, recorded on partition 0) is carried to
   // partition 0 (P - 1 passes along the chain of partitions), which fills and reports.
   std::vector<int> first{A_GRD};
   for (const Rhs& r : rhs) first.push_back(r.Gd);

@@ -2,15 +2,15 @@
 against the oracle's plain definition (dense inverse, G^< = G Sigma^< G^H) and against
 the one-chain GPU solve.
 
-Tolerances.  The partitioned elimination computes the separator system from fill-in
-chains over interior segments cut off from the contacts; at weak broadening their
-partial inverses reach 1/eta and the result loses digits to cancellation (the numpy
-study of the same elimination: G^R per block up to 3e-10, G^< up to 6e-8 of the energy's
-largest G^< block, at eta = 1e-3, n_b = 31 .. 64, against 1e-12 for one chain).  So:
-  * devices with strong broadening (BT Sigma of 0.2, eta 0.05): every block at 1e-11 --
-    each formula of the three phases enters these results at full weight;
-  * eta = 1e-3 long chains (n_b = 64): G^R at 2e-9 per block, G^< / G^> at 5e-7 of the
-    energy's largest block.
+Tolerances.  The separator system is built from fill-in chains over interior segments
+cut off from the contacts (at weak broadening their partial inverses reach 1/eta); the
+interiors' outputs come from the one-chain recurrences restarted from the exact
+left-connected functions of the separators, so they keep the one-chain accuracy up to
+the separator system's rounding (the numpy study of the same steps: G^R 6e-13 .. 4e-11,
+G^< 4e-12 .. 8e-11 of the energy's largest block at eta = 1e-3, n_b = 64, P = 2 .. 8).
+  * devices with strong broadening (BT Sigma of 0.2, eta 0.05): every block at 1e-11;
+  * eta = 1e-3 long chains (n_b = 64): every block at 1e-9 (G^< / G^> relative to the
+    energy's largest block).
 """
 import numpy as np
 import pytest
@@ -102,8 +102,7 @@ def test_partitions_long_chain_weak_broadening(ctx, P):
     out = solve(ctx, p, P)
     assert np.all(out["status"] == 0)
     e = errors(out, ref)
-    assert max(e[k] for k in RKEYS) < 2e-9, e
-    assert max(e[k] for k in ("GL_d", "GL_u", "GG_d", "GG_u")) < 5e-7, e
+    assert max(e.values()) < 1e-9, e
     one = solve(ctx, p, 0)
     e1 = errors(one, ref)
     assert max(e1.values()) < 1e-10, e1
