@@ -278,8 +278,10 @@ qtx_status qtx_rgf_get_stat(qtx_rgf_ctx ctx, int stat, int64_t* value);
 
 /* Autotuner.  Times every tile variant of the product kernel that the scheme
  * (prec, n_slices) uses on synthetic complex b x b x b products over `batch`
- * entries (deterministic pseudo-random operands in [-1, 1)), 1 warm-up and 3 timed
- * products each on hip_stream, and records the fastest for the shape (b, b, b),
+ * entries (deterministic pseudo-random operands in [-1, 1)) on hip_stream: two
+ * warm-up products of every variant, then two rounds of 3 timed products per
+ * variant in opposite orders (a variant's time is its faster round), and records the
+ * fastest for the shape (b, b, b),
  * the batch class ceil(log2(batch)) (classes 0..9) and the scheme (modulus count or
  * slice count).  Later products of that shape and scheme (in qtx_rgf_solve and
  * qtx_zgemm) take the recorded variant, from the record of the nearest batch class;
