@@ -163,7 +163,7 @@ def main():
                     help="skip the all-energy error check of the mixed schemes (then none qualifies)")
     ap.add_argument("--workload", default="realistic",
                     choices=["realistic", "hard", "kappa", "w", "fpx", "batch", "serve", "latency", "tiny", "memory",
-                             "longchain"],
+                             "longchain", "products"],
                     help="realistic (default, the headline line) | hard (the realistic shapes at eta = 1e-6, "
                          "condition numbers up to ~5e6) | kappa (error against the exact condition number, "
                          "n_b=8, b=128, eta 1e-3..1e-6) | w (screened Coulomb system: assembly + solve, n_b=16, "
@@ -172,7 +172,8 @@ def main():
                          "serve (Poisson arrivals, continuous batching, p50/p99) | latency (few energies) | "
                          "tiny (n_b=8, b=16, 32 energies; both CPU oracles) | memory (energies resident per GPU "
                          "under dense / diagonal Sigma and complex128 / FPX32 outputs) | longchain (latency of "
-                         "few energies on a long device: one chain, split, P-way partitions)")
+                         "few energies on a long device: one chain, split, P-way partitions) | products (INT8 "
+                         "product kernel per tile variant, operands per entry or shared by the whole batch)")
     ap.add_argument("--workspace-gb", type=float, default=0.0,
                     help="realistic/hard: library workspace cap in GiB (0 = a quarter of free HBM)")
     ap.add_argument("--split", action="store_true",
@@ -219,6 +220,8 @@ def main():
         return bench_memory(args)
     if args.workload == "longchain":
         return bench_longchain(args)
+    if args.workload == "products":
+        return bench_products(args)
 
     cfg = inputs.CONFIGS["realistic"]
     n_b, b, n_e = cfg["n_b"], cfg["b"], cfg["n_e"]
@@ -996,6 +999,49 @@ def bench_longchain(args):
             "speedup_vs_chain": {"%d:%s:%s" % (r["n_e"], r["prec"], r["mode"]): chain[(r["n_e"], r["prec"])] / r["p50_ms"]
                                  for r in rows if (r["n_e"], r["prec"]) in chain},
             "rows": rows}
+    print(json.dumps(line), flush=True)
+
+
+def bench_products(args):
+    """The INT8 product kernel alone (416^3 complex products over 256 entries, 10 moduli,
+    the library's per-launch HIP-event timer): every tile variant with operands per entry
+    and with the left, the right or both operands shared by the whole batch (batch
+    stride 0: every tile then reads the same residues, which stay in L2).  The shared
+    cases separate the cost of L2 misses from the rest of the strip pipeline."""
+    import torch
+    from paper_2606_25595_amd import qtx
+    b, batch, p = 416, 256, 10
+    ctx = qtx.Context(0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    A = torch.randn(batch, b, b, dtype=torch.complex128, device="cuda", generator=g)
+    B = torch.randn(batch, b, b, dtype=torch.complex128, device="cuda", generator=g)
+    A1, B1 = A[:1].clone(), B[:1].clone()
+    C = torch.empty_like(A)
+    rows = []
+    for v in range(64):
+        try:
+            ctx.set_int8_tile_variant(v)
+        except qtx.QtxError:
+            break                      # past the last variant
+        for name, a, bb in (("per_entry", A, B), ("shared_A", A1, B), ("shared_B", A, B1), ("shared_AB", A1, B1)):
+            ctx.zgemm(a, bb, C, prec="int8", n_slices=p)
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            ctx.profile_read(qtx.QTX_KERNEL_GEMM)
+            for _ in range(max(3, args.steps)):
+                ctx.zgemm(a, bb, C, prec="int8", n_slices=p)
+            torch.cuda.synchronize()
+            ctx.profile(False)
+            ms, n, ops = ctx.profile_read(qtx.QTX_KERNEL_GEMM)
+            rows.append({"variant": v, "operands": name, "ms": ms / n, "tops": ops / n / (ms / n * 1e-3) / 1e12})
+            log("bench products: variant %2d %-9s %.4f ms (%.0f TOP/s)" % (v, name, ms / n, rows[-1]["tops"]))
+    ctx.set_int8_tile_variant(-1)
+    ctx.close()
+    best = min((r for r in rows if r["operands"] == "per_entry"), key=lambda r: r["ms"])
+    line = {"metric": "INT8 product kernel, 416^3 x 256 complex, 10 moduli", "value": best["ms"], "unit": "ms",
+            "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "int8x10",
+            "config": {"workload": "products: 256 products of 416^3, operands per entry or shared"},
+            "best_variant": best["variant"], "rows": rows}
     print(json.dumps(line), flush=True)
 
 
