@@ -186,6 +186,9 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="serve workload: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve workload: arrival window (s)")
     ap.add_argument("--time-limit", type=float, default=150.0, help="serve workload: wall-clock cap (s)")
+    ap.add_argument("--serve-compact", type=int, default=0,
+                    help="serve workload: X in 16..56 stores the self-energies as b-vectors and the off-diagonal "
+                         "outputs as FPX X-bit bytes (0: dense complex128)")
     ap.add_argument("--prec", default="fp64", help="batch workload scheme (fp64 | int8:11 | int8:10/int8:11 | ...)")
     ap.add_argument("--mem-prec", default="int8:10/int8:10", help="memory workload scheme")
     ap.add_argument("--long-nb", type=int, default=128, help="longchain workload: blocks of the device")
@@ -1197,7 +1200,8 @@ def bench_serve(args):
     reqs = request_stream(rate=args.rate, duration=args.duration, seed=0)
     log("bench serve: %d requests over %.1f s at %.1f/s, budget %.1f GB" % (len(reqs), args.duration, args.rate,
                                                                            budget / 1e9))
-    ex = GpuExecutor(n_slots=3, workspace_per_slot=int(free * 0.08), split=args.split)
+    compact = dict(sigma_diag=True, out_bits=args.serve_compact) if args.serve_compact else {}
+    ex = GpuExecutor(n_slots=3, workspace_per_slot=int(free * 0.08), split=args.split, **compact)
     n_done = [0]
 
     def done(r):
@@ -1217,7 +1221,8 @@ def bench_serve(args):
                                                      x.get("n_slices_lesser", x.get("n_slices", 0)))
                                 for x in PRECISIONS.values()),
             "config": {"workload": "serve: Poisson %.1f/s for %.1f s, b 128..512, n_b 8..48, N_E 16..128"
-                                   % (args.rate, args.duration), "split_chain": bool(args.split)},
+                                   % (args.rate, args.duration), "split_chain": bool(args.split),
+                       "compact_out_bits": int(args.serve_compact) or None},
             "p50_latency_s": rep["p50_latency_s"], "p99_latency_s": rep["p99_latency_s"], "report": rep}
     print(json.dumps(line), flush=True)
 

@@ -53,7 +53,8 @@ class Request:
     seed: int
     precision: str = "fp64"
     t_arrive: float = 0.0
-    keep_blocks: bool = False        # copy every output block to the host (verification)
+    keep_blocks: bool = False        # copy every output block to the host (verification; FPX
+                                     # outputs as their bytes)
     # filled by the server
     t_admit: Optional[float] = None
     t_done: Optional[float] = None
@@ -258,7 +259,8 @@ class Server:
 class GpuExecutor:
     """Device state and launches for Server on one GPU."""
 
-    def __init__(self, n_slots: int = 3, device: int = 0, workspace_per_slot: int = 0, split: bool = False):
+    def __init__(self, n_slots: int = 3, device: int = 0, workspace_per_slot: int = 0, split: bool = False,
+                 sigma_diag: bool = False, out_bits: int = 64):
         import torch
         from . import qtx
         self.torch = torch
@@ -268,6 +270,16 @@ class GpuExecutor:
         # sequential steps per launch, the same results to rounding, twice the
         # library workspace per energy
         self.split = split
+        # compact storage (more energies fit the budget, same arithmetic):
+        # sigma_diag -- the device's self-energies are scalar multiples of I per
+        # block, so Sigma^R_ii and Sigma^<_ii travel as b-vectors (QTX_SIGMA_DIAG);
+        # out_bits < 64 -- G^R_{i,i+1}, G^R_{i+1,i}, G^<_{i,i+1} are written as FPX
+        # bytes of that width (Section V-A); the observables read only the
+        # diagonal blocks, which stay complex128.
+        if split and out_bits not in (0, 64):
+            raise ValueError("FPX outputs are not available for split chains")
+        self.sigma_diag = bool(sigma_diag)
+        self.out_bits = 64 if out_bits in (0, 64) else int(out_bits)
         self.device = device
         self.ctx = [qtx.Context(device, workspace_bytes=workspace_per_slot) for _ in range(n_slots)]
         if workspace_per_slot:
@@ -284,7 +296,9 @@ class GpuExecutor:
     # fixed per-slot cap (workspace_per_slot), outside this budget.
     def footprint(self, req: Request, n_energies: int) -> int:
         bb = req.b * req.b * 16
-        return n_energies * (2 * req.n_b + 5 * req.n_b - 3) * bb
+        sigma = 2 * req.n_b * (req.b * 16 if self.sigma_diag else bb)
+        off_block = bb if self.out_bits == 64 else req.b * req.b * self.out_bits // 4
+        return n_energies * (sigma + 2 * req.n_b * bb + 3 * (req.n_b - 1) * off_block)
 
     def request_bytes(self, req: Request) -> int:
         return (3 * req.n_b - 2) * req.b * req.b * 16
@@ -316,13 +330,23 @@ class GpuExecutor:
         H_d, H_u, H_l = self.H[req.rid]
         n_e, n_b, b = E.size, req.n_b, req.b
         kw = dict(dtype=torch.complex128, device="cuda")
+
+        def sigma(scal):
+            if not self.sigma_diag:
+                return inputs.diag_blocks_device(scal, b)
+            d = torch.from_numpy(np.ascontiguousarray(scal)).to("cuda")
+            return d[:, :, None].expand(n_e, n_b, b).contiguous()
+
+        def offdiag():
+            if self.out_bits == 64:
+                return torch.empty((n_e, n_b - 1, b, b), **kw)
+            return torch.empty((n_e, n_b - 1, b * b * self.out_bits // 4), dtype=torch.uint8, device="cuda")
         dp = self.qtx.DeviceProblem(
-            energies=E, H_d=H_d, H_u=H_u, H_l=H_l,
-            SR_d=inputs.diag_blocks_device(sr, b), SL_d=inputs.diag_blocks_device(sl, b),
-            GR_d=torch.empty((n_e, n_b, b, b), **kw), GR_u=torch.empty((n_e, n_b - 1, b, b), **kw),
-            GR_l=torch.empty((n_e, n_b - 1, b, b), **kw), GL_d=torch.empty((n_e, n_b, b, b), **kw),
-            GL_u=torch.empty((n_e, n_b - 1, b, b), **kw),
-            status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"), split=self.split)
+            energies=E, H_d=H_d, H_u=H_u, H_l=H_l, SR_d=sigma(sr), SL_d=sigma(sl),
+            GR_d=torch.empty((n_e, n_b, b, b), **kw), GR_u=offdiag(), GR_l=offdiag(),
+            GL_d=torch.empty((n_e, n_b, b, b), **kw), GL_u=offdiag(),
+            status=torch.full((n_e,), -1, dtype=torch.int32, device="cuda"), split=self.split,
+            sigma_diag=self.sigma_diag, out_bits=self.out_bits)
         c.handle = dp
 
     def launch(self, slot: int, chunks: List[Chunk]):

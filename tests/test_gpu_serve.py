@@ -103,3 +103,53 @@ def test_split_chains_in_serving_match_oracle(gpu):
         tol = 1e-10 if r.precision == "fp64" else 1e-6
         for k in KEYS:
             assert oracle.rel_fro_err(r.blocks[k], ref[k]).max() <= tol, (r.rid, k)
+
+
+def wide_stream(seed):
+    """Requests of the realistic block size (b = 256) arriving together."""
+    reqs = request_stream(rate=2000.0, duration=0.004, seed=seed, b_choices=[256], nb_range=(3, 5),
+                          ne_range=(3, 7), mixed_fraction=0.5)
+    assert len(reqs) >= 4
+    for r in reqs:
+        r.keep_blocks = True
+    return reqs
+
+
+def serve_with(reqs, **ex_kw):
+    ex = GpuExecutor(n_slots=3, workspace_per_slot=1 << 30, **ex_kw)
+    try:
+        srv = Server(ex, hbm_budget=1 << 31, chunk_energies=4)
+        rep = srv.run(reqs)
+    finally:
+        ex.close()
+    return srv, rep
+
+
+@pytest.mark.parametrize("out_bits", [32, 48])
+def test_compact_executor_at_b256(gpu, out_bits):
+    """The executor's compact forms (self-energies as b-vectors, FPX off-diagonal
+    outputs) on b = 256 requests: diagonal blocks and observables bitwise equal to the
+    dense executor's, FPX bytes equal to the oracle's encoding of the dense executor's
+    blocks, and the dense executor's FP64 results at the oracle's bar."""
+    dense = wide_stream(seed=21)
+    compact = [clone(r) for r in dense]
+    _, rep_d = serve_with(dense)
+    srv_c, rep_c = serve_with(compact, sigma_diag=True, out_bits=out_bits)
+    assert rep_d["completed"] == rep_c["completed"] == len(dense)
+    for rd, rc in zip(dense, compact):
+        assert np.all(rd.status == 0) and np.all(rc.status == 0)
+        for k in ("GR_d", "GL_d"):
+            assert np.array_equal(rd.blocks[k], rc.blocks[k]), (rd.rid, k)
+        assert np.array_equal(rd.T_L, rc.T_L) and np.array_equal(rd.j_L, rc.j_L)
+        for k in ("GR_u", "GR_l", "GL_u"):
+            v = rd.blocks[k]
+            flat = np.ascontiguousarray(v).view(np.float64).reshape(v.shape[0], v.shape[1], -1)
+            want = oracle.fpx_encode(flat, out_bits).reshape(v.shape[0], v.shape[1], -1)
+            assert rc.blocks[k].dtype == np.uint8 and np.array_equal(rc.blocks[k], want), (rd.rid, k)
+    for r in [q for q in dense if q.precision == "fp64"][:2]:
+        sr, sl = inputs.random_bt_scalars(r.n_b, r.energies)
+        p = inputs.BTProblem(energies=r.energies, H_d=r.blocks["H_d"], H_u=r.blocks["H_u"], H_l=r.blocks["H_l"],
+                             SR_d=inputs._diag_blocks(sr, r.b), SL_d=inputs._diag_blocks(sl, r.b))
+        ref = oracle.rgf_selected(p)
+        for k in KEYS:
+            assert oracle.rel_fro_err(r.blocks[k], ref[k]).max() <= 1e-10, (r.rid, k)

@@ -124,3 +124,18 @@ def test_on_done_called_once_per_completed_request_in_completion_order():
     small = Server(FakeExecutor(clock), hbm_budget=100, chunk_energies=4, clock=clock, on_done=on_done)
     assert not small.submit(rejected)
     assert len(seen) == 5   # a rejected request never completes
+
+
+def test_executor_footprint_compact_forms():
+    """Admission bytes of the GPU executor's storage forms (no device needed): dense
+    complex128 Sigma and outputs, b-vector Sigma, FPX off-diagonal outputs."""
+    from paper_2606_25595_amd.serve import GpuExecutor, Request
+    r = Request(rid=0, b=256, n_b=10, n_e=8, seed=1)
+    bb = 256 * 256 * 16
+    ex = object.__new__(GpuExecutor)
+    ex.sigma_diag, ex.out_bits = False, 64
+    assert ex.footprint(r, 3) == 3 * (2 * 10 + 5 * 10 - 3) * bb
+    ex.sigma_diag, ex.out_bits = True, 32
+    per = 2 * 10 * 256 * 16 + 2 * 10 * bb + 3 * 9 * (2 * 256 * 256 * 32 // 8)
+    assert ex.footprint(r, 3) == 3 * per
+    assert ex.footprint(r, 1) / (67 * bb) < 0.52                   # about half the dense bytes
