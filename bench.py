@@ -89,9 +89,10 @@ def kernel_hash(src):
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_from_profile(scheme):
+def traffic_from_profile(scheme, variant=None):
     """HBM bytes per product-kernel launch from the committed rocprofv3 --pmc
-    summary, if it was taken for this scheme on the current kernel source (else None)."""
+    summary, if it was taken for this scheme and tile variant on the current kernel
+    source (else None)."""
     prec = parse_scheme(scheme)["prec"]
     if prec not in PMC:
         return None
@@ -105,6 +106,8 @@ def traffic_from_profile(scheme):
             k, v = line[2:].split(":", 1)
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != kernel_hash(src) or kv.get("scheme") != scheme:
+        return None
+    if "tile_variant" in kv and variant is not None and int(kv["tile_variant"]) != variant:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -190,6 +193,10 @@ def main():
                     help="serve workload: X in 16..56 stores the self-energies as b-vectors and the off-diagonal "
                          "outputs as FPX X-bit bytes (0: dense complex128)")
     ap.add_argument("--prec", default="fp64", help="batch workload scheme (fp64 | int8:11 | int8:10/int8:11 | ...)")
+    ap.add_argument("--int8-variant", type=int, default=-1,
+                    help="realistic workload: force this INT8 product tile variant after the tuner ran (-1: the "
+                         "tuner's choice; counter runs use it, since a profiler's serialisation perturbs the "
+                         "tuner's timings)")
     ap.add_argument("--mem-prec", default="int8:10/int8:10", help="memory workload scheme")
     ap.add_argument("--long-nb", type=int, default=128, help="longchain workload: blocks of the device")
     ap.add_argument("--long-ne", default="1,4", help="longchain workload: energy counts")
@@ -326,6 +333,9 @@ def main():
     for prec in args.precs.split(","):
         skw = parse_scheme(prec)
         tuned.update(autotune(ctx, skw, [(b, n_e)]))
+        if args.int8_variant >= 0:
+            ctx.set_int8_tile_variant(args.int8_variant)
+            log("bench: INT8 tile variant forced to %d" % args.int8_variant)
         log("bench: %s warmup x%d" % (prec, args.warmup))
         for _ in range(args.warmup):
             ctx.solve(dp, **skw)
@@ -399,7 +409,12 @@ def main():
     g_ms, g_n, g_fl = r["gemm"]
     achieved = (g_fl / max(g_n, 1)) / (g_ms / max(g_n, 1) / 1e3) / 1e12 if g_n else None
     peak = PEAK[parse_scheme(best)["prec"]]
-    traffic = traffic_from_profile(best)
+    bsk = parse_scheme(best)
+    if bsk["prec"] == "int8" and args.int8_variant >= 0:
+        variant = args.int8_variant
+    else:
+        variant = tuned.get("%s:%d b=%d batch=%d" % (bsk["prec"], bsk.get("n_slices", 0), b, n_e), {}).get("variant")
+    traffic = traffic_from_profile(best, variant)
     kernel_name = {"fp64": "zgemm_mfma_kernel (v_mfma_f64_16x16x4)", "fp32": "zgemm_mfma_kernel (v_mfma_f32)",
                    "bf16": "zgemm_split_kernel (v_mfma_f32_16x16x32_bf16)",
                    "fp16": "zgemm_split_kernel (v_mfma_f32_16x16x32_f16)",

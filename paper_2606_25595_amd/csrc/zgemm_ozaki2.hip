@@ -8,9 +8,11 @@
 //
 // Residues.  For odd, pairwise coprime moduli m_0..m_{p-1} <= 255 each integer is
 // stored as its symmetric residue in [-(m-1)/2, (m-1)/2] (fits int8).  Layout per
-// batch entry: [p][KT][R][2][64] bytes (KT = ceil(K / 64) strips of 64 k, plane 0
-// = real, 1 = imaginary; k beyond K is zero), so the 64-row tile of one modulus
-// and one strip is one contiguous 8 KB block.
+// batch entry: [p][KT][4][R][32] bytes (KT = ceil(K / 64) strips of 64 k; part
+// P = 2 c + t of a strip holds plane c (0 = real, 1 = imaginary) and k = 32 t .. +31 of
+// the strip, one 32-byte run per row, i.e. the k of one 32-k matrix-core step; k beyond
+// K is zero).  32 rows of a part are one contiguous 1 KB run: one wave's global-to-LDS
+// copy.
 //
 // Product (4M).  For each modulus the INT32 matrix cores accumulate, exactly,
 //   rr = sum Ar' Br',  ii = sum Ai' Bi',  ri = sum Ar' Bi' + Ai' Br'
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(NT) void o2_residue_kernel(SplitDesc sd, O2Params P
         uint2 pk;
         pk.x = w[0];
         pk.y = w[1];
-        *(uint2*)(out + ((((int64_t)i * KT + kt) * sd.rows + r0 + r) * 2 + c) * KS + 32 * h + kq) = pk;
+        *(uint2*)(out + ((((int64_t)i * KT + kt) * 4 + 2 * c + h) * sd.rows + r0 + r) * 32 + kq) = pk;
       }
     }
   }
@@ -211,7 +213,8 @@ __global__ __launch_bounds__(64 * RB) void o2_convert_kernel(SplitDesc sd, O2Par
         w[j >> 2] |= ((uint32_t)rr & 0xffu) << (8 * (j & 3));
       }
       if (live) {
-        int8_t* dst = out + ((((int64_t)i * KT + kt) * sd.rows + r0 + r) * 2 + c) * KS + VPL * ks;
+        const int kk = VPL * ks;   // k within the strip (VPL <= 16 bytes never cross a 32-k part)
+        int8_t* dst = out + ((((int64_t)i * KT + kt) * 4 + 2 * c + kk / 32) * sd.rows + r0 + r) * 32 + kk % 32;
         if constexpr (VPL == 16) {
           u4 pk = {w[0], w[1], w[2], w[3]};
           *(u4*)dst = pk;
@@ -263,11 +266,13 @@ __device__ inline void crt_fold(int c, double m, double im, double u, double& S)
 // The (modulus, strip) tiles, modulus-major, stream through an NSTAGE-deep LDS
 // ring filled by direct global->LDS loads (no registers held for them), so
 // NSTAGE - 1 steps of SPI strips are in flight while one feeds the matrix
-// cores.  A stage holds SPI strips, each the BM A rows then the BN B rows, 128 bytes each
-// (two planes x 64 k); the 16-byte slot s of row r sits at slot s ^ ((r / 2) % 8).  The
-// LDS of gfx950 has 64 banks and serves a 16-byte-per-lane read 16 lanes per cycle; row r
-// covers banks 32 (r % 2) .. +31, so the 16 consecutive rows one cycle of a fragment read
-// touches (one slot each) fall into 16 distinct groups of four banks.  Each thread
+// cores.  A stage holds SPI strips, each A's 4 parts of BM rows then B's 4 parts of
+// BN rows (32 bytes per row and part, the global layout's order, with the halves of
+// rows 8..15 of every 16 swapped).  The LDS of gfx950 has 64 banks and serves a
+// 16-byte-per-lane read 16 lanes per cycle: the 16 consecutive rows one cycle of a
+// fragment read touches (one 16-byte half each) fall into 16 distinct groups of four
+// banks, and every fragment address is the lane's slot plus a compile-time offset.
+// Each thread
 // issues exactly LPT loads per strip, so "strip j has landed" is a fixed count
 // of outstanding vector-memory operations.  Rows beyond M (N) load row M - 1
 // (N - 1): they only feed outputs that are never stored.
@@ -279,7 +284,7 @@ __device__ inline void crt_fold(int c, double m, double im, double u, double& S)
 //   1: 64 x 64, one block per wave, 256 threads, 2 strips per step, 2 stages (64 KB,
 //      two per CU)
 //   2: 64 x 64, 256 threads, 1 strip per step, 3 stages (48 KB, two per CU)
-//   3: as 2, three per CU (registers capped at 168 per lane; some spill)
+//   3: as 2, three per CU (registers capped at 168 per lane; no spills in the strip loop)
 //   4: 64 x 64, 256 threads, 1 strip per step, 2 stages (32 KB, three per CU)
 //   5, 6: variants 4 and 1 with one tile per workgroup instead of persistent
 //      workgroups (the hardware then keeps a window of consecutive tiles -- the
@@ -310,7 +315,7 @@ struct O2Cfg {
   static constexpr int LPT = SPI * LPS;               // copies per thread per step
   static constexpr int WPC = WPC_;                    // workgroups per CU (LDS / registers)
   static constexpr int WAVES_PER_SIMD = (WPC * NT / 256) > 0 ? WPC * NT / 256 : 1;
-  static constexpr bool TWO_ACC = WPC * NT >= 768 || WM * WN > 1;   // O2Acc layout
+  static constexpr bool TWO_ACC = WM * WN > 1;   // O2Acc layout (two blocks per wave: two accumulators)
   static_assert(BM % (32 * WM) == 0 && BN % (32 * WN) == 0, "wave blocks");
   static_assert(STRIP_U4 % NT == 0 && (BM * 8) % NT == 0, "copy split");
   static_assert(NSTAGE >= 2 && NSTAGE <= 4, "ring depth");
@@ -333,8 +338,9 @@ typedef __attribute__((address_space(3))) double lds_f64;
 
 // Accumulators of one 32 x 32 output block.  INT32 sums of the current modulus:
 // with TWO, re = rr - ii in one accumulator (the imaginary B fragment negated in
-// registers: 16 fewer VGPRs per block, which the register-capped variants need) and
-// im = ri + ir; else rr, ii and ri + ir apart (no negation work).  The INT32 sums, and
+// registers: 16 fewer VGPRs per block, which the variants with two blocks per wave
+// need) and im = ri + ir; else rr, ii and ri + ir apart (no negation work in the
+// strip loop; the subtraction rr - ii happens once per modulus, in the fold).  The INT32 sums, and
 // so the results, are the same either way.
 template <bool TWO>
 struct O2Acc;
@@ -345,17 +351,23 @@ struct O2Acc<true> {
   __device__ inline void clear(int v) { are[v] = 0; aim[v] = 0; }
   __device__ inline int re(int v) const { return are[v]; }
   __device__ inline int im(int v) const { return aim[v]; }
-  // bn = the imaginary B fragment negated
+  // bn = the imaginary B fragment negated.  FIRST: the first k-step of a modulus, whose
+  // products start from zero (the matrix cores take the zero addend, so the sums of the
+  // previous modulus need no clearing).
+  template <bool FIRST>
   __device__ inline void step(i4 ar, i4 ai, i4 br, i4 bi, i4 bn) {
-    are = mfma_i8(ar, br, are);
-    aim = mfma_i8(ar, bi, aim);
+    const i16v z = {};
+    are = mfma_i8(ar, br, FIRST ? z : are);
+    aim = mfma_i8(ar, bi, FIRST ? z : aim);
     are = mfma_i8(ai, bn, are);
     aim = mfma_i8(ai, br, aim);
   }
   // the same with B conjugated (bi -> -bi): the negation moves to the other product
+  template <bool FIRST>
   __device__ inline void step_conj(i4 ar, i4 ai, i4 br, i4 bi, i4 bn) {
-    are = mfma_i8(ar, br, are);
-    aim = mfma_i8(ar, bn, aim);
+    const i16v z = {};
+    are = mfma_i8(ar, br, FIRST ? z : are);
+    aim = mfma_i8(ar, bn, FIRST ? z : aim);
     are = mfma_i8(ai, bi, are);
     aim = mfma_i8(ai, br, aim);
   }
@@ -367,13 +379,16 @@ struct O2Acc<false> {
   __device__ inline void clear(int v) { arr[v] = 0; aii[v] = 0; ari[v] = 0; }
   __device__ inline int re(int v) const { return arr[v] - aii[v]; }
   __device__ inline int im(int v) const { return ari[v]; }
+  template <bool FIRST>
   __device__ inline void step(i4 ar, i4 ai, i4 br, i4 bi, i4) {
-    arr = mfma_i8(ar, br, arr);
-    aii = mfma_i8(ai, bi, aii);
-    ari = mfma_i8(ar, bi, ari);
+    const i16v z = {};
+    arr = mfma_i8(ar, br, FIRST ? z : arr);
+    aii = mfma_i8(ai, bi, FIRST ? z : aii);
+    ari = mfma_i8(ar, bi, FIRST ? z : ari);
     ari = mfma_i8(ai, br, ari);
   }
-  __device__ inline void step_conj(i4 ar, i4 ai, i4 br, i4 bi, i4 bn) { step(ar, ai, br, bn, bi); }
+  template <bool FIRST>
+  __device__ inline void step_conj(i4 ar, i4 ai, i4 br, i4 bi, i4 bn) { step<FIRST>(ar, ai, br, bn, bi); }
 };
 
 // Per-thread constants of the strip loop.
@@ -382,10 +397,15 @@ struct O2Ctx {
   int off[LPS];              // byte offset (in A's or B's residues) of each of the thread's slots of a strip
   int sstride_a, sstride_b;  // bytes from one strip to the next (residue offsets are < 2^31)
   const lds_f64* cst;        // moduli, their reciprocals, the CRT factors u (LDS)
-  int tid, la[WM], lb[WN], lk, KT, K, NSTRIP;
+  int tid, wbase, lb[WN], lk, KT, K, NSTRIP;   // wbase: the wave's first thread (scalar)
+  int pa[WM], pb[WN];        // ring slot of the lane's 16 bytes (k half lk) in part 0 of A / of B
   bool live[WM][WN];         // the wave's 32 x 32 blocks that hold outputs (wave-uniform)
   bool wlive;                // any of them
 };
+
+// Ring position of 16-byte half h of a row's 32 bytes (an involution: the same map
+// takes a ring position back to the half stored there).
+__device__ inline int ring_half(int row, int h) { return h ^ ((row >> 3) & 1); }
 
 __device__ inline void lds_barrier() {
   asm volatile("" ::: "memory");
@@ -441,10 +461,12 @@ __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
       const int f = min(SPI * sd + q / LPS, c.NSTRIP - 1);
+      // the strip's offset is wave-uniform: it travels as the scalar offset, so the
+      // per-lane offset is the tile's fixed c.off and no vector add is needed per copy
       __builtin_amdgcn_raw_ptr_buffer_load_lds(q % LPS < CF::LPS_A ? ra : rb,
-                                               (__attribute__((address_space(3))) void*)(dma + q * CF::NT + (c.tid & ~63)),
-                                               16, c.off[q % LPS] + f * (q % LPS < CF::LPS_A ? c.sstride_a : c.sstride_b),
-                                               0, 0, 0);
+                                               (__attribute__((address_space(3))) void*)(dma + q * CF::NT + c.wbase),
+                                               16, c.off[q % LPS], f * (q % LPS < CF::LPS_A ? c.sstride_a : c.sstride_b),
+                                               0, 0);
     }
   }
   if (s < 0) return;
@@ -465,27 +487,31 @@ __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u
     for (int t = 0; t < 2; ++t) {
       if (t == 1 && !two) break;
       if (!c.wlive) break;
-      const int w = 2 * t + c.lk;
+      // parts t (real) and 2 + t (imaginary): the lane's slot plus a compile-time offset
       i4 far_[WM], fai[WM], fbr[WN], fbi[WN], fbn[WN];
 #pragma unroll
       for (int x = 0; x < WM; ++x) {
-        const int sa = (c.la[x] >> 1) & 7;
-        far_[x] = __builtin_bit_cast(i4, st[c.la[x] * 8 + (w ^ sa)]);
-        fai[x] = __builtin_bit_cast(i4, st[c.la[x] * 8 + ((4 + w) ^ sa)]);
+        far_[x] = __builtin_bit_cast(i4, st[c.pa[x] + t * 2 * CF::BM]);
+        fai[x] = __builtin_bit_cast(i4, st[c.pa[x] + (2 + t) * 2 * CF::BM]);
       }
 #pragma unroll
       for (int y = 0; y < WN; ++y) {
-        const int sb = (c.lb[y] >> 1) & 7;
-        fbr[y] = __builtin_bit_cast(i4, st[c.lb[y] * 8 + (w ^ sb)]);
-        fbi[y] = __builtin_bit_cast(i4, st[c.lb[y] * 8 + ((4 + w) ^ sb)]);
+        fbr[y] = __builtin_bit_cast(i4, st[c.pb[y] + t * 2 * CF::BN]);
+        fbi[y] = __builtin_bit_cast(i4, st[c.pb[y] + (2 + t) * 2 * CF::BN]);
         fbn[y] = (CF::TWO_ACC || CONJB) ? neg_i8x16(fbi[y]) : fbi[y];
       }
+      const bool first = t == 0 && kt == 0;   // wave-uniform
 #pragma unroll
       for (int x = 0; x < WM; ++x)
 #pragma unroll
         for (int y = 0; y < WN; ++y) {
-          if (CONJB) a[x][y].step_conj(far_[x], fai[x], fbr[y], fbi[y], fbn[y]);
-          else a[x][y].step(far_[x], fai[x], fbr[y], fbi[y], fbn[y]);
+          if (first) {
+            if (CONJB) a[x][y].template step_conj<true>(far_[x], fai[x], fbr[y], fbi[y], fbn[y]);
+            else a[x][y].template step<true>(far_[x], fai[x], fbr[y], fbi[y], fbn[y]);
+          } else {
+            if (CONJB) a[x][y].template step_conj<false>(far_[x], fai[x], fbr[y], fbi[y], fbn[y]);
+            else a[x][y].template step<false>(far_[x], fai[x], fbr[y], fbi[y], fbn[y]);
+          }
         }
     }
     if (kt == c.KT - 1) {
@@ -498,7 +524,6 @@ __device__ __attribute__((always_inline)) inline void o2_step(int s, const lds_u
           for (int v = 0; v < 16; ++v) {
             crt_fold(a[x][y].re(v), m, im, u, a[x][y].sre[v]);
             crt_fold(a[x][y].im(v), m, im, u, a[x][y].sim[v]);
-            a[x][y].clear(v);
           }
     }
   }
@@ -574,25 +599,38 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles, int persist) 
   __syncthreads();   // also drains these loads before the counted ring loads start
 
   // Per-thread source of each of its LPS slots of a strip (the strip offset added
-  // per strip): slot cs = q * NT + tid; A rows first, then B rows.
+  // per strip): slot cs = q * NT + tid; the ring holds a strip as A's 4 parts of BM
+  // rows, then B's 4 parts of BN rows, 32 bytes per row (slot = 2 (part * rows + row) +
+  // half), the two 16-byte halves of a row swapped when bit 3 of the row is set
+  // (ring_half): a matrix-core fragment read then takes 16 rows of one half in 16
+  // distinct groups of four of gfx950's 64 LDS banks.
   O2Ctx<LPS, WM, WN> c;
 #pragma unroll
   for (int q = 0; q < LPS; ++q) {
     const int cs = q * NT + tid;
-    const int row = cs >> 3, slot = cs & 7;
-    const int word = slot ^ ((row >> 1) & 7);
-    const int rg = row < BM ? min(m0 + row, M - 1) : min(n0 + row - BM, N - 1);   // q < LPS_A: A rows
-    c.off[q] = rg * 128 + 16 * word;
+    const bool isa = cs < 8 * BM;            // q < LPS_A: A
+    const int rows = isa ? BM : BN, ce = isa ? cs : cs - 8 * BM;
+    const int part = ce / (2 * rows), row = (ce % (2 * rows)) >> 1, half = ring_half(row, ce & 1);
+    const int rg = isa ? min(m0 + row, M - 1) : min(n0 + row, N - 1);
+    c.off[q] = ((part * (isa ? M : N) + rg) * 2 + half) * 16;
   }
   c.sstride_a = M * 128;
   c.sstride_b = N * 128;
   c.cst = (const lds_f64*)&cst[0];
   c.tid = tid;
-#pragma unroll
-  for (int x = 0; x < WM; ++x) c.la[x] = 32 * (WM * wm + x) + (lane & 31);
-#pragma unroll
-  for (int y = 0; y < WN; ++y) c.lb[y] = BM + 32 * (WN * wn + y) + (lane & 31);
+  c.wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
   c.lk = lane >> 5;
+#pragma unroll
+  for (int x = 0; x < WM; ++x) {
+    const int row = 32 * (WM * wm + x) + (lane & 31);
+    c.pa[x] = 2 * row + ring_half(row, c.lk);
+  }
+#pragma unroll
+  for (int y = 0; y < WN; ++y) {
+    const int row = 32 * (WN * wn + y) + (lane & 31);
+    c.lb[y] = BM + row;
+    c.pb[y] = 8 * BM + 2 * row + ring_half(row, c.lk);
+  }
   c.KT = KT;
   c.K = K;
   c.NSTRIP = NSTRIP;
@@ -619,11 +657,20 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles, int persist) 
         acc[x][y].clear(v);
         acc[x][y].sre[v] = 0.0; acc[x][y].sim[v] = 0.0;
       }
-  auto stage = [&](int f) { return (lds_u4*)&ring[(f + NSTAGE) % NSTAGE][0]; };   // f >= -NSTAGE
+  // Step s reads stage (s + NSTAGE) % NSTAGE and copies into stage (s - 1 + NSTAGE) % NSTAGE;
+  // unrolled NSTAGE steps at a time (s = st0 + u with st0 = 1 mod NSTAGE), so that both
+  // stages are compile-time constants and every LDS address is a register plus an
+  // immediate offset.
   const int nstep = (NSTRIP + SPI - 1) / SPI;
   int fi = 0, fkt = 0;
-  for (int st = -(NSTAGE - 1); st < nstep; ++st)
-    o2_step<CF, CONJB>(st, stage(st), stage(st + NSTAGE - 1), SA, SB, c, acc, fi, fkt);
+  for (int st0 = -(NSTAGE - 1); st0 < nstep; st0 += NSTAGE) {
+#pragma unroll
+    for (int u = 0; u < NSTAGE; ++u) {
+      if (st0 + u >= nstep) break;
+      o2_step<CF, CONJB>(st0 + u, (const lds_u4*)&ring[(u + 1) % NSTAGE][0], (lds_u4*)&ring[u][0], SA, SB, c, acc,
+                         fi, fkt);
+    }
+  }
 
   // epilogue in FP64 (same addend semantics as the FP64 kernels).  Its parameters are
   // read here from the kernel-argument segment through a pointer the compiler cannot
