@@ -207,6 +207,19 @@ def test_rgf_ragged_shapes(ctx, n_b, b, n_e):
     check_blocks(out, oracle.rgf_selected(p))
 
 
+@pytest.mark.parametrize("n_b,b", [(3, 700), (2, 1024)])
+@pytest.mark.parametrize("scheme,tol", [(dict(prec="fp64"), TOL),
+                                        (dict(prec="int8", n_slices=10, prec_lesser="int8", n_slices_lesser=11), 1e-6)])
+def test_rgf_largest_blocks(ctx, n_b, b, scheme, tol):
+    """Blocks past the single-pass limits: b = 700 and the largest b the library takes,
+    1024 (16-column inversion panels; the INT8 operands of K > 512 take the two-pass
+    conversion), against the oracle's recurrences."""
+    p = inputs.random_bt_problem(n_b, b, np.array([-0.7, 0.9]), seed=b, with_greater=True)
+    _, out = solve_gpu(ctx, p, **scheme)
+    assert np.all(out["status"] == 0)
+    check_blocks(out, oracle.rgf_selected(p), tol=tol, keys=("GR_d", "GR_u", "GR_l", "GL_d", "GL_u", "GG_d", "GG_u"))
+
+
 def test_rgf_general_overlap_and_bt_sigma_r(ctx):
     rng = np.random.default_rng(9)
     n_b, b = 4, 24
