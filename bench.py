@@ -189,6 +189,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="serve workload: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serve workload: arrival window (s)")
     ap.add_argument("--time-limit", type=float, default=150.0, help="serve workload: wall-clock cap (s)")
+    ap.add_argument("--serve-slots", type=int, default=3, help="serve workload: launches in flight (library contexts)")
+    ap.add_argument("--serve-chunk", type=int, default=16, help="serve workload: energies per chunk")
     ap.add_argument("--serve-compact", type=int, default=0,
                     help="serve workload: X in 16..56 stores the self-energies as b-vectors and the off-diagonal "
                          "outputs as FPX X-bit bytes (0: dense complex128)")
@@ -1216,7 +1218,8 @@ def bench_serve(args):
     log("bench serve: %d requests over %.1f s at %.1f/s, budget %.1f GB" % (len(reqs), args.duration, args.rate,
                                                                            budget / 1e9))
     compact = dict(sigma_diag=True, out_bits=args.serve_compact) if args.serve_compact else {}
-    ex = GpuExecutor(n_slots=3, workspace_per_slot=int(free * 0.08), split=args.split, **compact)
+    ex = GpuExecutor(n_slots=args.serve_slots, workspace_per_slot=int(free * 0.24 / args.serve_slots), split=args.split,
+                     **compact)
     n_done = [0]
 
     def done(r):
@@ -1225,7 +1228,7 @@ def bench_serve(args):
             log("bench serve: %d requests completed (latest: id %d, %d energies, %.2f s)"
                 % (n_done[0], r.rid, r.n_e, r.latency))
 
-    srv = Server(ex, hbm_budget=budget, chunk_energies=16, max_pending=512, on_done=done)
+    srv = Server(ex, hbm_budget=budget, chunk_energies=args.serve_chunk, max_pending=512, on_done=done)
     rep = srv.run(reqs, time_limit=args.time_limit)
     ex.close()
     line = {"metric": "served RGF energy points/sec with p50/p99 request latency",
@@ -1237,7 +1240,8 @@ def bench_serve(args):
                                 for x in PRECISIONS.values()),
             "config": {"workload": "serve: Poisson %.1f/s for %.1f s, b 128..512, n_b 8..48, N_E 16..128"
                                    % (args.rate, args.duration), "split_chain": bool(args.split),
-                       "compact_out_bits": int(args.serve_compact) or None},
+                       "compact_out_bits": int(args.serve_compact) or None, "slots": args.serve_slots,
+                       "chunk_energies": args.serve_chunk},
             "p50_latency_s": rep["p50_latency_s"], "p99_latency_s": rep["p99_latency_s"], "report": rep}
     print(json.dumps(line), flush=True)
 
