@@ -107,9 +107,11 @@ def traffic_from_profile(scheme, variant=None):
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != kernel_hash(src) or kv.get("scheme") != scheme:
         return None
-    if "tile_variant" in kv and variant is not None and int(kv["tile_variant"]) != variant:
-        return None
     try:
+        if variant is not None and "hbm_bytes_per_launch_variant_%d" % variant in kv:
+            return float(kv["hbm_bytes_per_launch_variant_%d" % variant])
+        if "tile_variant" in kv and variant is not None and int(kv["tile_variant"]) != variant:
+            return None
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
