@@ -276,10 +276,12 @@ class GpuExecutor:
         # out_bits < 64 -- G^R_{i,i+1}, G^R_{i+1,i}, G^<_{i,i+1} are written as FPX
         # bytes of that width (Section V-A); the observables read only the
         # diagonal blocks, which stay complex128.
-        if split and out_bits not in (0, 64):
-            raise ValueError("FPX outputs are not available for split chains")
         self.sigma_diag = bool(sigma_diag)
         self.out_bits = 64 if out_bits in (0, 64) else int(out_bits)
+        if self.out_bits != 64 and (self.out_bits % 8 or not 16 <= self.out_bits <= 56):
+            raise ValueError("out_bits: 64 (complex128) or an FPX width 16, 24, .., 56")
+        if split and self.out_bits != 64:
+            raise ValueError("FPX outputs are not available for split chains")
         self.device = device
         self.ctx = [qtx.Context(device, workspace_bytes=workspace_per_slot) for _ in range(n_slots)]
         if workspace_per_slot:

@@ -139,3 +139,13 @@ def test_executor_footprint_compact_forms():
     per = 2 * 10 * 256 * 16 + 2 * 10 * bb + 3 * 9 * (2 * 256 * 256 * 32 // 8)
     assert ex.footprint(r, 3) == 3 * per
     assert ex.footprint(r, 1) / (67 * bb) < 0.52                   # about half the dense bytes
+
+
+def test_executor_rejects_bad_storage_forms():
+    """Checked before any device work: an FPX width the library does not take, and FPX
+    outputs with split chains."""
+    import pytest
+    from paper_2606_25595_amd.serve import GpuExecutor
+    for kw in (dict(out_bits=20), dict(out_bits=8), dict(out_bits=60), dict(out_bits=32, split=True)):
+        with pytest.raises(ValueError):
+            GpuExecutor(**kw)
