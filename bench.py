@@ -193,6 +193,8 @@ def main():
     ap.add_argument("--time-limit", type=float, default=150.0, help="serve workload: wall-clock cap (s)")
     ap.add_argument("--serve-slots", type=int, default=3, help="serve workload: launches in flight (library contexts)")
     ap.add_argument("--serve-chunk", type=int, default=16, help="serve workload: energies per chunk")
+    ap.add_argument("--serve-policy", default="fifo", choices=["fifo", "sjf"],
+                    help="serve workload: admission order (arrival order, or least work first with aging)")
     ap.add_argument("--serve-compact", type=int, default=0,
                     help="serve workload: X in 16..56 stores the self-energies as b-vectors and the off-diagonal "
                          "outputs as FPX X-bit bytes (0: dense complex128)")
@@ -1230,7 +1232,8 @@ def bench_serve(args):
             log("bench serve: %d requests completed (latest: id %d, %d energies, %.2f s)"
                 % (n_done[0], r.rid, r.n_e, r.latency))
 
-    srv = Server(ex, hbm_budget=budget, chunk_energies=args.serve_chunk, max_pending=512, on_done=done)
+    srv = Server(ex, hbm_budget=budget, chunk_energies=args.serve_chunk, max_pending=512, on_done=done,
+                 policy=args.serve_policy)
     rep = srv.run(reqs, time_limit=args.time_limit)
     ex.close()
     line = {"metric": "served RGF energy points/sec with p50/p99 request latency",
@@ -1243,6 +1246,7 @@ def bench_serve(args):
             "config": {"workload": "serve: Poisson %.1f/s for %.1f s, b 128..512, n_b 8..48, N_E 16..128"
                                    % (args.rate, args.duration), "split_chain": bool(args.split),
                        "compact_out_bits": int(args.serve_compact) or None, "slots": args.serve_slots,
+                       "policy": args.serve_policy,
                        "chunk_energies": args.serve_chunk},
             "p50_latency_s": rep["p50_latency_s"], "p99_latency_s": rep["p99_latency_s"], "report": rep}
     print(json.dumps(line), flush=True)

@@ -121,9 +121,17 @@ class Server:
 
     def __init__(self, executor, hbm_budget: int, chunk_energies: int = 8, max_pending: int = 1 << 30,
                  clock: Callable[[], float] = time.perf_counter,
-                 on_done: Optional[Callable[[Request], None]] = None):
+                 on_done: Optional[Callable[[Request], None]] = None, policy: str = "fifo",
+                 max_wait: float = 10.0):
+        if policy not in ("fifo", "sjf"):
+            raise ValueError("policy: 'fifo' or 'sjf'")
         self.ex = executor
         self.on_done = on_done   # called with each request as it completes
+        # admission order: "fifo" = arrival order; "sjf" = the pending request with the
+        # least work first (flops of its selected solves), except that a request pending
+        # for max_wait seconds or more is admitted first (no starvation)
+        self.policy = policy
+        self.max_wait = float(max_wait)
         self.budget = int(hbm_budget)
         self.chunk_energies = int(chunk_energies)
         self.max_pending = int(max_pending)
@@ -175,15 +183,16 @@ class Server:
                         if self.on_done is not None:
                             self.on_done(r)
                 progress = True
-        # admit in arrival order while memory allows (head-of-line: no overtaking,
-        # so every request eventually runs)
+        # admit while memory allows, in the policy's order (the chosen chunk must fit:
+        # no overtaking past it, so every request eventually runs)
         while self.pending:
-            c = self.pending[0]
+            i = self._pick()
+            c = self.pending[i]
             r = c.req
             extra = 0 if r.rid in self.active_requests else self.ex.request_bytes(r)
             if self.used + c.nbytes + extra > self.budget:
                 break
-            self.pending.popleft()
+            del self.pending[i]
             if extra:
                 r.t_admit = self.clock()
                 self.ex.start_request(r)
@@ -206,6 +215,24 @@ class Server:
                 self.max_chunks_per_launch = max(self.max_chunks_per_launch, len(batch))
                 progress = True
         return progress
+
+    @staticmethod
+    def work(req: Request) -> float:
+        """Flops of a request's selected solves: [144 (n_b - 1) + 24] b^3 per energy."""
+        return req.n_e * (144.0 * (req.n_b - 1) + 24.0) * float(req.b) ** 3
+
+    def _pick(self) -> int:
+        """Index of the pending chunk to admit next."""
+        if self.policy == "fifo" or len(self.pending) <= 1:
+            return 0
+        if self.clock() - self.pending[0].req.t_arrive >= self.max_wait:
+            return 0          # the oldest request has waited long enough
+        best, best_w = 0, None
+        for i, c in enumerate(self.pending):
+            w = self.work(c.req)
+            if best_w is None or w < best_w:   # strict: the earliest chunk of the lightest request
+                best, best_w = i, w
+        return best
 
     def idle(self) -> bool:
         return not (self.pending or self.ready or self.inflight)

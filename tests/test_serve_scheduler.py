@@ -149,3 +149,52 @@ def test_executor_rejects_bad_storage_forms():
     for kw in (dict(out_bits=20), dict(out_bits=8), dict(out_bits=60), dict(out_bits=32, split=True)):
         with pytest.raises(ValueError):
             GpuExecutor(**kw)
+
+
+def _two_requests():
+    big = Request(rid=0, b=64, n_b=10, n_e=8, seed=1, t_arrive=0.0)
+    small = Request(rid=1, b=16, n_b=4, n_e=2, seed=2, t_arrive=0.001)
+    return big, small
+
+
+def test_sjf_admits_the_lighter_request_first():
+    """With room for one request at a time, shortest-job-first runs the later, lighter
+    request before the earlier heavy one; FIFO keeps arrival order."""
+    for policy, first in (("sjf", 1), ("fifo", 0)):
+        clock = VirtualClock()
+        ex = FakeExecutor(clock, n_slots=1, cost=0.05)
+        big, small = _two_requests()
+        budget = max(ex.footprint(big, 8) + ex.request_bytes(big), ex.footprint(small, 2) + ex.request_bytes(small))
+        srv = Server(ex, hbm_budget=budget, chunk_energies=8, clock=clock, policy=policy, max_wait=1e9)
+        # both pending before the first scheduling round
+        srv.submit(big)
+        srv.submit(small)
+        drive(srv, clock, [])
+        assert big.t_done is not None and small.t_done is not None
+        assert ex.launched[0][0][0] == first, (policy, ex.launched)
+
+
+def test_sjf_ages_waiting_requests():
+    """A request pending for max_wait is admitted first whatever its work."""
+    clock = VirtualClock()
+    ex = FakeExecutor(clock, n_slots=1, cost=0.05)
+    big, small = _two_requests()
+    budget = max(ex.footprint(big, 8) + ex.request_bytes(big), ex.footprint(small, 2) + ex.request_bytes(small))
+    srv = Server(ex, hbm_budget=budget, chunk_energies=8, clock=clock, policy="sjf", max_wait=0.5)
+    srv.submit(big)
+    srv.submit(small)
+    clock.t = 1.0          # the big request has waited 1 s > max_wait
+    drive(srv, clock, [])
+    assert ex.launched[0][0][0] == 0
+
+
+def test_sjf_completes_every_request_within_budget():
+    clock = VirtualClock()
+    ex = FakeExecutor(clock, n_slots=2, cost=0.002)
+    reqs = request_stream(rate=50.0, duration=2.0, seed=3, b_choices=[32, 64, 128], nb_range=(4, 12),
+                          ne_range=(4, 40))
+    budget = 4 * max(ex.footprint(r, 8) + ex.request_bytes(r) for r in reqs)
+    srv = Server(ex, hbm_budget=budget, chunk_energies=8, clock=clock, policy="sjf", max_wait=0.5)
+    drive(srv, clock, reqs)
+    assert all(r.t_done is not None for r in reqs)
+    assert srv.peak_used <= budget
