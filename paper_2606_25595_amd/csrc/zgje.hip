@@ -192,17 +192,16 @@ __global__ __launch_bounds__(PT) void gje_panel_kernel(int n, int k0, double2* X
 //  * the column loop is 2 rolled halves of 16 unrolled columns, so the current column
 //    and the pivot-column test are compile-time, and only the half that holds the
 //    column (wave-uniform) searches it;
-//  * every row is updated with one formula, v <- s v - m pr, where s = 0 and
-//    m = -1/pivot for the pivot row (which turns into pr / pivot) and s = 1,
-//    m = v_k / pivot for the others; the pivot column then takes the transform
-//    entry (1/pivot, resp. -v_k / pivot);
+//  * every row is updated with one formula, v <- v - m pr (four FMAs per complex
+//    value), where m = v_k / pivot, and m = -1/pivot for the pivot row, whose values
+//    are set to zero when it is posted (so it turns into pr / pivot); the pivot
+//    column then takes the transform entry (1/pivot, resp. -v_k / pivot);
 //  * the searching half reduces (|re| + |im|, row) over each thread's rows, then
-//    within 16-lane groups with DPP moves; each group's winner puts its half of the
-//    row in LDS next to its candidate, and every thread of that half posts its
-//    column-k values (the other half's multipliers); after a barrier every thread
-//    picks the best of the 16 candidates, the thread of the other half that holds
-//    the pivot row posts its half of it, and after a second barrier every thread
-//    updates its 16 columns.
+//    within 16-lane groups with DPP moves and selects (no branches), and posts each
+//    group's candidate and its column-k values (the other half's multipliers); after
+//    a barrier every thread picks the best of the 16 candidates, the two threads that
+//    hold the pivot row (one per half) post their halves of it, and after a second
+//    barrier every thread updates its 16 columns.
 template <int CTRL>
 __device__ inline void argmax_dpp(double& m, int& i) {
   const int2 mb = __builtin_bit_cast(int2, m);
@@ -211,7 +210,9 @@ __device__ inline void argmax_dpp(double& m, int& i) {
   ob.y = __builtin_amdgcn_update_dpp(0, mb.y, CTRL, 0xF, 0xF, false);
   const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
   const double om = __builtin_bit_cast(double, ob);
-  if (om > m || (om == m && oi < i)) { m = om; i = oi; }
+  const bool take = (om > m) | ((om == m) & (oi < i));
+  m = take ? om : m;
+  i = take ? oi : i;
 }
 __device__ inline void argmax_row16(double& m, int& i) {
   argmax_dpp<0xB1>(m, i);    // quad_perm [1,0,3,2]
@@ -233,10 +234,9 @@ __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double
   int32_t* __restrict__ prow = w.prow + (int64_t)z * n;
   int32_t* __restrict__ used = w.used + (int64_t)z * n;
 
-  __shared__ double2 cand_row[2][NG][HB];   // the searching half's columns of each group's candidate row
   __shared__ double cand_mag[2][NG];
   __shared__ int cand_idx[2][NG];
-  __shared__ double2 other_row[2][HB];      // the other half's columns of the pivot row
+  __shared__ double2 piv_row[2][2][HB];     // each half's columns of the pivot row
   __shared__ double2 colk[2][RPT * 256];    // column k of every row
   __shared__ int piv_of[NB];
 
@@ -279,12 +279,6 @@ __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double
           argmax_row16(mag, idx);
           const int grp = l >> 4;
           if ((lane & 15) == 0) { cand_mag[buf][grp] = mag; cand_idx[buf][grp] = idx; }
-#pragma unroll
-          for (int j = 0; j < RPT; ++j)
-            if (idx == l + 256 * j) {
-#pragma unroll
-              for (int c = 0; c < HB; ++c) cand_row[buf][grp][c] = v[j][c];
-            }
         }
         __syncthreads();
         double pm = cand_mag[buf][lane & (NG - 1)];
@@ -292,26 +286,27 @@ __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double
         argmax_row16(pm, p);
         // p is an unused row while k0 + k < n; pm == 0 means singular.  Defensive clamp only.
         if ((unsigned)p >= (unsigned)n) p = 0;
-        const int pl = p & 255, pj = p >> 8, pg = pl >> 4;
-        if (!srch && l == pl) {
+        const int pl = p & 255, pj = p >> 8;
+        if (l == pl) {
 #pragma unroll
           for (int j = 0; j < RPT; ++j)
             if (j == pj) {
 #pragma unroll
-              for (int c = 0; c < HB; ++c) other_row[buf][c] = v[j][c];
+              for (int c = 0; c < HB; ++c) {
+                piv_row[buf][h][c] = v[j][c];
+                v[j][c] = cmk(0.0, 0.0);
+              }
             }
         }
         __syncthreads();
-        const double2 pv = cand_row[buf][pg][kc];
+        const double2 pv = piv_row[buf][hk][kc];
         const double2 dinv = (pv.x == 0.0 && pv.y == 0.0) ? cmk(1.0, 0.0) : cinv(pv);
-        const double2* __restrict__ prs = srch ? &cand_row[buf][pg][0] : &other_row[buf][0];
-        double s[RPT];
+        const double2* __restrict__ prs = &piv_row[buf][h][0];
         double2 m[RPT], newk[RPT];
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
           const bool isp = (l + 256 * j == p);
           const double2 fd = cmul(colk[buf][l + 256 * j], dinv);
-          s[j] = isp ? 0.0 : 1.0;
           m[j] = isp ? cmk(-dinv.x, -dinv.y) : fd;
           newk[j] = isp ? dinv : cmk(-fd.x, -fd.y);
           u[j] = u[j] || isp;
@@ -328,8 +323,8 @@ __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double
             for (int q = 0; q < 8; ++q) {
               const int c = c8 + q;
               double2 nv;
-              nv.x = fma(s[j], v[j][c].x, -fma(m[j].x, pr[q].x, -m[j].y * pr[q].y));
-              nv.y = fma(s[j], v[j][c].y, -fma(m[j].x, pr[q].y, m[j].y * pr[q].x));
+              nv.x = fma(-m[j].x, pr[q].x, fma(m[j].y, pr[q].y, v[j][c].x));
+              nv.y = fma(-m[j].x, pr[q].y, fma(-m[j].y, pr[q].x, v[j][c].y));
               if (c == kc && srch) nv = newk[j];
               v[j][c] = nv;
             }
