@@ -206,9 +206,9 @@ template <int CTRL>
 __device__ inline void argmax_dpp(double& m, int& i) {
   const int2 mb = __builtin_bit_cast(int2, m);
   int2 ob;
-  ob.x = __builtin_amdgcn_update_dpp(0, mb.x, CTRL, 0xF, 0xF, false);
-  ob.y = __builtin_amdgcn_update_dpp(0, mb.y, CTRL, 0xF, 0xF, false);
-  const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
+  ob.x = __builtin_amdgcn_mov_dpp(mb.x, CTRL, 0xF, 0xF, true);
+  ob.y = __builtin_amdgcn_mov_dpp(mb.y, CTRL, 0xF, 0xF, true);
+  const int oi = __builtin_amdgcn_mov_dpp(i, CTRL, 0xF, 0xF, true);
   const double om = __builtin_bit_cast(double, ob);
   const bool take = (om > m) | ((om == m) & (oi < i));
   m = take ? om : m;
@@ -236,6 +236,7 @@ __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double
 
   __shared__ double cand_mag[2][NG];
   __shared__ int cand_idx[2][NG];
+  __shared__ double2 cand_val[2][NG];       // each candidate's column-k value
   __shared__ double2 piv_row[2][2][HB];     // each half's columns of the pivot row
   __shared__ double2 colk[2][RPT * 256];    // column k of every row
   __shared__ int piv_of[NB];
@@ -279,6 +280,9 @@ __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double
           argmax_row16(mag, idx);
           const int grp = l >> 4;
           if ((lane & 15) == 0) { cand_mag[buf][grp] = mag; cand_idx[buf][grp] = idx; }
+#pragma unroll
+          for (int j = 0; j < RPT; ++j)
+            if (idx == l + 256 * j) cand_val[buf][grp] = v[j][kc];
         }
         __syncthreads();
         double pm = cand_mag[buf][lane & (NG - 1)];
@@ -287,6 +291,10 @@ __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double
         // p is an unused row while k0 + k < n; pm == 0 means singular.  Defensive clamp only.
         if ((unsigned)p >= (unsigned)n) p = 0;
         const int pl = p & 255, pj = p >> 8;
+        const double2 pv = cand_val[buf][pl >> 4];   // the pivot (the winning candidate's value)
+        double2 ck[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) ck[j] = colk[buf][l + 256 * j];
         if (l == pl) {
 #pragma unroll
           for (int j = 0; j < RPT; ++j)
@@ -298,20 +306,21 @@ __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double
               }
             }
         }
-        __syncthreads();
-        const double2 pv = piv_row[buf][hk][kc];
+        // The reciprocal of the pivot and every row's multiplier (column k was posted
+        // before the first barrier) are formed while the pivot row is being posted.
         const double2 dinv = (pv.x == 0.0 && pv.y == 0.0) ? cmk(1.0, 0.0) : cinv(pv);
-        const double2* __restrict__ prs = &piv_row[buf][h][0];
         double2 m[RPT], newk[RPT];
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
           const bool isp = (l + 256 * j == p);
-          const double2 fd = cmul(colk[buf][l + 256 * j], dinv);
+          const double2 fd = cmul(ck[j], dinv);
           m[j] = isp ? cmk(-dinv.x, -dinv.y) : fd;
           newk[j] = isp ? dinv : cmk(-fd.x, -fd.y);
           u[j] = u[j] || isp;
           pivcol[j] = isp ? k : pivcol[j];
         }
+        __syncthreads();
+        const double2* __restrict__ prs = &piv_row[buf][h][0];
 #pragma unroll
         for (int c8 = 0; c8 < HB; c8 += 8) {
           double2 pr[8];
