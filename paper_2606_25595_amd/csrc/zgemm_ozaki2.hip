@@ -120,9 +120,9 @@ __global__ __launch_bounds__(NT) void o2_residue_kernel(SplitDesc sd, O2Params P
 // rows of S = op(X) over all of K in LDS (coalesced loads; element (r, k) at
 // r KP + (k ^ r), so the rows of one k fall in distinct banks), finds the row
 // exponents (wave w reduces row w), and writes every (modulus, strip) block of its
-// rows: RB rows x 2 planes x 64 bytes contiguous, 2 RB bytes per lane of a wave
-// (lane -> row l / (64 / RB), plane, 2 RB consecutive k of the strip); wave w
-// converts strips w, w + RB, ...
+// rows, 16 bytes per lane (lane -> strip of its wave's pass, row, plane, 16
+// consecutive k); wave w converts strips 8w / RB .. 8(w + 1) / RB - 1, then the next
+// RB such groups.
 constexpr int kO2FusedMaxK = 512;   // RB rows x 512 x 16 B of LDS (64 KB at RB = 8)
 constexpr int kO2ConvRows = 4;      // rows per conversion workgroup (4: five workgroups per CU at K = 512;
                                     // faster than 8 or 2 on MI355X for both load orders)
@@ -131,8 +131,6 @@ template <int RB>
 __global__ __launch_bounds__(64 * RB) void o2_convert_kernel(SplitDesc sd, O2Params P) {
   static_assert(RB == 2 || RB == 4 || RB == 8, "rows per workgroup");
   constexpr int CT = 64 * RB;          // threads
-  constexpr int LPR = 64 / RB;         // lanes per row in the residue phase
-  constexpr int VPL = 2 * RB;          // values (bytes) per lane and strip
   extern __shared__ double2 rows_lds[];   // [RB][KP], KP = KT * 64 (zero-padded), swizzled
   // 1-D grid over (entry, row group), remapped so that each XCD takes a contiguous run of
   // row groups of one entry: with trans = 1 a group is RB adjacent columns (RB * 16 bytes
@@ -186,46 +184,53 @@ __global__ __launch_bounds__(64 * RB) void o2_convert_kernel(SplitDesc sd, O2Par
     if (lane == 0 && r0 + r < sd.rows) sd.E[(int64_t)z * sd.e_stride + r0 + r] = e;
   }
   __syncthreads();   // the exponents are read back below (same workgroup)
-  const int r = lane / LPR, c = (lane / (LPR / 2)) & 1, ks = lane % (LPR / 2);
+  // Residues: a lane takes 16 consecutive k of one (row, plane) of a strip, so a wave
+  // covers SPW = 8 / RB strips per pass and stores 16 bytes per lane and modulus.  The
+  // symmetric residue a - m rint(a / m) is formed exactly with the rounding constant
+  // R = 1.5 2^52 (|a| <= 2^47, |a / m| < 2^40): fma(a, 1/m, R) - R is the nearest integer
+  // q to a / m (the fraction of a / m is a multiple of 1/m, m odd, so the rounded 1/m
+  // cannot move it across a half), and fma(-q, m, a + R) = R + (a - q m) exactly, whose
+  // low byte is the residue's two's-complement byte.
+  constexpr int SPW = 8 / RB;
+  const int ks = lane & 3, c = (lane >> 2) & 1, r = (lane >> 3) % RB, sub = lane / (8 * RB);
   const bool live = r0 + r < sd.rows;
   const int er = live ? sd.E[(int64_t)z * sd.e_stride + r0 + r] : 0;
   const bool fin = er != kExpNonFinite;   // a non-finite row gets zero residues
   const double sc = (live && fin) ? pow2(P.kbits + 1 - er) : 0.0;
+  constexpr double R = 6755399441055744.0;   // 1.5 * 2^52
   int8_t* out = (int8_t*)sd.S + (int64_t)z * sd.s_stride;
-  for (int kt = wave; kt < KT; kt += RB) {
-    double a[VPL];
+  for (int kt0 = wave * SPW; kt0 < KT; kt0 += RB * SPW) {
+    const int kt = kt0 + sub;
+    const bool ok = live && kt < KT;
+    double a[16], ar[16];
     const double2* src = rows_lds + r * pitch;
-    const int k0 = kt * KS + VPL * ks;
+    const int k0 = (kt < KT ? kt : KT - 1) * KS + 16 * ks;
 #pragma unroll
-    for (int j = 0; j < VPL; ++j) {
+    for (int j = 0; j < 16; ++j) {
       const double2 v = src[(k0 + j) ^ r];
       a[j] = fin ? rint((c ? v.y : v.x) * sc) : 0.0;
+      ar[j] = a[j] + R;
     }
-    for (int i = 0; i < P.p; ++i) {
-      const double m = P.m[i], im = P.inv_m[i];
-      uint32_t w[VPL / 4];
+    int8_t* dst = out + (((int64_t)kt * 4 + 2 * c + (ks >> 1)) * sd.rows + r0 + r) * 32 + 16 * (ks & 1);
+    const int64_t mstride = (int64_t)KT * 4 * sd.rows * 32;   // bytes per modulus
 #pragma unroll
-      for (int q = 0; q < VPL / 4; ++q) w[q] = 0u;
+    for (int i = 0; i < kO2MaxModuli; ++i) {
+      if (i < P.p) {
+        const double m = P.m[i], im = P.inv_m[i];
+        uint32_t lo[16];
 #pragma unroll
-      for (int j = 0; j < VPL; ++j) {
-        const double q = rint(a[j] * im);
-        const int rr = (int)fma(-q, m, a[j]);
-        w[j >> 2] |= ((uint32_t)rr & 0xffu) << (8 * (j & 3));
-      }
-      if (live) {
-        const int kk = VPL * ks;   // k within the strip (VPL <= 16 bytes never cross a 32-k part)
-        int8_t* dst = out + ((((int64_t)i * KT + kt) * 4 + 2 * c + kk / 32) * sd.rows + r0 + r) * 32 + kk % 32;
-        if constexpr (VPL == 16) {
-          u4 pk = {w[0], w[1], w[2], w[3]};
-          *(u4*)dst = pk;
-        } else if constexpr (VPL == 8) {
-          uint2 pk;
-          pk.x = w[0];
-          pk.y = w[1];
-          *(uint2*)dst = pk;
-        } else {
-          *(uint32_t*)dst = w[0];
+        for (int j = 0; j < 16; ++j) {
+          const double q = fma(a[j], im, R) - R;
+          lo[j] = (uint32_t)__builtin_bit_cast(uint64_t, fma(-q, m, ar[j]));
         }
+        u4 pk;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const uint32_t p01 = __builtin_amdgcn_perm(lo[4 * w + 1], lo[4 * w], 0x0c0c0400u);
+          const uint32_t p23 = __builtin_amdgcn_perm(lo[4 * w + 3], lo[4 * w + 2], 0x0c0c0400u);
+          pk[w] = __builtin_amdgcn_perm(p23, p01, 0x05040100u);
+        }
+        if (ok) *(u4*)(dst + i * mstride) = pk;
       }
     }
   }
