@@ -80,6 +80,9 @@ struct GemmDesc {
   // rule from the shape (the autotuner's choice when it has one).  Results do not depend
   // on it.
   int tile = 0;
+  // Inversion update only (C = X + A B with X = C): columns [skip_c0, skip_c1) of B are
+  // zero, so C keeps its values there and output tiles inside that range are skipped.
+  int skip_c0 = 0, skip_c1 = 0;
 };
 
 // Precision schemes of the complex block products.

@@ -279,6 +279,8 @@ __global__ __launch_bounds__(NT) void zgemm_update_kernel(GemmDesc d) {
   const int t = tile - z * per;
   const int m0 = (t % tiles_m) * BM;
   const int n0 = (t / tiles_m) * BN;
+  // a tile whose columns all lie where B is zero keeps X (workgroup-uniform)
+  if (n0 >= d.skip_c0 && min(n0 + BN, d.N) <= d.skip_c1) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1, li = lane & 15, lk = lane >> 4;
   const int M = d.M, N = d.N, K = d.K;

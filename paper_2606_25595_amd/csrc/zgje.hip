@@ -473,6 +473,7 @@ hipError_t launch_gje_invert(int n, double2* X, int64_t sX, double2* Out, int64_
     d.alpha = cmk(1.0, 0.0);
     d.add[0].X = X; d.add[0].ld = n; d.add[0].stride = sX; d.add[0].coef = cmk(1.0, 0.0);
     d.batch = batch;
+    d.skip_c0 = k0; d.skip_c1 = k0 + kw;   // Tp is zero in the panel's columns
     e = launch_zgemm_f64(d, s, GEMM_INV_UPDATE);
     if (e != hipSuccess) return e;
   }
