@@ -198,10 +198,11 @@ __global__ __launch_bounds__(PT) void gje_panel_kernel(int n, int k0, double2* X
 //    column then takes the transform entry (1/pivot, resp. -v_k / pivot);
 //  * the searching half reduces (|re| + |im|, row) over each thread's rows, then
 //    within 16-lane groups with DPP moves and selects (no branches), and posts each
-//    group's candidate and its column-k values (the other half's multipliers); after
-//    a barrier every thread picks the best of the 16 candidates, the two threads that
-//    hold the pivot row (one per half) post their halves of it, and after a second
-//    barrier every thread updates its 16 columns.
+//    group's candidate (magnitude, row and column-k value) and every row's column-k
+//    value; after a barrier every thread picks the best of the 16 candidates, the two
+//    threads that hold the pivot row (one per half) post their halves of it while
+//    every thread forms the pivot's reciprocal and its rows' multipliers, and after a
+//    second barrier every thread updates its 16 columns.
 template <int CTRL>
 __device__ inline void argmax_dpp(double& m, int& i) {
   const int2 mb = __builtin_bit_cast(int2, m);
