@@ -550,7 +550,8 @@ __device__ inline KGemmDesc& kernarg_desc() {
 // w % 8 and takes that XCD's tiles (a contiguous range) in rounds of the XCD's
 // workgroup count, so the workgroups sharing an L2 work on adjacent tiles of the
 // same energies in step and read each residue strip from HBM about once.
-// Otherwise one tile per workgroup.
+// Otherwise one tile per workgroup.  A skew-Hermitian product's tile index runs over
+// the tiles that reach the upper triangle only.
 template <class CF, bool CONJB>
 __global__ __launch_bounds__(CF::NT) __attribute__((amdgpu_waves_per_eu(CF::WAVES_PER_SIMD)))
 void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles, int persist) {
@@ -567,7 +568,14 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles, int persist) 
   }
   const int tiles_m = (g.d.M + BM - 1) / BM;
   const int tiles_n = (g.d.N + BN - 1) / BN;
-  const int per = tiles_m * tiles_n;
+  const bool skew = g.d.skew != 0;
+  // a skew-Hermitian result enumerates only the tiles that reach the upper triangle:
+  // column tn keeps the first ceil((tn + 1) BN / BM) row tiles
+  int per = tiles_m * tiles_n;
+  if (skew) {
+    per = 0;
+    for (int tn = 0; tn < tiles_n; ++tn) per += min(tiles_m, ((tn + 1) * BN + BM - 1) / BM);
+  }
   int first, last, step;
   if (persist) {
     const int nx = 8, x = blockIdx.x % nx, wpx = gridDim.x / nx;
@@ -582,11 +590,22 @@ void zgemm_o2_kernel(SplitGemmDesc g, O2Params P, int total_tiles, int persist) 
   }
   for (int tile = first; tile < last; tile += step) {
   const int z = tile / per;
-  const int t = tile - z * per;
-  const int m0 = (t % tiles_m) * BM;
-  const int n0 = (t / tiles_m) * BN;
-  const bool skew = g.d.skew != 0;
-  if (skew && m0 >= n0 + BN) continue;   // strictly below the diagonal (workgroup-uniform)
+  int t = tile - z * per;
+  int m0, n0;
+  if (skew) {
+    int tn = 0;
+    for (;;) {
+      const int cn = min(tiles_m, ((tn + 1) * BN + BM - 1) / BM);
+      if (t < cn) break;
+      t -= cn;
+      ++tn;
+    }
+    m0 = t * BM;
+    n0 = tn * BN;
+  } else {
+    m0 = (t % tiles_m) * BM;
+    n0 = (t / tiles_m) * BN;
+  }
   const int M = g.d.M, N = g.d.N, K = g.d.K;
   const int KT = (K + KS - 1) / KS;
   const int NSTRIP = P.p * KT;                  // (modulus, strip) pairs, modulus-major
@@ -816,7 +835,13 @@ namespace {
 template <class CF>
 hipError_t launch_o2_variant(const SplitGemmDesc& g, const O2Params& P, hipStream_t s, bool allow_persist) {
   const GemmDesc& d = g.d;
-  const int64_t total = (int64_t)((d.M + CF::BM - 1) / CF::BM) * ((d.N + CF::BN - 1) / CF::BN) * d.batch;
+  const int tm = (d.M + CF::BM - 1) / CF::BM, tn = (d.N + CF::BN - 1) / CF::BN;
+  int64_t per = (int64_t)tm * tn;
+  if (d.skew) {   // the tiles that reach the upper triangle (as the kernel enumerates them)
+    per = 0;
+    for (int j = 0; j < tn; ++j) per += std::min(tm, ((j + 1) * CF::BN + CF::BM - 1) / CF::BM);
+  }
+  const int64_t total = per * d.batch;
   if (total > 0x7fffffff) return hipErrorInvalidValue;
   // WPC workgroups per CU (what the kernel's LDS and registers admit) when there are more tiles
   static int cus[64] = {0};
@@ -846,9 +871,7 @@ hipError_t launch_zgemm_o2(const SplitGemmDesc& g, const O2Params& P, hipStream_
   if (d.skew && d.M != d.N) return hipErrorInvalidValue;
   if (o2_res_stride(d.M, d.K, P.p) > 0x7fffffff || o2_res_stride(d.N, d.K, P.p) > 0x7fffffff)
     return hipErrorInvalidValue;   // per-entry residue offsets are 32-bit in the kernel
-  // A skew-Hermitian result skips the tiles below the diagonal, which would leave
-  // persistent rounds unbalanced: such products always run one tile per workgroup.
-  const bool persist = !d.skew;
+  const bool persist = true;
   switch (variant) {
     case 0: return launch_o2_variant<O2V0>(g, P, s, persist);
     case 1: return launch_o2_variant<O2V1>(g, P, s, persist);
