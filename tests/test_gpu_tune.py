@@ -191,6 +191,41 @@ def test_variants_bitwise_equal_persistent_rounds(ctx, M, N, K, batch, ops):
     assert np.abs(outs[0] - ref).max() <= bound
 
 
+def test_skew_products_in_persistent_rounds_every_variant(ctx):
+    """A solve whose skew-Hermitian INT8 products (G^< blocks) have more upper-triangle
+    tiles than the persistent grid holds (b = 416, 40 energies: 28 x 40 = 1120 tiles of
+    64 x 64 against 768 workgroups of variant 4; 10 x 40 = 400 tiles of 128 x 128 against
+    256), under every forced tile variant: the same bits as the tuned solve, and the
+    tuned solve within the scheme's bound of the oracle on two energies."""
+    import torch
+    from paper_2606_25595_amd import qtx
+    p = inputs.random_bt_problem(3, 416, np.linspace(-1.8, 1.7, 40), seed=5)
+    keys = ("GR_d", "GR_u", "GR_l", "GL_d", "GL_u")
+
+    def solve():
+        dp = qtx.to_device(p)
+        ctx.solve(dp, prec="int8", n_slices=10, prec_lesser="int8", n_slices_lesser=11)
+        torch.cuda.synchronize()
+        assert bool((dp.status == 0).all())
+        return dp
+    ref_dp = solve()
+    try:
+        for v in range(N_VARIANTS):
+            ctx.set_int8_tile_variant(v)
+            dp = solve()
+            for k in keys:
+                a, b = getattr(dp, k), getattr(ref_dp, k)
+                assert torch.equal(torch.view_as_real(a), torch.view_as_real(b)), (v, k)
+            del dp
+    finally:
+        ctx.set_int8_tile_variant(-1)
+    sample = [3, 31]
+    ref = oracle.rgf_selected(p.subset(sample))
+    for k in keys:
+        got = getattr(ref_dp, k)[sample].cpu().numpy()
+        assert oracle.rel_fro_err(got, ref[k]).max() <= 1e-6, k
+
+
 @pytest.mark.parametrize("prec,ns", [("fp64", 0), ("fp32", 0), ("bf16", 4), ("fp16", 3)])
 def test_tile_tuning_bitwise_and_solve_unchanged(prec, ns):
     """FP64, FP32 and split products with 32 x 32 or 64 x 64 tiles (forced through the
