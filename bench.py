@@ -135,7 +135,7 @@ def _oracle_one_energy(args):
 
 def host_cores():
     """CPU cores this process may use (its affinity mask), at most 16 (one GPU's share
-    of the machine's host cores)."""
+    of the host's cores on an eight-GPU node)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:

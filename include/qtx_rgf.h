@@ -57,7 +57,7 @@ typedef enum {
   QTX_ERR_ARG = 1,          /* invalid argument (nothing enqueued)                 */
   QTX_ERR_NOMEM = 2,        /* workspace could not be allocated                    */
   QTX_ERR_HIP = 3,          /* a HIP runtime call failed (sticky for the context)  */
-  QTX_ERR_UNSUPPORTED = 4,  /* valid request this build does not implement          */
+  QTX_ERR_UNSUPPORTED = 4,  /* valid request the library does not implement        */
   QTX_ERR_SINGULAR = 5,     /* per energy: an exactly zero pivot in an inversion   */
   QTX_ERR_NONFINITE = 6     /* per energy: NaN or Inf in the result                */
 } qtx_status;
