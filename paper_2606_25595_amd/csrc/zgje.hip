@@ -241,6 +241,13 @@ __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double
   __shared__ double2 piv_row[2][2][HB];     // each half's columns of the pivot row
   __shared__ double2 colk[2][RPT * 256];    // column k of every row
   __shared__ int piv_of[NB];
+  // One half of the panel (16 columns of every row, pitch 17 so that the threads of a
+  // wave, one row each, read distinct banks): the panel moves between HBM and the
+  // threads' registers through it, 16 lanes per row (256 contiguous bytes), instead of
+  // one row per lane (16 bytes of 64 rows per load).
+  constexpr int SP = HB + 1;
+  __shared__ double2 stage[RPT * 256 * SP];
+  const int tot = n * HB;   // staged elements per half
 
   bool u[RPT];
   int pivcol[RPT];
@@ -250,11 +257,31 @@ __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double
     const int r = l + 256 * j;
     u[j] = (r >= n) || (used[r] != 0);
     pivcol[j] = -1;
+  }
+  for (int hh = 0; hh < 2; ++hh) {
+    for (int e0 = 0; e0 < tot; e0 += PT32 * 4) {
+      double2 t[4];
 #pragma unroll
-    for (int c = 0; c < HB; ++c) {
-      const int gc = HB * h + c;
-      v[j][c] = (r < n && gc < nbw) ? Xz[(int64_t)r * n + k0 + gc] : cmk(0.0, 0.0);
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + PT32 * q + tid, row = e >> 4, gc = HB * hh + (e & 15);
+        t[q] = (e < tot && gc < nbw) ? Xz[(int64_t)row * n + k0 + gc] : cmk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + PT32 * q + tid;
+        if (e < tot) stage[(e >> 4) * SP + (e & 15)] = t[q];
+      }
     }
+    __syncthreads();
+    if (h == hh) {
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const int r = l + 256 * j;
+#pragma unroll
+        for (int c = 0; c < HB; ++c) v[j][c] = (r < n) ? stage[r * SP + c] : cmk(0.0, 0.0);
+      }
+    }
+    __syncthreads();
   }
   bool singular = false;
 
@@ -349,22 +376,39 @@ __global__ __launch_bounds__(PT32) void gje_panel32_kernel(int n, int k0, double
   }
   __syncthreads();
 
-  // write back this half's panel columns, its columns of the shifted transform Wp, the usage flags
+  // write back the panel columns and the shifted transform Wp (the panel minus a unit at
+  // each pivot: row piv_of[k] of column k), one half at a time through the stage, and the
+  // usage flags
   double2* __restrict__ Wp = w.Wp + (int64_t)z * n * NB;
+  for (int hh = 0; hh < 2; ++hh) {
+    if (h == hh) {
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const int r = l + 256 * j;
+        if (r < n) {
+#pragma unroll
+          for (int c = 0; c < HB; ++c) stage[r * SP + c] = v[j][c];
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < tot; e += PT32) {
+      const int row = e >> 4, gc = HB * hh + (e & 15);
+      const double2 val = stage[row * SP + (e & 15)];
+      double2 wv = cmk(0.0, 0.0);
+      if (gc < nbw) {
+        Xz[(int64_t)row * n + k0 + gc] = val;
+        wv = val;
+        if (piv_of[gc] == row) wv.x -= 1.0;
+      }
+      Wp[(int64_t)row * NB + gc] = wv;
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
     const int r = l + 256 * j;
-    if (r < n) {
-#pragma unroll
-      for (int c = 0; c < HB; ++c) {
-        const int gc = HB * h + c;
-        if (gc < nbw) Xz[(int64_t)r * n + k0 + gc] = v[j][c];
-        double2 wv = (gc < nbw) ? v[j][c] : cmk(0.0, 0.0);
-        if (gc == pivcol[j]) wv.x -= 1.0;
-        Wp[(int64_t)r * NB + gc] = wv;
-      }
-      if (h == 0 && pivcol[j] >= 0) used[r] = 1;
-    }
+    if (r < n && h == 0 && pivcol[j] >= 0) used[r] = 1;
   }
   // pivot rows of this panel (pre-update values outside the panel), panel columns zeroed
   double2* __restrict__ Tp = w.Tp + (int64_t)z * NB * n;
