@@ -148,11 +148,12 @@ def test_zinv_update_tilings_bitwise(ctx):
     assert rel(o[0], np.linalg.inv(A[0])) <= 200 * np.linalg.cond(A[0]) * 2.2e-16
 
 
-def test_zinv_forced_pivoting(ctx):
-    """Zero leading entries force row exchanges in every panel."""
+@pytest.mark.parametrize("n", [96, 416, 512])
+def test_zinv_forced_pivoting(ctx, n):
+    """Zero leading entries force row exchanges in every panel (at n = 416 and 512 the
+    pivots come from both row halves of the panel's threads, rows >= 256 included)."""
     import torch
     rng = np.random.default_rng(1)
-    n = 96
     P = np.eye(n)[rng.permutation(n)]
     A = (P @ np.diag(rng.uniform(1, 2, n) * np.exp(1j * rng.uniform(0, 6, n))) + 1e-3 * crand(rng, n, n))
     A[np.abs(A) < 1e-2] = 0.0                           # exact zeros on most of the matrix
@@ -164,7 +165,7 @@ def test_zinv_forced_pivoting(ctx):
     assert rel(out.cpu().numpy()[0], np.linalg.inv(A)) < 1e-12
 
 
-@pytest.mark.parametrize("n,col", [(20, 5), (100, 40)])
+@pytest.mark.parametrize("n,col", [(20, 5), (100, 40), (416, 300), (512, 500)])
 def test_zinv_singular_is_flagged(ctx, n, col):
     import torch
     rng = np.random.default_rng(2)
